@@ -1,0 +1,413 @@
+/*
+ * CPU oracle for the LRI exact-exchange energy, forces and stress.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library, and it is deliberately plain:
+ * FP64 throughout, the quartet loop of the paper in the paper's order, no
+ * folding over lattice images, no symmetry tricks, no BLAS.
+ *
+ * What it computes (Gamma point, real tensors, one simulation cell):
+ *
+ *   E = - sum_{V blocks (A,B,R_B)} sum_{C blocks (A,F,R_F)} sum_{C blocks (B,G,R')}
+ *         sum C1[al][a][f] V[al][be] C2[be][b][g]
+ *             ( D(A,B)[a][b] D(F,G)[f][g] + D(A,G)[a][g] D(F,B)[f][b] )
+ *
+ *   This is the ABF-centred form of the LRI exchange energy (Methods, Eq.
+ *   exx_expand, from Eqs. Exx-LRI and ABFG_perspective), with the atom A of
+ *   the V block in the home cell, every partner an explicit lattice image, the
+ *   Gamma-point density matrix the same for every image pair (N_k = 1), and
+ *   Re[] dropped because every tensor is real.  Blocks removed by screening
+ *   simply do not take part (Sec. Sparsity exploitation).
+ *
+ *   Every block is a function of its own displacement r = tau_second + R.L -
+ *   tau_first, and the caller supplies d(block)/dr.  The force F^{X1} is the
+ *   six-term derivative of Eq. Fexx1 with D held fixed (the D-variation part
+ *   F^{X2} of Eq. Exx2 is not part of this quantity); here each quartet's
+ *   three derivative slots (the C of A, the V, the C of B; Eq.
+ *   Exx_energy_variation) are accumulated into a per-block gradient
+ *   g_b = dE/dr_b, from which F_first += g, F_second -= g.
+ *   The stress follows Eq. stress: sigma = -(1/Omega) sum_b g_b (x) r_b.
+ *
+ * Screening (Sec. Sparsity exploitation; thresholds as in Table thr_default
+ * and Sec. on the Cauchy-Schwarz screening), in the reading used by this
+ * project:
+ *   S1 (theta > 0): keep a C block iff max|C| > theta or max|dC| > theta;
+ *       keep a V block iff the max over the block and its mirror
+ *       (B,A,-R) of max|V|, max|dV| exceeds theta; keep the D pair (X,Y) iff
+ *       max|D_XY| > theta, taken on the block with X <= Y.
+ *   S2 (theta_cs > 0): keep a surviving V block iff
+ *       nv * S(A,B) > theta_cs, nv = max of the Frobenius norms of V, dV of
+ *       the block and its mirror, and
+ *       S(A,B) = sum_F sum_G c(A,F) c(B,G) [d(A,B) d(F,G) + d(A,G) d(F,B)],
+ *       c(A,F) = sum over kept C blocks (A,F,R) of max(|C|_F, |dC|_F),
+ *       d(X,Y) = |D_XY|_F of a kept D pair (block with X <= Y), else 0.
+ *       S is evaluated for A <= B and mirrored.  This is the Cauchy-Schwarz
+ *       bound of Sec. Sparsity exploitation summed over the items of one V
+ *       pair.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+  int32_t natom;
+  const double* tau;     /* [natom][3] */
+  const double* lat;     /* [3][3], rows are lattice vectors */
+  const int32_t* nao;    /* [natom] */
+  const int32_t* nabf;   /* [natom] */
+  int64_t nC;
+  const int32_t* C_first; const int32_t* C_second; const int32_t* C_R; const int64_t* C_off;
+  const double* C_val; const double* C_dval;
+  int64_t nV;
+  const int32_t* V_first; const int32_t* V_second; const int32_t* V_R; const int64_t* V_off;
+  const double* V_val; const double* V_dval;
+  const double* D;       /* dense [n_tot][n_tot] */
+} orc_input;
+
+/* ------------------------------------------------------------------------ */
+static int64_t ntot_of(const orc_input* in, int64_t* ao_off) {
+  int64_t s = 0;
+  for (int i = 0; i < in->natom; ++i) { ao_off[i] = s; s += in->nao[i]; }
+  ao_off[in->natom] = s;
+  return s;
+}
+
+static int64_t c_size(const orc_input* in, int64_t b) {
+  return (int64_t)in->nabf[in->C_first[b]] * in->nao[in->C_first[b]] * in->nao[in->C_second[b]];
+}
+static int64_t v_size(const orc_input* in, int64_t b) {
+  return (int64_t)in->nabf[in->V_first[b]] * in->nabf[in->V_second[b]];
+}
+
+static void block_norms(const double* val, const double* dval, int64_t n, double out[4]) {
+  double mv = 0, md = 0, sv = 0, sd = 0;
+  for (int64_t i = 0; i < n; ++i) { double x = fabs(val[i]); if (x > mv) mv = x; sv += val[i] * val[i]; }
+  for (int64_t i = 0; i < 3 * n; ++i) { double x = fabs(dval[i]); if (x > md) md = x; sd += dval[i] * dval[i]; }
+  out[0] = mv; out[1] = md; out[2] = sqrt(sv); out[3] = sqrt(sd);
+}
+
+/* mirror of V block b: the block (second, first, -R) */
+static int64_t v_mirror(const orc_input* in, int64_t b) {
+  for (int64_t j = 0; j < in->nV; ++j)
+    if (in->V_first[j] == in->V_second[b] && in->V_second[j] == in->V_first[b] &&
+        in->V_R[3 * j] == -in->V_R[3 * b] && in->V_R[3 * j + 1] == -in->V_R[3 * b + 1] &&
+        in->V_R[3 * j + 2] == -in->V_R[3 * b + 2])
+      return j;
+  return -1;
+}
+
+/*
+ * Screening decisions (S1 then S2).  keepC[nC], keepV[nV], keepD[natom*natom].
+ * Returns 0, or -1 if a V block has no mirror.
+ */
+int orc_screen(const orc_input* in, double theta, double theta_cs,
+               uint8_t* keepC, uint8_t* keepV, uint8_t* keepD, double* S_out) {
+  const int N = in->natom;
+  int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+  const int64_t nt = ntot_of(in, ao);
+  double* d = (double*)calloc((size_t)N * N, sizeof(double));
+  double* c = (double*)calloc((size_t)N * N, sizeof(double));
+  double* S = (double*)calloc((size_t)N * N, sizeof(double));
+  /* D pairs, decided on the block with X <= Y and mirrored */
+  for (int X = 0; X < N; ++X)
+    for (int Y = X; Y < N; ++Y) {
+      double mx = 0, ss = 0;
+      for (int i = 0; i < in->nao[X]; ++i)
+        for (int j = 0; j < in->nao[Y]; ++j) {
+          double v = in->D[(ao[X] + i) * nt + ao[Y] + j];
+          if (fabs(v) > mx) mx = fabs(v);
+          ss += v * v;
+        }
+      int keep = !(theta > 0) || mx > theta;
+      keepD[X * N + Y] = keepD[Y * N + X] = (uint8_t)keep;
+      d[X * N + Y] = d[Y * N + X] = keep ? sqrt(ss) : 0.0;
+    }
+  /* C blocks, and c(A,F) summed over kept images in key order */
+  for (int64_t b = 0; b < in->nC; ++b) {
+    double nr[4];
+    int64_t n = c_size(in, b);
+    block_norms(in->C_val + in->C_off[b], in->C_dval + 3 * in->C_off[b], n, nr);
+    int keep = !(theta > 0) || nr[0] > theta || nr[1] > theta;
+    keepC[b] = (uint8_t)keep;
+    if (keep) c[in->C_first[b] * N + in->C_second[b]] += (nr[2] > nr[3] ? nr[2] : nr[3]);
+  }
+  /* S(A,B) for A <= B, mirrored */
+  for (int A = 0; A < N; ++A)
+    for (int B = A; B < N; ++B) {
+      double s = 0;
+      for (int F = 0; F < N; ++F) {
+        double cAF = c[A * N + F];
+        if (cAF == 0) continue;
+        for (int G = 0; G < N; ++G) {
+          double cBG = c[B * N + G];
+          if (cBG == 0) continue;
+          s += cAF * cBG * (d[A * N + B] * d[F * N + G] + d[A * N + G] * d[F * N + B]);
+        }
+      }
+      S[A * N + B] = S[B * N + A] = s;
+    }
+  int rc = 0;
+  for (int64_t b = 0; b < in->nV; ++b) {
+    int64_t m = v_mirror(in, b);
+    if (m < 0) { rc = -1; keepV[b] = 0; continue; }
+    double n1[4], n2[4];
+    int64_t n = v_size(in, b);
+    block_norms(in->V_val + in->V_off[b], in->V_dval + 3 * in->V_off[b], n, n1);
+    block_norms(in->V_val + in->V_off[m], in->V_dval + 3 * in->V_off[m], n, n2);
+    double mx = fmax(fmax(n1[0], n1[1]), fmax(n2[0], n2[1]));
+    double nv = fmax(fmax(n1[2], n1[3]), fmax(n2[2], n2[3]));
+    int keep = !(theta > 0) || mx > theta;
+    if (keep && theta_cs > 0) keep = nv * S[in->V_first[b] * N + in->V_second[b]] > theta_cs;
+    keepV[b] = (uint8_t)keep;
+  }
+  if (S_out) memcpy(S_out, S, sizeof(double) * N * N);
+  free(ao); free(d); free(c); free(S);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* D block (X,Y) as a pointer into the dense matrix (row stride nt), or NULL */
+typedef struct { const double* p; int64_t ld; } dblk;
+
+static inline double dget(dblk m, int i, int j) { return m.p ? m.p[i * m.ld + j] : 0.0; }
+
+/*
+ * One quartet (C1 = C(A,F,R_F), V = V(A,B,R_B), C2 = C(B,G,R')): the item
+ *   sum C1[al][a][f] V[al][be] C2[be][b][g] K[a][f][b][g],
+ *   K = D(A,B)[a][b] D(F,G)[f][g] + D(A,G)[a][g] D(F,B)[f][b],
+ * and its derivative with respect to each of the three blocks, contracted
+ * with that block's d/dr.  E -= item; g -= d(item)/dr per slot.
+ */
+typedef struct { double* w; } scratch;
+
+static void quartet(int mA, int mB, int nA, int nF, int nB, int nG,
+                    const double* C1, const double* dC1, const double* V, const double* dV,
+                    const double* C2, const double* dC2,
+                    dblk DAB, dblk DFG, dblk DAG, dblk DFB, double* ws,
+                    double* E, double g1[3], double gv[3], double g2[3]) {
+  /* workspace: What[mB][nA][nF], Wtil[mA][nB][nG], T[nB][nF], U[nG][nF], P[nA][nG], Q[nF][nG] */
+  double* What = ws;
+  double* Wtil = What + (size_t)mB * nA * nF;
+  double* T = Wtil + (size_t)mA * nB * nG;
+  double* U = T + nB * nF;
+  double* P = U + nG * nF;
+  double* Q = P + nA * nG;
+
+  /* What[be][a][f] = sum_{b,g} C2[be][b][g] K[a][f][b][g]
+   *               = (D(A,B) C2_be D(F,G)^T)[a][f] + (D(A,G) C2_be^T D(F,B)^T)[a][f] */
+  for (int be = 0; be < mB; ++be) {
+    const double* c2 = C2 + (size_t)be * nB * nG;
+    for (int b = 0; b < nB; ++b)
+      for (int f = 0; f < nF; ++f) {
+        double s = 0;
+        for (int g = 0; g < nG; ++g) s += c2[b * nG + g] * dget(DFG, f, g);
+        T[b * nF + f] = s;
+      }
+    for (int g = 0; g < nG; ++g)
+      for (int f = 0; f < nF; ++f) {
+        double s = 0;
+        for (int b = 0; b < nB; ++b) s += c2[b * nG + g] * dget(DFB, f, b);
+        U[g * nF + f] = s;
+      }
+    double* w = What + (size_t)be * nA * nF;
+    for (int a = 0; a < nA; ++a)
+      for (int f = 0; f < nF; ++f) {
+        double s = 0;
+        for (int b = 0; b < nB; ++b) s += dget(DAB, a, b) * T[b * nF + f];
+        for (int g = 0; g < nG; ++g) s += dget(DAG, a, g) * U[g * nF + f];
+        w[a * nF + f] = s;
+      }
+  }
+  /* S[al][be] = sum_{a,f} C1[al][a][f] What[be][a][f]:  item = <V,S>, V slot = <dV,S>
+   * R1[al][af] = sum_be V[al][be] What[be][af]:          C1 slot = <dC1,R1>        */
+  const int k1 = nA * nF;
+  double item = 0, sv[3] = {0, 0, 0}, s1[3] = {0, 0, 0};
+  for (int al = 0; al < mA; ++al)
+    for (int be = 0; be < mB; ++be) {
+      double s = 0;
+      const double* c1 = C1 + (size_t)al * k1;
+      const double* w = What + (size_t)be * k1;
+      for (int k = 0; k < k1; ++k) s += c1[k] * w[k];
+      const int64_t e = (int64_t)al * mB + be;
+      item += V[e] * s;
+      for (int x = 0; x < 3; ++x) sv[x] += dV[(int64_t)x * mA * mB + e] * s;
+    }
+  for (int al = 0; al < mA; ++al)
+    for (int k = 0; k < k1; ++k) {
+      double r = 0;
+      for (int be = 0; be < mB; ++be) r += V[(int64_t)al * mB + be] * What[(size_t)be * k1 + k];
+      const int64_t e = (int64_t)al * k1 + k;
+      for (int x = 0; x < 3; ++x) s1[x] += dC1[(int64_t)x * mA * k1 + e] * r;
+    }
+  /* Wtil[al][b][g] = sum_{a,f} C1[al][a][f] K[a][f][b][g]
+   *               = (D(A,B)^T C1_al D(F,G))[b][g] + (D(F,B)^T C1_al^T D(A,G))[b][g]
+   * R2[be][bg] = sum_al V[al][be] Wtil[al][bg]:   C2 slot = <dC2,R2>             */
+  for (int al = 0; al < mA; ++al) {
+    const double* c1 = C1 + (size_t)al * k1;
+    for (int a = 0; a < nA; ++a)
+      for (int g = 0; g < nG; ++g) {
+        double s = 0;
+        for (int f = 0; f < nF; ++f) s += c1[a * nF + f] * dget(DFG, f, g);
+        P[a * nG + g] = s;
+      }
+    for (int f = 0; f < nF; ++f)
+      for (int g = 0; g < nG; ++g) {
+        double s = 0;
+        for (int a = 0; a < nA; ++a) s += c1[a * nF + f] * dget(DAG, a, g);
+        Q[f * nG + g] = s;
+      }
+    double* w = Wtil + (size_t)al * nB * nG;
+    for (int b = 0; b < nB; ++b)
+      for (int g = 0; g < nG; ++g) {
+        double s = 0;
+        for (int a = 0; a < nA; ++a) s += dget(DAB, a, b) * P[a * nG + g];
+        for (int f = 0; f < nF; ++f) s += dget(DFB, f, b) * Q[f * nG + g];
+        w[b * nG + g] = s;
+      }
+  }
+  const int k2 = nB * nG;
+  double s2[3] = {0, 0, 0};
+  for (int be = 0; be < mB; ++be)
+    for (int k = 0; k < k2; ++k) {
+      double r = 0;
+      for (int al = 0; al < mA; ++al) r += V[(int64_t)al * mB + be] * Wtil[(size_t)al * k2 + k];
+      const int64_t e = (int64_t)be * k2 + k;
+      for (int x = 0; x < 3; ++x) s2[x] += dC2[(int64_t)x * mB * k2 + e] * r;
+    }
+  *E -= item;
+  for (int x = 0; x < 3; ++x) { gv[x] -= sv[x]; g1[x] -= s1[x]; g2[x] -= s2[x]; }
+}
+
+/*
+ * Quartet loop over V blocks [v_begin, v_end) in key order; for each, the kept
+ * C blocks of A, then the kept C blocks of B (Algorithm 1's loop nest,
+ * extended to every term as the text after it describes).
+ *
+ * focus_kind: 0 = all quartets; 1 = only quartets that contain C block
+ * focus_idx; 2 = only quartets that contain V block focus_idx.
+ * E (scalar), gC[nC][3] and gV[nV][3] are accumulated (caller zeroes them).
+ * nthreads > 1 splits the V blocks over OpenMP threads with private
+ * accumulators, summed in thread order afterwards.
+ */
+int orc_contract(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV,
+                 const uint8_t* keepD, int64_t v_begin, int64_t v_end, int focus_kind,
+                 int64_t focus_idx, int nthreads, double* E, double* gC, double* gV) {
+  const int N = in->natom;
+  int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+  const int64_t nt = ntot_of(in, ao);
+  /* kept C blocks grouped by first atom, in key order */
+  int64_t* crow = (int64_t*)calloc(N + 1, sizeof(int64_t));
+  int64_t* clist = (int64_t*)malloc(sizeof(int64_t) * (in->nC + 1));
+  for (int64_t b = 0; b < in->nC; ++b) if (keepC[b]) crow[in->C_first[b] + 1]++;
+  for (int i = 0; i < N; ++i) crow[i + 1] += crow[i];
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * N);
+    for (int i = 0; i < N; ++i) fill[i] = crow[i];
+    for (int64_t b = 0; b < in->nC; ++b) if (keepC[b]) clist[fill[in->C_first[b]]++] = b;
+    free(fill);
+  }
+  int mmax = 0, nmax = 0;
+  for (int i = 0; i < N; ++i) { if (in->nabf[i] > mmax) mmax = in->nabf[i]; if (in->nao[i] > nmax) nmax = in->nao[i]; }
+  const size_t wsz = (size_t)2 * mmax * nmax * nmax + 4 * nmax * nmax + 16;
+  if (v_begin < 0) v_begin = 0;
+  if (v_end > in->nV) v_end = in->nV;
+  int nth = nthreads > 1 ? nthreads : 1;
+#ifndef _OPENMP
+  nth = 1;
+#endif
+  double* accE = (double*)calloc(nth, sizeof(double));
+  double* accC = (double*)calloc((size_t)nth * in->nC * 3, sizeof(double));
+  double* accV = (double*)calloc((size_t)nth * in->nV * 3, sizeof(double));
+  double** wsv = (double**)malloc(sizeof(double*) * nth);
+  for (int t = 0; t < nth; ++t) wsv[t] = (double*)malloc(sizeof(double) * wsz);
+
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+#endif
+  for (int64_t v = v_begin; v < v_end; ++v) {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    if (!keepV[v]) continue;
+    const int A = in->V_first[v], B = in->V_second[v];
+    const int mA = in->nabf[A], mB = in->nabf[B], nA = in->nao[A], nB = in->nao[B];
+    const double* V = in->V_val + in->V_off[v];
+    const double* dV = in->V_dval + 3 * in->V_off[v];
+    dblk DAB = {keepD[A * N + B] ? in->D + ao[A] * nt + ao[B] : NULL, nt};
+    for (int64_t i1 = crow[A]; i1 < crow[A + 1]; ++i1) {
+      const int64_t c1 = clist[i1];
+      const int F = in->C_second[c1], nF = in->nao[F];
+      dblk DFB = {keepD[F * N + B] ? in->D + ao[F] * nt + ao[B] : NULL, nt};
+      for (int64_t i2 = crow[B]; i2 < crow[B + 1]; ++i2) {
+        const int64_t c2 = clist[i2];
+        if (focus_kind == 1 && c1 != focus_idx && c2 != focus_idx) continue;
+        if (focus_kind == 2 && v != focus_idx) continue;
+        const int G = in->C_second[c2], nG = in->nao[G];
+        dblk DFG = {keepD[F * N + G] ? in->D + ao[F] * nt + ao[G] : NULL, nt};
+        dblk DAG = {keepD[A * N + G] ? in->D + ao[A] * nt + ao[G] : NULL, nt};
+        quartet(mA, mB, nA, nF, nB, nG,
+                in->C_val + in->C_off[c1], in->C_dval + 3 * in->C_off[c1], V, dV,
+                in->C_val + in->C_off[c2], in->C_dval + 3 * in->C_off[c2],
+                DAB, DFG, DAG, DFB, wsv[t], &accE[t],
+                accC + ((size_t)t * in->nC + c1) * 3, accV + ((size_t)t * in->nV + v) * 3,
+                accC + ((size_t)t * in->nC + c2) * 3);
+      }
+    }
+  }
+  for (int t = 0; t < nth; ++t) {
+    *E += accE[t];
+    for (int64_t i = 0; i < 3 * in->nC; ++i) gC[i] += accC[(size_t)t * in->nC * 3 + i];
+    for (int64_t i = 0; i < 3 * in->nV; ++i) gV[i] += accV[(size_t)t * in->nV * 3 + i];
+    free(wsv[t]);
+  }
+  free(wsv); free(accE); free(accC); free(accV); free(ao); free(crow); free(clist);
+  return 0;
+}
+
+/*
+ * Forces and stress from block gradients (Eq. Fexx1 and Eq. stress):
+ * block b with displacement r_b = tau_second + R.L - tau_first and
+ * g_b = dE/dr_b gives F_first += g_b, F_second -= g_b, W += g_b (x) r_b;
+ * sigma = -W / Omega.
+ */
+void orc_forces_stress(const orc_input* in, const double* gC, const double* gV, double* F, double* sigma) {
+  const int N = in->natom;
+  double W[9] = {0};
+  for (int i = 0; i < 3 * N; ++i) F[i] = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int64_t nb = pass ? in->nV : in->nC;
+    const int32_t* fi = pass ? in->V_first : in->C_first;
+    const int32_t* se = pass ? in->V_second : in->C_second;
+    const int32_t* R = pass ? in->V_R : in->C_R;
+    const double* g = pass ? gV : gC;
+    for (int64_t b = 0; b < nb; ++b) {
+      double r[3];
+      for (int x = 0; x < 3; ++x)
+        r[x] = in->tau[3 * se[b] + x] - in->tau[3 * fi[b] + x] + R[3 * b] * in->lat[x] +
+               R[3 * b + 1] * in->lat[3 + x] + R[3 * b + 2] * in->lat[6 + x];
+      for (int x = 0; x < 3; ++x) {
+        F[3 * fi[b] + x] += g[3 * b + x];
+        F[3 * se[b] + x] -= g[3 * b + x];
+        for (int y = 0; y < 3; ++y) W[3 * x + y] += g[3 * b + x] * r[y];
+      }
+    }
+  }
+  const double* L = in->lat;
+  double omega = fabs(L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
+                      L[2] * (L[3] * L[7] - L[4] * L[6]));
+  for (int i = 0; i < 9; ++i) sigma[i] = -W[i] / omega;
+}
+
+int orc_has_openmp(void) {
+#ifdef _OPENMP
+  return 1;
+#else
+  return 0;
+#endif
+}
