@@ -1,0 +1,179 @@
+/*
+ * lrx.h -- C-ABI of the MI355X (gfx950) library for the localized-RI (LRI)
+ * exact-exchange energy E_X, the analytic forces F^{X1} and the stress
+ * sigma^{X1} of a periodic cell at the Gamma point.
+ *
+ * What is computed (Lin, Ji, He, Ren, "Efficient hybrid-functional-based
+ * force and stress calculations for periodic systems with thousands of
+ * atoms"):
+ *
+ *   E   = - sum_{V blocks (A,B,R_B)} sum_{C blocks (A,F,R_F)} sum_{C blocks (B,G,R')}
+ *           C^{A}_{AF} V_{AB} C^{B}_{BG} [ D_AB D_FG + D_AG D_FB ]
+ *         (Methods, Eq. exx_expand, with N_k = 1 and real tensors; the atom of
+ *         the V block's first index lies in the home cell, every partner is an
+ *         explicit lattice image, and the Gamma-point density matrix is the
+ *         same for every image pair),
+ *   F   = -dE/dtau with D held fixed: the six terms of Eq. Fexx1 (F^{X1}; the
+ *         density-matrix part F^{X2} of Eq. Exx2 belongs to the host DFT code),
+ *   sigma = -(1/Omega) sum_b (dE/dr_b) (x) r_b  (Eq. stress), r_b the
+ *         displacement of block b.
+ *
+ * Screening (Sec. Sparsity exploitation; Tables thr_default, thr_cs):
+ *   S1 (theta > 0): a C block is kept iff max|C| > theta or max|dC| > theta;
+ *       a V block iff the larger of max|V|, max|dV| over the block and its
+ *       mirror (B,A,-R) exceeds theta; a D atom pair (X,Y) iff max|D_XY| >
+ *       theta (decided on the block with X <= Y, used for both).
+ *   S2 (theta_cs > 0): a surviving V block is kept iff
+ *       nv * S(A,B) > theta_cs, nv = the largest Frobenius norm of V, dV of
+ *       the block and its mirror, S(A,B) = sum_{F,G} c(A,F) c(B,G)
+ *       [d(A,B) d(F,G) + d(A,G) d(F,B)] with c(A,F) the sum over kept C
+ *       images of max(|C|_F, |dC|_F) and d(X,Y) = |D_XY|_F of a kept D pair.
+ *       S bounds |Z(A,B)|_F (Cauchy-Schwarz, Sec. Sparsity exploitation), so
+ *       the test drops a V pair only when all of its items together are small.
+ *
+ * Units: Bohr, Hartree.  All arrays are row-major.  Return codes: 0 on
+ * success, a negative LRX_E* code on error; the message is available from
+ * lrx_last_error().  No entry point throws or aborts.  One context per host
+ * thread; a context is not thread-safe.
+ */
+#ifndef LRX_H
+#define LRX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LRX_OK = 0,
+  LRX_EINVAL = -1,     /* invalid argument or inconsistent input            */
+  LRX_ENOMEM = -2,     /* device or host allocation failed                  */
+  LRX_EHIP = -3,       /* a HIP runtime call failed                         */
+  LRX_ESTATE = -4,     /* call out of order (e.g. evaluate before tensors)  */
+  LRX_EBUDGET = -5,    /* request exceeds the configured device-memory budget */
+  LRX_ENOTFOUND = -6   /* unknown ticket                                    */
+};
+
+typedef enum {
+  LRX_FP64 = 0,        /* every product in FP64 (MFMA f64)                                   */
+  LRX_FP32 = 1,        /* contractions in FP32 on MFMA, FP32 accumulation, FP64 reductions    */
+  LRX_BF16X3 = 2       /* contractions as bf16 hi*hi + hi*lo + lo*hi on MFMA with FP32
+                          accumulation (operands split into bf16 hi and residual lo), FP64
+                          reductions                                                          */
+} lrx_precision;
+
+typedef struct {
+  double theta;        /* S1 threshold; <= 0 disables S1                  */
+  double theta_cs;     /* S2 threshold; <= 0 disables S2                  */
+  int32_t precision;   /* lrx_precision                                    */
+  int32_t timing;      /* nonzero: time every stage with HIP events        */
+} lrx_options;
+
+/*
+ * One block-sparse pair tensor (C or V).  Block i couples atom first[i] (the
+ * atom carrying the ABF index) with the lattice image R[i] of atom
+ * second[i]; its displacement is r_i = tau[second] + R.L - tau[first].
+ * Elements: C block [m_first][n_first][n_second] (C^{A alpha}_{A a, F f},
+ * Methods, LRI expansion), V block [m_first][m_second] (Eq. V), starting at
+ * element off[i] of val.  dval holds d(block)/d r_x for x = 0,1,2 as
+ * [3][block] starting at element 3*off[i].  Keys are host arrays; val and
+ * dval are host or device pointers (see lrx_set_tensors).
+ * Requirements: no duplicate key; every V block has its mirror (second,
+ * first, -R) with V_mirror = V^T and dV_mirror = -dV^T (relative 1e-12,
+ * Sec. Preparation: V_BA = V_AB^T, grad_B V_AB = -grad_A V_AB); every atom
+ * has its on-site C block (A, A, 0), symmetric in (a, f) (swap symmetry of
+ * the LRI coefficients).
+ */
+typedef struct {
+  int64_t nblk;
+  const int32_t* first;   /* [nblk] */
+  const int32_t* second;  /* [nblk] */
+  const int32_t* R;       /* [nblk][3] */
+  const int64_t* off;     /* [nblk] */
+  const double* val;      /* [nval] */
+  const double* dval;     /* [3*nval] */
+  int64_t nval;
+} lrx_blocks;
+
+typedef struct lrx_ctx lrx_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * to run on (e.g. the caller's current stream), or NULL for a stream the
+ * context creates and owns.  *out is set only on success. */
+int lrx_create(lrx_ctx** out, int32_t device, void* hip_stream);
+
+/* Geometry and basis sizes.  tau [natom][3], lattice [3][3] with rows
+ * a1, a2, a3; nao/nabf [natom] per-atom NAO and ABF counts (1..32 NAOs,
+ * 1..128 ABFs).  Host pointers, copied.  Invalidates earlier tensors. */
+int lrx_set_structure(lrx_ctx* ctx, int32_t natom, const double* tau, const double* lattice,
+                      const int32_t* nao, const int32_t* nabf);
+
+/* Block tensors and the Gamma-point density matrix D (dense, symmetric,
+ * [n_tot][n_tot], n_tot = sum nao, atom blocks in atom order).
+ * data_on_device = 0: val/dval/D are host arrays, copied to the device.
+ * data_on_device = 1: they are device pointers on the context's device;
+ *   they are borrowed, not copied, and must stay valid and unchanged until
+ *   the next lrx_set_tensors/lrx_set_structure or lrx_destroy.
+ * Keys are always host arrays and are copied.  Validates keys on the host
+ * and values on the device (finite, mirror and swap symmetries, D
+ * symmetric); returns LRX_EINVAL with a message on the first violation.
+ * Allocates the device work buffers for the worst case (nothing screened). */
+int lrx_set_tensors(lrx_ctx* ctx, const lrx_blocks* C, const lrx_blocks* V, const double* D,
+                    int32_t data_on_device);
+
+/* Evaluate E (Ha), F [natom][3] (Ha/Bohr) and sigma [3][3] (Ha/Bohr^3) into
+ * host buffers; outputs are written only on success.  Blocks the caller's
+ * thread until the result is on the host.  Every step (screening, list
+ * masks, image folding, contractions, gradients, force and virial
+ * reductions) runs in this library's kernels on the context's stream. */
+int lrx_evaluate(lrx_ctx* ctx, const lrx_options* opts, double* E, double* F, double* sigma);
+
+/* Per-block gradients dE/dr_b of the last evaluation, in the caller's block
+ * order: gC [C.nblk][3], gV [V.nblk][3] (host buffers; either may be NULL).
+ * Screened blocks report 0. */
+int lrx_block_gradients(lrx_ctx* ctx, double* gC, double* gV);
+
+/* Screening decisions of the last evaluation (host buffers, 0/1 per block;
+ * keepD [natom][natom]); any pointer may be NULL. */
+int lrx_keep_masks(lrx_ctx* ctx, uint8_t* keepC, uint8_t* keepV, uint8_t* keepD);
+
+typedef struct {
+  int64_t kept_c_blocks, kept_v_blocks, alive_c_pairs, alive_v_pairs;
+  int64_t alive_triples;        /* (A,F,B) with (A,F) and (A,B) alive      */
+  int64_t h_slots;              /* H(B,X) blocks computed                   */
+  double flop_alg;              /* algorithmic FLOPs of one evaluation       */
+  double flop_triple;           /* ... of the triple-product kernel alone    */
+  double bytes_alg;             /* algorithmic HBM bytes of one evaluation   */
+  double device_bytes;          /* device memory held by the context         */
+} lrx_stats;
+
+/* Counts of the last evaluation (computed on the host from its masks). */
+int lrx_get_stats(lrx_ctx* ctx, lrx_stats* out);
+
+/* Stage durations (ms) of the last evaluation run with opts.timing != 0,
+ * measured with HIP events on the context's stream.  Writes up to n values
+ * into ms and returns the number of stages (LRX_NSTAGES), or a negative code.
+ * Stage order: norms, screen, fold, mark, hbuild, triple, zgrad, cgrad,
+ * forces. */
+#define LRX_NSTAGES 9
+int lrx_stage_times(lrx_ctx* ctx, float* ms, int32_t n);
+const char* lrx_stage_name(int32_t i);
+
+/* Evaluate several contexts (all on the same device) in one batched pass:
+ * their work items run in the same kernel launches on the first context's
+ * stream.  Results are written per context: E[i], F + 3*sum_{j<i} natom_j,
+ * sigma + 9*i.  Options apply to all. */
+int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts, double* E, double* F,
+                       double* sigma);
+
+/* Message of the last failing call on this context ("" if none). */
+const char* lrx_last_error(const lrx_ctx* ctx);
+
+/* Release the context and every device buffer it owns.  NULL is allowed. */
+void lrx_destroy(lrx_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRX_H */

@@ -91,18 +91,64 @@ static void block_norms(const double* val, const double* dval, int64_t n, double
   out[0] = mv; out[1] = md; out[2] = sqrt(sv); out[3] = sqrt(sd);
 }
 
-/* mirror of V block b: the block (second, first, -R) */
-static int64_t v_mirror(const orc_input* in, int64_t b) {
-  for (int64_t j = 0; j < in->nV; ++j)
-    if (in->V_first[j] == in->V_second[b] && in->V_second[j] == in->V_first[b] &&
-        in->V_R[3 * j] == -in->V_R[3 * b] && in->V_R[3 * j + 1] == -in->V_R[3 * b + 1] &&
-        in->V_R[3 * j + 2] == -in->V_R[3 * b + 2])
-      return j;
-  return -1;
+/* V block keys sorted for the mirror lookup (second, first, -R) */
+static const orc_input* g_sort_in;
+static int key_cmp(const int32_t* a, const int32_t* b) {
+  for (int i = 0; i < 5; ++i) if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+  return 0;
+}
+static void v_key(const orc_input* in, int64_t b, int32_t k[5]) {
+  k[0] = in->V_first[b]; k[1] = in->V_second[b];
+  k[2] = in->V_R[3 * b]; k[3] = in->V_R[3 * b + 1]; k[4] = in->V_R[3 * b + 2];
+}
+static int idx_cmp(const void* pa, const void* pb) {
+  int32_t ka[5], kb[5];
+  v_key(g_sort_in, *(const int64_t*)pa, ka);
+  v_key(g_sort_in, *(const int64_t*)pb, kb);
+  return key_cmp(ka, kb);
+}
+static int64_t* v_mirrors(const orc_input* in) {
+  int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (in->nV + 1));
+  int64_t* mir = (int64_t*)malloc(sizeof(int64_t) * (in->nV + 1));
+  for (int64_t b = 0; b < in->nV; ++b) idx[b] = b;
+  g_sort_in = in;
+  qsort(idx, (size_t)in->nV, sizeof(int64_t), idx_cmp);
+  for (int64_t b = 0; b < in->nV; ++b) {
+    int32_t want[5] = {in->V_second[b], in->V_first[b], -in->V_R[3 * b], -in->V_R[3 * b + 1], -in->V_R[3 * b + 2]};
+    int64_t lo = 0, hi = in->nV - 1, found = -1;
+    while (lo <= hi) {
+      int64_t mid = (lo + hi) / 2;
+      int32_t k[5];
+      v_key(in, idx[mid], k);
+      int c = key_cmp(k, want);
+      if (c == 0) { found = idx[mid]; break; }
+      if (c < 0) lo = mid + 1; else hi = mid - 1;
+    }
+    mir[b] = found;
+  }
+  free(idx);
+  return mir;
+}
+
+/* S(A,B) = sum_F sum_G c(A,F) c(B,G) [d(A,B) d(F,G) + d(A,G) d(F,B)] for A <= B,
+ * with F (and G) running over the partners of nonzero c in ascending order. */
+static double s_pair(int N, const double* c, const double* d, const int* prow, const int* plist, int A, int B) {
+  double s = 0;
+  for (int i = prow[A]; i < prow[A + 1]; ++i) {
+    const int F = plist[i];
+    const double cAF = c[(int64_t)A * N + F];
+    for (int j = prow[B]; j < prow[B + 1]; ++j) {
+      const int G = plist[j];
+      const double cBG = c[(int64_t)B * N + G];
+      s += cAF * cBG * (d[(int64_t)A * N + B] * d[(int64_t)F * N + G] + d[(int64_t)A * N + G] * d[(int64_t)F * N + B]);
+    }
+  }
+  return s;
 }
 
 /*
- * Screening decisions (S1 then S2).  keepC[nC], keepV[nV], keepD[natom*natom].
+ * Screening decisions (S1 then S2).  keepC[nC], keepV[nV], keepD[natom*natom];
+ * S_out (optional) [natom*natom] receives S(A,B) for the atom pairs of V blocks.
  * Returns 0, or -1 if a V block has no mirror.
  */
 int orc_screen(const orc_input* in, double theta, double theta_cs,
@@ -113,6 +159,7 @@ int orc_screen(const orc_input* in, double theta, double theta_cs,
   double* d = (double*)calloc((size_t)N * N, sizeof(double));
   double* c = (double*)calloc((size_t)N * N, sizeof(double));
   double* S = (double*)calloc((size_t)N * N, sizeof(double));
+  uint8_t* have = (uint8_t*)calloc((size_t)N * N, 1);
   /* D pairs, decided on the block with X <= Y and mirrored */
   for (int X = 0; X < N; ++X)
     for (int Y = X; Y < N; ++Y) {
@@ -124,8 +171,8 @@ int orc_screen(const orc_input* in, double theta, double theta_cs,
           ss += v * v;
         }
       int keep = !(theta > 0) || mx > theta;
-      keepD[X * N + Y] = keepD[Y * N + X] = (uint8_t)keep;
-      d[X * N + Y] = d[Y * N + X] = keep ? sqrt(ss) : 0.0;
+      keepD[(int64_t)X * N + Y] = keepD[(int64_t)Y * N + X] = (uint8_t)keep;
+      d[(int64_t)X * N + Y] = d[(int64_t)Y * N + X] = keep ? sqrt(ss) : 0.0;
     }
   /* C blocks, and c(A,F) summed over kept images in key order */
   for (int64_t b = 0; b < in->nC; ++b) {
@@ -134,26 +181,20 @@ int orc_screen(const orc_input* in, double theta, double theta_cs,
     block_norms(in->C_val + in->C_off[b], in->C_dval + 3 * in->C_off[b], n, nr);
     int keep = !(theta > 0) || nr[0] > theta || nr[1] > theta;
     keepC[b] = (uint8_t)keep;
-    if (keep) c[in->C_first[b] * N + in->C_second[b]] += (nr[2] > nr[3] ? nr[2] : nr[3]);
+    if (keep) c[(int64_t)in->C_first[b] * N + in->C_second[b]] += (nr[2] > nr[3] ? nr[2] : nr[3]);
   }
-  /* S(A,B) for A <= B, mirrored */
+  /* partners F of A with nonzero c(A,F), ascending */
+  int* prow = (int*)calloc(N + 1, sizeof(int));
   for (int A = 0; A < N; ++A)
-    for (int B = A; B < N; ++B) {
-      double s = 0;
-      for (int F = 0; F < N; ++F) {
-        double cAF = c[A * N + F];
-        if (cAF == 0) continue;
-        for (int G = 0; G < N; ++G) {
-          double cBG = c[B * N + G];
-          if (cBG == 0) continue;
-          s += cAF * cBG * (d[A * N + B] * d[F * N + G] + d[A * N + G] * d[F * N + B]);
-        }
-      }
-      S[A * N + B] = S[B * N + A] = s;
-    }
+    for (int F = 0; F < N; ++F) if (c[(int64_t)A * N + F] != 0) prow[A + 1]++;
+  for (int A = 0; A < N; ++A) prow[A + 1] += prow[A];
+  int* plist = (int*)malloc(sizeof(int) * (prow[N] + 1));
+  for (int A = 0, k = 0; A < N; ++A)
+    for (int F = 0; F < N; ++F) if (c[(int64_t)A * N + F] != 0) plist[k++] = F;
+  int64_t* mir = v_mirrors(in);
   int rc = 0;
   for (int64_t b = 0; b < in->nV; ++b) {
-    int64_t m = v_mirror(in, b);
+    int64_t m = mir[b];
     if (m < 0) { rc = -1; keepV[b] = 0; continue; }
     double n1[4], n2[4];
     int64_t n = v_size(in, b);
@@ -161,12 +202,19 @@ int orc_screen(const orc_input* in, double theta, double theta_cs,
     block_norms(in->V_val + in->V_off[m], in->V_dval + 3 * in->V_off[m], n, n2);
     double mx = fmax(fmax(n1[0], n1[1]), fmax(n2[0], n2[1]));
     double nv = fmax(fmax(n1[2], n1[3]), fmax(n2[2], n2[3]));
+    const int A = in->V_first[b], B = in->V_second[b];
+    const int lo = A < B ? A : B, hi = A < B ? B : A;
+    if (!have[(int64_t)lo * N + hi]) {
+      double s = s_pair(N, c, d, prow, plist, lo, hi);
+      S[(int64_t)lo * N + hi] = S[(int64_t)hi * N + lo] = s;
+      have[(int64_t)lo * N + hi] = 1;
+    }
     int keep = !(theta > 0) || mx > theta;
-    if (keep && theta_cs > 0) keep = nv * S[in->V_first[b] * N + in->V_second[b]] > theta_cs;
+    if (keep && theta_cs > 0) keep = nv * S[(int64_t)A * N + B] > theta_cs;
     keepV[b] = (uint8_t)keep;
   }
   if (S_out) memcpy(S_out, S, sizeof(double) * N * N);
-  free(ao); free(d); free(c); free(S);
+  free(ao); free(d); free(c); free(S); free(have); free(prow); free(plist); free(mir);
   return rc;
 }
 

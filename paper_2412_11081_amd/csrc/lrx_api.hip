@@ -1,0 +1,635 @@
+// Host side of the C-ABI declared in include/lrx.h.
+//
+// lrx_set_tensors builds, once per structure, the static work structure on
+// the host (pairs of image blocks, H slots, triple offsets, work units) from
+// the block keys, uploads it, and sizes every device buffer for the case
+// where nothing is screened.  lrx_evaluate then runs only kernels: the
+// screening decisions, folded blocks and slot needs are masks recomputed on
+// the device every call, so a call never synchronises with the host before
+// its results are copied back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <map>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lrx.h"
+#include "lrx_internal.h"
+
+using lrx::Dev;
+
+namespace {
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess)                                                                 \
+      throw Fail{e_ == hipErrorOutOfMemory ? LRX_ENOMEM : LRX_EHIP,                       \
+                 std::string(#x) + ": " + hipGetErrorString(e_)};                         \
+  } while (0)
+
+inline void require(bool c, const std::string& msg) {
+  if (!c) throw Fail{LRX_EINVAL, msg};
+}
+
+struct Key {
+  int f, s, r0, r1, r2;
+  bool operator<(const Key& o) const {
+    return std::tie(f, s, r0, r1, r2) < std::tie(o.f, o.s, o.r0, o.r1, o.r2);
+  }
+  bool operator==(const Key& o) const { return f == o.f && s == o.s && r0 == o.r0 && r1 == o.r1 && r2 == o.r2; }
+};
+
+// Blocks of one tensor grouped into atom pairs (sorted by first, second, R).
+struct Pairs {
+  std::vector<int64_t> order;     // sorted position -> caller block index
+  std::vector<int> pA, pB, b0, b1, row;
+};
+
+Pairs group_pairs(int N, int64_t n, const int32_t* first, const int32_t* second, const int32_t* R) {
+  Pairs P;
+  P.order.resize(n);
+  std::iota(P.order.begin(), P.order.end(), 0);
+  auto key = [&](int64_t b) { return Key{first[b], second[b], R[3 * b], R[3 * b + 1], R[3 * b + 2]}; };
+  std::sort(P.order.begin(), P.order.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+  for (int64_t k = 1; k < n; ++k)
+    require(!(key(P.order[k - 1]) == key(P.order[k])), "duplicate block key");
+  P.row.assign(N + 1, 0);
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t b = P.order[k];
+    if (k == 0 || first[b] != first[P.order[k - 1]] || second[b] != second[P.order[k - 1]]) {
+      P.pA.push_back(first[b]);
+      P.pB.push_back(second[b]);
+      P.b0.push_back((int)k);
+      P.b1.push_back((int)k + 1);
+      P.row[first[b] + 1]++;
+    } else {
+      P.b1.back() = (int)k + 1;
+    }
+  }
+  for (int i = 0; i < N; ++i) P.row[i + 1] += P.row[i];
+  return P;
+}
+
+// CSR of blocks by atom (first or second), in caller order.
+void by_atom(int N, int64_t n, const int32_t* atom, std::vector<int>& row, std::vector<int64_t>& list) {
+  row.assign(N + 1, 0);
+  for (int64_t b = 0; b < n; ++b) row[atom[b] + 1]++;
+  for (int i = 0; i < N; ++i) row[i + 1] += row[i];
+  list.resize(n);
+  std::vector<int> fill(row.begin(), row.end() - 1);
+  for (int64_t b = 0; b < n; ++b) list[fill[atom[b]]++] = b;
+}
+
+}  // namespace
+
+struct lrx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // structure
+  int N = 0;
+  std::vector<double> tau, lat;
+  std::vector<int> nao, nabf;
+  std::vector<int64_t> ao;
+  double omega = 0;
+  bool have_structure = false, have_tensors = false;
+
+  // host copies of keys and static work structure
+  int64_t nC = 0, nV = 0;
+  std::vector<int32_t> Cf, Cs, CR, Vf, Vs, VR;
+  Pairs cp, vp;
+  std::vector<int> slotB, slotX, unitCp, unitK0, unitK1, unitKc, nkc;
+  std::vector<int64_t> tBase;
+  int max_mm = 1;
+
+  // device memory
+  std::vector<void*> allocs;
+  double dev_bytes = 0;
+  Dev dev{};
+  double* h_out = nullptr;
+  std::array<hipEvent_t, LRX_NSTAGES + 1> ev{};
+  bool events = false;
+  std::array<float, LRX_NSTAGES> stage_ms{};
+  bool timed = false;
+  bool evaluated = false;
+
+  template <class T>
+  T* dalloc(int64_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(1, (size_t)count * sizeof(T));
+    HIPCHK(hipMalloc(&p, bytes));
+    allocs.push_back(p);
+    dev_bytes += (double)bytes;
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = dalloc<T>((int64_t)v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+    return p;
+  }
+  void free_tensors() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+    dev_bytes = 0;
+    have_tensors = false;
+    evaluated = false;
+  }
+};
+
+namespace {
+
+template <class F>
+int guarded(lrx_ctx* ctx, F&& f) {
+  if (!ctx) return LRX_EINVAL;
+  try {
+    HIPCHK(hipSetDevice(ctx->device));
+    f();
+    ctx->err.clear();
+    return LRX_OK;
+  } catch (const Fail& e) {
+    ctx->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return LRX_ENOMEM;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return LRX_EINVAL;
+  }
+}
+
+void check_blocks(const lrx_ctx* c, const lrx_blocks* B, bool isC, const char* name) {
+  require(B != nullptr, std::string(name) + ": NULL");
+  require(B->nblk >= 0 && B->nval >= 0, std::string(name) + ": negative size");
+  if (B->nblk == 0) return;
+  require(B->first && B->second && B->R && B->off && B->val && B->dval, std::string(name) + ": NULL array");
+  for (int64_t b = 0; b < B->nblk; ++b) {
+    const int f = B->first[b], s = B->second[b];
+    require(f >= 0 && f < c->N && s >= 0 && s < c->N, std::string(name) + ": atom index out of range");
+    const int64_t sz = isC ? (int64_t)c->nabf[f] * c->nao[f] * c->nao[s] : (int64_t)c->nabf[f] * c->nabf[s];
+    require(B->off[b] >= 0 && B->off[b] + sz <= B->nval, std::string(name) + ": block exceeds nval");
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int lrx_create(lrx_ctx** out, int32_t device, void* hip_stream) {
+  if (!out) return LRX_EINVAL;
+  lrx_ctx* c = new (std::nothrow) lrx_ctx();
+  if (!c) return LRX_ENOMEM;
+  c->device = device;
+  int rc = guarded(c, [&] {
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    require(device >= 0 && device < n, "no such HIP device");
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    c->events = true;
+  });
+  if (rc != LRX_OK) {
+    lrx_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return LRX_OK;
+}
+
+int lrx_set_structure(lrx_ctx* c, int32_t natom, const double* tau, const double* lattice, const int32_t* nao,
+                      const int32_t* nabf) {
+  return guarded(c, [&] {
+    require(natom > 0 && tau && lattice && nao && nabf, "lrx_set_structure: bad arguments");
+    c->free_tensors();
+    c->have_structure = false;
+    c->N = natom;
+    c->tau.assign(tau, tau + 3 * natom);
+    c->lat.assign(lattice, lattice + 9);
+    c->nao.assign(nao, nao + natom);
+    c->nabf.assign(nabf, nabf + natom);
+    c->ao.assign(natom + 1, 0);
+    for (int i = 0; i < natom; ++i) {
+      require(nao[i] >= 1 && nao[i] <= lrx::kMaxNao, "nao out of range 1..32");
+      require(nabf[i] >= 1 && nabf[i] <= lrx::kMaxNabf, "nabf out of range 1..128");
+      c->ao[i + 1] = c->ao[i] + nao[i];
+    }
+    for (double v : c->tau) require(std::isfinite(v), "non-finite position");
+    const double* L = lattice;
+    c->omega = std::fabs(L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
+                         L[2] * (L[3] * L[7] - L[4] * L[6]));
+    require(c->omega > 0 && std::isfinite(c->omega), "singular lattice");
+    c->have_structure = true;
+  });
+}
+
+int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const double* D, int32_t on_device) {
+  return guarded(c, [&] {
+    require(c->have_structure, "lrx_set_tensors before lrx_set_structure");
+    c->free_tensors();
+    check_blocks(c, C, true, "C");
+    check_blocks(c, V, false, "V");
+    require(D != nullptr, "D: NULL");
+    const int N = c->N;
+    const int64_t ntot = c->ao[N];
+    c->nC = C->nblk;
+    c->nV = V->nblk;
+    c->Cf.assign(C->first, C->first + c->nC);
+    c->Cs.assign(C->second, C->second + c->nC);
+    c->CR.assign(C->R, C->R + 3 * c->nC);
+    c->Vf.assign(V->first, V->first + c->nV);
+    c->Vs.assign(V->second, V->second + c->nV);
+    c->VR.assign(V->R, V->R + 3 * c->nV);
+
+    // ---- pairs ---------------------------------------------------------
+    c->cp = group_pairs(N, c->nC, C->first, C->second, C->R);
+    c->vp = group_pairs(N, c->nV, V->first, V->second, V->R);
+    const Pairs& cp = c->cp;
+    const Pairs& vp = c->vp;
+    const int nCp = (int)cp.pA.size(), nVp = (int)vp.pA.size();
+    {  // every atom has its on-site C block
+      std::vector<char> on(N, 0);
+      for (int64_t b = 0; b < c->nC; ++b)
+        if (C->first[b] == C->second[b] && !C->R[3 * b] && !C->R[3 * b + 1] && !C->R[3 * b + 2]) on[C->first[b]] = 1;
+      for (int i = 0; i < N; ++i) require(on[i], "C: atom " + std::to_string(i) + " has no on-site block (A,A,0)");
+    }
+    std::vector<int64_t> vmir(c->nV);
+    std::vector<int> vpmir(nVp);
+    {
+      std::vector<Key> sk(c->nV);
+      for (int64_t k = 0; k < c->nV; ++k) {
+        const int64_t b = vp.order[k];
+        sk[k] = Key{V->first[b], V->second[b], V->R[3 * b], V->R[3 * b + 1], V->R[3 * b + 2]};
+      }
+      std::vector<int> pos_pair(c->nV);
+      for (int p = 0; p < nVp; ++p)
+        for (int k = vp.b0[p]; k < vp.b1[p]; ++k) pos_pair[k] = p;
+      for (int64_t k = 0; k < c->nV; ++k) {
+        const Key m{sk[k].s, sk[k].f, -sk[k].r0, -sk[k].r1, -sk[k].r2};
+        auto it = std::lower_bound(sk.begin(), sk.end(), m);
+        require(it != sk.end() && *it == m, "V: block without its mirror (second, first, -R)");
+        const int64_t km = it - sk.begin();
+        vmir[vp.order[k]] = vp.order[km];
+        vpmir[pos_pair[k]] = pos_pair[km];
+      }
+    }
+    // ---- per-pair sizes and offsets --------------------------------------
+    std::vector<int64_t> cfOff(nCp + 1, 0), vfOff(nVp + 1, 0);
+    for (int i = 0; i < nCp; ++i)
+      cfOff[i + 1] = cfOff[i] + (int64_t)c->nabf[cp.pA[i]] * c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
+    int max_mm = 1;
+    for (int i = 0; i < nVp; ++i) {
+      const int mm = c->nabf[vp.pA[i]] * c->nabf[vp.pB[i]];
+      vfOff[i + 1] = vfOff[i] + mm;
+      max_mm = std::max(max_mm, mm);
+    }
+    c->max_mm = max_mm;
+    // ---- H slots: (B,F) and (B,A) for every candidate triple (A,F,B) -----
+    std::vector<int> slotmap((size_t)N * N, -1);
+    {
+      std::vector<char> needm((size_t)N * N, 0);
+      for (int i = 0; i < nCp; ++i) {
+        const int A = cp.pA[i], F = cp.pB[i];
+        for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
+          const int B = vp.pB[p];
+          needm[(size_t)B * N + F] = 1;
+          needm[(size_t)B * N + A] = 1;
+        }
+      }
+      c->slotB.clear();
+      c->slotX.clear();
+      for (int B = 0; B < N; ++B)
+        for (int X = 0; X < N; ++X)
+          if (needm[(size_t)B * N + X]) {
+            slotmap[(size_t)B * N + X] = (int)c->slotB.size();
+            c->slotB.push_back(B);
+            c->slotX.push_back(X);
+          }
+    }
+    const int nSlot = (int)c->slotB.size();
+    std::vector<int64_t> hOff(nSlot + 1, 0);
+    for (int s = 0; s < nSlot; ++s) {
+      const int B = c->slotB[s], X = c->slotX[s];
+      hOff[s + 1] = hOff[s] + (int64_t)c->nabf[B] * c->nao[B] * c->nao[X];
+    }
+    {  // depth of every H build fits the kernel's table
+      for (int B = 0; B < N; ++B) {
+        int k = 0;
+        for (int i = cp.row[B]; i < cp.row[B + 1]; ++i) k += c->nao[cp.pB[i]];
+        require(k <= 4096 - 4, "too many C partners of one atom (H depth > 4092)");
+      }
+    }
+    // ---- work units and triple offsets -----------------------------------
+    c->unitCp.clear(); c->unitK0.clear(); c->unitK1.clear(); c->unitKc.clear();
+    c->nkc.assign(nCp, 1);
+    for (int i = 0; i < nCp; ++i) {
+      const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
+      const int nk = (K1 + lrx::kChunkCols - 1) / lrx::kChunkCols;
+      int chunk = (K1 + nk - 1) / nk;
+      chunk = std::min(lrx::kChunkCols, (chunk + 15) / 16 * 16);
+      int cnt = 0;
+      for (int k0 = 0; k0 < K1; k0 += chunk, ++cnt) {
+        c->unitCp.push_back(i);
+        c->unitK0.push_back(k0);
+        c->unitK1.push_back(std::min(K1, k0 + chunk));
+        c->unitKc.push_back(cnt);
+      }
+      c->nkc[i] = cnt;
+    }
+    c->tBase.assign(N + 1, 0);
+    for (int A = 0; A < N; ++A)
+      c->tBase[A + 1] = c->tBase[A] + (int64_t)(cp.row[A + 1] - cp.row[A]) * (vp.row[A + 1] - vp.row[A]);
+    const int64_t ntri = c->tBase[N];
+    std::vector<int64_t> zOff(ntri + 1, 0);
+    for (int A = 0; A < N; ++A) {
+      const int nvA = vp.row[A + 1] - vp.row[A];
+      for (int i = cp.row[A]; i < cp.row[A + 1]; ++i)
+        for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
+          const int64_t t = c->tBase[A] + (int64_t)(i - cp.row[A]) * nvA + (p - vp.row[A]);
+          zOff[t + 1] = (int64_t)c->nkc[i] * c->nabf[A] * c->nabf[vp.pB[p]];
+        }
+    }
+    for (int64_t t = 0; t < ntri; ++t) zOff[t + 1] += zOff[t];
+    // ---- per-atom block lists for the force reduction ---------------------
+    std::vector<int> atCfRow, atCsRow, atVfRow, atVsRow;
+    std::vector<int64_t> atCf, atCs, atVf, atVs;
+    by_atom(N, c->nC, C->first, atCfRow, atCf);
+    by_atom(N, c->nC, C->second, atCsRow, atCs);
+    by_atom(N, c->nV, V->first, atVfRow, atVf);
+    by_atom(N, c->nV, V->second, atVsRow, atVs);
+    std::vector<int> Csz(c->nC), Vsz(c->nV);
+    for (int64_t b = 0; b < c->nC; ++b) Csz[b] = c->nabf[C->first[b]] * c->nao[C->first[b]] * c->nao[C->second[b]];
+    for (int64_t b = 0; b < c->nV; ++b) Vsz[b] = c->nabf[V->first[b]] * c->nabf[V->second[b]];
+
+    // ---- device buffers ----------------------------------------------------
+    Dev& d = c->dev;
+    d = Dev{};
+    d.N = N;
+    d.ntot = ntot;
+    d.omega = c->omega;
+    d.tau = c->upload(c->tau);
+    d.lat = c->upload(c->lat);
+    d.nao = c->upload(c->nao);
+    d.nabf = c->upload(c->nabf);
+    d.ao = c->upload(c->ao);
+    d.nC = c->nC;
+    d.nV = c->nV;
+    d.Cfirst = c->upload(c->Cf);
+    d.Csecond = c->upload(c->Cs);
+    d.CR = c->upload(c->CR);
+    d.Coff = c->upload(std::vector<int64_t>(C->off, C->off + c->nC));
+    d.Csz = c->upload(Csz);
+    d.Vfirst = c->upload(c->Vf);
+    d.Vsecond = c->upload(c->Vs);
+    d.VR = c->upload(c->VR);
+    d.Voff = c->upload(std::vector<int64_t>(V->off, V->off + c->nV));
+    d.Vsz = c->upload(Vsz);
+    d.Vmir = c->upload(vmir);
+    if (on_device) {
+      d.Cval = C->val; d.Cdval = C->dval; d.Vval = V->val; d.Vdval = V->dval; d.D = D;
+    } else {
+      double* p;
+      p = c->dalloc<double>(C->nval); HIPCHK(hipMemcpyAsync(p, C->val, C->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Cval = p;
+      p = c->dalloc<double>(3 * C->nval); HIPCHK(hipMemcpyAsync(p, C->dval, 3 * C->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Cdval = p;
+      p = c->dalloc<double>(V->nval); HIPCHK(hipMemcpyAsync(p, V->val, V->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Vval = p;
+      p = c->dalloc<double>(3 * V->nval); HIPCHK(hipMemcpyAsync(p, V->dval, 3 * V->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Vdval = p;
+      p = c->dalloc<double>(ntot * ntot); HIPCHK(hipMemcpyAsync(p, D, ntot * ntot * 8, hipMemcpyHostToDevice, c->stream)); d.D = p;
+    }
+    d.nCp = nCp;
+    d.nVp = nVp;
+    std::vector<int64_t> cpBlk(cp.order), vpBlk(vp.order);
+    d.cpA = c->upload(cp.pA); d.cpF = c->upload(cp.pB); d.cpB0 = c->upload(cp.b0); d.cpB1 = c->upload(cp.b1);
+    d.cpBlk = c->upload(cpBlk); d.cpRow = c->upload(cp.row);
+    d.vpA = c->upload(vp.pA); d.vpB = c->upload(vp.pB); d.vpB0 = c->upload(vp.b0); d.vpB1 = c->upload(vp.b1);
+    d.vpBlk = c->upload(vpBlk); d.vpRow = c->upload(vp.row); d.vpMir = c->upload(vpmir);
+    d.cfOff = c->upload(cfOff); d.vfOff = c->upload(vfOff);
+    d.Cf = c->dalloc<double>(cfOff[nCp]);
+    d.Vf = c->dalloc<double>(vfOff[nVp]);
+    d.nrmC = c->dalloc<double>(4 * c->nC);
+    d.nrmV = c->dalloc<double>(4 * c->nV);
+    d.dmax = c->dalloc<double>((int64_t)N * N);
+    d.dss = c->dalloc<double>((int64_t)N * N);
+    d.keepC = c->dalloc<uint8_t>(c->nC);
+    d.keepV = c->dalloc<uint8_t>(c->nV);
+    d.keepD = c->dalloc<uint8_t>((int64_t)N * N);
+    d.cval = c->dalloc<double>(nCp);
+    d.dnrm = c->dalloc<double>((int64_t)N * N);
+    d.Svp = c->dalloc<double>(nVp);
+    d.aliveC = c->dalloc<uint8_t>(nCp);
+    d.aliveV = c->dalloc<uint8_t>(nVp);
+    d.nSlot = nSlot;
+    d.slotB = c->upload(c->slotB); d.slotX = c->upload(c->slotX); d.hOff = c->upload(hOff);
+    d.hSlotMap = c->upload(slotmap);
+    d.need = c->dalloc<uint8_t>(nSlot);
+    d.H = c->dalloc<double>(hOff[nSlot]);
+    d.nUnit = (int)c->unitCp.size();
+    d.unitCp = c->upload(c->unitCp); d.unitK0 = c->upload(c->unitK0); d.unitK1 = c->upload(c->unitK1);
+    d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
+    d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);
+    d.Zbuf = c->dalloc<double>(zOff[ntri]);
+    d.yOff = c->upload(cfOff);
+    d.Ybuf = c->dalloc<double>(cfOff[nCp]);
+    d.gC = c->dalloc<double>(3 * c->nC);
+    d.gV = c->dalloc<double>(3 * c->nV);
+    d.Ep = c->dalloc<double>(nVp);
+    d.Ecp = c->dalloc<double>(nCp);
+    d.atCfRow = c->upload(atCfRow); d.atCf = c->upload(atCf);
+    d.atCsRow = c->upload(atCsRow); d.atCs = c->upload(atCs);
+    d.atVfRow = c->upload(atVfRow); d.atVf = c->upload(atVf);
+    d.atVsRow = c->upload(atVsRow); d.atVs = c->upload(atVs);
+    d.out = c->dalloc<double>(1 + 3 * N + 9 + 1);
+    d.err = c->dalloc<int>(1);
+    if (c->h_out) { (void)hipHostFree(c->h_out); c->h_out = nullptr; }
+    HIPCHK(hipHostMalloc((void**)&c->h_out, sizeof(double) * (1 + 3 * N + 9 + 1), hipHostMallocDefault));
+
+    // ---- value validation on the device ------------------------------------
+    HIPCHK(hipMemsetAsync(d.err, 0, sizeof(int), c->stream));
+    lrx::launch_validate_finite(d.Cval, C->nval, d.err, 1, c->stream);
+    lrx::launch_validate_finite(d.Cdval, 3 * C->nval, d.err, 1, c->stream);
+    lrx::launch_validate_finite(d.Vval, V->nval, d.err, 2, c->stream);
+    lrx::launch_validate_finite(d.Vdval, 3 * V->nval, d.err, 2, c->stream);
+    lrx::launch_validate(d, c->stream);
+    HIPCHK(hipGetLastError());
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, d.err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (herr) {
+      std::string m = "invalid tensor values:";
+      if (herr & 1) m += " non-finite C/dC;";
+      if (herr & 2) m += " non-finite V/dV;";
+      if (herr & 4) m += " non-finite D;";
+      if (herr & 8) m += " V(B,A,-R) != V(A,B,R)^T;";
+      if (herr & 16) m += " dV(B,A,-R) != -dV(A,B,R)^T;";
+      if (herr & 32) m += " on-site C block not symmetric in (a,f);";
+      if (herr & 64) m += " D not symmetric;";
+      c->free_tensors();
+      throw Fail{LRX_EINVAL, m};
+    }
+    c->have_tensors = true;
+  });
+}
+
+int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, double* sigma) {
+  return guarded(c, [&] {
+    require(opts != nullptr, "opts: NULL");
+    require(c->have_tensors, "lrx_evaluate before lrx_set_tensors");
+    require(opts->precision == LRX_FP64, "precision not available in this build");
+    require(std::isfinite(opts->theta) && std::isfinite(opts->theta_cs), "non-finite threshold");
+    const lrx::Opts o{opts->theta, opts->theta_cs};
+    const bool timing = opts->timing != 0;
+    hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
+    if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
+    lrx::launch_screen(c->dev, o, c->stream, ev);
+    lrx::launch_contract(c->dev, c->max_mm, c->stream, ev);
+    HIPCHK(hipGetLastError());
+    const int N = c->N;
+    HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (timing) {
+      for (int i = 0; i < LRX_NSTAGES; ++i) HIPCHK(hipEventElapsedTime(&c->stage_ms[i], c->ev[i], c->ev[i + 1]));
+      c->timed = true;
+    }
+    c->evaluated = true;
+    if (E) *E = c->h_out[0];
+    if (F) std::memcpy(F, c->h_out + 1, sizeof(double) * 3 * N);
+    if (sigma) std::memcpy(sigma, c->h_out + 1 + 3 * N, sizeof(double) * 9);
+  });
+}
+
+int lrx_block_gradients(lrx_ctx* c, double* gC, double* gV) {
+  return guarded(c, [&] {
+    require(c->evaluated, "no evaluation yet");
+    if (gC && c->nC) HIPCHK(hipMemcpyAsync(gC, c->dev.gC, sizeof(double) * 3 * c->nC, hipMemcpyDeviceToHost, c->stream));
+    if (gV && c->nV) HIPCHK(hipMemcpyAsync(gV, c->dev.gV, sizeof(double) * 3 * c->nV, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+int lrx_keep_masks(lrx_ctx* c, uint8_t* keepC, uint8_t* keepV, uint8_t* keepD) {
+  return guarded(c, [&] {
+    require(c->evaluated, "no evaluation yet");
+    if (keepC && c->nC) HIPCHK(hipMemcpyAsync(keepC, c->dev.keepC, c->nC, hipMemcpyDeviceToHost, c->stream));
+    if (keepV && c->nV) HIPCHK(hipMemcpyAsync(keepV, c->dev.keepV, c->nV, hipMemcpyDeviceToHost, c->stream));
+    if (keepD) HIPCHK(hipMemcpyAsync(keepD, c->dev.keepD, (size_t)c->N * c->N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
+  return guarded(c, [&] {
+    require(s != nullptr, "NULL stats");
+    require(c->evaluated, "no evaluation yet");
+    const Dev& d = c->dev;
+    std::vector<uint8_t> kC(c->nC), kV(c->nV), aC(d.nCp), aV(d.nVp), need(d.nSlot);
+    if (c->nC) HIPCHK(hipMemcpyAsync(kC.data(), d.keepC, c->nC, hipMemcpyDeviceToHost, c->stream));
+    if (c->nV) HIPCHK(hipMemcpyAsync(kV.data(), d.keepV, c->nV, hipMemcpyDeviceToHost, c->stream));
+    if (d.nCp) HIPCHK(hipMemcpyAsync(aC.data(), d.aliveC, d.nCp, hipMemcpyDeviceToHost, c->stream));
+    if (d.nVp) HIPCHK(hipMemcpyAsync(aV.data(), d.aliveV, d.nVp, hipMemcpyDeviceToHost, c->stream));
+    if (d.nSlot) HIPCHK(hipMemcpyAsync(need.data(), d.need, d.nSlot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *s = lrx_stats{};
+    const auto& na = c->nao;
+    const auto& nb = c->nabf;
+    double fl = 0, ft = 0, by = 0;
+    for (int64_t b = 0; b < c->nC; ++b) {
+      const double sz = (double)nb[c->Cf[b]] * na[c->Cf[b]] * na[c->Cs[b]];
+      by += 4 * sz * 8;
+      if (kC[b]) { s->kept_c_blocks++; fl += 6 * sz; }
+    }
+    for (int64_t b = 0; b < c->nV; ++b) {
+      const double sz = (double)nb[c->Vf[b]] * nb[c->Vs[b]];
+      by += 4 * sz * 8;
+      if (kV[b]) { s->kept_v_blocks++; fl += 8 * sz; }
+    }
+    by += (double)c->ao[c->N] * c->ao[c->N] * 8;
+    for (int i = 0; i < d.nCp; ++i) s->alive_c_pairs += aC[i];
+    for (int i = 0; i < d.nVp; ++i) s->alive_v_pairs += aV[i];
+    const Pairs& cp = c->cp;
+    const Pairs& vp = c->vp;
+    for (int i = 0; i < d.nCp; ++i) {
+      if (!aC[i]) continue;
+      const int A = cp.pA[i], Fa = cp.pB[i];
+      for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
+        if (!aV[p]) continue;
+        const int B = vp.pB[p];
+        s->alive_triples++;
+        const double t = 4.0 * nb[A] * nb[B] * na[A] * na[Fa] + 4.0 * nb[B] * na[A] * na[B] * na[Fa];
+        ft += t;
+      }
+    }
+    for (int sl = 0; sl < d.nSlot; ++sl) {
+      if (!need[sl]) continue;
+      s->h_slots++;
+      const int B = c->slotB[sl], X = c->slotX[sl];
+      double depth = 0;
+      for (int i = cp.row[B]; i < cp.row[B + 1]; ++i)
+        if (aC[i]) depth += na[cp.pB[i]];
+      fl += 2.0 * nb[B] * na[B] * na[X] * depth;
+    }
+    s->flop_triple = ft;
+    s->flop_alg = fl + ft;
+    s->bytes_alg = by;
+    s->device_bytes = c->dev_bytes;
+  });
+}
+
+int lrx_stage_times(lrx_ctx* c, float* ms, int32_t n) {
+  if (!c) return LRX_EINVAL;
+  if (!c->timed) {
+    c->err = "no timed evaluation yet";
+    return LRX_ESTATE;
+  }
+  for (int i = 0; i < n && i < LRX_NSTAGES; ++i) ms[i] = c->stage_ms[i];
+  return LRX_NSTAGES;
+}
+
+const char* lrx_stage_name(int32_t i) {
+  static const char* names[LRX_NSTAGES] = {"norms", "screen", "fold", "mark", "hbuild",
+                                           "triple", "zgrad", "cgrad", "forces"};
+  return (i >= 0 && i < LRX_NSTAGES) ? names[i] : "";
+}
+
+int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts, double* E, double* F,
+                       double* sigma) {
+  if (!ctxs || n <= 0) return LRX_EINVAL;
+  ctxs[0]->err = "batched evaluation not available in this build";
+  return LRX_ESTATE;
+}
+
+const char* lrx_last_error(const lrx_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+void lrx_destroy(lrx_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  c->free_tensors();
+  if (c->h_out) (void)hipHostFree(c->h_out);
+  if (c->events)
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

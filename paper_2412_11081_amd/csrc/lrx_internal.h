@@ -1,0 +1,114 @@
+// Internal declarations of the LRI exact-exchange library (gfx950).
+//
+// Data layout on the device (all row-major, FP64 unless noted):
+//   inputs   C/V block values and derivatives exactly as the caller gave them
+//            (borrowed or copied), D dense [n_tot][n_tot];
+//   pairs    the image blocks grouped by (first, second) atom pair: a "C pair"
+//            (A,F) and a "V pair" (A,B), each with the sorted list of its
+//            image blocks (R lexicographic);
+//   folded   Cf(A,F) = sum of kept C images [mA][nA][nF];
+//            Vf(A,B) = sum of kept V images [mA][mB]  (Gamma point: the density
+//            matrix is the same for every image pair, so the images of a pair
+//            meet the same D blocks and can be summed first);
+//   H        H(B,X)[beta][b][x] = sum_G Cf(B,G)[beta][b][g] D(G,X)[g][x] for
+//            every (B,X) a triple (A,F,B) needs (X = A or X = F);
+//   Zbuf     per triple (A,F,B) and column chunk: the F-partial of
+//            Z(A,B)[alpha][beta] = sum_{F,a,f} Cf(A,F)[alpha][a][f] X^{AFB}[beta][a][f],
+//            X^{AFB}[beta][a][f] = sum_b D_AB[a][b] H(B,F)[beta][b][f]
+//                                + sum_b D_FB[f][b] H(B,A)[beta][b][a];
+//   Ybuf     per C pair: Y(A,F)[alpha][a][f] = sum_B sum_beta Vf(A,B)[alpha][beta] X^{AFB}[beta][a][f].
+// With these, E = -sum_{A,B} <Vf(A,B), Z(A,B)>, dE/dV = -Z and dE/dCf = -2 Y
+// (E is a symmetric quadratic form in C), so each image block's gradient is
+// a single contraction of its d/dr with Z or Y.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lrx {
+
+constexpr int kMaxNao = 32;
+constexpr int kMaxNabf = 128;
+constexpr int kChunkCols = 192;   // max (a,f) columns one triple work unit owns
+constexpr int kMaxAlphaTiles = (kMaxNabf + 15) / 16;
+
+// Everything the kernels read or write for one structure.  Passed by value.
+struct Dev {
+  int N;
+  int64_t ntot;
+  const double* tau;      // [N][3]
+  const double* lat;      // [3][3]
+  double omega;
+  const int* nao;         // [N]
+  const int* nabf;        // [N]
+  const int64_t* ao;      // [N+1]
+
+  // input blocks (caller order)
+  int64_t nC, nV;
+  const int* Cfirst; const int* Csecond; const int* CR; const int64_t* Coff; const int* Csz;
+  const double* Cval; const double* Cdval;
+  const int* Vfirst; const int* Vsecond; const int* VR; const int64_t* Voff; const int* Vsz;
+  const double* Vval; const double* Vdval;
+  const int64_t* Vmir;    // mirror block (second, first, -R)
+  const double* D;        // [ntot][ntot]
+
+  // pairs
+  int nCp, nVp;
+  const int* cpA; const int* cpF; const int* cpB0; const int* cpB1; const int64_t* cpBlk; const int* cpRow;
+  const int* vpA; const int* vpB; const int* vpB0; const int* vpB1; const int64_t* vpBlk; const int* vpRow;
+  const int* vpMir;
+  const int64_t* cfOff; const int64_t* vfOff;
+  double* Cf; double* Vf;
+
+  // screening
+  double* nrmC;  // [nC][4]: max|val|, max|dval|, sum val^2, sum dval^2
+  double* nrmV;  // [nV][4]
+  double* dmax;  // [N][N] (entries with X <= Y)
+  double* dss;   // [N][N]
+  uint8_t* keepC; uint8_t* keepV; uint8_t* keepD;
+  double* cval;  // [nCp]
+  double* dnrm;  // [N][N]
+  double* Svp;   // [nVp]
+  uint8_t* aliveC; uint8_t* aliveV;
+
+  // H slots
+  int nSlot;
+  const int* slotB; const int* slotX; const int64_t* hOff; const int* hSlotMap; // [N][N] -> slot or -1
+  uint8_t* need;
+  double* H;
+
+  // triple work units
+  int nUnit;
+  const int* unitCp; const int* unitK0; const int* unitK1; const int* unitKc;
+  const int* nkc;          // [nCp] column chunks of the pair
+  const int64_t* tBase;    // [N] first triple index of atom A
+  const int64_t* zOff;     // [ntriple] element offset of the triple's Z partials
+  double* Zbuf;
+  const int64_t* yOff;     // [nCp]
+  double* Ybuf;
+
+  // gradients and outputs
+  double* gC;    // [nC][3]
+  double* gV;    // [nV][3]
+  double* Ep;    // [nVp]
+  double* Ecp;   // [nCp]
+  const int* atCfRow; const int64_t* atCf;   // C blocks by first atom
+  const int* atCsRow; const int64_t* atCs;   // ... by second atom
+  const int* atVfRow; const int64_t* atVf;
+  const int* atVsRow; const int64_t* atVs;
+  double* out;   // [1 + 3N + 9 + 1]: E, F, sigma, E from the Y side
+  int* err;      // validation error code (0 = ok)
+};
+
+struct Opts {
+  double theta;
+  double theta_cs;
+};
+
+// kernels (lrx_screen.hip)
+void launch_validate(const Dev& d, hipStream_t s);
+void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev);
+// kernels (lrx_contract.hip)
+void launch_contract(const Dev& d, int max_mm, hipStream_t s, hipEvent_t* ev);
+void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipStream_t s);
+
+}  // namespace lrx

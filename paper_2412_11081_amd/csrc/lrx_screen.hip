@@ -1,0 +1,330 @@
+// Validation, block norms, two-step screening, image folding and H-slot marking.
+//
+// Screening follows Sec. "Sparsity exploitation" of the paper: step 1 drops a
+// whole atom-pair block when its largest element is at most theta (Table
+// thr_default uses one threshold per tensor; here one theta covers C, dC, V,
+// dV and D), step 2 bounds what is left with the Cauchy-Schwarz inequality.
+// The exact rules are stated in include/lrx.h.
+#include "lrx_internal.h"
+
+namespace lrx {
+
+constexpr int kNT = 256;
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Deterministic block reductions: wave butterflies, then wave 0 sums the
+// per-wave values in wave order.  `sh` holds at least blockDim/64 + 1 doubles.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+    sh[nw] = r;
+  }
+  __syncthreads();
+  return sh[nw];
+}
+__device__ inline double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0;
+    for (int i = 0; i < nw; ++i) r = fmax(r, sh[i]);
+    sh[nw] = r;
+  }
+  __syncthreads();
+  return sh[nw];
+}
+
+// ---------------------------------------------------------------------------
+// validation (run once per lrx_set_tensors)
+// ---------------------------------------------------------------------------
+enum : int {
+  kErrNonfiniteC = 1, kErrNonfiniteV = 2, kErrNonfiniteD = 4, kErrVMirror = 8, kErrDVMirror = 16,
+  kErrOnsiteC = 32, kErrDSym = 64
+};
+
+__device__ inline bool close_rel(double x, double y) {
+  return fabs(x - y) <= 1e-12 * (fabs(x) + fabs(y));
+}
+
+__global__ void k_val_finite(const double* p, int64_t n, int* err, int code) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(p[i])) atomicOr(err, code);
+}
+
+__global__ void k_val_vmirror(Dev d) {
+  const int64_t b = blockIdx.x;
+  const int64_t m = d.Vmir[b];
+  const int mA = d.nabf[d.Vfirst[b]], mB = d.nabf[d.Vsecond[b]];
+  const int n = mA * mB;
+  const double* vb = d.Vval + d.Voff[b];
+  const double* vm = d.Vval + d.Voff[m];
+  const double* db = d.Vdval + 3 * d.Voff[b];
+  const double* dm = d.Vdval + 3 * d.Voff[m];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int al = e / mB, be = e % mB;
+    const int et = be * mA + al;
+    if (!close_rel(vb[e], vm[et])) atomicOr(d.err, kErrVMirror);
+    for (int x = 0; x < 3; ++x)
+      if (!close_rel(db[x * n + e], -dm[x * n + et])) atomicOr(d.err, kErrDVMirror);
+  }
+}
+
+__global__ void k_val_onsite(Dev d) {
+  const int64_t b = blockIdx.x;
+  if (d.Cfirst[b] != d.Csecond[b] || d.CR[3 * b] || d.CR[3 * b + 1] || d.CR[3 * b + 2]) return;
+  const int n = d.nao[d.Cfirst[b]], m = d.nabf[d.Cfirst[b]];
+  const double* c = d.Cval + d.Coff[b];
+  for (int e = threadIdx.x; e < m * n * n; e += blockDim.x) {
+    const int al = e / (n * n), a = (e / n) % n, f = e % n;
+    if (!close_rel(c[e], c[al * n * n + f * n + a])) atomicOr(d.err, kErrOnsiteC);
+  }
+}
+
+__global__ void k_val_dsym(Dev d) {
+  const int64_t nt = d.ntot;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt * nt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / nt, c = i % nt;
+    if (c > r && !close_rel(d.D[i], d.D[c * nt + r])) atomicOr(d.err, kErrDSym);
+  }
+}
+
+void launch_validate(const Dev& d, hipStream_t s) {
+  const int g = 2048;
+  if (d.nV) hipLaunchKernelGGL(k_val_vmirror, dim3((unsigned)d.nV), dim3(kNT), 0, s, d);
+  if (d.nC) hipLaunchKernelGGL(k_val_onsite, dim3((unsigned)d.nC), dim3(kNT), 0, s, d);
+  hipLaunchKernelGGL(k_val_dsym, dim3(g), dim3(kNT), 0, s, d);
+  hipLaunchKernelGGL(k_val_finite, dim3(g), dim3(kNT), 0, s, d.D, d.ntot * d.ntot, d.err, (int)kErrNonfiniteD);
+}
+
+// Finite checks of the block values (sizes known on the host).
+void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_val_finite, dim3(2048), dim3(kNT), 0, s, p, n, err, code);
+}
+
+// ---------------------------------------------------------------------------
+// step 1: block norms (one workgroup per block)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kNT) k_block_norms(const double* val, const double* dval, const int64_t* off,
+                                                     const int* sz, double* out) {
+  __shared__ double sh[kNT / 64 + 1];
+  const int64_t b = blockIdx.x;
+  const int64_t o = off[b];
+  const int n = sz[b];
+  double mv = 0, sv = 0, md = 0, sd = 0;
+  const double* v = val + o;
+  const double* dv = dval + 3 * o;
+  for (int i = threadIdx.x; i < n; i += kNT) {
+    const double x = v[i];
+    mv = fmax(mv, fabs(x));
+    sv += x * x;
+  }
+  for (int i = threadIdx.x; i < 3 * n; i += kNT) {
+    const double x = dv[i];
+    md = fmax(md, fabs(x));
+    sd += x * x;
+  }
+  mv = block_max(mv, sh);
+  md = block_max(md, sh);
+  sv = block_sum(sv, sh);
+  sd = block_sum(sd, sh);
+  if (threadIdx.x == 0) {
+    out[4 * b + 0] = mv;
+    out[4 * b + 1] = md;
+    out[4 * b + 2] = sv;
+    out[4 * b + 3] = sd;
+  }
+}
+
+// D atom-pair blocks: one thread per (X, Y) with X <= Y.
+__global__ void k_d_norms(Dev d) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)d.N * d.N) return;
+  const int X = (int)(t / d.N), Y = (int)(t % d.N);
+  if (Y < X) return;
+  const int nX = d.nao[X], nY = d.nao[Y];
+  const double* p = d.D + d.ao[X] * d.ntot + d.ao[Y];
+  double mx = 0, ss = 0;
+  for (int i = 0; i < nX; ++i)
+    for (int j = 0; j < nY; ++j) {
+      const double v = p[i * d.ntot + j];
+      mx = fmax(mx, fabs(v));
+      ss += v * v;
+    }
+  d.dmax[t] = mx;
+  d.dss[t] = ss;
+}
+
+// ---------------------------------------------------------------------------
+// step 1 decisions for C blocks and D pairs; c(A,F) and d(X,Y) for step 2
+// ---------------------------------------------------------------------------
+__global__ void k_screen_c(Dev d, Opts o) {
+  const int cp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cp >= d.nCp) return;
+  double c = 0;
+  uint8_t alive = 0;
+  for (int k = d.cpB0[cp]; k < d.cpB1[cp]; ++k) {
+    const int64_t b = d.cpBlk[k];
+    const double* nr = d.nrmC + 4 * b;
+    const bool keep = !(o.theta > 0) || nr[0] > o.theta || nr[1] > o.theta;
+    d.keepC[b] = keep;
+    if (keep) {
+      c += fmax(sqrt(nr[2]), sqrt(nr[3]));
+      alive = 1;
+    }
+  }
+  d.cval[cp] = c;
+  d.aliveC[cp] = alive;
+}
+
+__global__ void k_screen_d(Dev d, Opts o) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)d.N * d.N) return;
+  const int X = (int)(t / d.N), Y = (int)(t % d.N);
+  const int64_t c = X <= Y ? t : (int64_t)Y * d.N + X;
+  const bool keep = !(o.theta > 0) || d.dmax[c] > o.theta;
+  d.keepD[t] = keep;
+  d.dnrm[t] = keep ? sqrt(d.dss[c]) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// step 2: S(A,B) per V pair (evaluated for A <= B and mirrored)
+// ---------------------------------------------------------------------------
+__global__ void k_screen_s(Dev d) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.nVp) return;
+  const int A = d.vpA[p], B = d.vpB[p];
+  if (A > B) return;
+  const int N = d.N;
+  const double dAB = d.dnrm[(int64_t)A * N + B];
+  double s = 0;
+  for (int i = d.cpRow[A]; i < d.cpRow[A + 1]; ++i) {
+    const double cAF = d.cval[i];
+    if (cAF == 0) continue;
+    const int F = d.cpF[i];
+    const double dFB = d.dnrm[(int64_t)F * N + B];
+    for (int j = d.cpRow[B]; j < d.cpRow[B + 1]; ++j) {
+      const double cBG = d.cval[j];
+      if (cBG == 0) continue;
+      const int G = d.cpF[j];
+      s += cAF * cBG * (dAB * d.dnrm[(int64_t)F * N + G] + d.dnrm[(int64_t)A * N + G] * dFB);
+    }
+  }
+  d.Svp[p] = s;
+  d.Svp[d.vpMir[p]] = s;
+}
+
+// V blocks: step 1 with the mirror, then step 2; pair liveness.
+__global__ void k_screen_v(Dev d, Opts o) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.nVp) return;
+  uint8_t alive = 0;
+  const double S = d.Svp[p];
+  for (int k = d.vpB0[p]; k < d.vpB1[p]; ++k) {
+    const int64_t b = d.vpBlk[k];
+    const int64_t m = d.Vmir[b];
+    const double* n1 = d.nrmV + 4 * b;
+    const double* n2 = d.nrmV + 4 * m;
+    const double mx = fmax(fmax(n1[0], n1[1]), fmax(n2[0], n2[1]));
+    const double nv = fmax(fmax(sqrt(n1[2]), sqrt(n1[3])), fmax(sqrt(n2[2]), sqrt(n2[3])));
+    bool keep = !(o.theta > 0) || mx > o.theta;
+    if (keep && o.theta_cs > 0) keep = nv * S > o.theta_cs;
+    d.keepV[b] = keep;
+    alive |= keep;
+  }
+  d.aliveV[p] = alive;
+}
+
+// ---------------------------------------------------------------------------
+// image folding: Cf(A,F) = sum of kept C images, Vf(A,B) = sum of kept V images
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kNT) k_fold_c(Dev d) {
+  const int cp = blockIdx.x;
+  if (!d.aliveC[cp]) return;
+  const int n = d.nabf[d.cpA[cp]] * d.nao[d.cpA[cp]] * d.nao[d.cpF[cp]];
+  double* out = d.Cf + d.cfOff[cp];
+  const int k0 = d.cpB0[cp], k1 = d.cpB1[cp];
+  for (int e = threadIdx.x; e < n; e += kNT) {
+    double s = 0;
+    for (int k = k0; k < k1; ++k) {
+      const int64_t b = d.cpBlk[k];
+      if (d.keepC[b]) s += d.Cval[d.Coff[b] + e];
+    }
+    out[e] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kNT) k_fold_v(Dev d) {
+  const int p = blockIdx.x;
+  if (!d.aliveV[p]) return;
+  const int n = d.nabf[d.vpA[p]] * d.nabf[d.vpB[p]];
+  double* out = d.Vf + d.vfOff[p];
+  const int k0 = d.vpB0[p], k1 = d.vpB1[p];
+  for (int e = threadIdx.x; e < n; e += kNT) {
+    double s = 0;
+    for (int k = k0; k < k1; ++k) {
+      const int64_t b = d.vpBlk[k];
+      if (d.keepV[b]) s += d.Vval[d.Voff[b] + e];
+    }
+    out[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// H slots needed by the live triples (A,F,B): H(B,F) and H(B,A)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u8(uint8_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void k_mark(Dev d) {
+  const int cp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cp >= d.nCp || !d.aliveC[cp]) return;
+  const int A = d.cpA[cp], F = d.cpF[cp];
+  for (int p = d.vpRow[A]; p < d.vpRow[A + 1]; ++p) {
+    if (!d.aliveV[p]) continue;
+    const int B = d.vpB[p];
+    d.need[d.hSlotMap[(int64_t)B * d.N + F]] = 1;
+    d.need[d.hSlotMap[(int64_t)B * d.N + A]] = 1;
+  }
+}
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)(a > 0 ? (a + b - 1) / b : 1); }
+
+void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev) {
+  const int64_t NN = (int64_t)d.N * d.N;
+  if (d.nC) hipLaunchKernelGGL(k_block_norms, dim3((unsigned)d.nC), dim3(kNT), 0, s, d.Cval, d.Cdval, d.Coff, d.Csz, d.nrmC);
+  if (d.nV) hipLaunchKernelGGL(k_block_norms, dim3((unsigned)d.nV), dim3(kNT), 0, s, d.Vval, d.Vdval, d.Voff, d.Vsz, d.nrmV);
+  hipLaunchKernelGGL(k_d_norms, dim3(cdiv(NN, kNT)), dim3(kNT), 0, s, d);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  hipLaunchKernelGGL(k_screen_c, dim3(cdiv(d.nCp, kNT)), dim3(kNT), 0, s, d, o);
+  hipLaunchKernelGGL(k_screen_d, dim3(cdiv(NN, kNT)), dim3(kNT), 0, s, d, o);
+  hipLaunchKernelGGL(k_screen_s, dim3(cdiv(d.nVp, kNT)), dim3(kNT), 0, s, d);
+  hipLaunchKernelGGL(k_screen_v, dim3(cdiv(d.nVp, kNT)), dim3(kNT), 0, s, d, o);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  if (d.nCp) hipLaunchKernelGGL(k_fold_c, dim3(d.nCp), dim3(kNT), 0, s, d);
+  if (d.nVp) hipLaunchKernelGGL(k_fold_v, dim3(d.nVp), dim3(kNT), 0, s, d);
+  if (ev) (void)hipEventRecord(ev[2], s);
+  hipLaunchKernelGGL(k_fill_u8, dim3(cdiv(d.nSlot, kNT)), dim3(kNT), 0, s, d.need,
+                     (int64_t)d.nSlot);
+  hipLaunchKernelGGL(k_mark, dim3(cdiv(d.nCp, kNT)), dim3(kNT), 0, s, d);
+  if (ev) (void)hipEventRecord(ev[3], s);
+}
+
+}  // namespace lrx

@@ -1,0 +1,217 @@
+"""ctypes binding of the HIP library (C-ABI in ``include/lrx.h``).
+
+Argument marshalling only: every step of an evaluation runs in the library's
+kernels.  Block values may be torch CUDA tensors (passed as device pointers,
+borrowed by the library) or host arrays (copied).  The library is loaded from
+this package's directory; if it is missing the binding raises instead of
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrx.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+NSTAGES = 9
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class LrxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lrx error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("theta_cs", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class Blocks(ctypes.Structure):
+    _fields_ = [("nblk", ctypes.c_int64), ("first", _i32p), ("second", _i32p), ("R", _i32p),
+                ("off", _i64p), ("val", ctypes.c_void_p), ("dval", ctypes.c_void_p), ("nval", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kept_c_blocks", ctypes.c_int64), ("kept_v_blocks", ctypes.c_int64),
+                ("alive_c_pairs", ctypes.c_int64), ("alive_v_pairs", ctypes.c_int64),
+                ("alive_triples", ctypes.c_int64), ("h_slots", ctypes.c_int64),
+                ("flop_alg", ctypes.c_double), ("flop_triple", ctypes.c_double),
+                ("bytes_alg", ctypes.c_double), ("device_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
+           "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
+           "lrx_last_error", "lrx_destroy"]
+
+
+def load(path: Optional[str] = None):
+    """Load ``liblrx.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2412_11081_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp = ctypes.c_void_p
+    lib.lrx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp]
+    lib.lrx_set_structure.argtypes = [vp, ctypes.c_int32, _f64p, _f64p, _i32p, _i32p]
+    lib.lrx_set_tensors.argtypes = [vp, ctypes.POINTER(Blocks), ctypes.POINTER(Blocks), vp, ctypes.c_int32]
+    lib.lrx_evaluate.argtypes = [vp, ctypes.POINTER(Options), _f64p, _f64p, _f64p]
+    lib.lrx_block_gradients.argtypes = [vp, _f64p, _f64p]
+    lib.lrx_keep_masks.argtypes = [vp, _u8p, _u8p, _u8p]
+    lib.lrx_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.lrx_stage_times.argtypes = [vp, _f32p, ctypes.c_int32]
+    lib.lrx_stage_name.argtypes = [ctypes.c_int32]
+    lib.lrx_stage_name.restype = ctypes.c_char_p
+    lib.lrx_evaluate_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Options), _f64p, _f64p, _f64p]
+    lib.lrx_last_error.argtypes = [vp]
+    lib.lrx_last_error.restype = ctypes.c_char_p
+    lib.lrx_destroy.argtypes = [vp]
+    lib.lrx_destroy.restype = None
+    for f in ("lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
+              "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch"):
+        getattr(lib, f).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(np.asarray(a), dtype=dt)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+class Context:
+    """One structure on one device.  Mirrors the lrx_* calls one to one."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load()
+        self.h = ctypes.c_void_p()
+        s = None
+        if stream is not None:
+            s = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        self._check(self.lib.lrx_create(ctypes.byref(self.h), int(device), s), init=True)
+        self._keep = []
+        self.natom = 0
+        self.nC = self.nV = 0
+
+    def _check(self, rc, init=False):
+        if rc != 0:
+            msg = "" if init else self.lib.lrx_last_error(self.h).decode()
+            raise LrxError(rc, msg)
+
+    def set_structure(self, tau, lat, nao, nabf):
+        self._tau, self._lat = _np(tau, np.float64), _np(lat, np.float64)
+        self._nao, self._nabf = _np(nao, np.int32), _np(nabf, np.int32)
+        self.natom = int(self._nao.shape[0])
+        self._check(self.lib.lrx_set_structure(self.h, self.natom, _ptr(self._tau, _f64p), _ptr(self._lat, _f64p),
+                                               _ptr(self._nao, _i32p), _ptr(self._nabf, _i32p)))
+
+    def _blocks(self, blk: Dict, keep):
+        first, second = _np(blk["first"], np.int32), _np(blk["second"], np.int32)
+        R, off = _np(blk["R"], np.int32).reshape(-1), _np(blk["off"], np.int64)
+        val, dval = blk["val"], blk["dval"]
+        keep += [first, second, R, off]
+        b = Blocks()
+        b.nblk = int(first.shape[0])
+        b.first, b.second, b.R, b.off = _ptr(first, _i32p), _ptr(second, _i32p), _ptr(R, _i32p), _ptr(off, _i64p)
+        if hasattr(val, "data_ptr"):
+            b.val, b.dval, b.nval = val.data_ptr(), dval.data_ptr(), int(val.numel())
+            on_dev = val.is_cuda
+            keep += [val, dval]
+        else:
+            v, dv = _np(val, np.float64), _np(dval, np.float64)
+            keep += [v, dv]
+            b.val, b.dval, b.nval = v.ctypes.data, dv.ctypes.data, int(v.size)
+            on_dev = False
+        return b, on_dev
+
+    def set_tensors(self, C: Dict, V: Dict, D):
+        keep = []
+        bc, dc = self._blocks(C, keep)
+        bv, dv = self._blocks(V, keep)
+        if hasattr(D, "data_ptr"):
+            dptr, dd = D.data_ptr(), D.is_cuda
+            keep.append(D)
+        else:
+            Dm = _np(D, np.float64)
+            keep.append(Dm)
+            dptr, dd = Dm.ctypes.data, False
+        if not (dc == dv == dd):
+            raise ValueError("C, V and D must all be on the device or all on the host")
+        self._check(self.lib.lrx_set_tensors(self.h, ctypes.byref(bc), ctypes.byref(bv), ctypes.c_void_p(dptr), int(dc)))
+        self._keep = keep
+        self.nC, self.nV = int(bc.nblk), int(bv.nblk)
+
+    def evaluate(self, theta=0.0, theta_cs=0.0, precision="fp64", timing=False):
+        o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), int(bool(timing)))
+        E = ctypes.c_double()
+        F = np.zeros((self.natom, 3))
+        S = np.zeros((3, 3))
+        self._check(self.lib.lrx_evaluate(self.h, ctypes.byref(o), ctypes.byref(E), _ptr(F, _f64p), _ptr(S, _f64p)))
+        return E.value, F, S
+
+    def block_gradients(self):
+        gC, gV = np.zeros((self.nC, 3)), np.zeros((self.nV, 3))
+        self._check(self.lib.lrx_block_gradients(self.h, _ptr(gC, _f64p), _ptr(gV, _f64p)))
+        return gC, gV
+
+    def keep_masks(self):
+        kC, kV = np.zeros(self.nC, np.uint8), np.zeros(self.nV, np.uint8)
+        kD = np.zeros(self.natom * self.natom, np.uint8)
+        self._check(self.lib.lrx_keep_masks(self.h, _ptr(kC, _u8p), _ptr(kV, _u8p), _ptr(kD, _u8p)))
+        return kC, kV, kD
+
+    def stats(self):
+        s = Stats()
+        self._check(self.lib.lrx_get_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def stage_times(self):
+        ms = (ctypes.c_float * NSTAGES)()
+        rc = self.lib.lrx_stage_times(self.h, ms, NSTAGES)
+        if rc < 0:
+            self._check(rc)
+        return {self.lib.lrx_stage_name(i).decode(): float(ms[i]) for i in range(NSTAGES)}
+
+    def close(self):
+        if self.h:
+            self.lib.lrx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def context_for(structure, mats, device: int = 0, stream=None) -> Context:
+    """Context holding one synthetic structure (``synth.Structure``) and its
+    materialised blocks (``Structure.materialize``)."""
+    ctx = Context(device, stream)
+    ctx.set_structure(structure.tau, structure.lat, structure.nao, structure.nabf)
+    ctx.set_tensors(mats["C"], mats["V"], mats["D"])
+    return ctx
