@@ -102,7 +102,9 @@ def enumerate_pairs(tau: np.ndarray, lat: np.ndarray, rcut: float):
 
 
 def displacement(tau, lat, first, second, R):
-    return tau[second] + R.astype(np.float64) @ lat - tau[first]
+    """r = (tau_second - tau_first) + R.L, associated so that the mirror block
+    (second, first, -R) gets exactly -r (IEEE negation is exact)."""
+    return (tau[second] - tau[first]) + R.astype(np.float64) @ lat
 
 
 # ----------------------------------------------------------------------------
