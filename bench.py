@@ -1,0 +1,152 @@
+"""Benchmark: force+stress evaluations per second of the LRI exact-exchange
+hot path on one MI355X.
+
+One step = one full evaluation (screening, image folding, H build, triple
+products, gradients, force and virial reductions) of the 1080-atom strained,
+substituted ABX3 perovskite cell (6x6x6 cubic cells, a = 11.6 Bohr, 4 species,
+13-22 NAOs / 75-100 ABFs, orbital cutoff 8 Bohr, Coulomb range 20 Bohr,
+theta = 1e-5, theta_cs = 1e-8) with synthetic block tensors resident in HBM.
+
+Prints one JSON line.  Besides the contract fields it carries
+``roofline`` (the triple-product kernel, timed with HIP events inside the
+library on the stream it runs on) and ``cpu_baseline`` (the CPU oracle on a
+bounded sample of the same workload).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+WORKLOADS = {
+    1: "sc8: 8-atom simple-cubic cell, 13 NAO / 40 ABF, rC 7, rV 14, theta 0",
+    2: "diamond64: 64-atom diamond-like cell, 13 NAO / 75 ABF, rC 8, rV 20, theta 1e-4",
+    3: "abx3_320: 320-atom ABX3 perovskite, 3 species, rC 8, rV 20, theta 1e-4",
+    4: "abx3_1080: 1080-atom ABX3 perovskite, 1% strain, 2% B-site substitution, rC 8, rV 20, theta 1e-5",
+}
+
+
+def cpu_baseline(st, mats, target_s=12.0, threads=None):
+    """The CPU oracle on the V blocks of a few atoms, scaled to the whole cell.
+
+    The sample is every V block whose first atom is in the sampled set (and the
+    blocks those quartets and their screening need).  Its oracle time is scaled
+    by (kept V blocks of the cell) / (kept V blocks of the sample)."""
+    import numpy as np
+
+    import oracle
+    from tests.helpers import gather_blocks
+
+    oracle.build(force=False)
+    threads = threads or min(16, os.cpu_count() or 1)
+    C, V = mats["C"], mats["V"]
+    cf = np.asarray(C["first"])
+    vf, vs = np.asarray(V["first"]), np.asarray(V["second"])
+    rng = np.random.default_rng(7)
+    order = rng.permutation(st.natom)
+    spent, nblk_sample, picked = 0.0, 0, []
+    kept_total = None
+    for a in order:
+        picked.append(int(a))
+        vsel = np.nonzero(np.isin(vf, picked) | np.isin(vs, picked))[0]
+        atoms = set(picked) | set(vs[vsel].tolist())
+        csel = np.nonzero(np.isin(cf, sorted(atoms)))[0]
+        pr = oracle.Problem(st.tau, st.lat, st.nao, st.nabf, gather_blocks(st, C, "C", csel),
+                            gather_blocks(st, V, "V", vsel), st.D)
+        keep = pr.screen(st.theta, st.theta_cs)
+        loc_first = vf[vsel]
+        mine = np.isin(loc_first, picked)
+        # contract only the V blocks whose first atom is sampled
+        kv = keep[1].copy()
+        kv[~mine] = 0
+        t0 = time.perf_counter()
+        pr.contract((keep[0], kv, keep[2]), nthreads=threads)
+        spent = time.perf_counter() - t0
+        nblk_sample = int(kv.sum())
+        if spent >= target_s or len(picked) >= st.natom:
+            break
+    return spent, nblk_sample, picked, threads
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=4)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2412_11081_amd import lrx, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.time()
+    st = synth.workload(args.workload).build()
+    mats = st.materialize("cuda")
+    torch.cuda.synchronize()
+    print(f"# inputs built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    ctx = lrx.context_for(st, mats, stream=stream)
+    for _ in range(args.warmup):
+        ctx.evaluate(st.theta, st.theta_cs, precision=args.precision, timing=True)
+    torch.cuda.synchronize()
+    stage_sum = None
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.evaluate(st.theta, st.theta_cs, precision=args.precision, timing=True)
+        ms = ctx.stage_times()
+        stage_sum = ms if stage_sum is None else {k: stage_sum[k] + ms[k] for k in ms}
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    stats = ctx.stats()
+    ms_per_step = 1e3 * elapsed / args.steps
+    stage_avg = {k: v / args.steps for k, v in stage_sum.items()}
+    t_triple = stage_avg["triple"] * 1e-3
+    achieved = stats["flop_triple"] / t_triple / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    out = {
+        "metric": "EXX force+stress evals/s",
+        "value": 1e3 / ms_per_step,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "natom": st.natom,
+                   "theta": st.theta, "theta_cs": st.theta_cs, "precision": args.precision},
+        "tflops_alg": stats["flop_alg"] / (ms_per_step * 1e-3) / 1e12,
+        "stage_ms": stage_avg,
+        "roofline": {"bound": "mfma", "kernel": "k_triple", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "flop_per_launch": stats["flop_triple"], "launch_ms": stage_avg["triple"]},
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        spent, nsample, picked, threads = cpu_baseline(st, mats)
+        total_kept = stats["kept_v_blocks"]
+        t_full = spent * total_kept / max(1, nsample)
+        out["cpu_baseline"] = {"value": 1.0 / t_full, "unit": "evals/s", "cores": threads, "kind": "oracle",
+                               "sample": f"quartets of the {nsample} kept V blocks whose first atom is one of "
+                                         f"{len(picked)} sampled atoms ({spent:.1f} s), scaled by "
+                                         f"{total_kept}/{nsample} kept V blocks"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
