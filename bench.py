@@ -30,46 +30,50 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(st, mats, target_s=12.0, threads=None):
-    """The CPU oracle on the V blocks of a few atoms, scaled to the whole cell.
-
-    The sample is every V block whose first atom is in the sampled set (and the
-    blocks those quartets and their screening need).  Its oracle time is scaled
-    by (kept V blocks of the cell) / (kept V blocks of the sample)."""
+def _oracle_sample(st, mats, picked, threads):
+    """Oracle time for the quartets of the kept V blocks whose first atom is
+    in ``picked`` (with every block those quartets and their screening need)."""
     import numpy as np
 
     import oracle
     from tests.helpers import gather_blocks
 
-    oracle.build(force=False)
-    threads = threads or min(16, os.cpu_count() or 1)
     C, V = mats["C"], mats["V"]
     cf = np.asarray(C["first"])
     vf, vs = np.asarray(V["first"]), np.asarray(V["second"])
-    rng = np.random.default_rng(7)
-    order = rng.permutation(st.natom)
-    spent, nblk_sample, picked = 0.0, 0, []
-    kept_total = None
-    for a in order:
-        picked.append(int(a))
-        vsel = np.nonzero(np.isin(vf, picked) | np.isin(vs, picked))[0]
-        atoms = set(picked) | set(vs[vsel].tolist())
-        csel = np.nonzero(np.isin(cf, sorted(atoms)))[0]
-        pr = oracle.Problem(st.tau, st.lat, st.nao, st.nabf, gather_blocks(st, C, "C", csel),
-                            gather_blocks(st, V, "V", vsel), st.D)
-        keep = pr.screen(st.theta, st.theta_cs)
-        loc_first = vf[vsel]
-        mine = np.isin(loc_first, picked)
-        # contract only the V blocks whose first atom is sampled
-        kv = keep[1].copy()
-        kv[~mine] = 0
-        t0 = time.perf_counter()
-        pr.contract((keep[0], kv, keep[2]), nthreads=threads)
-        spent = time.perf_counter() - t0
-        nblk_sample = int(kv.sum())
-        if spent >= target_s or len(picked) >= st.natom:
-            break
-    return spent, nblk_sample, picked, threads
+    vsel = np.nonzero(np.isin(vf, picked) | np.isin(vs, picked))[0]
+    atoms = set(picked) | set(vs[vsel].tolist()) | set(vf[vsel].tolist())
+    csel = np.nonzero(np.isin(cf, sorted(atoms)))[0]
+    pr = oracle.Problem(st.tau, st.lat, st.nao, st.nabf, gather_blocks(st, C, "C", csel),
+                        gather_blocks(st, V, "V", vsel), st.D)
+    kC, kV, kD, _ = pr.screen(st.theta, st.theta_cs)
+    kV = kV.copy()
+    kV[~np.isin(vf[vsel], picked)] = 0
+    t0 = time.perf_counter()
+    pr.contract((kC, kV, kD), nthreads=threads)
+    return time.perf_counter() - t0, int(kV.sum())
+
+
+def cpu_baseline(st, mats, target_s=15.0, threads=None):
+    """The CPU oracle on the V blocks of a few atoms, scaled to the whole cell.
+
+    One atom calibrates the cost; then a sample of atoms sized for about
+    ``target_s`` seconds is timed.  The time is scaled by
+    (kept V blocks of the cell) / (kept V blocks of the sample)."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    threads = threads or min(16, os.cpu_count() or 1)
+    order = [int(a) for a in np.random.default_rng(7).permutation(st.natom)]
+    t1, n1 = _oracle_sample(st, mats, order[:1], threads)
+    k = int(min(st.natom, max(1, round(target_s / max(t1, 1e-3)))))
+    print(f"# cpu baseline: 1 atom {t1:.2f}s, sampling {k} atoms on {threads} threads", file=sys.stderr, flush=True)
+    if k == 1:
+        return t1, n1, order[:1], threads
+    spent, n = _oracle_sample(st, mats, order[:k], threads)
+    return spent, n, order[:k], threads
 
 
 def main():
@@ -101,6 +105,7 @@ def main():
     for _ in range(args.warmup):
         ctx.evaluate(st.theta, st.theta_cs, precision=args.precision, timing=True)
     torch.cuda.synchronize()
+    print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
     stage_sum = None
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -109,6 +114,7 @@ def main():
         stage_sum = ms if stage_sum is None else {k: stage_sum[k] + ms[k] for k in ms}
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    print(f"# timed {args.steps} steps in {elapsed:.2f}s", file=sys.stderr, flush=True)
     stats = ctx.stats()
     ms_per_step = 1e3 * elapsed / args.steps
     stage_avg = {k: v / args.steps for k, v in stage_sum.items()}
