@@ -115,7 +115,7 @@ struct lrx_ctx {
   Pairs cp, vp;
   std::vector<int> slotB, slotX, unitCp, unitK0, unitK1, unitKc, nkc;
   std::vector<int64_t> tBase;
-  int max_mm = 1;
+  int max_mm = 1, max_depth = 4;
 
   // device memory
   std::vector<void*> allocs;
@@ -334,11 +334,20 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       const int B = c->slotB[s], X = c->slotX[s];
       hOff[s + 1] = hOff[s] + (int64_t)c->nabf[B] * c->nao[B] * c->nao[X];
     }
-    {  // depth of every H build fits the kernel's table
-      for (int B = 0; B < N; ++B) {
-        int k = 0;
-        for (int i = cp.row[B]; i < cp.row[B + 1]; ++i) k += c->nao[cp.pB[i]];
-        require(k <= 4096 - 4, "too many C partners of one atom (H depth > 4092)");
+    std::vector<int> slotRow(N + 1, 0), hbB, hbR0;
+    for (int s = 0; s < nSlot; ++s) slotRow[c->slotB[s] + 1]++;
+    for (int B = 0; B < N; ++B) slotRow[B + 1] += slotRow[B];
+    c->max_depth = 4;
+    for (int B = 0; B < N; ++B) {  // depth of every H build fits the kernel's table
+      int k = 0;
+      for (int i = cp.row[B]; i < cp.row[B + 1]; ++i) k += c->nao[cp.pB[i]];
+      require(k + 3 <= lrx::kHMaxDepth,
+              "atom " + std::to_string(B) + ": its C partners have more than 276 NAOs in total");
+      c->max_depth = std::max(c->max_depth, (k + 3) & ~3);
+      const int rows = c->nabf[B] * c->nao[B];
+      for (int r0 = 0; r0 < rows; r0 += lrx::kHRows) {
+        hbB.push_back(B);
+        hbR0.push_back(r0);
       }
     }
     // ---- work units and triple offsets -----------------------------------
@@ -346,9 +355,10 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     c->nkc.assign(nCp, 1);
     for (int i = 0; i < nCp; ++i) {
       const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
-      const int nk = (K1 + lrx::kChunkCols - 1) / lrx::kChunkCols;
+      const int cols = lrx::unit_cols((c->nabf[cp.pA[i]] + 15) / 16);
+      const int nk = (K1 + cols - 1) / cols;
       int chunk = (K1 + nk - 1) / nk;
-      chunk = std::min(lrx::kChunkCols, (chunk + 15) / 16 * 16);
+      chunk = std::min(cols, (chunk + 15) / 16 * 16);
       int cnt = 0;
       for (int k0 = 0; k0 < K1; k0 += chunk, ++cnt) {
         c->unitCp.push_back(i);
@@ -445,6 +455,20 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.need = c->dalloc<uint8_t>(nSlot);
     d.H = c->dalloc<double>(hOff[nSlot]);
     d.nUnit = (int)c->unitCp.size();
+    std::vector<int> unitOrder(d.nUnit);
+    {
+      std::iota(unitOrder.begin(), unitOrder.end(), 0);
+      auto mt = [&](int u) { return (c->nabf[cp.pA[c->unitCp[u]]] + 15) / 16; };
+      std::stable_sort(unitOrder.begin(), unitOrder.end(), [&](int a, int b) { return mt(a) < mt(b); });
+      for (int m = 0; m <= lrx::kMaxAlphaTiles + 1; ++m) d.mtStart[m] = 0;
+      for (int u = 0; u < d.nUnit; ++u) d.mtStart[mt(u) + 1]++;
+      for (int m = 0; m <= lrx::kMaxAlphaTiles; ++m) d.mtStart[m + 1] += d.mtStart[m];
+    }
+    d.unitOrder = c->upload(unitOrder);
+    d.slotRow = c->upload(slotRow);
+    d.nHB = (int)hbB.size();
+    d.hbB = c->upload(hbB);
+    d.hbR0 = c->upload(hbR0);
     d.unitCp = c->upload(c->unitCp); d.unitK0 = c->upload(c->unitK0); d.unitK1 = c->upload(c->unitK1);
     d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
     d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);
@@ -502,7 +526,7 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
     hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
     if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
     lrx::launch_screen(c->dev, o, c->stream, ev);
-    lrx::launch_contract(c->dev, c->max_mm, c->stream, ev);
+    lrx::launch_contract(c->dev, c->max_mm, c->max_depth, c->stream, ev);
     HIPCHK(hipGetLastError());
     const int N = c->N;
     HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost,

@@ -23,9 +23,6 @@ __device__ inline d4 mfma_f64(double a, double b, d4 c) {
 
 constexpr int kNT = 256;
 constexpr int kWaves = kNT / 64;
-constexpr int kMaxJW = (kChunkCols / 16 + kWaves - 1) / kWaves;   // column tiles per wave
-constexpr int kXS = kChunkCols + 1;                                // odd LDS row stride (doubles)
-constexpr int kMaxK = 4096;                                        // concatenated H-build depth
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -57,173 +54,307 @@ __device__ inline int xcd_remap(int b, int G) {
 }
 
 // ---------------------------------------------------------------------------
-// H(B,X)[beta][b][x] = sum_{G alive} sum_g Cf(B,G)[beta][b][g] D(G,X)[g][x]
-// rows (beta,b), columns x, depth = the g index of all live C pairs of B.
+// H(B,X)[b][beta][x] = sum_{G alive} sum_g Cf(B,G)[beta][b][g] D(G,X)[g][x].
+// One workgroup per (B, 64 rows of (beta,b)): the rows of Cf(B, live G) are
+// staged once in LDS (depth = the g index of every live C pair of B) and
+// reused for every X of B; wave w owns row tile w.  H is stored with b
+// outermost so that the triple kernel reads 16 consecutive (beta,x) per b.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
-  __shared__ int ktab[kMaxK];
+  __shared__ int ktab[kHMaxDepth];
   __shared__ int kdepth;
-  const int s = blockIdx.x;
-  if (!d.need[s]) return;
-  const int B = d.slotB[s], X = d.slotX[s];
-  const int mB = d.nabf[B], nB = d.nao[B], nX = d.nao[X];
-  if (threadIdx.x == 0) {
+  extern __shared__ double As[];   // [kHRows][depth + 1]
+  const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x];
+  const int mB = d.nabf[B], nB = d.nao[B], rows = mB * nB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  if (tid == 0) {
     int k = 0;
     for (int cp = d.cpRow[B]; cp < d.cpRow[B + 1]; ++cp) {
       if (!d.aliveC[cp]) continue;
       const int nG = d.nao[d.cpF[cp]];
-      for (int gg = 0; gg < nG && k < kMaxK; ++gg) ktab[k++] = (cp << 6) | gg;
+      for (int gg = 0; gg < nG && k < kHMaxDepth; ++gg) ktab[k++] = (cp << 6) | gg;
     }
     const int kp = (k + 3) & ~3;
-    for (int i = k; i < kp && i < kMaxK; ++i) ktab[i] = -1;
+    for (int i = k; i < kp; ++i) ktab[i] = -1;
     kdepth = kp;
   }
   __syncthreads();
   const int K = kdepth;
-  const int rows = mB * nB;
-  const int RT = (rows + 15) >> 4, XT = (nX + 15) >> 4;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane & 15, g = lane >> 4;
-  double* Hout = d.H + d.hOff[s];
-  for (int t = w; t < RT * XT; t += kWaves) {
-    const int rt = t / XT, xt = t % XT;
-    const int row = 16 * rt + q, x = 16 * xt + q;
-    d4 acc = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int e = ktab[k0 + g];
-      double a = 0, b = 0;
-      if (e >= 0) {
-        const int cp = e >> 6, gg = e & 63;
-        const int G = d.cpF[cp], nG = d.nao[G];
-        if (row < rows) a = d.Cf[d.cfOff[cp] + (int64_t)row * nG + gg];
-        if (x < nX && d.keepD[(int64_t)G * d.N + X]) b = d.D[(d.ao[G] + gg) * d.ntot + d.ao[X] + x];
-      }
-      acc = mfma_f64(a, b, acc);
+  const int AS = K + 1;
+  for (int e = tid; e < kHRows * K; e += kNT) {
+    const int r = e / K, k = e - r * K;
+    const int row = r0 + r, t = ktab[k];
+    double v = 0;
+    if (row < rows && t >= 0) {
+      const int cp = t >> 6, gg = t & 63;
+      v = d.Cf[d.cfOff[cp] + (int64_t)row * d.nao[d.cpF[cp]] + gg];
     }
+    As[r * AS + k] = v;
+  }
+  __syncthreads();
+  const int row = r0 + 16 * w + q;            // A-operand row of this lane
+  for (int s = d.slotRow[B]; s < d.slotRow[B + 1]; ++s) {
+    if (!d.need[s]) continue;
+    const int X = d.slotX[s], nX = d.nao[X];
+    double* Hout = d.H + d.hOff[s];
+    for (int xt = 0; xt * 16 < nX; ++xt) {
+      const int x = 16 * xt + q;
+      d4 acc = {0, 0, 0, 0};
+      for (int k0 = 0; k0 < K; k0 += 4) {
+        const int t = ktab[k0 + g];
+        double b = 0;
+        if (t >= 0 && x < nX) {
+          const int cp = t >> 6, G = d.cpF[cp];
+          if (d.keepD[(int64_t)G * d.N + X]) b = d.D[(d.ao[G] + (t & 63)) * d.ntot + d.ao[X] + x];
+        }
+        acc = mfma_f64(As[(16 * w + q) * AS + k0 + g], b, acc);
+      }
+      for (int i = 0; i < 4; ++i) {
+        const int r = r0 + 16 * w + g + 4 * i;
+        if (r < rows && x < nX) {
+          const int be = r / nB, bb = r - be * nB;
+          Hout[((int64_t)bb * mB + be) * nX + x] = acc[i];
+        }
+      }
+    }
+  }
+  (void)row;
+}
+
+// ---------------------------------------------------------------------------
+// Triple products.  One workgroup of 8 waves per unit (C pair (A,F), column
+// chunk [k0,k1) of the (a,f) index), for every live V pair (A,B) and every
+// 16 rows beta0..beta0+15 of B's ABFs:
+//   X-build (all waves, MFMA):  X1[beta][a f] = sum_b D_AB[a][b] H(B,F)[b][beta][f]
+//                               X2[beta][a f] = sum_b D_FB[f][b] H(B,A)[b][beta][a]
+//   Z waves 0-3 (split K):      Z(A,B)[alpha][beta] partial over (a,f) in the chunk,
+//                               Cf(A,F) fragments resident in registers, summed
+//                               over the four waves through LDS -> Zbuf
+//   Y waves 4-7:                Y(A,F)[alpha][a f] += Vf(A,B)[alpha][beta] X[beta][a f]
+//                               (accumulators resident for the whole unit)
+// ---------------------------------------------------------------------------
+template <int MT>
+struct TripleCfg {
+  static constexpr int kCols = unit_cols(MT);
+  static constexpr int kKSW = kCols / 16;           // Z k-steps per Z wave
+  static constexpr int kJW = (kCols / 16 + 3) / 4;  // Y column tiles per Y wave
+  static constexpr int kXS = kCols + 1;
+  static constexpr size_t lds_bytes() {
+    return sizeof(double) * (2 * 16 * kXS + 4 * MT * 256 + 2 * kMaxNao * kMaxNao);
+  }
+};
+
+constexpr int kTNT = 512;
+
+// Geometry of one triple work unit, shared by both wave roles.
+struct UnitGeo {
+  int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, T1, T2, fpos, vp0, nVpA;
+};
+
+// X-build for one (B, beta0) chunk: all 8 waves share the MFMA tiles.
+__device__ inline void xbuild(const Dev& d, const UnitGeo& U, int w, int q, int g, int mB, int nB, int b0,
+                              const double* hBF, const double* hBA, const double* Dab, const double* Dfb,
+                              double* X1, double* X2) {
+  const int SB = (nB + 3) >> 2;
+  for (int t = w; t < U.T1 + U.T2; t += 8) {
+    const bool one = t < U.T1;
+    const int tt = one ? t : t - U.T1;
+    const int ncol = one ? U.nF : U.nA;   // AO count of the atom along the columns
+    const int nrow = one ? U.nA : U.nF;
+    const int tr = tt / ncol, tc = tt - tr * ncol;
+    const double* Ds = one ? Dab : Dfb;
+    const double* hp = one ? hBF : hBA;
+    const int c = 16 * tc + q;            // (beta_local, x) flattened, x < ncol
+    const bool cvalid = b0 * ncol + c < mB * ncol;
+    const int64_t hrow = (int64_t)mB * ncol;
+    double hv[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int b = 4 * s + g;
+      hv[s] = (s < SB && b < nB && cvalid) ? hp[(int64_t)b * hrow + b0 * ncol + c] : 0.0;
+    }
+    d4 acc = {0, 0, 0, 0};
+    const int r = 16 * tr + q;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (s < SB) {
+        const int b = 4 * s + g;
+        const double av = (r < nrow && b < nB) ? Ds[r * nB + b] : 0.0;
+        acc = mfma_f64(av, hv[s], acc);
+      }
+    }
+    const int bl = c / ncol, xo = c - bl * ncol;
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = 16 * rt + g + 4 * i;
-      if (r < rows && x < nX) Hout[(int64_t)r * nX + x] = acc[i];
+      const int rr = 16 * tr + g + 4 * i;
+      if (rr < nrow) {
+        const int k = one ? rr * U.nF + xo : xo * U.nF + rr;
+        const int cl = k - U.k0;
+        if (cl >= 0 && cl < U.Kc) (one ? X1 : X2)[bl * U.XS + cl] = acc[i];
+      }
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// Triple products.  One workgroup per unit (C pair (A,F), column chunk
-// [k0,k1) of the (a,f) index).  For every live V pair (A,B):
-//   X[beta][k] (16 rows at a time, in LDS) = sum_b D_AB[a][b] H(B,F)[beta][b][f]
-//                                         + sum_b D_FB[f][b] H(B,A)[beta][b][a],
-//   Z partial [alpha][beta] = sum_{k in chunk} Cf(A,F)[alpha][k] X[beta][k]  -> Zbuf,
-//   Y[alpha][k] += sum_beta Vf(A,B)[alpha][beta] X[beta][k]                 (registers).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kNT) k_triple(Dev d) {
-  __shared__ double Xs[16 * kXS];
-  __shared__ double Dab[kMaxNao * kMaxNao];
-  __shared__ double Dfb[kMaxNao * kMaxNao];
-  const int u = xcd_remap(blockIdx.x, gridDim.x);
-  const int cp = d.unitCp[u];
-  if (!d.aliveC[cp]) return;
-  const int A = d.cpA[cp], F = d.cpF[cp];
-  const int mA = d.nabf[A], nA = d.nao[A], nF = d.nao[F], K1 = nA * nF;
-  const int k0 = d.unitK0[u], k1 = d.unitK1[u], kc = d.unitKc[u];
-  const int Kc = k1 - k0, NTc = (Kc + 15) >> 4, Kcp = NTc * 16;
-  const int MT = (mA + 15) >> 4;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
-  const double* Cfp = d.Cf + d.cfOff[cp];
+// Loop over the live V pairs (A,B) of the unit and the 16-row chunks of B.
+// ZROLE waves compute the Z partials, the other waves the Y accumulators;
+// both run the same barrier sequence.
+template <int MT, bool ZROLE>
+__device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int tid, int w, int lane, int q, int g) {
+  using Cfg = TripleCfg<MT>;
+  double* X1 = lds;
+  double* X2 = lds + 16 * Cfg::kXS;
+  double* Zred = lds + 32 * Cfg::kXS;
+  double* Dab = Zred + 4 * MT * 256;
+  double* Dfb = Dab + kMaxNao * kMaxNao;
+  const int ww = w & 3;
   const int N = d.N;
-  const int fpos = cp - d.cpRow[A];
-  const int vp0 = d.vpRow[A], nVpA = d.vpRow[A + 1] - vp0;
+  const int64_t nt = d.ntot;
+  const int mA = U.mA, XS = U.XS;
 
-  d4 yacc[kMaxAlphaTiles][kMaxJW];
+  double cfr[ZROLE ? MT : 1][ZROLE ? Cfg::kKSW : 1];
+  d4 yacc[ZROLE ? 1 : MT][ZROLE ? 1 : Cfg::kJW];
+  if constexpr (ZROLE) {
+    const double* Cfp = d.Cf + d.cfOff[U.cp];
 #pragma unroll
-  for (int i = 0; i < kMaxAlphaTiles; ++i)
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
-    for (int j = 0; j < kMaxJW; ++j) yacc[i][j] = d4{0, 0, 0, 0};
+      for (int t = 0; t < Cfg::kKSW; ++t) {
+        const int ks = ww + 4 * t, c = 4 * ks + g, al = 16 * i + q;
+        cfr[i][t] = (ks < U.KS && c < U.Kc && al < mA) ? Cfp[(int64_t)al * U.K1 + U.k0 + c] : 0.0;
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::kJW; ++j) yacc[i][j] = d4{0, 0, 0, 0};
+  }
 
-  for (int p = vp0; p < vp0 + nVpA; ++p) {
+  for (int p = U.vp0; p < U.vp0 + U.nVpA; ++p) {
     if (!d.aliveV[p]) continue;
     const int B = d.vpB[p], mB = d.nabf[B], nB = d.nao[B];
-    double* Zdst = d.Zbuf + d.zOff[d.tBase[A] + (int64_t)fpos * nVpA + (p - vp0)] + (int64_t)kc * mA * mB;
+    double* Zdst = d.Zbuf + d.zOff[d.tBase[U.A] + (int64_t)U.fpos * U.nVpA + (p - U.vp0)] + (int64_t)U.kc * mA * mB;
     const double* Vfp = d.Vf + d.vfOff[p];
-    const double* hBF = d.H + d.hOff[d.hSlotMap[(int64_t)B * N + F]];
-    const double* hBA = d.H + d.hOff[d.hSlotMap[(int64_t)B * N + A]];
-    const bool kAB = d.keepD[(int64_t)A * N + B], kFB = d.keepD[(int64_t)F * N + B];
-    __syncthreads();
-    for (int e = tid; e < nA * nB; e += kNT)
-      Dab[e] = kAB ? d.D[(d.ao[A] + e / nB) * d.ntot + d.ao[B] + e % nB] : 0.0;
-    for (int e = tid; e < nF * nB; e += kNT)
-      Dfb[e] = kFB ? d.D[(d.ao[F] + e / nB) * d.ntot + d.ao[B] + e % nB] : 0.0;
+    const double* hBF = d.H + d.hOff[d.hSlotMap[(int64_t)B * N + U.F]];
+    const double* hBA = d.H + d.hOff[d.hSlotMap[(int64_t)B * N + U.A]];
+    const bool kAB = d.keepD[(int64_t)U.A * N + B], kFB = d.keepD[(int64_t)U.F * N + B];
+    for (int e = tid; e < U.nA * nB; e += kTNT)
+      Dab[e] = kAB ? d.D[(d.ao[U.A] + e / nB) * nt + d.ao[B] + e % nB] : 0.0;
+    for (int e = tid; e < U.nF * nB; e += kTNT)
+      Dfb[e] = kFB ? d.D[(d.ao[U.F] + e / nB) * nt + d.ao[B] + e % nB] : 0.0;
     __syncthreads();
     for (int b0 = 0; b0 < mB; b0 += 16) {
-      for (int e = tid; e < 16 * Kcp; e += kNT) {
-        const int r = e / Kcp, c = e - r * Kcp;
-        const int be = b0 + r;
-        double sacc = 0;
-        if (be < mB && c < Kc) {
-          const int k = k0 + c;
-          const int a = k / nF, f = k - a * nF;
-          const double* h1 = hBF + (int64_t)be * nB * nF + f;
-          const double* h2 = hBA + (int64_t)be * nB * nA + a;
-          for (int b = 0; b < nB; ++b) sacc += Dab[a * nB + b] * h1[b * nF] + Dfb[f * nB + b] * h2[b * nA];
-        }
-        Xs[r * kXS + c] = sacc;
-      }
+      xbuild(d, U, w, q, g, mB, nB, b0, hBF, hBA, Dab, Dfb, X1, X2);
       __syncthreads();
-      // Z partial: alpha tiles w, w + 4, ...
-      for (int i = w; i < MT; i += kWaves) {
-        d4 acc = {0, 0, 0, 0};
-        const int al = 16 * i + q;
-        const double* crow = Cfp + (int64_t)al * K1 + k0;
-        for (int kk = 0; kk < Kcp; kk += 4) {
-          const int c = kk + g;
-          const double a = (al < mA && c < Kc) ? crow[c] : 0.0;
-          acc = mfma_f64(a, Xs[q * kXS + c], acc);
-        }
-        for (int r = 0; r < 4; ++r) {
-          const int alr = 16 * i + g + 4 * r, be = b0 + q;
-          if (alr < mA && be < mB) Zdst[(int64_t)alr * mB + be] = acc[r];
-        }
-      }
-      // Y += Vf[:, b0:b0+16] X
+      if constexpr (ZROLE) {
+        d4 zp[MT];
 #pragma unroll
-      for (int i = 0; i < kMaxAlphaTiles; ++i) {
-        if (i < MT) {
-          const int al = 16 * i + q;
-          double av[4];
+        for (int i = 0; i < MT; ++i) zp[i] = d4{0, 0, 0, 0};
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int be = b0 + 4 * s + g;
-            av[s] = (al < mA && be < mB) ? Vfp[(int64_t)al * mB + be] : 0.0;
+        for (int t = 0; t < Cfg::kKSW; ++t) {
+          const int ks = ww + 4 * t;
+          if (ks < U.KS) {
+            const int c = 4 * ks + g;
+            const double xb = X1[q * XS + c] + X2[q * XS + c];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) zp[i] = mfma_f64(cfr[i][t], xb, zp[i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < MT; ++i) *(d4*)&Zred[(ww * MT + i) * 256 + lane * 4] = zp[i];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int bl = 4 * s + g, be = b0 + bl;
+          double av[MT];
+#pragma unroll
+          for (int i = 0; i < MT; ++i) {
+            const int al = 16 * i + q;
+            av[i] = (al < mA && be < mB) ? Vfp[(int64_t)al * mB + be] : 0.0;
           }
 #pragma unroll
-          for (int jj = 0; jj < kMaxJW; ++jj) {
-            const int j = w + kWaves * jj;
-            if (j < NTc) {
+          for (int jj = 0; jj < Cfg::kJW; ++jj) {
+            const int j = ww + 4 * jj;
+            if (j < U.NTc) {
+              const double xb = X1[bl * XS + 16 * j + q] + X2[bl * XS + 16 * j + q];
 #pragma unroll
-              for (int s = 0; s < 4; ++s) yacc[i][jj] = mfma_f64(av[s], Xs[(4 * s + g) * kXS + 16 * j + q], yacc[i][jj]);
+              for (int i = 0; i < MT; ++i) yacc[i][jj] = mfma_f64(av[i], xb, yacc[i][jj]);
             }
           }
         }
       }
       __syncthreads();
-    }
-  }
-  double* Y = d.Ybuf + d.yOff[cp];
+      if constexpr (ZROLE) {
+        for (int i = ww; i < MT; i += 4) {
+          d4 z = *(const d4*)&Zred[i * 256 + lane * 4];
+          for (int v = 1; v < 4; ++v) z += *(const d4*)&Zred[(v * MT + i) * 256 + lane * 4];
+          const int be = b0 + q;
 #pragma unroll
-  for (int i = 0; i < kMaxAlphaTiles; ++i)
-#pragma unroll
-    for (int jj = 0; jj < kMaxJW; ++jj) {
-      const int j = w + kWaves * jj;
-      if (i < MT && j < NTc) {
-        for (int r = 0; r < 4; ++r) {
-          const int al = 16 * i + g + 4 * r, c = 16 * j + q;
-          if (al < mA && c < Kc) Y[(int64_t)al * K1 + k0 + c] = yacc[i][jj][r];
+          for (int rr = 0; rr < 4; ++rr) {
+            const int al = 16 * i + g + 4 * rr;
+            if (al < mA && be < mB) Zdst[(int64_t)al * mB + be] = z[rr];
+          }
         }
       }
     }
+  }
+  if constexpr (!ZROLE) {
+    double* Y = d.Ybuf + d.yOff[U.cp];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int jj = 0; jj < Cfg::kJW; ++jj) {
+        const int j = ww + 4 * jj;
+        if (j < U.NTc) {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int al = 16 * i + g + 4 * rr, c = 16 * j + q;
+            if (al < mA && c < U.Kc) Y[(int64_t)al * U.K1 + U.k0 + c] = yacc[i][jj][rr];
+          }
+        }
+      }
+  }
+}
+
+template <int MT>
+__global__ void __launch_bounds__(kTNT, 1) k_triple(Dev d, const int* __restrict__ ulist) {
+  using Cfg = TripleCfg<MT>;
+  extern __shared__ __attribute__((aligned(32))) double lds[];
+  const int u = ulist[xcd_remap(blockIdx.x, gridDim.x)];
+  UnitGeo U;
+  U.cp = d.unitCp[u];
+  if (!d.aliveC[U.cp]) return;
+  U.A = d.cpA[U.cp];
+  U.F = d.cpF[U.cp];
+  U.mA = d.nabf[U.A];
+  U.nA = d.nao[U.A];
+  U.nF = d.nao[U.F];
+  U.K1 = U.nA * U.nF;
+  U.k0 = d.unitK0[u];
+  U.Kc = d.unitK1[u] - U.k0;
+  U.kc = d.unitKc[u];
+  U.NTc = (U.Kc + 15) >> 4;
+  U.KS = U.NTc * 4;
+  U.XS = U.NTc * 16 + 1;
+  U.T1 = ((U.nA + 15) >> 4) * U.nF;
+  U.T2 = ((U.nF + 15) >> 4) * U.nA;
+  U.fpos = U.cp - d.cpRow[U.A];
+  U.vp0 = d.vpRow[U.A];
+  U.nVpA = d.vpRow[U.A + 1] - U.vp0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  for (int e = tid; e < 32 * Cfg::kXS; e += kTNT) lds[e] = 0.0;
+  __syncthreads();
+  if (w < 4)
+    triple_role<MT, true>(d, U, lds, tid, w, lane, q, g);
+  else
+    triple_role<MT, false>(d, U, lds, tid, w, lane, q, g);
 }
 
 // ---------------------------------------------------------------------------
-// Z(A,B) = sum over live (A,F) of the Z partials; E and V-block gradients.
+// Z(A,B) = sum over live (A,F) and column chunks of the Z partials; then, in
+// one pass over the pair's blocks, E = -<Vf, Z> and g_v = -<dV_v, Z>.
 // ---------------------------------------------------------------------------
+constexpr int kZB = 4;   // V image blocks contracted per pass over Z
 __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
   extern __shared__ double Zs[];
   __shared__ double sh[kWaves + 1];
@@ -239,6 +370,8 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
     return;
   }
   const int vp0 = d.vpRow[A], nVpA = d.vpRow[A + 1] - vp0, bpos = p - vp0;
+  const double* vf = d.Vf + d.vfOff[p];
+  double es = 0;
   for (int e = threadIdx.x; e < n; e += kNT) {
     double z = 0;
     for (int cp = d.cpRow[A]; cp < d.cpRow[A + 1]; ++cp) {
@@ -247,25 +380,41 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
       for (int kc = 0; kc < d.nkc[cp]; ++kc) z += zp[(int64_t)kc * n + e];
     }
     Zs[e] = z;
+    es += vf[e] * z;
   }
-  __syncthreads();
-  const double* vf = d.Vf + d.vfOff[p];
-  double s = 0;
-  for (int e = threadIdx.x; e < n; e += kNT) s += vf[e] * Zs[e];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) d.Ep[p] = -s;
-  for (int k = d.vpB0[p]; k < d.vpB1[p]; ++k) {
-    const int64_t b = d.vpBlk[k];
-    if (!d.keepV[b]) {
-      if (threadIdx.x == 0) d.gV[3 * b] = d.gV[3 * b + 1] = d.gV[3 * b + 2] = 0.0;
-      continue;
+  es = block_sum(es, sh);
+  if (threadIdx.x == 0) d.Ep[p] = -es;
+  for (int k0 = d.vpB0[p]; k0 < d.vpB1[p]; k0 += kZB) {
+    const int nb = min(kZB, d.vpB1[p] - k0);
+    const double* dv[kZB];
+    bool kp[kZB];
+#pragma unroll
+    for (int j = 0; j < kZB; ++j) {
+      const int64_t b = d.vpBlk[k0 + (j < nb ? j : 0)];
+      kp[j] = j < nb && d.keepV[b];
+      dv[j] = d.Vdval + 3 * d.Voff[b];
     }
-    const double* dv = d.Vdval + 3 * d.Voff[b];
-    for (int x = 0; x < 3; ++x) {
-      double t = 0;
-      for (int e = threadIdx.x; e < n; e += kNT) t += dv[(int64_t)x * n + e] * Zs[e];
-      t = block_sum(t, sh);
-      if (threadIdx.x == 0) d.gV[3 * b + x] = -t;
+    double t[kZB][3];
+#pragma unroll
+    for (int j = 0; j < kZB; ++j) t[j][0] = t[j][1] = t[j][2] = 0.0;
+    for (int e = threadIdx.x; e < n; e += kNT) {
+      const double z = Zs[e];
+#pragma unroll
+      for (int j = 0; j < kZB; ++j)
+        if (kp[j]) {
+          t[j][0] += dv[j][e] * z;
+          t[j][1] += dv[j][n + e] * z;
+          t[j][2] += dv[j][2 * n + e] * z;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kZB; ++j) {
+      if (j >= nb) break;
+      const int64_t b = d.vpBlk[k0 + j];
+      for (int x = 0; x < 3; ++x) {
+        const double r = block_sum(t[j][x], sh);
+        if (threadIdx.x == 0) d.gV[3 * b + x] = kp[j] ? -r : 0.0;
+      }
     }
   }
 }
@@ -361,10 +510,34 @@ __global__ void __launch_bounds__(kFinalNT) k_final(Dev d) {
 
 static inline unsigned grid1(int64_t n, int64_t b) { return (unsigned)(n > 0 ? (n + b - 1) / b : 1); }
 
-void launch_contract(const Dev& d, int max_mm, hipStream_t s, hipEvent_t* ev) {
-  if (d.nSlot) hipLaunchKernelGGL(k_hbuild, dim3(d.nSlot), dim3(kNT), 0, s, d);
+template <int MT>
+static void launch_triple(const Dev& d, hipStream_t s) {
+  const int n = d.mtStart[MT + 1] - d.mtStart[MT];
+  if (n <= 0) return;
+  const size_t lds = TripleCfg<MT>::lds_bytes();
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_triple<MT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_triple<MT>, dim3(n), dim3(kTNT), lds, s, d, d.unitOrder + d.mtStart[MT]);
+}
+
+void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, hipEvent_t* ev) {
+  if (d.nHB) {
+    const size_t lds = (size_t)kHRows * (max_depth + 1) * sizeof(double);
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_hbuild, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_hbuild, dim3(d.nHB), dim3(kNT), lds, s, d);
+  }
   if (ev) (void)hipEventRecord(ev[4], s);
-  if (d.nUnit) hipLaunchKernelGGL(k_triple, dim3(d.nUnit), dim3(kNT), 0, s, d);
+  launch_triple<1>(d, s);
+  launch_triple<2>(d, s);
+  launch_triple<3>(d, s);
+  launch_triple<4>(d, s);
+  launch_triple<5>(d, s);
+  launch_triple<6>(d, s);
+  launch_triple<7>(d, s);
+  launch_triple<8>(d, s);
   if (ev) (void)hipEventRecord(ev[5], s);
   if (d.nVp) {
     const size_t lds = (size_t)max_mm * sizeof(double);

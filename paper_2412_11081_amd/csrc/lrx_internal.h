@@ -28,8 +28,14 @@ namespace lrx {
 
 constexpr int kMaxNao = 32;
 constexpr int kMaxNabf = 128;
-constexpr int kChunkCols = 192;   // max (a,f) columns one triple work unit owns
 constexpr int kMaxAlphaTiles = (kMaxNabf + 15) / 16;
+
+// Columns of the (a,f) index one triple work unit owns, by the number of
+// 16-row ABF tiles of its atom A (the unit keeps fragments of Cf(A,F) for
+// these columns and the Y tiles of these columns in registers).
+__host__ __device__ constexpr int unit_cols(int alpha_tiles) { return alpha_tiles <= 5 ? 176 : 128; }
+constexpr int kHRows = 64;         // rows (beta,b) of H one H-build workgroup owns
+constexpr int kHMaxDepth = 280;    // max sum of NAOs over the C partners of one atom
 
 // Everything the kernels read or write for one structure.  Passed by value.
 struct Dev {
@@ -73,12 +79,16 @@ struct Dev {
   // H slots
   int nSlot;
   const int* slotB; const int* slotX; const int64_t* hOff; const int* hSlotMap; // [N][N] -> slot or -1
+  const int* slotRow;      // [N+1] slots of atom B are slotRow[B] .. slotRow[B+1]-1 (sorted by X)
+  int nHB; const int* hbB; const int* hbR0;   // H-build work items: (B, first row)
   uint8_t* need;
   double* H;
 
   // triple work units
   int nUnit;
   const int* unitCp; const int* unitK0; const int* unitK1; const int* unitKc;
+  const int* unitOrder;    // units grouped by the alpha-tile count of their atom A
+  int mtStart[kMaxAlphaTiles + 2];
   const int* nkc;          // [nCp] column chunks of the pair
   const int64_t* tBase;    // [N] first triple index of atom A
   const int64_t* zOff;     // [ntriple] element offset of the triple's Z partials
@@ -108,7 +118,7 @@ struct Opts {
 void launch_validate(const Dev& d, hipStream_t s);
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev);
 // kernels (lrx_contract.hip)
-void launch_contract(const Dev& d, int max_mm, hipStream_t s, hipEvent_t* ev);
+void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, hipEvent_t* ev);
 void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipStream_t s);
 
 }  // namespace lrx
