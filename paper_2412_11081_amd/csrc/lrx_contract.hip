@@ -60,10 +60,39 @@ __device__ inline int xcd_remap(int b, int G) {
 // reused for every X of B; wave w owns row tile w.  H is stored with b
 // outermost so that the triple kernel reads 16 consecutive (beta,x) per b.
 // ---------------------------------------------------------------------------
+constexpr int kHStage = 18;   // D elements per thread staged for the next slot (18 x 256 >= 144 x 32)
+__device__ inline void hstage_load(const Dev& d, const int* krow, const int* kG, int K, int X, int tid, double* st) {
+  const int nX = d.nao[X];
+  const int64_t col0 = d.ao[X];
+#pragma unroll
+  for (int j = 0; j < kHStage; ++j) {
+    const int e = tid + kNT * j;
+    double v = 0;
+    if (e < K * nX) {
+      const int k = e / nX, x = e - k * nX;
+      const int G = kG[k];
+      if (G >= 0 && d.keepD[(int64_t)G * d.N + X]) v = d.D[(int64_t)krow[k] * d.ntot + col0 + x];
+    }
+    st[j] = v;
+  }
+}
+__device__ inline void hstage_store(int K, int nX, int tid, const double* st, double* Ds) {
+#pragma unroll
+  for (int j = 0; j < kHStage; ++j) {
+    const int e = tid + kNT * j;
+    if (e < K * nX) {
+      const int k = e / nX, x = e - k * nX;
+      Ds[k * 32 + x] = st[j];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
-  __shared__ int ktab[kHMaxDepth];
+  __shared__ int krow[kHMaxDepth];   // D row (ao[G] + g) of depth index k
+  __shared__ int kG[kHMaxDepth];     // atom G, or -1 for padding
+  __shared__ int kcp[kHMaxDepth];
   __shared__ int kdepth;
-  extern __shared__ double As[];   // [kHRows][depth + 1]
+  extern __shared__ double hl[];     // As[kHRows][depth + 1], Ds[2][depth][32]
   const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x];
   const int mB = d.nabf[B], nB = d.nao[B], rows = mB * nB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
@@ -71,44 +100,53 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
     int k = 0;
     for (int cp = d.cpRow[B]; cp < d.cpRow[B + 1]; ++cp) {
       if (!d.aliveC[cp]) continue;
-      const int nG = d.nao[d.cpF[cp]];
-      for (int gg = 0; gg < nG && k < kHMaxDepth; ++gg) ktab[k++] = (cp << 6) | gg;
+      const int G = d.cpF[cp], nG = d.nao[G];
+      for (int gg = 0; gg < nG && k < kHMaxDepth; ++gg) {
+        krow[k] = (int)(d.ao[G] + gg);
+        kG[k] = G;
+        kcp[k] = (cp << 6) | gg;
+        ++k;
+      }
     }
     const int kp = (k + 3) & ~3;
-    for (int i = k; i < kp; ++i) ktab[i] = -1;
+    for (int i = k; i < kp; ++i) { krow[i] = 0; kG[i] = -1; kcp[i] = -1; }
     kdepth = kp;
   }
   __syncthreads();
   const int K = kdepth;
   const int AS = K + 1;
+  double* As = hl;
+  double* Ds0 = hl + kHRows * AS;
   for (int e = tid; e < kHRows * K; e += kNT) {
     const int r = e / K, k = e - r * K;
-    const int row = r0 + r, t = ktab[k];
+    const int row = r0 + r, t = kcp[k];
     double v = 0;
-    if (row < rows && t >= 0) {
-      const int cp = t >> 6, gg = t & 63;
-      v = d.Cf[d.cfOff[cp] + (int64_t)row * d.nao[d.cpF[cp]] + gg];
-    }
+    if (row < rows && t >= 0) v = d.Cf[d.cfOff[t >> 6] + (int64_t)row * d.nao[d.cpF[t >> 6]] + (t & 63)];
     As[r * AS + k] = v;
   }
+  // first needed slot
+  const int s1 = d.slotRow[B + 1];
+  int s = d.slotRow[B];
+  while (s < s1 && !d.need[s]) ++s;
+  double st[kHStage];
+  if (s < s1) {
+    hstage_load(d, krow, kG, K, d.slotX[s], tid, st);
+    hstage_store(K, d.nao[d.slotX[s]], tid, st, Ds0);
+  }
   __syncthreads();
-  const int row = r0 + 16 * w + q;            // A-operand row of this lane
-  for (int s = d.slotRow[B]; s < d.slotRow[B + 1]; ++s) {
-    if (!d.need[s]) continue;
+  int buf = 0;
+  while (s < s1) {
+    int sn = s + 1;
+    while (sn < s1 && !d.need[sn]) ++sn;
+    if (sn < s1) hstage_load(d, krow, kG, K, d.slotX[sn], tid, st);
     const int X = d.slotX[s], nX = d.nao[X];
+    const double* Ds = Ds0 + buf * K * 32;
     double* Hout = d.H + d.hOff[s];
     for (int xt = 0; xt * 16 < nX; ++xt) {
       const int x = 16 * xt + q;
       d4 acc = {0, 0, 0, 0};
-      for (int k0 = 0; k0 < K; k0 += 4) {
-        const int t = ktab[k0 + g];
-        double b = 0;
-        if (t >= 0 && x < nX) {
-          const int cp = t >> 6, G = d.cpF[cp];
-          if (d.keepD[(int64_t)G * d.N + X]) b = d.D[(d.ao[G] + (t & 63)) * d.ntot + d.ao[X] + x];
-        }
-        acc = mfma_f64(As[(16 * w + q) * AS + k0 + g], b, acc);
-      }
+      for (int k0 = 0; k0 < K; k0 += 4)
+        acc = mfma_f64(As[(16 * w + q) * AS + k0 + g], x < nX ? Ds[(k0 + g) * 32 + x] : 0.0, acc);
       for (int i = 0; i < 4; ++i) {
         const int r = r0 + 16 * w + g + 4 * i;
         if (r < rows && x < nX) {
@@ -117,8 +155,11 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
         }
       }
     }
+    if (sn < s1) hstage_store(K, d.nao[d.slotX[sn]], tid, st, Ds0 + (buf ^ 1) * K * 32);
+    __syncthreads();
+    buf ^= 1;
+    s = sn;
   }
-  (void)row;
 }
 
 // ---------------------------------------------------------------------------
@@ -244,6 +285,18 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int tid
       Dfb[e] = kFB ? d.D[(d.ao[U.F] + e / nB) * nt + d.ao[B] + e % nB] : 0.0;
     __syncthreads();
     for (int b0 = 0; b0 < mB; b0 += 16) {
+      // V fragments of this chunk, requested before the X-build so their
+      // latency is covered by it
+      double avn[ZROLE ? 1 : 4][ZROLE ? 1 : MT];
+      if constexpr (!ZROLE) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int i = 0; i < MT; ++i) {
+            const int al = 16 * i + q, be = b0 + 4 * s + g;
+            avn[s][i] = (al < mA && be < mB) ? Vfp[(int64_t)al * mB + be] : 0.0;
+          }
+      }
       xbuild(d, U, w, q, g, mB, nB, b0, hBF, hBA, Dab, Dfb, X1, X2);
       __syncthreads();
       if constexpr (ZROLE) {
@@ -265,13 +318,8 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int tid
       } else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const int bl = 4 * s + g, be = b0 + bl;
-          double av[MT];
-#pragma unroll
-          for (int i = 0; i < MT; ++i) {
-            const int al = 16 * i + q;
-            av[i] = (al < mA && be < mB) ? Vfp[(int64_t)al * mB + be] : 0.0;
-          }
+          const int bl = 4 * s + g;
+          const double* av = avn[s];
 #pragma unroll
           for (int jj = 0; jj < Cfg::kJW; ++jj) {
             const int j = ww + 4 * jj;
@@ -354,10 +402,33 @@ __global__ void __launch_bounds__(kTNT, 1) k_triple(Dev d, const int* __restrict
 // Z(A,B) = sum over live (A,F) and column chunks of the Z partials; then, in
 // one pass over the pair's blocks, E = -<Vf, Z> and g_v = -<dV_v, Z>.
 // ---------------------------------------------------------------------------
-constexpr int kZB = 4;   // V image blocks contracted per pass over Z
+constexpr int kZB = 4;      // V image blocks contracted per pass over Z
+constexpr int kZMax = 64;   // Z partials (live C pairs x column chunks) of one V pair
+
+// Block-wide sums of NV values at once (fixed order; result in every thread).
+template <int NV>
+__device__ inline void block_sum_n(double* v, double* sh) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) sh[w * NV + j] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    double r = 0;
+    for (int i = 0; i < nw; ++i) r += sh[i * NV + j];
+    v[j] = r;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
-  extern __shared__ double Zs[];
-  __shared__ double sh[kWaves + 1];
+  __shared__ double sh[kWaves * (1 + 3 * kZB)];
+  __shared__ int64_t zoff[kZMax];
+  __shared__ int nz;
   const int p = blockIdx.x;
   const int A = d.vpA[p], B = d.vpB[p];
   const int mA = d.nabf[A], mB = d.nabf[B], n = mA * mB;
@@ -369,53 +440,55 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
     if (threadIdx.x == 0) d.Ep[p] = 0.0;
     return;
   }
-  const int vp0 = d.vpRow[A], nVpA = d.vpRow[A + 1] - vp0, bpos = p - vp0;
-  const double* vf = d.Vf + d.vfOff[p];
-  double es = 0;
-  for (int e = threadIdx.x; e < n; e += kNT) {
-    double z = 0;
+  if (threadIdx.x == 0) {
+    const int vp0 = d.vpRow[A], nVpA = d.vpRow[A + 1] - vp0, bpos = p - vp0;
+    int k = 0;
     for (int cp = d.cpRow[A]; cp < d.cpRow[A + 1]; ++cp) {
       if (!d.aliveC[cp]) continue;
-      const double* zp = d.Zbuf + d.zOff[d.tBase[A] + (int64_t)(cp - d.cpRow[A]) * nVpA + bpos];
-      for (int kc = 0; kc < d.nkc[cp]; ++kc) z += zp[(int64_t)kc * n + e];
+      const int64_t base = d.zOff[d.tBase[A] + (int64_t)(cp - d.cpRow[A]) * nVpA + bpos];
+      for (int kc = 0; kc < d.nkc[cp] && k < kZMax; ++kc) zoff[k++] = base + (int64_t)kc * n;
     }
-    Zs[e] = z;
-    es += vf[e] * z;
+    nz = k;
   }
-  es = block_sum(es, sh);
-  if (threadIdx.x == 0) d.Ep[p] = -es;
-  for (int k0 = d.vpB0[p]; k0 < d.vpB1[p]; k0 += kZB) {
-    const int nb = min(kZB, d.vpB1[p] - k0);
+  __syncthreads();
+  const int NZ = nz;
+  const double* vf = d.Vf + d.vfOff[p];
+  const int kb0 = d.vpB0[p], kb1 = d.vpB1[p];
+  for (int k0 = kb0; k0 < kb1 || k0 == kb0; k0 += kZB) {
+    const int nb = max(0, min(kZB, kb1 - k0));
     const double* dv[kZB];
     bool kp[kZB];
 #pragma unroll
     for (int j = 0; j < kZB; ++j) {
-      const int64_t b = d.vpBlk[k0 + (j < nb ? j : 0)];
+      const int64_t b = d.vpBlk[j < nb ? k0 + j : kb0];
       kp[j] = j < nb && d.keepV[b];
       dv[j] = d.Vdval + 3 * d.Voff[b];
     }
-    double t[kZB][3];
+    double acc[1 + 3 * kZB];
 #pragma unroll
-    for (int j = 0; j < kZB; ++j) t[j][0] = t[j][1] = t[j][2] = 0.0;
+    for (int j = 0; j < 1 + 3 * kZB; ++j) acc[j] = 0.0;
+    const bool first = k0 == kb0;
     for (int e = threadIdx.x; e < n; e += kNT) {
-      const double z = Zs[e];
+      double z = 0;
+      for (int k = 0; k < NZ; ++k) z += d.Zbuf[zoff[k] + e];
+      if (first) acc[0] += vf[e] * z;
 #pragma unroll
       for (int j = 0; j < kZB; ++j)
         if (kp[j]) {
-          t[j][0] += dv[j][e] * z;
-          t[j][1] += dv[j][n + e] * z;
-          t[j][2] += dv[j][2 * n + e] * z;
+          acc[1 + 3 * j] += dv[j][e] * z;
+          acc[2 + 3 * j] += dv[j][n + e] * z;
+          acc[3 + 3 * j] += dv[j][2 * n + e] * z;
         }
     }
-#pragma unroll
-    for (int j = 0; j < kZB; ++j) {
-      if (j >= nb) break;
-      const int64_t b = d.vpBlk[k0 + j];
-      for (int x = 0; x < 3; ++x) {
-        const double r = block_sum(t[j][x], sh);
-        if (threadIdx.x == 0) d.gV[3 * b + x] = kp[j] ? -r : 0.0;
+    block_sum_n<1 + 3 * kZB>(acc, sh);
+    if (threadIdx.x == 0) {
+      if (first) d.Ep[p] = -acc[0];
+      for (int j = 0; j < nb; ++j) {
+        const int64_t b = d.vpBlk[k0 + j];
+        for (int x = 0; x < 3; ++x) d.gV[3 * b + x] = kp[j] ? -acc[1 + 3 * j + x] : 0.0;
       }
     }
+    if (kb1 <= kb0) break;
   }
 }
 
@@ -525,7 +598,7 @@ static void launch_triple(const Dev& d, hipStream_t s) {
 
 void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, hipEvent_t* ev) {
   if (d.nHB) {
-    const size_t lds = (size_t)kHRows * (max_depth + 1) * sizeof(double);
+    const size_t lds = ((size_t)kHRows * (max_depth + 1) + 2 * (size_t)max_depth * 32) * sizeof(double);
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_hbuild, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_hbuild, dim3(d.nHB), dim3(kNT), lds, s, d);
   }
@@ -539,11 +612,7 @@ void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, hip
   launch_triple<7>(d, s);
   launch_triple<8>(d, s);
   if (ev) (void)hipEventRecord(ev[5], s);
-  if (d.nVp) {
-    const size_t lds = (size_t)max_mm * sizeof(double);
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_zgrad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_zgrad, dim3(d.nVp), dim3(kNT), lds, s, d);
-  }
+  if (d.nVp) hipLaunchKernelGGL(k_zgrad, dim3(d.nVp), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[6], s);
   if (d.nCp) hipLaunchKernelGGL(k_cgrad, dim3(d.nCp), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[7], s);
