@@ -342,7 +342,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       int k = 0;
       for (int i = cp.row[B]; i < cp.row[B + 1]; ++i) k += c->nao[cp.pB[i]];
       require(k + 3 <= lrx::kHMaxDepth,
-              "atom " + std::to_string(B) + ": its C partners have more than 140 NAOs in total");
+              "atom " + std::to_string(B) + ": its C partners have more than 1020 NAOs in total");
       c->max_depth = std::max(c->max_depth, (k + 3) & ~3);
       const int rows = c->nabf[B] * c->nao[B];
       for (int r0 = 0; r0 < rows; r0 += lrx::kHRows) {

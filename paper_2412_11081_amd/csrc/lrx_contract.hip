@@ -61,7 +61,8 @@ __device__ inline int xcd_remap(int b, int G) {
 // outermost so that the triple kernel reads 16 consecutive (beta,x) per b.
 // ---------------------------------------------------------------------------
 constexpr int kHStage = 18;   // D elements per thread staged for the next slot (18 x 256 >= 144 x 32)
-__device__ inline void hstage_load(const Dev& d, const int* krow, const int* kG, int K, int X, int tid, double* st) {
+__device__ inline void hstage_load(const Dev& d, const int* krow, const int* kG, int kb, int K, int X, int tid,
+                                   double* st) {
   const int nX = d.nao[X];
   const int64_t col0 = d.ao[X];
 #pragma unroll
@@ -70,8 +71,8 @@ __device__ inline void hstage_load(const Dev& d, const int* krow, const int* kG,
     double v = 0;
     if (e < K * nX) {
       const int k = e / nX, x = e - k * nX;
-      const int G = kG[k];
-      if (G >= 0 && d.keepD[(int64_t)G * d.N + X]) v = d.D[(int64_t)krow[k] * d.ntot + col0 + x];
+      const int G = kG[kb + k];
+      if (G >= 0 && d.keepD[(int64_t)G * d.N + X]) v = d.D[(int64_t)krow[kb + k] * d.ntot + col0 + x];
     }
     st[j] = v;
   }
@@ -87,12 +88,16 @@ __device__ inline void hstage_store(int K, int nX, int tid, const double* st, do
   }
 }
 
+// One workgroup per (B, 64 rows of (beta,b)).  The depth index (every g of
+// every live C pair (B,G)) is processed in passes of at most kHPass; each
+// pass stages its rows of Cf(B, .) in LDS once and loops over all needed X of
+// B with the D(G, X) tile of the next X staged while the current one runs.
 __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
   __shared__ int krow[kHMaxDepth];   // D row (ao[G] + g) of depth index k
   __shared__ int kG[kHMaxDepth];     // atom G, or -1 for padding
   __shared__ int kcp[kHMaxDepth];
   __shared__ int kdepth;
-  extern __shared__ double hl[];     // As[kHRows][depth + 1], Ds[2][depth][32]
+  extern __shared__ double hl[];     // As[kHRows][pass depth + 1], Ds[2][pass depth][32]
   const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x];
   const int mB = d.nabf[B], nB = d.nao[B], rows = mB * nB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
@@ -113,52 +118,56 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
     kdepth = kp;
   }
   __syncthreads();
-  const int K = kdepth;
-  const int AS = K + 1;
-  double* As = hl;
-  double* Ds0 = hl + kHRows * AS;
-  for (int e = tid; e < kHRows * K; e += kNT) {
-    const int r = e / K, k = e - r * K;
-    const int row = r0 + r, t = kcp[k];
-    double v = 0;
-    if (row < rows && t >= 0) v = d.Cf[d.cfOff[t >> 6] + (int64_t)row * d.nao[d.cpF[t >> 6]] + (t & 63)];
-    As[r * AS + k] = v;
-  }
-  // first needed slot
+  const int Kall = kdepth;
   const int s1 = d.slotRow[B + 1];
-  int s = d.slotRow[B];
-  while (s < s1 && !d.need[s]) ++s;
-  double st[kHStage];
-  if (s < s1) {
-    hstage_load(d, krow, kG, K, d.slotX[s], tid, st);
-    hstage_store(K, d.nao[d.slotX[s]], tid, st, Ds0);
-  }
-  __syncthreads();
-  int buf = 0;
-  while (s < s1) {
-    int sn = s + 1;
-    while (sn < s1 && !d.need[sn]) ++sn;
-    if (sn < s1) hstage_load(d, krow, kG, K, d.slotX[sn], tid, st);
-    const int X = d.slotX[s], nX = d.nao[X];
-    const double* Ds = Ds0 + buf * K * 32;
-    double* Hout = d.H + d.hOff[s];
-    for (int xt = 0; xt * 16 < nX; ++xt) {
-      const int x = 16 * xt + q;
-      d4 acc = {0, 0, 0, 0};
-      for (int k0 = 0; k0 < K; k0 += 4)
-        acc = mfma_f64(As[(16 * w + q) * AS + k0 + g], x < nX ? Ds[(k0 + g) * 32 + x] : 0.0, acc);
-      for (int i = 0; i < 4; ++i) {
-        const int r = r0 + 16 * w + g + 4 * i;
-        if (r < rows && x < nX) {
-          const int be = r / nB, bb = r - be * nB;
-          Hout[((int64_t)bb * mB + be) * nX + x] = acc[i];
+  for (int kb = 0; kb < Kall || (kb == 0 && Kall == 0); kb += kHPass) {
+    const int K = min(kHPass, Kall - kb);
+    const int AS = K + 1;
+    double* As = hl;
+    double* Ds0 = hl + kHRows * AS;
+    for (int e = tid; e < kHRows * K; e += kNT) {
+      const int r = e / K, k = e - r * K;
+      const int row = r0 + r, t = kcp[kb + k];
+      double v = 0;
+      if (row < rows && t >= 0) v = d.Cf[d.cfOff[t >> 6] + (int64_t)row * d.nao[d.cpF[t >> 6]] + (t & 63)];
+      As[r * AS + k] = v;
+    }
+    int s = d.slotRow[B];
+    while (s < s1 && !d.need[s]) ++s;
+    double st[kHStage];
+    if (s < s1) {
+      hstage_load(d, krow, kG, kb, K, d.slotX[s], tid, st);
+      hstage_store(K, d.nao[d.slotX[s]], tid, st, Ds0);
+    }
+    __syncthreads();
+    int buf = 0;
+    while (s < s1) {
+      int sn = s + 1;
+      while (sn < s1 && !d.need[sn]) ++sn;
+      if (sn < s1) hstage_load(d, krow, kG, kb, K, d.slotX[sn], tid, st);
+      const int X = d.slotX[s], nX = d.nao[X];
+      const double* Ds = Ds0 + buf * K * 32;
+      double* Hout = d.H + d.hOff[s];
+      for (int xt = 0; xt * 16 < nX; ++xt) {
+        const int x = 16 * xt + q;
+        d4 acc = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < K; k0 += 4)
+          acc = mfma_f64(As[(16 * w + q) * AS + k0 + g], x < nX ? Ds[(k0 + g) * 32 + x] : 0.0, acc);
+        for (int i = 0; i < 4; ++i) {
+          const int r = r0 + 16 * w + g + 4 * i;
+          if (r < rows && x < nX) {
+            const int be = r / nB, bb = r - be * nB;
+            double* hp = Hout + ((int64_t)bb * mB + be) * nX + x;
+            *hp = kb == 0 ? acc[i] : *hp + acc[i];
+          }
         }
       }
+      if (sn < s1) hstage_store(K, d.nao[d.slotX[sn]], tid, st, Ds0 + (buf ^ 1) * K * 32);
+      __syncthreads();
+      buf ^= 1;
+      s = sn;
     }
-    if (sn < s1) hstage_store(K, d.nao[d.slotX[sn]], tid, st, Ds0 + (buf ^ 1) * K * 32);
-    __syncthreads();
-    buf ^= 1;
-    s = sn;
+    if (Kall == 0) break;
   }
 }
 
@@ -598,7 +607,8 @@ static void launch_triple(const Dev& d, hipStream_t s) {
 
 void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, hipEvent_t* ev) {
   if (d.nHB) {
-    const size_t lds = ((size_t)kHRows * (max_depth + 1) + 2 * (size_t)max_depth * 32) * sizeof(double);
+    const int kp = max_depth < kHPass ? max_depth : kHPass;
+    const size_t lds = ((size_t)kHRows * (kp + 1) + 2 * (size_t)kp * 32) * sizeof(double);
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_hbuild, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_hbuild, dim3(d.nHB), dim3(kNT), lds, s, d);
   }

@@ -35,7 +35,8 @@ constexpr int kMaxAlphaTiles = (kMaxNabf + 15) / 16;
 // these columns and the Y tiles of these columns in registers).
 __host__ __device__ constexpr int unit_cols(int alpha_tiles) { return alpha_tiles <= 5 ? 176 : 128; }
 constexpr int kHRows = 64;         // rows (beta,b) of H one H-build workgroup owns
-constexpr int kHMaxDepth = 144;    // max sum of NAOs over the C partners of one atom
+constexpr int kHMaxDepth = 1024;   // max sum of NAOs over the C partners of one atom
+constexpr int kHPass = 144;        // depth of one H-build pass
 
 // Everything the kernels read or write for one structure.  Passed by value.
 struct Dev {
