@@ -334,7 +334,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       const int B = c->slotB[s], X = c->slotX[s];
       hOff[s + 1] = hOff[s] + (int64_t)c->nabf[B] * c->nao[B] * c->nao[X];
     }
-    std::vector<int> slotRow(N + 1, 0), hbB, hbR0;
+    std::vector<int> slotRow(N + 1, 0), hbB, hbR0, hbC0, hColRow(N + 1, 0), hColSlot, hColX;
     for (int s = 0; s < nSlot; ++s) slotRow[c->slotB[s] + 1]++;
     for (int B = 0; B < N; ++B) slotRow[B + 1] += slotRow[B];
     c->max_depth = 4;
@@ -344,11 +344,21 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       require(k + 3 <= lrx::kHMaxDepth,
               "atom " + std::to_string(B) + ": its C partners have more than 1020 NAOs in total");
       c->max_depth = std::max(c->max_depth, (k + 3) & ~3);
-      const int rows = c->nabf[B] * c->nao[B];
-      for (int r0 = 0; r0 < rows; r0 += lrx::kHRows) {
-        hbB.push_back(B);
-        hbR0.push_back(r0);
-      }
+    }
+    for (int B = 0; B < N; ++B) {
+      for (int s = slotRow[B]; s < slotRow[B + 1]; ++s)
+        for (int x = 0; x < c->nao[c->slotX[s]]; ++x) {
+          hColSlot.push_back(s);
+          hColX.push_back(x);
+        }
+      hColRow[B + 1] = (int)hColSlot.size();
+      const int rows = c->nabf[B] * c->nao[B], cols = hColRow[B + 1] - hColRow[B];
+      for (int r0 = 0; r0 < rows; r0 += lrx::kHRows)
+        for (int c0 = 0; c0 < cols; c0 += 64) {
+          hbB.push_back(B);
+          hbR0.push_back(r0);
+          hbC0.push_back(c0);
+        }
     }
     // ---- work units and triple offsets -----------------------------------
     c->unitCp.clear(); c->unitK0.clear(); c->unitK1.clear(); c->unitKc.clear();
@@ -474,6 +484,10 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.nHB = (int)hbB.size();
     d.hbB = c->upload(hbB);
     d.hbR0 = c->upload(hbR0);
+    d.hbC0 = c->upload(hbC0);
+    d.hColRow = c->upload(hColRow);
+    d.hColSlot = c->upload(hColSlot);
+    d.hColX = c->upload(hColX);
     d.unitCp = c->upload(c->unitCp); d.unitK0 = c->upload(c->unitK0); d.unitK1 = c->upload(c->unitK1);
     d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
     d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);

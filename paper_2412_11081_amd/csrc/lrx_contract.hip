@@ -60,46 +60,23 @@ __device__ inline int xcd_remap(int b, int G) {
 // reused for every X of B; wave w owns row tile w.  H is stored with b
 // outermost so that the triple kernel reads 16 consecutive (beta,x) per b.
 // ---------------------------------------------------------------------------
-constexpr int kHStage = 18;   // D elements per thread staged for the next slot (18 x 256 >= 144 x 32)
-__device__ inline void hstage_load(const Dev& d, const int* krow, const int* kG, int kb, int K, int X, int tid,
-                                   double* st) {
-  const int nX = d.nao[X];
-  const int64_t col0 = d.ao[X];
-#pragma unroll
-  for (int j = 0; j < kHStage; ++j) {
-    const int e = tid + kNT * j;
-    double v = 0;
-    if (e < K * nX) {
-      const int k = e / nX, x = e - k * nX;
-      const int G = kG[kb + k];
-      if (G >= 0 && d.keepD[(int64_t)G * d.N + X]) v = d.D[(int64_t)krow[kb + k] * d.ntot + col0 + x];
-    }
-    st[j] = v;
-  }
-}
-__device__ inline void hstage_store(int K, int nX, int tid, const double* st, double* Ds) {
-#pragma unroll
-  for (int j = 0; j < kHStage; ++j) {
-    const int e = tid + kNT * j;
-    if (e < K * nX) {
-      const int k = e / nX, x = e - k * nX;
-      Ds[k * 32 + x] = st[j];
-    }
-  }
-}
-
-// One workgroup per (B, 64 rows of (beta,b)).  The depth index (every g of
-// every live C pair (B,G)) is processed in passes of at most kHPass; each
-// pass stages its rows of Cf(B, .) in LDS once and loops over all needed X of
-// B with the D(G, X) tile of the next X staged while the current one runs.
+// One workgroup per (B, 64 rows of (beta,b), 64 columns): the columns are
+// the (X, x) pairs of every H slot of B concatenated, so one D tile staged in
+// LDS serves four 16-column MFMA tiles per wave, and the Cf(B, .) fragments
+// of the wave's row tile stay in registers for the whole tile.  The depth
+// (every g of every live C pair (B,G)) runs in passes of at most kHPass.
+constexpr int kHCols = 64;
 __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
   __shared__ int krow[kHMaxDepth];   // D row (ao[G] + g) of depth index k
   __shared__ int kG[kHMaxDepth];     // atom G, or -1 for padding
   __shared__ int kcp[kHMaxDepth];
   __shared__ int kdepth;
-  extern __shared__ double hl[];     // As[kHRows][pass depth + 1], Ds[2][pass depth][32]
-  const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x];
+  __shared__ double Ds[kHPass * kHCols];
+  const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x], c0 = d.hbC0[blockIdx.x];
   const int mB = d.nabf[B], nB = d.nao[B], rows = mB * nB;
+  const int ncols = d.hColRow[B + 1] - d.hColRow[B];
+  const int* colSlot = d.hColSlot + d.hColRow[B];
+  const int* colX = d.hColX + d.hColRow[B];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
   if (tid == 0) {
     int k = 0;
@@ -119,55 +96,48 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
   }
   __syncthreads();
   const int Kall = kdepth;
-  const int s1 = d.slotRow[B + 1];
-  for (int kb = 0; kb < Kall || (kb == 0 && Kall == 0); kb += kHPass) {
+  const int row = r0 + 16 * w + q;    // A-operand row of this lane
+  d4 acc[kHCols / 16];
+#pragma unroll
+  for (int j = 0; j < kHCols / 16; ++j) acc[j] = d4{0, 0, 0, 0};
+  for (int kb = 0; kb < Kall; kb += kHPass) {
     const int K = min(kHPass, Kall - kb);
-    const int AS = K + 1;
-    double* As = hl;
-    double* Ds0 = hl + kHRows * AS;
-    for (int e = tid; e < kHRows * K; e += kNT) {
-      const int r = e / K, k = e - r * K;
-      const int row = r0 + r, t = kcp[kb + k];
+    // stage D[(G,g)][column] for this pass
+    for (int e = tid; e < K * kHCols; e += kNT) {
+      const int k = e / kHCols, cl = e - k * kHCols, c = c0 + cl;
       double v = 0;
-      if (row < rows && t >= 0) v = d.Cf[d.cfOff[t >> 6] + (int64_t)row * d.nao[d.cpF[t >> 6]] + (t & 63)];
-      As[r * AS + k] = v;
-    }
-    int s = d.slotRow[B];
-    while (s < s1 && !d.need[s]) ++s;
-    double st[kHStage];
-    if (s < s1) {
-      hstage_load(d, krow, kG, kb, K, d.slotX[s], tid, st);
-      hstage_store(K, d.nao[d.slotX[s]], tid, st, Ds0);
+      if (c < ncols) {
+        const int s = colSlot[c], X = d.slotX[s], G = kG[kb + k];
+        if (G >= 0 && d.need[s] && d.keepD[(int64_t)G * d.N + X])
+          v = d.D[(int64_t)krow[kb + k] * d.ntot + d.ao[X] + colX[c]];
+      }
+      Ds[k * kHCols + cl] = v;
     }
     __syncthreads();
-    int buf = 0;
-    while (s < s1) {
-      int sn = s + 1;
-      while (sn < s1 && !d.need[sn]) ++sn;
-      if (sn < s1) hstage_load(d, krow, kG, kb, K, d.slotX[sn], tid, st);
-      const int X = d.slotX[s], nX = d.nao[X];
-      const double* Ds = Ds0 + buf * K * 32;
-      double* Hout = d.H + d.hOff[s];
-      for (int xt = 0; xt * 16 < nX; ++xt) {
-        const int x = 16 * xt + q;
-        d4 acc = {0, 0, 0, 0};
-        for (int k0 = 0; k0 < K; k0 += 4)
-          acc = mfma_f64(As[(16 * w + q) * AS + k0 + g], x < nX ? Ds[(k0 + g) * 32 + x] : 0.0, acc);
-        for (int i = 0; i < 4; ++i) {
-          const int r = r0 + 16 * w + g + 4 * i;
-          if (r < rows && x < nX) {
-            const int be = r / nB, bb = r - be * nB;
-            double* hp = Hout + ((int64_t)bb * mB + be) * nX + x;
-            *hp = kb == 0 ? acc[i] : *hp + acc[i];
-          }
-        }
-      }
-      if (sn < s1) hstage_store(K, d.nao[d.slotX[sn]], tid, st, Ds0 + (buf ^ 1) * K * 32);
-      __syncthreads();
-      buf ^= 1;
-      s = sn;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int t = kcp[kb + k0 + g];
+      double a = 0;
+      if (row < rows && t >= 0) a = d.Cf[d.cfOff[t >> 6] + (int64_t)row * d.nao[d.cpF[t >> 6]] + (t & 63)];
+#pragma unroll
+      for (int j = 0; j < kHCols / 16; ++j) acc[j] = mfma_f64(a, Ds[(k0 + g) * kHCols + 16 * j + q], acc[j]);
     }
-    if (Kall == 0) break;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < kHCols / 16; ++j) {
+    const int c = c0 + 16 * j + q;
+    if (c >= ncols) continue;
+    const int s = colSlot[c];
+    if (!d.need[s]) continue;
+    const int X = d.slotX[s], nX = d.nao[X], x = colX[c];
+    double* Hout = d.H + d.hOff[s];
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + 16 * w + g + 4 * i;
+      if (r < rows) {
+        const int be = r / nB, bb = r - be * nB;
+        Hout[((int64_t)bb * mB + be) * nX + x] = acc[j][i];
+      }
+    }
   }
 }
 
@@ -201,48 +171,67 @@ struct UnitGeo {
   int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, T1, T2, fpos, vp0, nVpA;
 };
 
-// X-build for one (B, beta0) chunk: all 8 waves share the MFMA tiles.
-__device__ inline void xbuild(const Dev& d, const UnitGeo& U, int w, int q, int g, int mB, int nB, int b0,
+// X-build for one (B, beta0) chunk, done by the four Y waves (yw = 0..3);
+// the tiles of a wave are taken two at a time so both tiles' H loads are in
+// flight together.
+__device__ inline void xbuild_tile_load(const UnitGeo& U, int t, int q, int g, int mB, int nB, int b0, int SB,
+                                        const double* hBF, const double* hBA, double* hv) {
+  const bool one = t < U.T1;
+  const int tt = one ? t : t - U.T1;
+  const int ncol = one ? U.nF : U.nA;
+  const int tc = tt - (tt / ncol) * ncol;
+  const double* hp = one ? hBF : hBA;
+  const int c = 16 * tc + q;
+  const bool cvalid = b0 * ncol + c < mB * ncol;
+  const int64_t hrow = (int64_t)mB * ncol;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int b = 4 * s + g;
+    hv[s] = (s < SB && b < nB && cvalid) ? hp[(int64_t)b * hrow + b0 * ncol + c] : 0.0;
+  }
+}
+__device__ inline void xbuild_tile_mma(const UnitGeo& U, int t, int q, int g, int nB, int SB, const double* hv,
+                                       const double* Dab, const double* Dfb, double* X1, double* X2) {
+  const bool one = t < U.T1;
+  const int tt = one ? t : t - U.T1;
+  const int ncol = one ? U.nF : U.nA;
+  const int nrow = one ? U.nA : U.nF;
+  const int tr = tt / ncol, tc = tt - tr * ncol;
+  const double* Ds = one ? Dab : Dfb;
+  d4 acc = {0, 0, 0, 0};
+  const int r = 16 * tr + q;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    if (s < SB) {
+      const int b = 4 * s + g;
+      const double av = (r < nrow && b < nB) ? Ds[r * nB + b] : 0.0;
+      acc = mfma_f64(av, hv[s], acc);
+    }
+  }
+  const int c = 16 * tc + q;
+  const int bl = c / ncol, xo = c - bl * ncol;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rr = 16 * tr + g + 4 * i;
+    if (rr < nrow) {
+      const int k = one ? rr * U.nF + xo : xo * U.nF + rr;
+      const int cl = k - U.k0;
+      if (cl >= 0 && cl < U.Kc) (one ? X1 : X2)[bl * U.XS + cl] = acc[i];
+    }
+  }
+}
+__device__ inline void xbuild(const Dev& d, const UnitGeo& U, int yw, int q, int g, int mB, int nB, int b0,
                               const double* hBF, const double* hBA, const double* Dab, const double* Dfb,
                               double* X1, double* X2) {
   const int SB = (nB + 3) >> 2;
-  for (int t = w; t < U.T1 + U.T2; t += 8) {
-    const bool one = t < U.T1;
-    const int tt = one ? t : t - U.T1;
-    const int ncol = one ? U.nF : U.nA;   // AO count of the atom along the columns
-    const int nrow = one ? U.nA : U.nF;
-    const int tr = tt / ncol, tc = tt - tr * ncol;
-    const double* Ds = one ? Dab : Dfb;
-    const double* hp = one ? hBF : hBA;
-    const int c = 16 * tc + q;            // (beta_local, x) flattened, x < ncol
-    const bool cvalid = b0 * ncol + c < mB * ncol;
-    const int64_t hrow = (int64_t)mB * ncol;
-    double hv[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int b = 4 * s + g;
-      hv[s] = (s < SB && b < nB && cvalid) ? hp[(int64_t)b * hrow + b0 * ncol + c] : 0.0;
-    }
-    d4 acc = {0, 0, 0, 0};
-    const int r = 16 * tr + q;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      if (s < SB) {
-        const int b = 4 * s + g;
-        const double av = (r < nrow && b < nB) ? Ds[r * nB + b] : 0.0;
-        acc = mfma_f64(av, hv[s], acc);
-      }
-    }
-    const int bl = c / ncol, xo = c - bl * ncol;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int rr = 16 * tr + g + 4 * i;
-      if (rr < nrow) {
-        const int k = one ? rr * U.nF + xo : xo * U.nF + rr;
-        const int cl = k - U.k0;
-        if (cl >= 0 && cl < U.Kc) (one ? X1 : X2)[bl * U.XS + cl] = acc[i];
-      }
-    }
+  const int T = U.T1 + U.T2;
+  for (int t = yw; t < T; t += 8) {
+    const int t2 = t + 4;
+    double h0[8], h1[8];
+    xbuild_tile_load(U, t, q, g, mB, nB, b0, SB, hBF, hBA, h0);
+    if (t2 < T) xbuild_tile_load(U, t2, q, g, mB, nB, b0, SB, hBF, hBA, h1);
+    xbuild_tile_mma(U, t, q, g, nB, SB, h0, Dab, Dfb, X1, X2);
+    if (t2 < T) xbuild_tile_mma(U, t2, q, g, nB, SB, h1, Dab, Dfb, X1, X2);
   }
 }
 
@@ -306,7 +295,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int tid
             avn[s][i] = (al < mA && be < mB) ? Vfp[(int64_t)al * mB + be] : 0.0;
           }
       }
-      xbuild(d, U, w, q, g, mB, nB, b0, hBF, hBA, Dab, Dfb, X1, X2);
+      if constexpr (!ZROLE) xbuild(d, U, ww, q, g, mB, nB, b0, hBF, hBA, Dab, Dfb, X1, X2);
       __syncthreads();
       if constexpr (ZROLE) {
         d4 zp[MT];
@@ -606,12 +595,8 @@ static void launch_triple(const Dev& d, hipStream_t s) {
 }
 
 void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, hipEvent_t* ev) {
-  if (d.nHB) {
-    const int kp = max_depth < kHPass ? max_depth : kHPass;
-    const size_t lds = ((size_t)kHRows * (kp + 1) + 2 * (size_t)kp * 32) * sizeof(double);
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_hbuild, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_hbuild, dim3(d.nHB), dim3(kNT), lds, s, d);
-  }
+  (void)max_depth;
+  if (d.nHB) hipLaunchKernelGGL(k_hbuild, dim3(d.nHB), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[4], s);
   launch_triple<1>(d, s);
   launch_triple<2>(d, s);

@@ -36,7 +36,7 @@ constexpr int kMaxAlphaTiles = (kMaxNabf + 15) / 16;
 __host__ __device__ constexpr int unit_cols(int alpha_tiles) { return alpha_tiles <= 5 ? 176 : 128; }
 constexpr int kHRows = 64;         // rows (beta,b) of H one H-build workgroup owns
 constexpr int kHMaxDepth = 1024;   // max sum of NAOs over the C partners of one atom
-constexpr int kHPass = 144;        // depth of one H-build pass
+constexpr int kHPass = 128;        // depth of one H-build pass
 
 // Everything the kernels read or write for one structure.  Passed by value.
 struct Dev {
@@ -81,7 +81,9 @@ struct Dev {
   int nSlot;
   const int* slotB; const int* slotX; const int64_t* hOff; const int* hSlotMap; // [N][N] -> slot or -1
   const int* slotRow;      // [N+1] slots of atom B are slotRow[B] .. slotRow[B+1]-1 (sorted by X)
-  int nHB; const int* hbB; const int* hbR0;   // H-build work items: (B, first row)
+  int nHB; const int* hbB; const int* hbR0; const int* hbC0;   // H-build work items: (B, first row, first column)
+  const int* hColRow;      // [N+1] columns of atom B: the (slot, x) of every H slot of B, concatenated
+  const int* hColSlot; const int* hColX;
   uint8_t* need;
   double* H;
 
