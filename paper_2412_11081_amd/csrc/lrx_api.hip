@@ -332,7 +332,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     std::vector<int64_t> hOff(nSlot + 1, 0);
     for (int s = 0; s < nSlot; ++s) {
       const int B = c->slotB[s], X = c->slotX[s];
-      hOff[s + 1] = hOff[s] + (int64_t)c->nabf[B] * c->nao[B] * c->nao[X];
+      hOff[s + 1] = hOff[s] + (int64_t)((c->nabf[B] + 15) / 16 * 16) * c->nao[B] * c->nao[X];
     }
     std::vector<int> slotRow(N + 1, 0), hbB, hbR0, hbC0, hColRow(N + 1, 0), hColSlot, hColX;
     for (int s = 0; s < nSlot; ++s) slotRow[c->slotB[s] + 1]++;
@@ -397,6 +397,34 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
         }
     }
     for (int64_t t = 0; t < ntri; ++t) zOff[t + 1] += zOff[t];
+    std::vector<int64_t> triHF(std::max<int64_t>(1, ntri)), triHA(std::max<int64_t>(1, ntri));
+    for (int A = 0; A < N; ++A) {
+      const int nvA = vp.row[A + 1] - vp.row[A];
+      for (int i = cp.row[A]; i < cp.row[A + 1]; ++i)
+        for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
+          const int64_t t = c->tBase[A] + (int64_t)(i - cp.row[A]) * nvA + (p - vp.row[A]);
+          const int B = vp.pB[p];
+          triHF[t] = hOff[slotmap[(size_t)B * N + cp.pB[i]]];
+          triHA[t] = hOff[slotmap[(size_t)B * N + A]];
+        }
+    }
+    // static depth tables of the H build: every g of every C pair (B, G)
+    std::vector<int> hdRow(N + 1, 0), hdRowD, hdG, hdCp;
+    for (int B = 0; B < N; ++B) {
+      int k = 0;
+      for (int i = cp.row[B]; i < cp.row[B + 1]; ++i)
+        for (int gg = 0; gg < c->nao[cp.pB[i]]; ++gg, ++k) {
+          hdRowD.push_back((int)(c->ao[cp.pB[i]] + gg));
+          hdG.push_back(cp.pB[i]);
+          hdCp.push_back((i << 6) | gg);
+        }
+      for (; k & 3; ++k) {
+        hdRowD.push_back(0);
+        hdG.push_back(-1);
+        hdCp.push_back(-1);
+      }
+      hdRow[B + 1] = (int)hdRowD.size();
+    }
     // ---- per-atom block lists for the force reduction ---------------------
     std::vector<int> atCfRow, atCsRow, atVfRow, atVsRow;
     std::vector<int64_t> atCf, atCs, atVf, atVs;
@@ -469,6 +497,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.hSlotMap = c->upload(slotmap);
     d.need = c->dalloc<uint8_t>(nSlot);
     d.H = c->dalloc<double>(hOff[nSlot]);
+    HIPCHK(hipMemsetAsync(d.H, 0, sizeof(double) * std::max<int64_t>(1, hOff[nSlot]), c->stream));
     d.nUnit = (int)c->unitCp.size();
     std::vector<int> unitOrder(d.nUnit);
     {
@@ -491,6 +520,8 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.unitCp = c->upload(c->unitCp); d.unitK0 = c->upload(c->unitK0); d.unitK1 = c->upload(c->unitK1);
     d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
     d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);
+    d.triHF = c->upload(triHF); d.triHA = c->upload(triHA);
+    d.hdRow = c->upload(hdRow); d.hdRowD = c->upload(hdRowD); d.hdG = c->upload(hdG); d.hdCp = c->upload(hdCp);
     d.Zbuf = c->dalloc<double>(zOff[ntri]);
     d.yOff = c->upload(cfOff);
     d.Ybuf = c->dalloc<double>(cfOff[nCp]);

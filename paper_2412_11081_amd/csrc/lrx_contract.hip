@@ -78,24 +78,20 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
   const int* colSlot = d.hColSlot + d.hColRow[B];
   const int* colX = d.hColX + d.hColRow[B];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
-  if (tid == 0) {
-    int k = 0;
-    for (int cp = d.cpRow[B]; cp < d.cpRow[B + 1]; ++cp) {
-      if (!d.aliveC[cp]) continue;
-      const int G = d.cpF[cp], nG = d.nao[G];
-      for (int gg = 0; gg < nG && k < kHMaxDepth; ++gg) {
-        krow[k] = (int)(d.ao[G] + gg);
-        kG[k] = G;
-        kcp[k] = (cp << 6) | gg;
-        ++k;
-      }
+  {
+    const int h0 = d.hdRow[B], hn = d.hdRow[B + 1] - h0;
+    for (int k = tid; k < hn; k += kNT) {
+      const int t = d.hdCp[h0 + k];
+      const bool live = t >= 0 && d.aliveC[t >> 6];
+      krow[k] = d.hdRowD[h0 + k];
+      kG[k] = live ? d.hdG[h0 + k] : -1;
+      kcp[k] = live ? t : -1;
     }
-    const int kp = (k + 3) & ~3;
-    for (int i = k; i < kp; ++i) { krow[i] = 0; kG[i] = -1; kcp[i] = -1; }
-    kdepth = kp;
+    if (tid == 0) kdepth = hn;
   }
   __syncthreads();
   const int Kall = kdepth;
+  const int mBp = (mB + 15) & ~15;
   const int row = r0 + 16 * w + q;    // A-operand row of this lane
   d4 acc[kHCols / 16];
 #pragma unroll
@@ -135,7 +131,7 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
       const int r = r0 + 16 * w + g + 4 * i;
       if (r < rows) {
         const int be = r / nB, bb = r - be * nB;
-        Hout[((int64_t)bb * mB + be) * nX + x] = acc[j][i];
+        Hout[((int64_t)bb * mBp + be) * nX + x] = acc[j][i];
       }
     }
   }
@@ -143,15 +139,18 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
 
 // ---------------------------------------------------------------------------
 // Triple products.  One workgroup of 8 waves per unit (C pair (A,F), column
-// chunk [k0,k1) of the (a,f) index), for every live V pair (A,B) and every
-// 16 rows beta0..beta0+15 of B's ABFs:
-//   X-build (all waves, MFMA):  X1[beta][a f] = sum_b D_AB[a][b] H(B,F)[b][beta][f]
-//                               X2[beta][a f] = sum_b D_FB[f][b] H(B,A)[b][beta][a]
-//   Z waves 0-3 (split K):      Z(A,B)[alpha][beta] partial over (a,f) in the chunk,
-//                               Cf(A,F) fragments resident in registers, summed
-//                               over the four waves through LDS -> Zbuf
-//   Y waves 4-7:                Y(A,F)[alpha][a f] += Vf(A,B)[alpha][beta] X[beta][a f]
-//                               (accumulators resident for the whole unit)
+// chunk [k0,k1) of the (a,f) index), looping over "chunks" = (live V pair
+// (A,B), 16 rows beta0..beta0+15 of B's ABFs):
+//   X-build (all waves, MFMA, operands in LDS):
+//       X1[beta][a f] = sum_b D_AB[a][b] H(B,F)[b][beta][f]
+//       X2[beta][a f] = sum_b D_FB[f][b] H(B,A)[b][beta][a]
+//   Z waves 0-3 (K split four ways, Cf(A,F) fragments in registers):
+//       Z(A,B)[alpha][beta] partial over (a,f) in the chunk -> Zbuf
+//   Y waves 4-7 (accumulators resident for the whole unit):
+//       Y(A,F)[alpha][a f] += Vf(A,B)[alpha][beta] X[beta][a f]
+// The H slices (and, when B changes, the D blocks) of the next chunk are
+// brought into LDS with direct global->LDS loads issued right after the
+// X-build of the current chunk, so they arrive while its MFMAs run.
 // ---------------------------------------------------------------------------
 template <int MT>
 struct TripleCfg {
@@ -159,56 +158,121 @@ struct TripleCfg {
   static constexpr int kKSW = kCols / 16;           // Z k-steps per Z wave
   static constexpr int kJW = (kCols / 16 + 3) / 4;  // Y column tiles per Y wave
   static constexpr int kXS = kCols + 1;
-  static constexpr size_t lds_bytes() {
-    return sizeof(double) * (2 * 16 * kXS + 4 * MT * 256 + 2 * kMaxNao * kMaxNao);
-  }
+  static constexpr int kHs = 8160;                  // doubles of staged H per chunk
+  static constexpr size_t lds_doubles() { return 2 * 16 * kXS + 3 * MT * 256 + 2 * kMaxNao * kMaxNao + kHs; }
+  static constexpr size_t lds_bytes() { return sizeof(double) * lds_doubles(); }
 };
 
 constexpr int kTNT = 512;
 
-// Geometry of one triple work unit, shared by both wave roles.
 struct UnitGeo {
   int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, T1, T2, fpos, vp0, nVpA;
 };
 
-// X-build for one (B, beta0) chunk, done by the four Y waves (yw = 0..3);
-// the tiles of a wave are taken two at a time so both tiles' H loads are in
-// flight together.
-__device__ inline void xbuild_tile_load(const UnitGeo& U, int t, int q, int g, int mB, int nB, int b0, int SB,
-                                        const double* hBF, const double* hBA, double* hv) {
-  const bool one = t < U.T1;
-  const int tt = one ? t : t - U.T1;
-  const int ncol = one ? U.nF : U.nA;
-  const int tc = tt - (tt / ncol) * ncol;
-  const double* hp = one ? hBF : hBA;
-  const int c = 16 * tc + q;
-  const bool cvalid = b0 * ncol + c < mB * ncol;
-  const int64_t hrow = (int64_t)mB * ncol;
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int b = 4 * s + g;
-    hv[s] = (s < SB && b < nB && cvalid) ? hp[(int64_t)b * hrow + b0 * ncol + c] : 0.0;
+struct Chunk {
+  int p, B, mB, nB, b0;   // p < 0: no chunk
+};
+
+__device__ inline Chunk chunk_at(const Dev& d, const UnitGeo& U, int p, int b0) {
+  Chunk c;
+  for (; p < U.vp0 + U.nVpA && !d.aliveV[p]; ++p) {
+  }
+  c.p = p < U.vp0 + U.nVpA ? p : -1;
+  c.b0 = b0;
+  if (c.p >= 0) {
+    c.B = d.vpB[c.p];
+    c.mB = d.nabf[c.B];
+    c.nB = d.nao[c.B];
+  } else {
+    c.B = c.mB = c.nB = 0;
+  }
+  return c;
+}
+__device__ inline Chunk chunk_next(const Dev& d, const UnitGeo& U, const Chunk& c) {
+  if (c.p < 0) return c;
+  if (c.b0 + 16 < c.mB) {
+    Chunk n = c;
+    n.b0 += 16;
+    return n;
+  }
+  return chunk_at(d, U, c.p + 1, 0);
+}
+__device__ inline int64_t chunk_tri(const Dev& d, const UnitGeo& U, const Chunk& c) {
+  return d.tBase[U.A] + (int64_t)U.fpos * U.nVpA + (c.p - U.vp0);
+}
+// doubles of H staged for a chunk: HF[b][16 nF] then HA[b][16 nA]
+__device__ inline int chunk_hs(const UnitGeo& U, const Chunk& c) { return c.nB * 16 * (U.nF + U.nA); }
+
+// Direct global->LDS copy of the chunk's H slices (16-byte pieces).
+__device__ inline void stage_h(const Dev& d, const UnitGeo& U, const Chunk& c, double* Hs, int w, int lane) {
+  const int64_t t = chunk_tri(d, U, c);
+  const double* hF = d.H + d.triHF[t];
+  const double* hA = d.H + d.triHA[t];
+  const int mBp = (c.mB + 15) & ~15;
+  const int pF = 8 * U.nF, pA = 8 * U.nA;            // 16-byte pieces per row
+  const int P = c.nB * (pF + pA);
+  for (int j = w; j * 64 < P; j += 8) {
+    const int pc = j * 64 + lane;
+    if (pc < P) {
+      const double* src;
+      if (pc < c.nB * pF) {
+        const int b = pc / pF, m = pc - b * pF;
+        src = hF + ((int64_t)b * mBp + c.b0) * U.nF + 2 * m;
+      } else {
+        const int pp = pc - c.nB * pF;
+        const int b = pp / pA, m = pp - b * pA;
+        src = hA + ((int64_t)b * mBp + c.b0) * U.nA + 2 * m;
+      }
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                       (__attribute__((address_space(3))) void*)(Hs + 128 * j), 16, 0, 0);
+    }
   }
 }
-__device__ inline void xbuild_tile_mma(const UnitGeo& U, int t, int q, int g, int nB, int SB, const double* hv,
-                                       const double* Dab, const double* Dfb, double* X1, double* X2) {
+
+// Direct global->LDS copy of D(A,B) and D(F,B) (4-byte pieces; rows of the
+// dense D are not 16-byte aligned in general).
+__device__ inline void stage_d(const Dev& d, const UnitGeo& U, int B, int nB, double* Dab, double* Dfb, int w,
+                               int lane) {
+  const int PA = 2 * U.nA * nB, PF = 2 * U.nF * nB;
+  for (int j = w; j * 64 < PA + PF; j += 8) {
+    const int pc = j * 64 + lane;
+    // a wave instruction writes 64 consecutive dwords, so the two blocks are
+    // staged as one contiguous image: Dab then Dfb
+    if (pc < PA + PF) {
+      const bool ab = pc < PA;
+      const int pp = ab ? pc : pc - PA;
+      const int e = pp >> 1, hlf = pp & 1;
+      const int r = e / nB, b = e - r * nB;
+      const double* src = d.D + (d.ao[ab ? U.A : U.F] + r) * d.ntot + d.ao[B] + b;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((const char*)src + 4 * hlf),
+                                       (__attribute__((address_space(3))) void*)((char*)Dab + 256 * j), 4, 0, 0);
+    }
+  }
+  (void)Dfb;
+}
+
+// One X-build tile from LDS operands.
+__device__ inline void xbuild_tile(const UnitGeo& U, int t, int q, int g, int nB, const double* Hs,
+                                   const double* Dab, const double* Dfb, bool kAB, bool kFB, double* X1, double* X2) {
   const bool one = t < U.T1;
   const int tt = one ? t : t - U.T1;
   const int ncol = one ? U.nF : U.nA;
   const int nrow = one ? U.nA : U.nF;
   const int tr = tt / ncol, tc = tt - tr * ncol;
   const double* Ds = one ? Dab : Dfb;
-  d4 acc = {0, 0, 0, 0};
-  const int r = 16 * tr + q;
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    if (s < SB) {
-      const int b = 4 * s + g;
-      const double av = (r < nrow && b < nB) ? Ds[r * nB + b] : 0.0;
-      acc = mfma_f64(av, hv[s], acc);
-    }
-  }
+  const double* hs = one ? Hs : Hs + nB * 16 * U.nF;
+  const bool keep = one ? kAB : kFB;
   const int c = 16 * tc + q;
+  const int r = 16 * tr + q;
+  d4 acc = {0, 0, 0, 0};
+  const int SB = (nB + 3) >> 2;
+  for (int s = 0; s < SB; ++s) {
+    const int b = 4 * s + g;
+    const bool ok = keep && b < nB;
+    const double av = (ok && r < nrow) ? Ds[r * nB + b] : 0.0;
+    const double hv = ok ? hs[b * 16 * ncol + c] : 0.0;
+    acc = mfma_f64(av, hv, acc);
+  }
   const int bl = c / ncol, xo = c - bl * ncol;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -220,35 +284,56 @@ __device__ inline void xbuild_tile_mma(const UnitGeo& U, int t, int q, int g, in
     }
   }
 }
-__device__ inline void xbuild(const Dev& d, const UnitGeo& U, int yw, int q, int g, int mB, int nB, int b0,
-                              const double* hBF, const double* hBA, const double* Dab, const double* Dfb,
-                              double* X1, double* X2) {
+
+// The H slice of a chunk that does not fit the LDS stage is read directly.
+__device__ inline void xbuild_tile_direct(const Dev& d, const UnitGeo& U, const Chunk& ch, int t, int q, int g,
+                                          const double* Dab, const double* Dfb, bool kAB, bool kFB, double* X1,
+                                          double* X2) {
+  const int64_t tri = chunk_tri(d, U, ch);
+  const bool one = t < U.T1;
+  const int tt = one ? t : t - U.T1;
+  const int ncol = one ? U.nF : U.nA;
+  const int nrow = one ? U.nA : U.nF;
+  const int tr = tt / ncol, tc = tt - tr * ncol;
+  const double* Ds = one ? Dab : Dfb;
+  const double* hp = d.H + (one ? d.triHF[tri] : d.triHA[tri]);
+  const int mBp = (ch.mB + 15) & ~15;
+  const bool keep = one ? kAB : kFB;
+  const int c = 16 * tc + q;
+  const int r = 16 * tr + q;
+  const int nB = ch.nB;
+  d4 acc = {0, 0, 0, 0};
   const int SB = (nB + 3) >> 2;
-  const int T = U.T1 + U.T2;
-  for (int t = yw; t < T; t += 8) {
-    const int t2 = t + 4;
-    double h0[8], h1[8];
-    xbuild_tile_load(U, t, q, g, mB, nB, b0, SB, hBF, hBA, h0);
-    if (t2 < T) xbuild_tile_load(U, t2, q, g, mB, nB, b0, SB, hBF, hBA, h1);
-    xbuild_tile_mma(U, t, q, g, nB, SB, h0, Dab, Dfb, X1, X2);
-    if (t2 < T) xbuild_tile_mma(U, t2, q, g, nB, SB, h1, Dab, Dfb, X1, X2);
+  for (int s = 0; s < SB; ++s) {
+    const int b = 4 * s + g;
+    const bool ok = keep && b < nB;
+    const double av = (ok && r < nrow) ? Ds[r * nB + b] : 0.0;
+    const double hv = ok ? hp[((int64_t)b * mBp + ch.b0) * ncol + c] : 0.0;
+    acc = mfma_f64(av, hv, acc);
+  }
+  const int bl = c / ncol, xo = c - bl * ncol;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rr = 16 * tr + g + 4 * i;
+    if (rr < nrow) {
+      const int k = one ? rr * U.nF + xo : xo * U.nF + rr;
+      const int cl = k - U.k0;
+      if (cl >= 0 && cl < U.Kc) (one ? X1 : X2)[bl * U.XS + cl] = acc[i];
+    }
   }
 }
 
-// Loop over the live V pairs (A,B) of the unit and the 16-row chunks of B.
-// ZROLE waves compute the Z partials, the other waves the Y accumulators;
-// both run the same barrier sequence.
 template <int MT, bool ZROLE>
-__device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int tid, int w, int lane, int q, int g) {
+__device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int w, int lane, int q, int g) {
   using Cfg = TripleCfg<MT>;
   double* X1 = lds;
   double* X2 = lds + 16 * Cfg::kXS;
-  double* Zred = lds + 32 * Cfg::kXS;
-  double* Dab = Zred + 4 * MT * 256;
-  double* Dfb = Dab + kMaxNao * kMaxNao;
+  double* Zred = lds + 32 * Cfg::kXS;          // partials of Z waves 1-3
+  double* Dab = Zred + 3 * MT * 256;
+  double* Dfb = Dab;                            // set per B (contiguous after Dab)
+  double* Hs = Dab + 2 * kMaxNao * kMaxNao;
   const int ww = w & 3;
   const int N = d.N;
-  const int64_t nt = d.ntot;
   const int mA = U.mA, XS = U.XS;
 
   double cfr[ZROLE ? MT : 1][ZROLE ? Cfg::kKSW : 1];
@@ -269,80 +354,97 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int tid
       for (int j = 0; j < Cfg::kJW; ++j) yacc[i][j] = d4{0, 0, 0, 0};
   }
 
-  for (int p = U.vp0; p < U.vp0 + U.nVpA; ++p) {
-    if (!d.aliveV[p]) continue;
-    const int B = d.vpB[p], mB = d.nabf[B], nB = d.nao[B];
-    double* Zdst = d.Zbuf + d.zOff[d.tBase[U.A] + (int64_t)U.fpos * U.nVpA + (p - U.vp0)] + (int64_t)U.kc * mA * mB;
-    const double* Vfp = d.Vf + d.vfOff[p];
-    const double* hBF = d.H + d.hOff[d.hSlotMap[(int64_t)B * N + U.F]];
-    const double* hBA = d.H + d.hOff[d.hSlotMap[(int64_t)B * N + U.A]];
-    const bool kAB = d.keepD[(int64_t)U.A * N + B], kFB = d.keepD[(int64_t)U.F * N + B];
-    for (int e = tid; e < U.nA * nB; e += kTNT)
-      Dab[e] = kAB ? d.D[(d.ao[U.A] + e / nB) * nt + d.ao[B] + e % nB] : 0.0;
-    for (int e = tid; e < U.nF * nB; e += kTNT)
-      Dfb[e] = kFB ? d.D[(d.ao[U.F] + e / nB) * nt + d.ao[B] + e % nB] : 0.0;
+  // prologue: stage the first chunk
+  Chunk ch = chunk_at(d, U, U.vp0, 0);
+  if (ch.p >= 0) {
+    stage_d(d, U, ch.B, ch.nB, Dab, Dfb, w, lane);
+    if (chunk_hs(U, ch) <= Cfg::kHs) stage_h(d, U, ch, Hs, w, lane);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  while (ch.p >= 0) {
+    const Chunk nx = chunk_next(d, U, ch);
+    const bool kAB = d.keepD[(int64_t)U.A * N + ch.B], kFB = d.keepD[(int64_t)U.F * N + ch.B];
+    Dfb = Dab + U.nA * ch.nB;
+    const int64_t tri = chunk_tri(d, U, ch);
+    double* Zdst = d.Zbuf + d.zOff[tri] + (int64_t)U.kc * mA * ch.mB;
+    const double* Vfp = d.Vf + d.vfOff[ch.p];
+    // V fragments of this chunk (Y waves); their latency is covered by the X-build
+    double avn[ZROLE ? 1 : 4][ZROLE ? 1 : MT];
+    if constexpr (!ZROLE) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          const int al = 16 * i + q, be = ch.b0 + 4 * s + g;
+          avn[s][i] = (al < mA && be < ch.mB) ? Vfp[(int64_t)al * ch.mB + be] : 0.0;
+        }
+    }
+    // ---- X-build of this chunk (all waves) ------------------------------
+    const bool staged = chunk_hs(U, ch) <= Cfg::kHs;
+    for (int t = w; t < U.T1 + U.T2; t += 8) {
+      if (staged)
+        xbuild_tile(U, t, q, g, ch.nB, Hs, Dab, Dfb, kAB, kFB, X1, X2);
+      else
+        xbuild_tile_direct(d, U, ch, t, q, g, Dab, Dfb, kAB, kFB, X1, X2);
+    }
     __syncthreads();
-    for (int b0 = 0; b0 < mB; b0 += 16) {
-      // V fragments of this chunk, requested before the X-build so their
-      // latency is covered by it
-      double avn[ZROLE ? 1 : 4][ZROLE ? 1 : MT];
-      if constexpr (!ZROLE) {
+    // ---- stage the next chunk while this one is contracted -------------
+    if (nx.p >= 0) {
+      if (nx.p != ch.p) stage_d(d, U, nx.B, nx.nB, Dab, Dfb, w, lane);
+      if (chunk_hs(U, nx) <= Cfg::kHs) stage_h(d, U, nx, Hs, w, lane);
+    }
+    if constexpr (ZROLE) {
+      d4 zp[MT];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+      for (int i = 0; i < MT; ++i) zp[i] = d4{0, 0, 0, 0};
 #pragma unroll
-          for (int i = 0; i < MT; ++i) {
-            const int al = 16 * i + q, be = b0 + 4 * s + g;
-            avn[s][i] = (al < mA && be < mB) ? Vfp[(int64_t)al * mB + be] : 0.0;
-          }
-      }
-      if constexpr (!ZROLE) xbuild(d, U, ww, q, g, mB, nB, b0, hBF, hBA, Dab, Dfb, X1, X2);
-      __syncthreads();
-      if constexpr (ZROLE) {
-        d4 zp[MT];
+      for (int t = 0; t < Cfg::kKSW; ++t) {
+        const int ks = ww + 4 * t;
+        if (ks < U.KS) {
+          const int c = 4 * ks + g;
+          const double xb = X1[q * XS + c] + X2[q * XS + c];
 #pragma unroll
-        for (int i = 0; i < MT; ++i) zp[i] = d4{0, 0, 0, 0};
-#pragma unroll
-        for (int t = 0; t < Cfg::kKSW; ++t) {
-          const int ks = ww + 4 * t;
-          if (ks < U.KS) {
-            const int c = 4 * ks + g;
-            const double xb = X1[q * XS + c] + X2[q * XS + c];
-#pragma unroll
-            for (int i = 0; i < MT; ++i) zp[i] = mfma_f64(cfr[i][t], xb, zp[i]);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < MT; ++i) *(d4*)&Zred[(ww * MT + i) * 256 + lane * 4] = zp[i];
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int bl = 4 * s + g;
-          const double* av = avn[s];
-#pragma unroll
-          for (int jj = 0; jj < Cfg::kJW; ++jj) {
-            const int j = ww + 4 * jj;
-            if (j < U.NTc) {
-              const double xb = X1[bl * XS + 16 * j + q] + X2[bl * XS + 16 * j + q];
-#pragma unroll
-              for (int i = 0; i < MT; ++i) yacc[i][jj] = mfma_f64(av[i], xb, yacc[i][jj]);
-            }
-          }
+          for (int i = 0; i < MT; ++i) zp[i] = mfma_f64(cfr[i][t], xb, zp[i]);
         }
       }
+      if (ww > 0) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i) *(d4*)&Zred[((ww - 1) * MT + i) * 256 + lane * 4] = zp[i];
+      }
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      if constexpr (ZROLE) {
-        for (int i = ww; i < MT; i += 4) {
-          d4 z = *(const d4*)&Zred[i * 256 + lane * 4];
-          for (int v = 1; v < 4; ++v) z += *(const d4*)&Zred[(v * MT + i) * 256 + lane * 4];
-          const int be = b0 + q;
+      if (ww == 0) {
+        const int be = ch.b0 + q;
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          d4 z = zp[i];
+          for (int v = 0; v < 3; ++v) z += *(const d4*)&Zred[(v * MT + i) * 256 + lane * 4];
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
             const int al = 16 * i + g + 4 * rr;
-            if (al < mA && be < mB) Zdst[(int64_t)al * mB + be] = z[rr];
+            if (al < mA && be < ch.mB) Zdst[(int64_t)al * ch.mB + be] = z[rr];
           }
         }
       }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int bl = 4 * s + g;
+#pragma unroll
+        for (int jj = 0; jj < Cfg::kJW; ++jj) {
+          const int j = ww + 4 * jj;
+          if (j < U.NTc) {
+            const double xb = X1[bl * XS + 16 * j + q] + X2[bl * XS + 16 * j + q];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) yacc[i][jj] = mfma_f64(avn[s][i], xb, yacc[i][jj]);
+          }
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
     }
+    ch = nx;
   }
   if constexpr (!ZROLE) {
     double* Y = d.Ybuf + d.yOff[U.cp];
@@ -391,9 +493,9 @@ __global__ void __launch_bounds__(kTNT, 1) k_triple(Dev d, const int* __restrict
   for (int e = tid; e < 32 * Cfg::kXS; e += kTNT) lds[e] = 0.0;
   __syncthreads();
   if (w < 4)
-    triple_role<MT, true>(d, U, lds, tid, w, lane, q, g);
+    triple_role<MT, true>(d, U, lds, w, lane, q, g);
   else
-    triple_role<MT, false>(d, U, lds, tid, w, lane, q, g);
+    triple_role<MT, false>(d, U, lds, w, lane, q, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -438,17 +540,24 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
     if (threadIdx.x == 0) d.Ep[p] = 0.0;
     return;
   }
-  if (threadIdx.x == 0) {
+  __shared__ int64_t zb[kZMax];
+  __shared__ int zk[kZMax];
+  {
     const int vp0 = d.vpRow[A], nVpA = d.vpRow[A + 1] - vp0, bpos = p - vp0;
-    int k = 0;
-    for (int cp = d.cpRow[A]; cp < d.cpRow[A + 1]; ++cp) {
-      if (!d.aliveC[cp]) continue;
-      const int64_t base = d.zOff[d.tBase[A] + (int64_t)(cp - d.cpRow[A]) * nVpA + bpos];
-      for (int kc = 0; kc < d.nkc[cp] && k < kZMax; ++kc) zoff[k++] = base + (int64_t)kc * n;
+    const int c0 = d.cpRow[A], ncp = d.cpRow[A + 1] - c0;
+    for (int i = threadIdx.x; i < ncp && i < kZMax; i += kNT) {
+      zk[i] = d.aliveC[c0 + i] ? d.nkc[c0 + i] : 0;
+      zb[i] = d.zOff[d.tBase[A] + (int64_t)i * nVpA + bpos];
     }
-    nz = k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int k = 0;
+      for (int i = 0; i < ncp && i < kZMax; ++i)
+        for (int kc = 0; kc < zk[i] && k < kZMax; ++kc) zoff[k++] = zb[i] + (int64_t)kc * n;
+      nz = k;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int NZ = nz;
   const double* vf = d.Vf + d.vfOff[p];
   const int kb0 = d.vpB0[p], kb1 = d.vpB1[p];

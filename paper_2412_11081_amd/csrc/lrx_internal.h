@@ -10,8 +10,9 @@
 //            Vf(A,B) = sum of kept V images [mA][mB]  (Gamma point: the density
 //            matrix is the same for every image pair, so the images of a pair
 //            meet the same D blocks and can be summed first);
-//   H        H(B,X)[beta][b][x] = sum_G Cf(B,G)[beta][b][g] D(G,X)[g][x] for
-//            every (B,X) a triple (A,F,B) needs (X = A or X = F);
+//   H        H(B,X)[b][beta][x] = sum_G Cf(B,G)[beta][b][g] D(G,X)[g][x] for
+//            every (B,X) a triple (A,F,B) needs (X = A or X = F); beta runs
+//            over the ABFs of B rounded up to 16 (padding rows stay zero);
 //   Zbuf     per triple (A,F,B) and column chunk: the F-partial of
 //            Z(A,B)[alpha][beta] = sum_{F,a,f} Cf(A,F)[alpha][a][f] X^{AFB}[beta][a][f],
 //            X^{AFB}[beta][a][f] = sum_b D_AB[a][b] H(B,F)[beta][b][f]
@@ -95,6 +96,12 @@ struct Dev {
   const int* nkc;          // [nCp] column chunks of the pair
   const int64_t* tBase;    // [N] first triple index of atom A
   const int64_t* zOff;     // [ntriple] element offset of the triple's Z partials
+  const int64_t* triHF;    // [ntriple] offset of H(B,F) in H
+  const int64_t* triHA;    // [ntriple] offset of H(B,A) in H
+  const int* hdRow;        // [N+1] static H-build depth table of atom B (multiple of 4 entries):
+  const int* hdRowD;       //   D row ao[G] + g,
+  const int* hdG;          //   atom G (-1: padding),
+  const int* hdCp;         //   (C pair << 6) | g
   double* Zbuf;
   const int64_t* yOff;     // [nCp]
   double* Ybuf;
