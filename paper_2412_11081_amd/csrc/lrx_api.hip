@@ -113,7 +113,7 @@ struct lrx_ctx {
   int64_t nC = 0, nV = 0;
   std::vector<int32_t> Cf, Cs, CR, Vf, Vs, VR;
   Pairs cp, vp;
-  std::vector<int> slotB, slotX, unitCp, unitK0, unitK1, unitKc, nkc;
+  std::vector<int> slotB, slotX, unitCp, unitK0, unitK1, unitKc, unitV0, unitV1, unitS, nkc, nsplit;
   std::vector<int64_t> tBase;
   int max_mm = 1, max_depth = 4;
 
@@ -123,6 +123,8 @@ struct lrx_ctx {
   Dev dev{};
   double* h_out = nullptr;
   std::array<hipEvent_t, LRX_NSTAGES + 1> ev{};
+  std::array<hipStream_t, lrx::kSideStreams> side{};
+  std::array<hipEvent_t, lrx::kSideStreams + 1> fork{};
   bool events = false;
   std::array<float, LRX_NSTAGES> stage_ms{};
   bool timed = false;
@@ -209,6 +211,8 @@ int lrx_create(lrx_ctx** out, int32_t device, void* hip_stream) {
       c->own_stream = true;
     }
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    for (auto& e : c->fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& st : c->side) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     c->events = true;
   });
   if (rc != LRX_OK) {
@@ -334,7 +338,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       const int B = c->slotB[s], X = c->slotX[s];
       hOff[s + 1] = hOff[s] + (int64_t)((c->nabf[B] + 15) / 16 * 16) * c->nao[B] * c->nao[X];
     }
-    std::vector<int> slotRow(N + 1, 0), hbB, hbR0, hbC0, hColRow(N + 1, 0), hColSlot, hColX;
+    std::vector<int> slotRow(N + 1, 0), hbB, hbR0, hbC0, hColRow(N + 1, 0), hColSlot, hColX, hColD, hColAtom;
     for (int s = 0; s < nSlot; ++s) slotRow[c->slotB[s] + 1]++;
     for (int B = 0; B < N; ++B) slotRow[B + 1] += slotRow[B];
     c->max_depth = 4;
@@ -342,7 +346,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       int k = 0;
       for (int i = cp.row[B]; i < cp.row[B + 1]; ++i) k += c->nao[cp.pB[i]];
       require(k + 3 <= lrx::kHMaxDepth,
-              "atom " + std::to_string(B) + ": its C partners have more than 1020 NAOs in total");
+              "atom " + std::to_string(B) + ": its C partners have more than 508 NAOs in total");
       c->max_depth = std::max(c->max_depth, (k + 3) & ~3);
     }
     for (int B = 0; B < N; ++B) {
@@ -350,6 +354,8 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
         for (int x = 0; x < c->nao[c->slotX[s]]; ++x) {
           hColSlot.push_back(s);
           hColX.push_back(x);
+          hColD.push_back((int)(c->ao[c->slotX[s]] + x));
+          hColAtom.push_back(c->slotX[s]);
         }
       hColRow[B + 1] = (int)hColSlot.size();
       const int rows = c->nabf[B] * c->nao[B], cols = hColRow[B + 1] - hColRow[B];
@@ -362,7 +368,27 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     }
     // ---- work units and triple offsets -----------------------------------
     c->unitCp.clear(); c->unitK0.clear(); c->unitK1.clear(); c->unitKc.clear();
+    c->unitV0.clear(); c->unitV1.clear(); c->unitS.clear();
     c->nkc.assign(nCp, 1);
+    // B-split: the V partners of a C pair are divided into nsplit ranges (Y
+    // partials summed later) so every alpha-tile group has enough units to
+    // fill the device.
+    c->nsplit.assign(nCp, 1);
+    {
+      std::vector<int64_t> per_mt(lrx::kMaxAlphaTiles + 2, 0);
+      for (int i = 0; i < nCp; ++i) {
+        const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
+        const int mt = (c->nabf[cp.pA[i]] + 15) / 16;
+        const int cols = lrx::unit_cols(mt);
+        per_mt[mt] += (K1 + cols - 1) / cols;
+      }
+      for (int i = 0; i < nCp; ++i) {
+        const int mt = (c->nabf[cp.pA[i]] + 15) / 16;
+        const int nv = vp.row[cp.pA[i] + 1] - vp.row[cp.pA[i]];
+        const int64_t want = (3 * 256 + per_mt[mt] - 1) / std::max<int64_t>(1, per_mt[mt]);
+        c->nsplit[i] = (int)std::max<int64_t>(1, std::min<int64_t>({want, (int64_t)nv, 16}));
+      }
+    }
     for (int i = 0; i < nCp; ++i) {
       const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
       const int cols = lrx::unit_cols((c->nabf[cp.pA[i]] + 15) / 16);
@@ -370,12 +396,18 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       int chunk = (K1 + nk - 1) / nk;
       chunk = std::min(cols, (chunk + 15) / 16 * 16);
       int cnt = 0;
-      for (int k0 = 0; k0 < K1; k0 += chunk, ++cnt) {
-        c->unitCp.push_back(i);
-        c->unitK0.push_back(k0);
-        c->unitK1.push_back(std::min(K1, k0 + chunk));
-        c->unitKc.push_back(cnt);
-      }
+      const int A = cp.pA[i];
+      const int nv = vp.row[A + 1] - vp.row[A], ns = c->nsplit[i];
+      for (int k0 = 0; k0 < K1; k0 += chunk, ++cnt)
+        for (int sp = 0; sp < ns; ++sp) {
+          c->unitCp.push_back(i);
+          c->unitK0.push_back(k0);
+          c->unitK1.push_back(std::min(K1, k0 + chunk));
+          c->unitKc.push_back(cnt);
+          c->unitV0.push_back(vp.row[A] + (int)((int64_t)nv * sp / ns));
+          c->unitV1.push_back(vp.row[A] + (int)((int64_t)nv * (sp + 1) / ns));
+          c->unitS.push_back(sp);
+        }
       c->nkc[i] = cnt;
     }
     for (int A = 0; A < N; ++A) {
@@ -409,7 +441,8 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
         }
     }
     // static depth tables of the H build: every g of every C pair (B, G)
-    std::vector<int> hdRow(N + 1, 0), hdRowD, hdG, hdCp;
+    std::vector<int> hdRow(N + 1, 0), hdRowD, hdG, hdCp, hdStride;
+    std::vector<int64_t> hdCf;
     for (int B = 0; B < N; ++B) {
       int k = 0;
       for (int i = cp.row[B]; i < cp.row[B + 1]; ++i)
@@ -417,11 +450,15 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
           hdRowD.push_back((int)(c->ao[cp.pB[i]] + gg));
           hdG.push_back(cp.pB[i]);
           hdCp.push_back((i << 6) | gg);
+          hdCf.push_back(cfOff[i] + gg);
+          hdStride.push_back(c->nao[cp.pB[i]]);
         }
       for (; k & 3; ++k) {
         hdRowD.push_back(0);
         hdG.push_back(-1);
         hdCp.push_back(-1);
+        hdCf.push_back(0);
+        hdStride.push_back(0);
       }
       hdRow[B + 1] = (int)hdRowD.size();
     }
@@ -517,14 +554,21 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.hColRow = c->upload(hColRow);
     d.hColSlot = c->upload(hColSlot);
     d.hColX = c->upload(hColX);
+    d.hColD = c->upload(hColD);
+    d.hColAtom = c->upload(hColAtom);
     d.unitCp = c->upload(c->unitCp); d.unitK0 = c->upload(c->unitK0); d.unitK1 = c->upload(c->unitK1);
     d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
+    d.unitV0 = c->upload(c->unitV0); d.unitV1 = c->upload(c->unitV1); d.unitS = c->upload(c->unitS);
+    d.nsplit = c->upload(c->nsplit);
     d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);
     d.triHF = c->upload(triHF); d.triHA = c->upload(triHA);
     d.hdRow = c->upload(hdRow); d.hdRowD = c->upload(hdRowD); d.hdG = c->upload(hdG); d.hdCp = c->upload(hdCp);
+    d.hdCf = c->upload(hdCf); d.hdStride = c->upload(hdStride);
     d.Zbuf = c->dalloc<double>(zOff[ntri]);
-    d.yOff = c->upload(cfOff);
-    d.Ybuf = c->dalloc<double>(cfOff[nCp]);
+    std::vector<int64_t> yOff(nCp + 1, 0);
+    for (int i = 0; i < nCp; ++i) yOff[i + 1] = yOff[i] + (cfOff[i + 1] - cfOff[i]) * c->nsplit[i];
+    d.yOff = c->upload(yOff);
+    d.Ybuf = c->dalloc<double>(yOff[nCp]);
     d.gC = c->dalloc<double>(3 * c->nC);
     d.gV = c->dalloc<double>(3 * c->nV);
     d.Ep = c->dalloc<double>(nVp);
@@ -576,7 +620,7 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
     hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
     if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
     lrx::launch_screen(c->dev, o, c->stream, ev);
-    lrx::launch_contract(c->dev, c->max_mm, c->max_depth, c->stream, ev);
+    lrx::launch_contract(c->dev, c->max_mm, c->max_depth, c->stream, c->side.data(), c->fork.data(), ev);
     HIPCHK(hipGetLastError());
     const int N = c->N;
     HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost,
@@ -700,8 +744,11 @@ void lrx_destroy(lrx_ctx* c) {
   (void)hipSetDevice(c->device);
   c->free_tensors();
   if (c->h_out) (void)hipHostFree(c->h_out);
-  if (c->events)
+  if (c->events) {
     for (auto& e : c->ev) (void)hipEventDestroy(e);
+    for (auto& e : c->fork) (void)hipEventDestroy(e);
+    for (auto& st : c->side) (void)hipStreamDestroy(st);
+  }
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

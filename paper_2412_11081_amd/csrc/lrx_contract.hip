@@ -68,15 +68,15 @@ __device__ inline int xcd_remap(int b, int G) {
 constexpr int kHCols = 64;
 __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
   __shared__ int krow[kHMaxDepth];   // D row (ao[G] + g) of depth index k
-  __shared__ int kG[kHMaxDepth];     // atom G, or -1 for padding
-  __shared__ int kcp[kHMaxDepth];
+  __shared__ int kG[kHMaxDepth];     // atom G, or -1 (padding or screened pair)
+  __shared__ int64_t kcf[kHMaxDepth];
+  __shared__ int kst[kHMaxDepth];
+  __shared__ int cD[kHCols], cAt[kHCols], cSl[kHCols], cX[kHCols];
   __shared__ int kdepth;
   __shared__ double Ds[kHPass * kHCols];
   const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x], c0 = d.hbC0[blockIdx.x];
   const int mB = d.nabf[B], nB = d.nao[B], rows = mB * nB;
   const int ncols = d.hColRow[B + 1] - d.hColRow[B];
-  const int* colSlot = d.hColSlot + d.hColRow[B];
-  const int* colX = d.hColX + d.hColRow[B];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
   {
     const int h0 = d.hdRow[B], hn = d.hdRow[B + 1] - h0;
@@ -85,7 +85,17 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
       const bool live = t >= 0 && d.aliveC[t >> 6];
       krow[k] = d.hdRowD[h0 + k];
       kG[k] = live ? d.hdG[h0 + k] : -1;
-      kcp[k] = live ? t : -1;
+      kcf[k] = d.hdCf[h0 + k];
+      kst[k] = d.hdStride[h0 + k];
+    }
+    for (int cl = tid; cl < kHCols; cl += kNT) {
+      const int c = c0 + cl;
+      const bool in = c < ncols;
+      const int s = in ? d.hColSlot[d.hColRow[B] + c] : 0;
+      cSl[cl] = in && d.need[s] ? s : -1;
+      cD[cl] = in ? d.hColD[d.hColRow[B] + c] : 0;
+      cAt[cl] = in ? d.hColAtom[d.hColRow[B] + c] : 0;
+      cX[cl] = in ? d.hColX[d.hColRow[B] + c] : 0;
     }
     if (tid == 0) kdepth = hn;
   }
@@ -98,34 +108,38 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
   for (int j = 0; j < kHCols / 16; ++j) acc[j] = d4{0, 0, 0, 0};
   for (int kb = 0; kb < Kall; kb += kHPass) {
     const int K = min(kHPass, Kall - kb);
-    // stage D[(G,g)][column] for this pass
+    // A fragments of this pass, all requested before any MFMA
+    double af[kHPass / 4];
+#pragma unroll
+    for (int s = 0; s < kHPass / 4; ++s) {
+      const int k = kb + 4 * s + g;
+      af[s] = (4 * s < K && row < rows && kG[k] >= 0) ? d.Cf[kcf[k] + (int64_t)row * kst[k]] : 0.0;
+    }
+    // D[(G,g)][column] tile of this pass
     for (int e = tid; e < K * kHCols; e += kNT) {
-      const int k = e / kHCols, cl = e - k * kHCols, c = c0 + cl;
+      const int k = e / kHCols, cl = e - k * kHCols;
+      const int G = kG[kb + k];
       double v = 0;
-      if (c < ncols) {
-        const int s = colSlot[c], X = d.slotX[s], G = kG[kb + k];
-        if (G >= 0 && d.need[s] && d.keepD[(int64_t)G * d.N + X])
-          v = d.D[(int64_t)krow[kb + k] * d.ntot + d.ao[X] + colX[c]];
-      }
+      if (G >= 0 && cSl[cl] >= 0 && d.keepD[(int64_t)G * d.N + cAt[cl]])
+        v = d.D[(int64_t)krow[kb + k] * d.ntot + cD[cl]];
       Ds[k * kHCols + cl] = v;
     }
     __syncthreads();
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int t = kcp[kb + k0 + g];
-      double a = 0;
-      if (row < rows && t >= 0) a = d.Cf[d.cfOff[t >> 6] + (int64_t)row * d.nao[d.cpF[t >> 6]] + (t & 63)];
 #pragma unroll
-      for (int j = 0; j < kHCols / 16; ++j) acc[j] = mfma_f64(a, Ds[(k0 + g) * kHCols + 16 * j + q], acc[j]);
+    for (int s = 0; s < kHPass / 4; ++s) {
+      if (4 * s < K) {
+#pragma unroll
+        for (int j = 0; j < kHCols / 16; ++j) acc[j] = mfma_f64(af[s], Ds[(4 * s + g) * kHCols + 16 * j + q], acc[j]);
+      }
     }
     __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < kHCols / 16; ++j) {
-    const int c = c0 + 16 * j + q;
-    if (c >= ncols) continue;
-    const int s = colSlot[c];
-    if (!d.need[s]) continue;
-    const int X = d.slotX[s], nX = d.nao[X], x = colX[c];
+    const int cl = 16 * j + q;
+    const int s = cSl[cl];
+    if (s < 0) continue;
+    const int nX = d.nao[d.slotX[s]], x = cX[cl];
     double* Hout = d.H + d.hOff[s];
     for (int i = 0; i < 4; ++i) {
       const int r = r0 + 16 * w + g + 4 * i;
@@ -166,7 +180,7 @@ struct TripleCfg {
 constexpr int kTNT = 512;
 
 struct UnitGeo {
-  int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, T1, T2, fpos, vp0, nVpA;
+  int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, T1, T2, fpos, vp0, nVpA, vb, ve, split;
 };
 
 struct Chunk {
@@ -175,9 +189,9 @@ struct Chunk {
 
 __device__ inline Chunk chunk_at(const Dev& d, const UnitGeo& U, int p, int b0) {
   Chunk c;
-  for (; p < U.vp0 + U.nVpA && !d.aliveV[p]; ++p) {
+  for (; p < U.ve && !d.aliveV[p]; ++p) {
   }
-  c.p = p < U.vp0 + U.nVpA ? p : -1;
+  c.p = p < U.ve ? p : -1;
   c.b0 = b0;
   if (c.p >= 0) {
     c.B = d.vpB[c.p];
@@ -355,7 +369,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int w, 
   }
 
   // prologue: stage the first chunk
-  Chunk ch = chunk_at(d, U, U.vp0, 0);
+  Chunk ch = chunk_at(d, U, U.vb, 0);
   if (ch.p >= 0) {
     stage_d(d, U, ch.B, ch.nB, Dab, Dfb, w, lane);
     if (chunk_hs(U, ch) <= Cfg::kHs) stage_h(d, U, ch, Hs, w, lane);
@@ -447,7 +461,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, double* lds, int w, 
     ch = nx;
   }
   if constexpr (!ZROLE) {
-    double* Y = d.Ybuf + d.yOff[U.cp];
+    double* Y = d.Ybuf + d.yOff[U.cp] + (int64_t)U.split * mA * U.K1;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -489,6 +503,9 @@ __global__ void __launch_bounds__(kTNT, 1) k_triple(Dev d, const int* __restrict
   U.fpos = U.cp - d.cpRow[U.A];
   U.vp0 = d.vpRow[U.A];
   U.nVpA = d.vpRow[U.A + 1] - U.vp0;
+  U.vb = d.unitV0[u];
+  U.ve = d.unitV1[u];
+  U.split = d.unitS[u];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
   for (int e = tid; e < 32 * Cfg::kXS; e += kTNT) lds[e] = 0.0;
   __syncthreads();
@@ -603,7 +620,7 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
 // C-block gradients: g_c = -2 <dC_c, Y(A,F)>; E from the Y side for checking.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kNT) k_cgrad(Dev d) {
-  __shared__ double sh[kWaves + 1];
+  __shared__ double sh[kWaves * 4];
   const int cp = blockIdx.x;
   const int A = d.cpA[cp], F = d.cpF[cp];
   const int n = d.nabf[A] * d.nao[A] * d.nao[F];
@@ -616,11 +633,16 @@ __global__ void __launch_bounds__(kNT) k_cgrad(Dev d) {
     return;
   }
   const double* Y = d.Ybuf + d.yOff[cp];
+  const int ns = d.nsplit[cp];
   const double* cf = d.Cf + d.cfOff[cp];
-  double s = 0;
-  for (int e = threadIdx.x; e < n; e += kNT) s += cf[e] * Y[e];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) d.Ecp[cp] = -s;
+  double s[4] = {0, 0, 0, 0};
+  for (int e = threadIdx.x; e < n; e += kNT) {
+    double y = 0;
+    for (int k = 0; k < ns; ++k) y += Y[(int64_t)k * n + e];
+    s[0] += cf[e] * y;
+  }
+  block_sum_n<1>(s, sh);
+  if (threadIdx.x == 0) d.Ecp[cp] = -s[0];
   for (int k = d.cpB0[cp]; k < d.cpB1[cp]; ++k) {
     const int64_t b = d.cpBlk[k];
     if (!d.keepC[b]) {
@@ -628,12 +650,17 @@ __global__ void __launch_bounds__(kNT) k_cgrad(Dev d) {
       continue;
     }
     const double* dc = d.Cdval + 3 * d.Coff[b];
-    for (int x = 0; x < 3; ++x) {
-      double t = 0;
-      for (int e = threadIdx.x; e < n; e += kNT) t += dc[(int64_t)x * n + e] * Y[e];
-      t = block_sum(t, sh);
-      if (threadIdx.x == 0) d.gC[3 * b + x] = -2.0 * t;
+    double t[3] = {0, 0, 0};
+    for (int e = threadIdx.x; e < n; e += kNT) {
+      double y = 0;
+      for (int kk = 0; kk < ns; ++kk) y += Y[(int64_t)kk * n + e];
+      t[0] += dc[e] * y;
+      t[1] += dc[n + e] * y;
+      t[2] += dc[2 * n + e] * y;
     }
+    block_sum_n<3>(t, sh);
+    if (threadIdx.x == 0)
+      for (int x = 0; x < 3; ++x) d.gC[3 * b + x] = -2.0 * t[x];
   }
 }
 
@@ -703,18 +730,44 @@ static void launch_triple(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_triple<MT>, dim3(n), dim3(kTNT), lds, s, d, d.unitOrder + d.mtStart[MT]);
 }
 
-void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, hipEvent_t* ev) {
+void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, const hipStream_t* side,
+                     const hipEvent_t* fork, hipEvent_t* ev) {
+  (void)max_mm;
   (void)max_depth;
   if (d.nHB) hipLaunchKernelGGL(k_hbuild, dim3(d.nHB), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[4], s);
-  launch_triple<1>(d, s);
-  launch_triple<2>(d, s);
-  launch_triple<3>(d, s);
-  launch_triple<4>(d, s);
-  launch_triple<5>(d, s);
-  launch_triple<6>(d, s);
-  launch_triple<7>(d, s);
-  launch_triple<8>(d, s);
+  // The alpha-tile groups are independent: the largest runs on the main
+  // stream, the others on side streams that join before the gradients.
+  int order[kMaxAlphaTiles];
+  int ng = 0;
+  for (int mt = 1; mt <= kMaxAlphaTiles; ++mt)
+    if (d.mtStart[mt + 1] > d.mtStart[mt]) order[ng++] = mt;
+  for (int i = 1; i < ng; ++i)
+    for (int j = i; j > 0 && d.mtStart[order[j] + 1] - d.mtStart[order[j]] >
+                                 d.mtStart[order[j - 1] + 1] - d.mtStart[order[j - 1]]; --j) {
+      const int t = order[j];
+      order[j] = order[j - 1];
+      order[j - 1] = t;
+    }
+  (void)hipEventRecord(fork[0], s);
+  for (int i = 0; i < ng; ++i) {
+    const hipStream_t st = i == 0 ? s : side[(i - 1) % kSideStreams];
+    if (i > 0 && i <= kSideStreams) (void)hipStreamWaitEvent(st, fork[0], 0);
+    switch (order[i]) {
+      case 1: launch_triple<1>(d, st); break;
+      case 2: launch_triple<2>(d, st); break;
+      case 3: launch_triple<3>(d, st); break;
+      case 4: launch_triple<4>(d, st); break;
+      case 5: launch_triple<5>(d, st); break;
+      case 6: launch_triple<6>(d, st); break;
+      case 7: launch_triple<7>(d, st); break;
+      default: launch_triple<8>(d, st); break;
+    }
+  }
+  for (int i = 1; i <= kSideStreams && i < ng; ++i) {
+    (void)hipEventRecord(fork[i], side[i - 1]);
+    (void)hipStreamWaitEvent(s, fork[i], 0);
+  }
   if (ev) (void)hipEventRecord(ev[5], s);
   if (d.nVp) hipLaunchKernelGGL(k_zgrad, dim3(d.nVp), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[6], s);

@@ -17,7 +17,8 @@
 //            Z(A,B)[alpha][beta] = sum_{F,a,f} Cf(A,F)[alpha][a][f] X^{AFB}[beta][a][f],
 //            X^{AFB}[beta][a][f] = sum_b D_AB[a][b] H(B,F)[beta][b][f]
 //                                + sum_b D_FB[f][b] H(B,A)[beta][b][a];
-//   Ybuf     per C pair: Y(A,F)[alpha][a][f] = sum_B sum_beta Vf(A,B)[alpha][beta] X^{AFB}[beta][a][f].
+//   Ybuf     per C pair and V-pair range s: Y_s(A,F)[alpha][a][f] = sum_{B in range s}
+//            sum_beta Vf(A,B)[alpha][beta] X^{AFB}[beta][a][f]  (Y = sum_s Y_s).
 // With these, E = -sum_{A,B} <Vf(A,B), Z(A,B)>, dE/dV = -Z and dE/dCf = -2 Y
 // (E is a symmetric quadratic form in C), so each image block's gradient is
 // a single contraction of its d/dr with Z or Y.
@@ -35,9 +36,10 @@ constexpr int kMaxAlphaTiles = (kMaxNabf + 15) / 16;
 // 16-row ABF tiles of its atom A (the unit keeps fragments of Cf(A,F) for
 // these columns and the Y tiles of these columns in registers).
 __host__ __device__ constexpr int unit_cols(int alpha_tiles) { return alpha_tiles <= 5 ? 176 : 128; }
+constexpr int kSideStreams = 3;    // extra streams: alpha-tile groups of the triple kernel run concurrently
 constexpr int kHRows = 64;         // rows (beta,b) of H one H-build workgroup owns
-constexpr int kHMaxDepth = 1024;   // max sum of NAOs over the C partners of one atom
-constexpr int kHPass = 128;        // depth of one H-build pass
+constexpr int kHMaxDepth = 512;    // max sum of NAOs over the C partners of one atom
+constexpr int kHPass = 64;         // depth of one H-build pass
 
 // Everything the kernels read or write for one structure.  Passed by value.
 struct Dev {
@@ -84,13 +86,15 @@ struct Dev {
   const int* slotRow;      // [N+1] slots of atom B are slotRow[B] .. slotRow[B+1]-1 (sorted by X)
   int nHB; const int* hbB; const int* hbR0; const int* hbC0;   // H-build work items: (B, first row, first column)
   const int* hColRow;      // [N+1] columns of atom B: the (slot, x) of every H slot of B, concatenated
-  const int* hColSlot; const int* hColX;
+  const int* hColSlot; const int* hColX; const int* hColD; const int* hColAtom;
   uint8_t* need;
   double* H;
 
   // triple work units
   int nUnit;
   const int* unitCp; const int* unitK0; const int* unitK1; const int* unitKc;
+  const int* unitV0; const int* unitV1; const int* unitS;   // V-pair range and split index of a unit
+  const int* nsplit;       // [nCp] number of V-pair ranges (Y partials) of a C pair
   const int* unitOrder;    // units grouped by the alpha-tile count of their atom A
   int mtStart[kMaxAlphaTiles + 2];
   const int* nkc;          // [nCp] column chunks of the pair
@@ -101,7 +105,9 @@ struct Dev {
   const int* hdRow;        // [N+1] static H-build depth table of atom B (multiple of 4 entries):
   const int* hdRowD;       //   D row ao[G] + g,
   const int* hdG;          //   atom G (-1: padding),
-  const int* hdCp;         //   (C pair << 6) | g
+  const int* hdCp;         //   (C pair << 6) | g,
+  const int64_t* hdCf;     //   offset of Cf(B,G)[0][0][g],
+  const int* hdStride;     //   n_G (row stride of Cf(B,G) over (beta,b))
   double* Zbuf;
   const int64_t* yOff;     // [nCp]
   double* Ybuf;
@@ -128,7 +134,8 @@ struct Opts {
 void launch_validate(const Dev& d, hipStream_t s);
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev);
 // kernels (lrx_contract.hip)
-void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, hipEvent_t* ev);
+void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, const hipStream_t* side,
+                     const hipEvent_t* fork, hipEvent_t* ev);
 void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipStream_t s);
 
 }  // namespace lrx
