@@ -116,6 +116,9 @@ struct lrx_ctx {
   std::vector<int> slotB, slotX, unitCp, unitK0, unitK1, unitKc, unitV0, unitV1, unitS, nkc, nsplit;
   std::vector<int64_t> tBase;
   int max_mm = 1, max_depth = 4;
+  // sizes of the FP32 buffers of the reduced-precision forms
+  int64_t n_cf = 0, n_vf = 0, n_h = 0, n_z = 0, n_y = 0;
+  bool have_f32 = false;
 
   // device memory
   std::vector<void*> allocs;
@@ -534,6 +537,9 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.hSlotMap = c->upload(slotmap);
     d.need = c->dalloc<uint8_t>(nSlot);
     d.H = c->dalloc<double>(hOff[nSlot]);
+    c->n_cf = cfOff[nCp];
+    c->n_vf = vfOff[nVp];
+    c->n_h = hOff[nSlot];
     HIPCHK(hipMemsetAsync(d.H, 0, sizeof(double) * std::max<int64_t>(1, hOff[nSlot]), c->stream));
     d.nUnit = (int)c->unitCp.size();
     std::vector<int> unitOrder(d.nUnit);
@@ -565,10 +571,14 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.hdRow = c->upload(hdRow); d.hdRowD = c->upload(hdRowD); d.hdG = c->upload(hdG); d.hdCp = c->upload(hdCp);
     d.hdCf = c->upload(hdCf); d.hdStride = c->upload(hdStride);
     d.Zbuf = c->dalloc<double>(zOff[ntri]);
+    c->n_z = zOff[ntri];
     std::vector<int64_t> yOff(nCp + 1, 0);
     for (int i = 0; i < nCp; ++i) yOff[i + 1] = yOff[i] + (cfOff[i + 1] - cfOff[i]) * c->nsplit[i];
     d.yOff = c->upload(yOff);
     d.Ybuf = c->dalloc<double>(yOff[nCp]);
+    c->n_y = yOff[nCp];
+    c->have_f32 = false;
+    d.Cf32 = nullptr; d.Vf32 = nullptr; d.D32 = nullptr; d.H32 = nullptr; d.Zbuf32 = nullptr; d.Ybuf32 = nullptr;
     d.gC = c->dalloc<double>(3 * c->nC);
     d.gV = c->dalloc<double>(3 * c->nV);
     d.Ep = c->dalloc<double>(nVp);
@@ -613,14 +623,27 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
   return guarded(c, [&] {
     require(opts != nullptr, "opts: NULL");
     require(c->have_tensors, "lrx_evaluate before lrx_set_tensors");
-    require(opts->precision == LRX_FP64, "precision not available in this build");
+    require(opts->precision == LRX_FP64 || opts->precision == LRX_FP32 || opts->precision == LRX_BF16X3,
+            "unknown precision");
     require(std::isfinite(opts->theta) && std::isfinite(opts->theta_cs), "non-finite threshold");
-    const lrx::Opts o{opts->theta, opts->theta_cs};
+    if (opts->precision != LRX_FP64 && !c->have_f32) {
+      Dev& d = c->dev;
+      const int64_t nt = c->ao[c->N];
+      d.Cf32 = c->dalloc<float>(c->n_cf);
+      d.Vf32 = c->dalloc<float>(c->n_vf);
+      d.D32 = c->dalloc<float>(nt * nt);
+      d.H32 = c->dalloc<float>(c->n_h);
+      HIPCHK(hipMemsetAsync(d.H32, 0, sizeof(float) * std::max<int64_t>(1, c->n_h), c->stream));
+      d.Zbuf32 = c->dalloc<float>(c->n_z);
+      d.Ybuf32 = c->dalloc<float>(c->n_y);
+      c->have_f32 = true;
+    }
+    const lrx::Opts o{opts->theta, opts->theta_cs, opts->precision};
     const bool timing = opts->timing != 0;
     hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
     if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
     lrx::launch_screen(c->dev, o, c->stream, ev);
-    lrx::launch_contract(c->dev, c->max_mm, c->max_depth, c->stream, c->side.data(), c->fork.data(), ev);
+    lrx::launch_contract(c->dev, opts->precision, c->stream, c->side.data(), c->fork.data(), ev);
     HIPCHK(hipGetLastError());
     const int N = c->N;
     HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost,

@@ -41,6 +41,8 @@ constexpr int kHRows = 64;         // rows (beta,b) of H one H-build workgroup o
 constexpr int kHMaxDepth = 512;    // max sum of NAOs over the C partners of one atom
 constexpr int kHPass = 64;         // depth of one H-build pass
 
+enum Prec : int { kP64 = 0, kP32 = 1, kPB3 = 2 };
+
 // Everything the kernels read or write for one structure.  Passed by value.
 struct Dev {
   int N;
@@ -68,6 +70,8 @@ struct Dev {
   const int* vpMir;
   const int64_t* cfOff; const int64_t* vfOff;
   double* Cf; double* Vf;
+  // FP32 copies used by the reduced-precision forms (allocated on first use)
+  float* Cf32; float* Vf32; float* D32; float* H32; float* Zbuf32; float* Ybuf32;
 
   // screening
   double* nrmC;  // [nC][4]: max|val|, max|dval|, sum val^2, sum dval^2
@@ -128,14 +132,15 @@ struct Dev {
 struct Opts {
   double theta;
   double theta_cs;
+  int prec;
 };
 
 // kernels (lrx_screen.hip)
 void launch_validate(const Dev& d, hipStream_t s);
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev);
 // kernels (lrx_contract.hip)
-void launch_contract(const Dev& d, int max_mm, int max_depth, hipStream_t s, const hipStream_t* side,
-                     const hipEvent_t* fork, hipEvent_t* ev);
+void launch_contract(const Dev& d, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork,
+                     hipEvent_t* ev);
 void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipStream_t s);
 
 }  // namespace lrx

@@ -254,11 +254,12 @@ __global__ void k_screen_v(Dev d, Opts o) {
 // ---------------------------------------------------------------------------
 // image folding: Cf(A,F) = sum of kept C images, Vf(A,B) = sum of kept V images
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kNT) k_fold_c(Dev d) {
+__global__ void __launch_bounds__(kNT) k_fold_c(Dev d, int prec) {
   const int cp = blockIdx.x;
   if (!d.aliveC[cp]) return;
   const int n = d.nabf[d.cpA[cp]] * d.nao[d.cpA[cp]] * d.nao[d.cpF[cp]];
   double* out = d.Cf + d.cfOff[cp];
+  float* out32 = prec != kP64 ? d.Cf32 + d.cfOff[cp] : nullptr;
   const int k0 = d.cpB0[cp], k1 = d.cpB1[cp];
   for (int e = threadIdx.x; e < n; e += kNT) {
     double s = 0;
@@ -267,14 +268,16 @@ __global__ void __launch_bounds__(kNT) k_fold_c(Dev d) {
       if (d.keepC[b]) s += d.Cval[d.Coff[b] + e];
     }
     out[e] = s;
+    if (out32) out32[e] = (float)s;
   }
 }
 
-__global__ void __launch_bounds__(kNT) k_fold_v(Dev d) {
+__global__ void __launch_bounds__(kNT) k_fold_v(Dev d, int prec) {
   const int p = blockIdx.x;
   if (!d.aliveV[p]) return;
   const int n = d.nabf[d.vpA[p]] * d.nabf[d.vpB[p]];
   double* out = d.Vf + d.vfOff[p];
+  float* out32 = prec != kP64 ? d.Vf32 + d.vfOff[p] : nullptr;
   const int k0 = d.vpB0[p], k1 = d.vpB1[p];
   for (int e = threadIdx.x; e < n; e += kNT) {
     double s = 0;
@@ -283,7 +286,13 @@ __global__ void __launch_bounds__(kNT) k_fold_v(Dev d) {
       if (d.keepV[b]) s += d.Vval[d.Voff[b] + e];
     }
     out[e] = s;
+    if (out32) out32[e] = (float)s;
   }
+}
+
+__global__ void k_to_f32(const double* in, float* out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -318,8 +327,9 @@ void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev) {
   hipLaunchKernelGGL(k_screen_s, dim3(cdiv(d.nVp, kNT)), dim3(kNT), 0, s, d);
   hipLaunchKernelGGL(k_screen_v, dim3(cdiv(d.nVp, kNT)), dim3(kNT), 0, s, d, o);
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (d.nCp) hipLaunchKernelGGL(k_fold_c, dim3(d.nCp), dim3(kNT), 0, s, d);
-  if (d.nVp) hipLaunchKernelGGL(k_fold_v, dim3(d.nVp), dim3(kNT), 0, s, d);
+  if (d.nCp) hipLaunchKernelGGL(k_fold_c, dim3(d.nCp), dim3(kNT), 0, s, d, o.prec);
+  if (d.nVp) hipLaunchKernelGGL(k_fold_v, dim3(d.nVp), dim3(kNT), 0, s, d, o.prec);
+  if (o.prec != kP64) hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kNT), 0, s, d.D, d.D32, d.ntot * d.ntot);
   if (ev) (void)hipEventRecord(ev[2], s);
   hipLaunchKernelGGL(k_fill_u8, dim3(cdiv(d.nSlot, kNT)), dim3(kNT), 0, s, d.need,
                      (int64_t)d.nSlot);
