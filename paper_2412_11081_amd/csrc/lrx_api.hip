@@ -261,6 +261,8 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     require(D != nullptr, "D: NULL");
     const int N = c->N;
     const int64_t ntot = c->ao[N];
+    // rows of D are addressed with 24-bit byte strides inside the kernels
+    require(ntot * (int64_t)sizeof(double) < (int64_t)1 << 24, "D: more than 2097151 NAOs in the cell");
     c->nC = C->nblk;
     c->nV = V->nblk;
     c->Cf.assign(C->first, C->first + c->nC);
@@ -309,7 +311,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     int max_mm = 1;
     for (int i = 0; i < nVp; ++i) {
       const int mm = c->nabf[vp.pA[i]] * c->nabf[vp.pB[i]];
-      vfOff[i + 1] = vfOff[i] + mm;
+      vfOff[i + 1] = vfOff[i] + (int64_t)c->nabf[vp.pA[i]] * ((c->nabf[vp.pB[i]] + 15) & ~15);   // rows padded
       max_mm = std::max(max_mm, mm);
     }
     c->max_mm = max_mm;

@@ -147,7 +147,8 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
   const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x], c0 = d.hbC0[blockIdx.x];
   const int mB = d.nabf[B], nB = d.nao[B], rows = mB * nB;
   const int ncols = d.hColRow[B + 1] - d.hColRow[B];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, q = lane & 15, g = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
   {
     const int h0 = d.hdRow[B], hn = d.hdRow[B + 1] - h0;
     for (int k = tid; k < hn; k += kNT) {
@@ -226,33 +227,59 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
 // "chunks" = (live V pair (A,B), 16 rows beta0..beta0+15 of B's ABFs):
 //   X-build (all waves, matrix cores, operands in LDS):
 //       X1[beta][a f] = sum_b D_AB[a][b] H(B,F)[b][beta][f]
-//       X2[beta][a f] = sum_b D_FB[f][b] H(B,A)[b][beta][a]
+//           tiles of 16 rows a x 16 columns of the flattened (beta, f) index
+//       X2[beta][a f] = sum_b H(B,A)[b][beta][a] D_FB[f][b]
+//           tiles of one a: 16 rows beta x 16 columns f
+//       Only the tiles that reach the unit's column chunk are formed; each
+//       wave keeps two tiles in flight.
 //   Z waves 0-3 (K split four ways, Cf(A,F) fragments in registers):
-//       Z(A,B)[alpha][beta] partial over (a,f) in the chunk -> Zbuf
+//       Z(A,B)[alpha][beta] over (a,f) in the chunk; the four partial sums
+//       of alpha tile i meet in LDS and are added by Z wave (i mod 4)
 //   Y waves 4-7 (accumulators resident for the whole unit):
 //       Y(A,F)[alpha][a f] += Vf(A,B)[alpha][beta] X[beta][a f]
-// The H slices (and, when B changes, the D blocks) of the next chunk are
-// brought into LDS with direct global->LDS loads issued right after the
-// X-build of the current chunk, so they arrive while its products run.
+// The V slice and the H slices (and, when B changes, the D blocks) of the
+// next chunk are brought into LDS with direct global->LDS loads issued
+// right after the X-build of the current chunk, so they arrive while its
+// products run; the Y waves copy their V fragments out of the stage before
+// the X-build of the chunk that uses them.
 // ---------------------------------------------------------------------------
 template <int MT, int P>
 struct TripleCfg {
   using T = typename std::conditional<P == kP64, double, float>::type;
+  using A = T;                                                               // Z partial sums
   static constexpr int kCols = unit_cols(MT);
   static constexpr int kKSW = P == kPB3 ? (kCols / 16 + 3) / 4 : kCols / 16;   // Z k-steps per Z wave
   static constexpr int kJW = (kCols / 16 + 3) / 4;                            // Y column tiles per Y wave
   static constexpr int kXS = kCols + 1;
-  static constexpr int kHsBytes = 65280;
-  static constexpr int kHs = kHsBytes / sizeof(T);                            // staged H elements per chunk
-  static constexpr size_t lds_bytes() {
-    return sizeof(T) * (2 * 16 * kXS + 3 * MT * 256 + 2 * kMaxNao * kMaxNao) + kHsBytes;
-  }
+  static constexpr int kNUZ = (P == kP64 && MT >= 5) ? 1 : 2;                 // X-build tiles in flight: Z waves
+  static constexpr int kNUY = (P == kP64 && MT > 3) ? 1 : 2;                  // Y waves (accumulators resident)
+  static constexpr int kLds = 163840;
+  static constexpr int kE = 16 / sizeof(T);
+  static constexpr int kStage =
+      (kLds - (int)sizeof(T) * 2 * 16 * kXS - (int)sizeof(A) * 3 * MT * 256) / (int)sizeof(T) / kE * kE;
+  static_assert(2 * kMaxNao * kMaxNao + 16 * 16 * MT + kE <= kStage, "stage holds D and V of any chunk");
+  static constexpr size_t lds_bytes() { return kLds; }
 };
 
 constexpr int kTNT = 512;
 
+// Exact x / d for 0 <= x < 2^16 and 1 <= d < 2^16: with m = ceil(2^32 / d),
+// x * m / 2^32 exceeds x / d by less than x / 2^32 < 1 / d.
+struct Div {
+  unsigned m;
+  int one;
+  __device__ void init(int d) {
+    one = d == 1;
+    m = one ? 0u : 0xFFFFFFFFu / (unsigned)d + 1u;
+  }
+  __device__ int operator()(int x) const { return one ? x : (int)__umulhi((unsigned)x, m); }
+};
+
 struct UnitGeo {
-  int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, T1, T2, fpos, vp0, nVpA, vb, ve, split;
+  int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, fpos, vp0, nVpA, vb, ve, split;
+  int a0, tr0, N1, N2, TF;   // X-build tiles: rows a0.. of term 1, a's of term 2
+  int pF, pA;                // 16-byte pieces per staged H row (F and A slices)
+  Div dnF, dpF, dpA;
 };
 
 struct Chunk {
@@ -286,104 +313,221 @@ __device__ inline Chunk chunk_next(const Dev& d, const UnitGeo& U, const Chunk& 
 __device__ inline int64_t chunk_tri(const Dev& d, const UnitGeo& U, const Chunk& c) {
   return d.tBase[U.A] + (int64_t)U.fpos * U.nVpA + (c.p - U.vp0);
 }
-// elements of H staged for a chunk: HF[b][16 nF] then HA[b][16 nA]
-__device__ inline int chunk_hs(const UnitGeo& U, const Chunk& c) { return c.nB * 16 * (U.nF + U.nA); }
 
-// Direct global->LDS copy of the chunk's H slices (16-byte pieces; H rows
-// are 16-element aligned by construction).
+// Chunk stage in LDS (elements of T):
+//   [0, nA nB)            D(A,B)[a][b]       (rewritten only when B changes)
+//   [nA nB, (nA+nF) nB)   D(F,B)[f][b]
+//   [vo, vo + 16 mA)      Vf(A,B)[alpha][beta0 .. beta0+15], 16-byte pieces of a
+//                         row stored in XOR-swizzled order (conflict-free reads)
+//   [ho, ...)             H(B,F)[b][beta][f] then H(B,A)[b][beta][a], 16 rows beta
+// vo = (nA+nF) nB rounded up to 16 bytes, ho = vo + 16 mA.  Everything is
+// brought in with direct global->LDS loads; H only when it fits.
+struct StageGeo {
+  int vo, ho, hend;
+};
 template <class T>
-__device__ inline void stage_h(const Dev& d, const UnitGeo& U, const Chunk& c, T* Hs, int w, int lane) {
-  constexpr int E = 16 / sizeof(T);                 // elements per piece
-  const int64_t t = chunk_tri(d, U, c);
-  const T* H = Buf<T>::H(d);
-  const T* hF = H + d.triHF[t];
-  const T* hA = H + d.triHA[t];
-  const int mBp = (c.mB + 15) & ~15;
-  const int pF = 16 * U.nF / E, pA = 16 * U.nA / E;   // pieces per row
-  const int P = c.nB * (pF + pA);
-  for (int j = w; j * 64 < P; j += 8) {
-    const int pc = j * 64 + lane;
-    if (pc < P) {
-      const T* src;
-      if (pc < c.nB * pF) {
-        const int b = pc / pF, m = pc - b * pF;
-        src = hF + ((int64_t)b * mBp + c.b0) * U.nF + E * m;
-      } else {
-        const int pp = pc - c.nB * pF;
-        const int b = pp / pA, m = pp - b * pA;
-        src = hA + ((int64_t)b * mBp + c.b0) * U.nA + E * m;
+__device__ inline StageGeo stage_geo(const UnitGeo& U, int nB) {
+  constexpr int E = 16 / sizeof(T);
+  StageGeo s;
+  s.vo = ((U.nA + U.nF) * nB + E - 1) / E * E;
+  s.ho = s.vo + 16 * U.mA;
+  s.hend = s.ho + nB * 16 * (U.nF + U.nA);
+  return s;
+}
+
+// The direct global->LDS loads that stage one chunk, as a list of 64-lane
+// instructions: [D(A,B), D(F,B): 4-byte pieces, only when B changes]
+// [V: 16-byte pieces] [H(B,F), H(B,A): 16-byte pieces, only when they fit].
+// issue(J) sends instruction J, so the list can be spread over the products
+// of the current chunk instead of stalling the waves in one burst.
+template <class T>
+struct Stager {
+  static constexpr int E = 16 / sizeof(T);          // elements per 16-byte piece
+  static constexpr int PR = 16 / E;                 // pieces per staged V row (16 elements)
+  static constexpr int W = sizeof(T) / 4;           // dwords per element
+  int nD, nV, n;                                    // instruction counts: D, D + V, all
+  const char* dA;                                   // D rows of A at column ao[B]
+  const char* dF;
+  unsigned dRow;                                    // bytes per D row
+  int nB, PA, PD;
+  Div dB;
+  const char* v0;
+  unsigned vRow;                                    // bytes per folded V row
+  int PV;
+  const char* hF;
+  const char* hA;
+  unsigned hRowF, hRowA;                            // bytes between b rows of the H slots
+  int PF, PH;
+  char* sD;
+  char* sV;
+  char* sH;
+
+  __device__ void init(const Dev& d, const UnitGeo& U, const Chunk& c, const StageGeo& sg, bool with_d, bool with_h,
+                       T* S) {
+    const T* Dm = Buf<T>::D(d);
+    nB = c.nB;
+    dRow = (unsigned)(d.ntot * sizeof(T));
+    dA = (const char*)(Dm + d.ao[U.A] * d.ntot + d.ao[c.B]);
+    dF = (const char*)(Dm + d.ao[U.F] * d.ntot + d.ao[c.B]);
+    dB.init(nB);
+    PA = W * U.nA * nB;
+    PD = with_d ? PA + W * U.nF * nB : 0;
+    const int mBp = (c.mB + 15) & ~15;
+    v0 = (const char*)(Buf<T>::Vf(d) + d.vfOff[c.p] + c.b0);
+    vRow = (unsigned)(mBp * sizeof(T));
+    PV = PR * U.mA;
+    const int64_t t = chunk_tri(d, U, c);
+    const T* H = Buf<T>::H(d);
+    hF = (const char*)(H + d.triHF[t] + (int64_t)c.b0 * U.nF);
+    hA = (const char*)(H + d.triHA[t] + (int64_t)c.b0 * U.nA);
+    hRowF = (unsigned)(mBp * U.nF * sizeof(T));
+    hRowA = (unsigned)(mBp * U.nA * sizeof(T));
+    PF = c.nB * U.pF;
+    PH = with_h ? PF + c.nB * U.pA : 0;
+    sD = (char*)S;
+    sV = (char*)(S + sg.vo);
+    sH = (char*)(S + sg.ho);
+    nD = (PD + 63) >> 6;
+    nV = nD + ((PV + 63) >> 6);
+    n = nV + ((PH + 63) >> 6);
+  }
+
+  __device__ void issue(int J, int lane, const UnitGeo& U) const {
+    // J is uniform: the part is chosen by scalar branches; addresses are
+    // 32-bit byte offsets from the part's base (24-bit products)
+    if (J < nD) {
+      const int pc = J * 64 + lane;
+      if (pc < PD) {
+        const bool ab = pc < PA;
+        const int pp = ab ? pc : pc - PA;
+        const int e = W == 2 ? pp >> 1 : pp, part = pp - e * W;
+        const int r = dB(e), b = e - r * nB;
+        const unsigned off = __umul24((unsigned)r, dRow) + (unsigned)(b * (int)sizeof(T) + 4 * part);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((ab ? dA : dF) + off),
+                                         (__attribute__((address_space(3))) void*)(sD + 256 * J), 4, 0, 0);
       }
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
-                                       (__attribute__((address_space(3))) void*)((char*)Hs + 1024 * j), 16, 0, 0);
+    } else if (J < nV) {
+      const int j = J - nD, pc = j * 64 + lane;
+      if (pc < PV) {
+        const int al = pc / PR, k = pc - al * PR;
+        const unsigned off = __umul24((unsigned)al, vRow) + 16u * (unsigned)(k ^ (al & (PR - 1)));
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(v0 + off),
+                                         (__attribute__((address_space(3))) void*)(sV + 1024 * j), 16, 0, 0);
+      }
+    } else {
+      const int j = J - nV, pc = j * 64 + lane;
+      if (pc < PH) {
+        const char* src;
+        if (pc < PF) {
+          const int b = U.dpF(pc);
+          src = hF + (__umul24((unsigned)b, hRowF) + 16u * (unsigned)(pc - b * U.pF));
+        } else {
+          const int pp = pc - PF, b = U.dpA(pp);
+          src = hA + (__umul24((unsigned)b, hRowA) + 16u * (unsigned)(pp - b * U.pA));
+        }
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(sH + 1024 * j), 16, 0, 0);
+      }
     }
   }
-}
+};
 
-// Direct global->LDS copy of D(A,B) then D(F,B) (4-byte pieces; rows of the
-// dense D are not 16-byte aligned in general).
+// Element (alpha, beta) of the staged V chunk.
 template <class T>
-__device__ inline void stage_d(const Dev& d, const UnitGeo& U, int B, int nB, T* Dab, int w, int lane) {
-  constexpr int W = sizeof(T) / 4;                  // dwords per element
-  const T* Dm = Buf<T>::D(d);
-  const int PA = W * U.nA * nB, PF = W * U.nF * nB;
-  for (int j = w; j * 64 < PA + PF; j += 8) {
-    const int pc = j * 64 + lane;
-    if (pc < PA + PF) {
-      const bool ab = pc < PA;
-      const int pp = ab ? pc : pc - PA;
-      const int e = pp / W, part = pp - e * W;
-      const int r = e / nB, b = e - r * nB;
-      const T* src = Dm + (d.ao[ab ? U.A : U.F] + r) * d.ntot + d.ao[B] + b;
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((const char*)src + 4 * part),
-                                       (__attribute__((address_space(3))) void*)((char*)Dab + 256 * j), 4, 0, 0);
-    }
-  }
+__device__ inline int vs_index(int al, int be) {
+  constexpr int E = 16 / sizeof(T), PR = 16 / E;
+  return (al * PR + ((be / E) ^ (al & (PR - 1)))) * E + (be & (E - 1));
 }
 
-// One X-build tile.  DIRECT: the H slice is read from global memory (chunks
-// whose slices exceed the LDS stage).
-template <class T, bool DIRECT>
-__device__ inline void xbuild_tile(const Dev& d, const UnitGeo& U, const Chunk& ch, int t, int q, int g,
-                                   const T* Hs, const T* Dab, const T* Dfb, bool kAB, bool kFB, T* X1, T* X2) {
-  using M = M4<T>;
-  const bool one = t < U.T1;
-  const int tt = one ? t : t - U.T1;
-  const int ncol = one ? U.nF : U.nA;
-  const int nrow = one ? U.nA : U.nF;
-  const int tr = tt / ncol, tc = tt - tr * ncol;
-  const T* Ds = one ? Dab : Dfb;
-  const bool keep = one ? kAB : kFB;
-  const int c = 16 * tc + q;
-  const int r = 16 * tr + q;
-  const int nB = ch.nB;
-  const T* hs;
-  int64_t hstride;
-  if constexpr (DIRECT) {
-    const int64_t tri = chunk_tri(d, U, ch);
-    const int mBp = (ch.mB + 15) & ~15;
-    hs = Buf<T>::H(d) + (one ? d.triHF[tri] : d.triHA[tri]) + (int64_t)ch.b0 * ncol;
-    hstride = (int64_t)mBp * ncol;
-  } else {
-    hs = one ? Hs : Hs + nB * 16 * U.nF;
-    hstride = 16 * ncol;
-  }
-  typename M::acc acc = {0, 0, 0, 0};
+// Barrier for LDS hand-offs only: no wait on outstanding global stores.
+__device__ inline void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// X-build of one chunk: this wave's tiles t = w, w+8, ... of the N1 term-1
+// tiles followed by the N2 term-2 tiles, NU at a time.  The b index runs in
+// k-steps of 4, two steps per pass (a step past nB has zero operands).
+// DIRECT: the H slices are read from global memory (chunks whose slices
+// exceed the LDS stage); otherwise from the stage.
+template <class T, bool DIRECT, int NU>
+__device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, int hsF, const T* HA, int hsA,
+                                       const T* Dab, const T* Dfb, bool kAB, bool kFB, T* X1, T* X2, int w, int q,
+                                       int g) {
   const int SB = (nB + 3) >> 2;
-  for (int s = 0; s < SB; ++s) {
-    const int b = 4 * s + g;
-    const bool ok = keep && b < nB;
-    const T av = (ok && r < nrow) ? Ds[r * nB + b] : T(0);
-    const T hv = ok ? hs[b * hstride + c] : T(0);
-    acc = M::mma(av, hv, acc);
-  }
-  const int bl = c / ncol, xo = c - bl * ncol;
+  using M = M4<T>;
+  const int NT = U.N1 + U.N2;
+  for (int t0 = w; t0 < NT; t0 += 8 * NU) {
+    const T* ap[NU];
+    const T* bp[NU];
+    T* xb[NU];
+    int as[NU], bs[NU], kb[NU], ks[NU], rs[NU], rl[NU];
+    bool on[NU], lok[NU], kp[NU];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int rr = 16 * tr + M::row(g, i);
-    if (rr < nrow) {
-      const int k = one ? rr * U.nF + xo : xo * U.nF + rr;
-      const int cl = k - U.k0;
-      if (cl >= 0 && cl < U.Kc) (one ? X1 : X2)[bl * U.XS + cl] = acc[i];
+    for (int u = 0; u < NU; ++u) {
+      const int t = t0 + 8 * u;
+      on[u] = t < NT;
+      const int tt = on[u] ? t : t0;
+      if (tt < U.N1) {
+        const int rt = U.dnF(tt), tr = U.tr0 + rt, tc = tt - rt * U.nF;
+        ap[u] = Dab + min(16 * tr + q, U.nA - 1) * nB;
+        as[u] = 1;
+        const int c = 16 * tc + q, be = U.dnF(c), f = c - be * U.nF;
+        bp[u] = HF + c;
+        bs[u] = hsF;
+        xb[u] = X1 + be * U.XS;
+        kb[u] = 16 * tr * U.nF + f - U.k0;
+        ks[u] = U.nF;
+        rs[u] = 0;
+        rl[u] = U.nA - 16 * tr;
+        lok[u] = true;
+        kp[u] = kAB;
+      } else {
+        const int t2 = tt - U.N1, ai = U.TF == 2 ? t2 >> 1 : t2, tf = t2 - ai * U.TF, a = U.a0 + ai;
+        const int f = 16 * tf + q;
+        ap[u] = HA + q * U.nA + a;
+        as[u] = hsA;
+        bp[u] = Dfb + min(f, U.nF - 1) * nB;
+        bs[u] = 1;
+        xb[u] = X2;
+        kb[u] = a * U.nF + f - U.k0;
+        ks[u] = 0;
+        rs[u] = U.XS;
+        rl[u] = 16;
+        lok[u] = f < U.nF;
+        kp[u] = kFB;
+      }
+    }
+    typename M::acc acc[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
+#pragma unroll 1
+    for (int s0 = 0; s0 < SB; s0 += 2) {
+      T av[NU][2], bv[NU][2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int b = 4 * (s0 + s) + g, bc = min(b, nB - 1);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const T a = ap[u][bc * as[u]];
+          av[u][s] = b < nB ? a : T(0);
+          bv[u][s] = bp[u][bc * bs[u]];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][s], bv[u][s], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (!on[u]) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = M::row(g, i), k = kb[u] + r * ks[u];
+        if (lok[u] && r < rl[u] && k >= 0 && k < U.Kc) xb[u][k + r * rs[u]] = kp[u] ? acc[u][i] : T(0);
+      }
     }
   }
 }
@@ -394,18 +538,18 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
   using T = typename Cfg::T;
   using M = M4<T>;
   using Acc = typename M::acc;           // d4 (FP64) or f4 (FP32, BF16x3)
-  using A = typename std::conditional<P == kP64, double, float>::type;
+  using A = typename Cfg::A;
   constexpr bool B3 = P == kPB3;
+  constexpr int NU = ZROLE ? Cfg::kNUZ : Cfg::kNUY;
   T* X1 = (T*)ldsb;
   T* X2 = X1 + 16 * Cfg::kXS;
-  A* Zred = (A*)(X2 + 16 * Cfg::kXS);   // partials of Z waves 1-3
-  T* Dab = (T*)(Zred + 3 * MT * 256);
-  T* Hs = Dab + 2 * kMaxNao * kMaxNao;
+  A* Zred = (A*)(X2 + 16 * Cfg::kXS);   // partial Z tiles on their way to the owning wave
+  T* S = (T*)(Zred + 3 * MT * 256);     // chunk stage
   const int ww = w & 3;
   const int N = d.N;
   const int mA = U.mA, XS = U.XS;
   const T* Cf = Buf<T>::Cf(d);
-  const T* Vf = Buf<T>::Vf(d);
+  const T* Hg = Buf<T>::H(d);
 
   // ---- resident operands / accumulators of the role ----------------------
   constexpr int ZI = ZROLE ? MT : 1, ZT = ZROLE ? Cfg::kKSW : 1;
@@ -440,36 +584,35 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
 #pragma unroll
       for (int j = 0; j < Cfg::kJW; ++j) yacc[i][j] = Acc{0, 0, 0, 0};
   }
+  // column tiles of this Y wave that reach the chunk's columns
+  const int nYJ = min(Cfg::kJW, (U.NTc - ww + 3) >> 2);
 
   // prologue: stage the first chunk
   Chunk ch = chunk_at(d, U, U.vb, 0);
+  StageGeo sg = stage_geo<T>(U, ch.nB);
   if (ch.p >= 0) {
-    stage_d<T>(d, U, ch.B, ch.nB, Dab, w, lane);
-    if (chunk_hs(U, ch) <= Cfg::kHs) stage_h<T>(d, U, ch, Hs, w, lane);
+    Stager<T> st;
+    st.init(d, U, ch, sg, true, sg.hend <= Cfg::kStage, S);
+    for (int J = w; J < st.n; J += 8) st.issue(J, lane, U);
   }
   __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+  lds_sync();
   while (ch.p >= 0) {
     const Chunk nx = chunk_next(d, U, ch);
     const bool kAB = d.keepD[(int64_t)U.A * N + ch.B], kFB = d.keepD[(int64_t)U.F * N + ch.B];
-    const T* Dfb = Dab + U.nA * ch.nB;
     const int64_t tri = chunk_tri(d, U, ch);
-    T* Zdst = Buf<T>::Z(d) + d.zOff[tri] + (int64_t)U.kc * mA * ch.mB;
-    const T* Vfp = Vf + d.vfOff[ch.p];
-    // V fragments of this chunk (Y waves); their latency is covered by the X-build
+    // V fragments of this chunk (Y waves), read before the stage is reused
     T avn[(ZROLE || B3) ? 1 : 4][(ZROLE || B3) ? 1 : MT];
     s4 avh[(!ZROLE && B3) ? MT : 1], avl[(!ZROLE && B3) ? MT : 1];
     if constexpr (!ZROLE) {
+      const T* Vs = S + sg.vo;
       if constexpr (B3) {
 #pragma unroll
         for (int i = 0; i < MT; ++i) {
           const int al = 16 * i + q;
           float v[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int be = ch.b0 + 4 * g + j;
-            v[j] = (al < mA && be < ch.mB) ? Vfp[(int64_t)al * ch.mB + be] : 0.f;
-          }
+          for (int j = 0; j < 4; ++j) v[j] = al < mA ? Vs[vs_index<T>(al, 4 * g + j)] : 0.f;
           split4(v, avh[i], avl[i]);
         }
       } else {
@@ -477,111 +620,139 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int i = 0; i < MT; ++i) {
-            const int al = 16 * i + q, be = ch.b0 + 4 * s + g;
-            avn[s][i] = (al < mA && be < ch.mB) ? Vfp[(int64_t)al * ch.mB + be] : T(0);
+            const int al = 16 * i + q;
+            avn[s][i] = al < mA ? Vs[vs_index<T>(al, 4 * s + g)] : T(0);
           }
       }
     }
     // ---- X-build of this chunk (all waves) ------------------------------
-    const bool staged = chunk_hs(U, ch) <= Cfg::kHs;
-    for (int t = w; t < U.T1 + U.T2; t += 8) {
-      if (staged)
-        xbuild_tile<T, false>(d, U, ch, t, q, g, Hs, Dab, Dfb, kAB, kFB, X1, X2);
-      else
-        xbuild_tile<T, true>(d, U, ch, t, q, g, Hs, Dab, Dfb, kAB, kFB, X1, X2);
+    if (sg.hend <= Cfg::kStage) {
+      xbuild<T, false, NU>(U, ch.nB, S + sg.ho, 16 * U.nF, S + sg.ho + ch.nB * 16 * U.nF, 16 * U.nA, S,
+                              S + U.nA * ch.nB, kAB, kFB, X1, X2, w, q, g);
+    } else {
+      const int mBp = (ch.mB + 15) & ~15;
+      xbuild<T, true, NU>(U, ch.nB, Hg + d.triHF[tri] + (int64_t)ch.b0 * U.nF, mBp * U.nF,
+                             Hg + d.triHA[tri] + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * ch.nB, kAB, kFB,
+                             X1, X2, w, q, g);
     }
-    __syncthreads();
-    // ---- stage the next chunk while this one is contracted -------------
+    lds_sync();
+    // ---- stage the next chunk while this one is contracted --------------
+    const StageGeo sn = stage_geo<T>(U, nx.nB);
     if (nx.p >= 0) {
-      if (nx.p != ch.p) stage_d<T>(d, U, nx.B, nx.nB, Dab, w, lane);
-      if (chunk_hs(U, nx) <= Cfg::kHs) stage_h<T>(d, U, nx, Hs, w, lane);
+      Stager<T> st;
+      st.init(d, U, nx, sn, nx.p != ch.p, sn.hend <= Cfg::kStage, S);
+      for (int J = w; J < st.n; J += 8) st.issue(J, lane, U);
     }
     if constexpr (ZROLE) {
       Acc zp[MT];
 #pragma unroll
       for (int i = 0; i < MT; ++i) zp[i] = Acc{0, 0, 0, 0};
+      if constexpr (B3) {
+        // k-steps past the chunk's columns meet zero Cf fragments; their X
+        // reads may leave the row, so the values are dropped as well
 #pragma unroll
-      for (int t = 0; t < Cfg::kKSW; ++t) {
-        if constexpr (B3) {
+        for (int t = 0; t < Cfg::kKSW; ++t) {
           const int ks = ww + 4 * t;
-          if (ks < U.NTc) {
-            float v[4];
+          float v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int c = 16 * ks + 4 * g + j;
-              v[j] = X1[q * XS + c] + X2[q * XS + c];
-            }
-            s4 bh, bl;
-            split4(v, bh, bl);
-#pragma unroll
-            for (int i = 0; i < MT; ++i) zp[i] = mma_bf16x3(cfh[i][t], cfl[i][t], bh, bl, zp[i]);
+          for (int j = 0; j < 4; ++j) {
+            const int c = min(16 * ks + 4 * g + j, XS - 1);
+            v[j] = ks < U.NTc ? X1[q * XS + c] + X2[q * XS + c] : 0.f;
           }
-        } else {
-          const int ks = ww + 4 * t;
-          if (ks < U.KS) {
-            const int c = 4 * ks + g;
-            const T xb = X1[q * XS + c] + X2[q * XS + c];
+          s4 bh, bl;
+          split4(v, bh, bl);
 #pragma unroll
-            for (int i = 0; i < MT; ++i) zp[i] = M::mma(cfr[i][t], xb, zp[i]);
-          }
+          for (int i = 0; i < MT; ++i) zp[i] = mma_bf16x3(cfh[i][t], cfl[i][t], bh, bl, zp[i]);
         }
-      }
-      if (ww > 0) {
+      } else {
+        // columns 4 ks + g < kCols < XS; past the chunk's columns X and the
+        // Cf fragments are zero
+        T xb[Cfg::kKSW];
 #pragma unroll
-        for (int i = 0; i < MT; ++i) *(Acc*)&Zred[((ww - 1) * MT + i) * 256 + lane * 4] = zp[i];
+        for (int t = 0; t < Cfg::kKSW; ++t) {
+          const int c = 4 * (ww + 4 * t) + g;
+          xb[t] = X1[q * XS + c] + X2[q * XS + c];
+        }
+#pragma unroll
+        for (int t = 0; t < Cfg::kKSW; ++t)
+#pragma unroll
+          for (int i = 0; i < MT; ++i) zp[i] = M::mma(cfr[i][t], xb[t], zp[i]);
+      }
+      // tile i is owned by Z wave (i mod 4); the other three park their partials
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        const int own = i & 3;
+        if (own != ww) *(Acc*)&Zred[((((ww - own - 1) & 3) * MT) + i) * 256 + lane * 4] = zp[i];
       }
       __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (ww == 0) {
-        const int be = ch.b0 + q;
+      lds_sync();
+      T* Zdst = Buf<T>::Z(d) + d.zOff[tri] + (int64_t)U.kc * mA * ch.mB;
+      const int be = ch.b0 + q;
 #pragma unroll
-        for (int i = 0; i < MT; ++i) {
-          Acc z = zp[i];
-          for (int v = 0; v < 3; ++v) z += *(const Acc*)&Zred[(v * MT + i) * 256 + lane * 4];
+      for (int i = 0; i < MT; ++i) {
+        if ((i & 3) != ww) continue;
+        Acc z = zp[i];
 #pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int al = 16 * i + M::row(g, rr);
-            if (al < mA && be < ch.mB) Zdst[(int64_t)al * ch.mB + be] = z[rr];
-          }
+        for (int v = 0; v < 3; ++v) z += *(const Acc*)&Zred[(v * MT + i) * 256 + lane * 4];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int al = 16 * i + M::row(g, rr);
+          if (al < mA && be < ch.mB) Zdst[(int64_t)al * ch.mB + be] = z[rr];
         }
       }
     } else {
       if constexpr (B3) {
+        // column tiles j >= NTc accumulate values that are never stored
 #pragma unroll
         for (int jj = 0; jj < Cfg::kJW; ++jj) {
+          if (jj == Cfg::kJW - 1 && jj >= nYJ) break;
           const int j = ww + 4 * jj;
-          if (j < U.NTc) {
-            float v[4];
+          float v[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const int bl = 4 * g + k;
-              v[k] = X1[bl * XS + 16 * j + q] + X2[bl * XS + 16 * j + q];
-            }
-            s4 bh, blo;
-            split4(v, bh, blo);
-#pragma unroll
-            for (int i = 0; i < MT; ++i) yacc[i][jj] = mma_bf16x3(avh[i], avl[i], bh, blo, yacc[i][jj]);
+          for (int k = 0; k < 4; ++k) {
+            const int bl = 4 * g + k, c = min(16 * j + q, XS - 1);
+            v[k] = X1[bl * XS + c] + X2[bl * XS + c];
           }
+          s4 bh, blo;
+          split4(v, bh, blo);
+#pragma unroll
+          for (int i = 0; i < MT; ++i) yacc[i][jj] = mma_bf16x3(avh[i], avl[i], bh, blo, yacc[i][jj]);
         }
       } else {
+        // column tiles j >= NTc accumulate values that are never stored; the
+        // last tile of a wave is skipped when it lies past the chunk
+        constexpr int JF = Cfg::kJW - 1;
+        T xb[4][Cfg::kJW];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int bl = 4 * s + g;
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int jj = 0; jj < Cfg::kJW; ++jj) {
-            const int j = ww + 4 * jj;
-            if (j < U.NTc) {
-              const T xb = X1[bl * XS + 16 * j + q] + X2[bl * XS + 16 * j + q];
-#pragma unroll
-              for (int i = 0; i < MT; ++i) yacc[i][jj] = M::mma(avn[s][i], xb, yacc[i][jj]);
-            }
+          for (int jj = 0; jj < JF; ++jj) {
+            const int bl = 4 * s + g, c = min(16 * (ww + 4 * jj) + q, XS - 1);
+            xb[s][jj] = X1[bl * XS + c] + X2[bl * XS + c];
           }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int jj = 0; jj < JF; ++jj)
+#pragma unroll
+            for (int i = 0; i < MT; ++i) yacc[i][jj] = M::mma(avn[s][i], xb[s][jj], yacc[i][jj]);
+        if (JF < nYJ) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int bl = 4 * s + g, c = 16 * (ww + 4 * JF) + q;
+            xb[s][JF] = X1[bl * XS + c] + X2[bl * XS + c];
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < MT; ++i) yacc[i][JF] = M::mma(avn[s][i], xb[s][JF], yacc[i][JF]);
         }
       }
       __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
+      lds_sync();
     }
     ch = nx;
+    sg = sn;
   }
   if constexpr (!ZROLE) {
     T* Y = Buf<T>::Y(d) + d.yOff[U.cp] + (int64_t)U.split * mA * U.K1;
@@ -622,15 +793,25 @@ __global__ void __launch_bounds__(kTNT, 1) k_triple(Dev d, const int* __restrict
   U.NTc = (U.Kc + 15) >> 4;
   U.KS = U.NTc * 4;
   U.XS = U.NTc * 16 + 1;
-  U.T1 = ((U.nA + 15) >> 4) * U.nF;
-  U.T2 = ((U.nF + 15) >> 4) * U.nA;
   U.fpos = U.cp - d.cpRow[U.A];
   U.vp0 = d.vpRow[U.A];
   U.nVpA = d.vpRow[U.A + 1] - U.vp0;
   U.vb = d.unitV0[u];
   U.ve = d.unitV1[u];
   U.split = d.unitS[u];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  U.dnF.init(U.nF);
+  U.a0 = U.dnF(U.k0);
+  const int a1 = U.dnF(U.k0 + U.Kc - 1);
+  U.tr0 = U.a0 >> 4;
+  U.N1 = ((a1 >> 4) - U.tr0 + 1) * U.nF;
+  U.TF = (U.nF + 15) >> 4;
+  U.N2 = (a1 - U.a0 + 1) * U.TF;
+  U.pF = 16 * U.nF * (int)sizeof(T) / 16;
+  U.pA = 16 * U.nA * (int)sizeof(T) / 16;
+  U.dpF.init(U.pF);
+  U.dpA.init(U.pA);
+  const int tid = threadIdx.x, lane = tid & 63, q = lane & 15, g = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
   T* X = (T*)ldsb;
   for (int e = tid; e < 32 * Cfg::kXS; e += kTNT) X[e] = T(0);
   __syncthreads();
@@ -683,7 +864,10 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
     __syncthreads();
   }
   const int NZ = nz;
-  const double* vf = d.Vf + d.vfOff[p];
+  const double* vf = d.Vf + d.vfOff[p];   // rows padded to 16 elements
+  const int mBp = (mB + 15) & ~15;
+  Div dmB;
+  dmB.init(mB);
   const int kb0 = d.vpB0[p], kb1 = d.vpB1[p];
   for (int k0 = kb0; k0 < kb1 || k0 == kb0; k0 += kZB) {
     const int nb = max(0, min(kZB, kb1 - k0));
@@ -702,7 +886,10 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
     for (int e = threadIdx.x; e < n; e += kNT) {
       double z = 0;
       for (int k = 0; k < NZ; ++k) z += (double)Zb[zoff[k] + e];
-      if (first) acc[0] += vf[e] * z;
+      if (first) {
+        const int al = dmB(e);
+        acc[0] += vf[al * mBp + (e - al * mB)] * z;
+      }
 #pragma unroll
       for (int j = 0; j < kZB; ++j)
         if (kp[j]) {

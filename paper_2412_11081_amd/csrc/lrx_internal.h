@@ -69,7 +69,8 @@ struct Dev {
   const int* vpA; const int* vpB; const int* vpB0; const int* vpB1; const int64_t* vpBlk; const int* vpRow;
   const int* vpMir;
   const int64_t* cfOff; const int64_t* vfOff;
-  double* Cf; double* Vf;
+  double* Cf;             // folded C pair blocks [mA][nA][nF] at cfOff
+  double* Vf;             // folded V pair blocks [mA][mB padded to 16] at vfOff (zero padding)
   // FP32 copies used by the reduced-precision forms (allocated on first use)
   float* Cf32; float* Vf32; float* D32; float* H32; float* Zbuf32; float* Ybuf32;
 

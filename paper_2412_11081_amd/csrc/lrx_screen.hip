@@ -275,16 +275,19 @@ __global__ void __launch_bounds__(kNT) k_fold_c(Dev d, int prec) {
 __global__ void __launch_bounds__(kNT) k_fold_v(Dev d, int prec) {
   const int p = blockIdx.x;
   if (!d.aliveV[p]) return;
-  const int n = d.nabf[d.vpA[p]] * d.nabf[d.vpB[p]];
+  // folded block [mA][mBp]: rows padded with zeros to 16 elements
+  const int mA = d.nabf[d.vpA[p]], mB = d.nabf[d.vpB[p]], mBp = (mB + 15) & ~15;
   double* out = d.Vf + d.vfOff[p];
   float* out32 = prec != kP64 ? d.Vf32 + d.vfOff[p] : nullptr;
   const int k0 = d.vpB0[p], k1 = d.vpB1[p];
-  for (int e = threadIdx.x; e < n; e += kNT) {
+  for (int e = threadIdx.x; e < mA * mBp; e += kNT) {
+    const int al = e / mBp, be = e - al * mBp;
     double s = 0;
-    for (int k = k0; k < k1; ++k) {
-      const int64_t b = d.vpBlk[k];
-      if (d.keepV[b]) s += d.Vval[d.Voff[b] + e];
-    }
+    if (be < mB)
+      for (int k = k0; k < k1; ++k) {
+        const int64_t b = d.vpBlk[k];
+        if (d.keepV[b]) s += d.Vval[d.Voff[b] + al * mB + be];
+      }
     out[e] = s;
     if (out32) out32[e] = (float)s;
   }
