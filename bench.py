@@ -13,6 +13,7 @@ library on the stream it runs on) and ``cpu_baseline`` (the CPU oracle on a
 bounded sample of the same workload).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +23,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_11081_amd", "csrc", "lrx_contract.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_triple_abx3_1080_fp64_hbm_traffic.txt")
+
+
+def measured_traffic(precision, workload):
+    """HBM bytes per launch of the triple-product stage from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the summary is
+    for another configuration or the kernel source changed since it was taken."""
+    if precision != "fp64" or workload != 4 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != digest:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 WORKLOADS = {
     1: "sc8: 8-atom simple-cubic cell, 13 NAO / 40 ABF, rC 7, rV 14, theta 0",
     2: "diamond64: 64-atom diamond-like cell, 13 NAO / 75 ABF, rC 8, rV 20, theta 1e-4",
@@ -54,7 +74,7 @@ def _oracle_sample(st, mats, picked, threads):
     return time.perf_counter() - t0, int(kV.sum())
 
 
-def cpu_baseline(st, mats, target_s=15.0, threads=None):
+def cpu_baseline(st, mats, target_s=40.0, threads=None):
     """The CPU oracle on the V blocks of a few atoms, scaled to the whole cell.
 
     One atom calibrates the cost; then a sample of atoms sized for about
@@ -151,7 +171,8 @@ def main():
         "tflops_alg": stats["flop_alg"] / (ms_per_step * 1e-3) / 1e12,
         "stage_ms": stage_avg,
         "roofline": {"bound": "mfma", "kernel": "k_triple", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(args.precision, args.workload),
                      "flop_per_launch": stats["flop_triple"], "launch_ms": stage_avg["triple"]},
     }
     ctx.close()

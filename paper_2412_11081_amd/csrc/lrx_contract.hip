@@ -251,8 +251,11 @@ struct TripleCfg {
   static constexpr int kKSW = P == kPB3 ? (kCols / 16 + 3) / 4 : kCols / 16;   // Z k-steps per Z wave
   static constexpr int kJW = (kCols / 16 + 3) / 4;                            // Y column tiles per Y wave
   static constexpr int kXS = kCols + 1;
-  static constexpr int kNUZ = (P == kP64 && MT >= 5) ? 1 : 2;                 // X-build tiles in flight: Z waves
-  static constexpr int kNUY = (P == kP64 && MT > 3) ? 1 : 2;                  // Y waves (accumulators resident)
+  // X-build by all eight waves; FP64 with many alpha tiles leaves the Y
+  // waves registers for one tile in flight only
+  static constexpr int kXW = 8;                                              // waves taking part
+  static constexpr int kNUZ = 2;                                             // tiles in flight: Z waves
+  static constexpr int kNUY = (P == kP64 && MT >= 5) ? 1 : 2;                 // Y waves
   static constexpr int kLds = 163840;
   static constexpr int kE = 16 / sizeof(T);
   static constexpr int kStage =
@@ -446,19 +449,20 @@ __device__ inline void lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// X-build of one chunk: this wave's tiles t = w, w+8, ... of the N1 term-1
-// tiles followed by the N2 term-2 tiles, NU at a time.  The b index runs in
+// X-build of one chunk: this wave's tiles t = w, w+XW, ... of the N1 term-1
+// tiles followed by the N2 term-2 tiles (XW waves take part), NU at a time
+// (NU independent accumulation chains on the matrix core).  The b index runs in
 // k-steps of 4, two steps per pass (a step past nB has zero operands).
 // DIRECT: the H slices are read from global memory (chunks whose slices
 // exceed the LDS stage); otherwise from the stage.
-template <class T, bool DIRECT, int NU>
+template <class T, bool DIRECT, int NU, int XW>
 __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, int hsF, const T* HA, int hsA,
                                        const T* Dab, const T* Dfb, bool kAB, bool kFB, T* X1, T* X2, int w, int q,
                                        int g) {
   const int SB = (nB + 3) >> 2;
   using M = M4<T>;
   const int NT = U.N1 + U.N2;
-  for (int t0 = w; t0 < NT; t0 += 8 * NU) {
+  for (int t0 = w; t0 < NT; t0 += XW * NU) {
     const T* ap[NU];
     const T* bp[NU];
     T* xb[NU];
@@ -466,17 +470,17 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
     bool on[NU], lok[NU], kp[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      const int t = t0 + 8 * u;
+      const int t = t0 + XW * u;
       on[u] = t < NT;
       const int tt = on[u] ? t : t0;
       if (tt < U.N1) {
         const int rt = U.dnF(tt), tr = U.tr0 + rt, tc = tt - rt * U.nF;
-        ap[u] = Dab + min(16 * tr + q, U.nA - 1) * nB;
+        ap[u] = Dab + __umul24((unsigned)min(16 * tr + q, U.nA - 1), (unsigned)nB);
         as[u] = 1;
         const int c = 16 * tc + q, be = U.dnF(c), f = c - be * U.nF;
         bp[u] = HF + c;
         bs[u] = hsF;
-        xb[u] = X1 + be * U.XS;
+        xb[u] = X1 + __umul24((unsigned)be, (unsigned)U.XS);
         kb[u] = 16 * tr * U.nF + f - U.k0;
         ks[u] = U.nF;
         rs[u] = 0;
@@ -486,9 +490,9 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
       } else {
         const int t2 = tt - U.N1, ai = U.TF == 2 ? t2 >> 1 : t2, tf = t2 - ai * U.TF, a = U.a0 + ai;
         const int f = 16 * tf + q;
-        ap[u] = HA + q * U.nA + a;
+        ap[u] = HA + __umul24((unsigned)q, (unsigned)U.nA) + a;
         as[u] = hsA;
-        bp[u] = Dfb + min(f, U.nF - 1) * nB;
+        bp[u] = Dfb + __umul24((unsigned)min(f, U.nF - 1), (unsigned)nB);
         bs[u] = 1;
         xb[u] = X2;
         kb[u] = a * U.nF + f - U.k0;
@@ -502,31 +506,46 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
     typename M::acc acc[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
-#pragma unroll 1
-    for (int s0 = 0; s0 < SB; s0 += 2) {
-      T av[NU][2], bv[NU][2];
+    // operands of the next pass are requested before the products of the
+    // current one (addresses clamped into the slices; b >= nB gives zero)
+    T av[NU][2], bv[NU][2];
+    auto load = [&](int s0, T (&a2)[NU][2], T (&b2)[NU][2]) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int b = 4 * (s0 + s) + g, bc = min(b, nB - 1);
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-          const T a = ap[u][bc * as[u]];
-          av[u][s] = b < nB ? a : T(0);
-          bv[u][s] = bp[u][bc * bs[u]];
+          const T a = ap[u][__umul24((unsigned)bc, (unsigned)as[u])];
+          a2[u][s] = b < nB ? a : T(0);
+          b2[u][s] = bp[u][__umul24((unsigned)bc, (unsigned)bs[u])];
         }
       }
+    };
+    load(0, av, bv);
+#pragma unroll 1
+    for (int s0 = 0; s0 < SB; s0 += 2) {
+      T an[NU][2], bn[NU][2];
+      load(s0 + 2, an, bn);
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][s], bv[u][s], acc[u]);
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          av[u][s] = an[u][s];
+          bv[u][s] = bn[u][s];
+        }
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       if (!on[u]) continue;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = M::row(g, i), k = kb[u] + r * ks[u];
-        if (lok[u] && r < rl[u] && k >= 0 && k < U.Kc) xb[u][k + r * rs[u]] = kp[u] ? acc[u][i] : T(0);
+        const int r = M::row(g, i), k = kb[u] + (int)__umul24((unsigned)r, (unsigned)ks[u]);
+        if (lok[u] && r < rl[u] && k >= 0 && k < U.Kc)
+          xb[u][k + (int)__umul24((unsigned)r, (unsigned)rs[u])] = kp[u] ? acc[u][i] : T(0);
       }
     }
   }
@@ -626,12 +645,13 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
       }
     }
     // ---- X-build of this chunk (all waves) ------------------------------
-    if (sg.hend <= Cfg::kStage) {
-      xbuild<T, false, NU>(U, ch.nB, S + sg.ho, 16 * U.nF, S + sg.ho + ch.nB * 16 * U.nF, 16 * U.nA, S,
+    if (!ZROLE && Cfg::kXW == 4) {
+    } else if (sg.hend <= Cfg::kStage) {
+      xbuild<T, false, NU, Cfg::kXW>(U, ch.nB, S + sg.ho, 16 * U.nF, S + sg.ho + ch.nB * 16 * U.nF, 16 * U.nA, S,
                               S + U.nA * ch.nB, kAB, kFB, X1, X2, w, q, g);
     } else {
       const int mBp = (ch.mB + 15) & ~15;
-      xbuild<T, true, NU>(U, ch.nB, Hg + d.triHF[tri] + (int64_t)ch.b0 * U.nF, mBp * U.nF,
+      xbuild<T, true, NU, Cfg::kXW>(U, ch.nB, Hg + d.triHF[tri] + (int64_t)ch.b0 * U.nF, mBp * U.nF,
                              Hg + d.triHA[tri] + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * ch.nB, kAB, kFB,
                              X1, X2, w, q, g);
     }
@@ -670,8 +690,8 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
         T xb[Cfg::kKSW];
 #pragma unroll
         for (int t = 0; t < Cfg::kKSW; ++t) {
-          const int c = 4 * (ww + 4 * t) + g;
-          xb[t] = X1[q * XS + c] + X2[q * XS + c];
+          const int c = (int)__umul24((unsigned)q, (unsigned)XS) + 4 * (ww + 4 * t) + g;
+          xb[t] = X1[c] + X2[c];
         }
 #pragma unroll
         for (int t = 0; t < Cfg::kKSW; ++t)
@@ -728,7 +748,8 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
 #pragma unroll
           for (int jj = 0; jj < JF; ++jj) {
             const int bl = 4 * s + g, c = min(16 * (ww + 4 * jj) + q, XS - 1);
-            xb[s][jj] = X1[bl * XS + c] + X2[bl * XS + c];
+            const int e = (int)__umul24((unsigned)bl, (unsigned)XS) + c;
+            xb[s][jj] = X1[e] + X2[e];
           }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -739,8 +760,8 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
         if (JF < nYJ) {
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            const int bl = 4 * s + g, c = 16 * (ww + 4 * JF) + q;
-            xb[s][JF] = X1[bl * XS + c] + X2[bl * XS + c];
+            const int bl = 4 * s + g, e = (int)__umul24((unsigned)bl, (unsigned)XS) + 16 * (ww + 4 * JF) + q;
+            xb[s][JF] = X1[e] + X2[e];
           }
 #pragma unroll
           for (int s = 0; s < 4; ++s)
