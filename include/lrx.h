@@ -63,11 +63,17 @@ typedef enum {
                           reductions                                                          */
 } lrx_precision;
 
+/* lrx_options.flags (lrx_evaluate_batch only) */
+#define LRX_BATCH_EAGER 1     /* launch the kernels one by one instead of replaying the captured graph */
+#define LRX_BATCH_NO_TUNE 2   /* skip the launch-shape autotuner (one workgroup per work item)        */
+
 typedef struct {
   double theta;        /* S1 threshold; <= 0 disables S1                  */
   double theta_cs;     /* S2 threshold; <= 0 disables S2                  */
   int32_t precision;   /* lrx_precision                                    */
-  int32_t timing;      /* nonzero: time every stage with HIP events        */
+  int32_t timing;      /* nonzero: time every stage with HIP events (lrx_evaluate) */
+  int32_t flags;       /* LRX_BATCH_* bits; 0 for the defaults             */
+  int32_t reserved;    /* set to 0                                         */
 } lrx_options;
 
 /*
@@ -160,12 +166,30 @@ int lrx_get_stats(lrx_ctx* ctx, lrx_stats* out);
 int lrx_stage_times(lrx_ctx* ctx, float* ms, int32_t n);
 const char* lrx_stage_name(int32_t i);
 
-/* Evaluate several contexts (all on the same device) in one batched pass:
- * their work items run in the same kernel launches on the first context's
- * stream.  Results are written per context: E[i], F + 3*sum_{j<i} natom_j,
- * sigma + 9*i.  Options apply to all. */
+/* Evaluate several contexts (distinct, all on one device) in one batched
+ * pass on the first context's stream.  Per alpha-tile group (the work units
+ * of atoms with ceil(n_abf/16) = MT) one triple-product launch serves up to 4
+ * structures, their units interleaved as work items; the other kernels run
+ * per structure in the same sequence.  The first call for a given list of
+ * contexts and options builds a plan: one eager run, a timing of each
+ * group's launch shapes (one workgroup per item, or a persistent grid that
+ * pulls items through counters), then the capture of the whole kernel
+ * sequence in a HIP graph; later calls replay the graph (LRX_BATCH_EAGER
+ * launches kernel by kernel instead).  A plan is dropped when one of its
+ * contexts gets new tensors, a new structure or is destroyed.
+ * Results are written per context: E[i], F + 3*sum_{j<i} natom_j,
+ * sigma + 9*i (host buffers); every context's block gradients and masks are
+ * then available as after lrx_evaluate.  The contexts must not be used by
+ * another thread during the call. */
 int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts, double* E, double* F,
                        double* sigma);
+
+/* Launch shapes the autotuner chose for the last plan built with this
+ * context first: mode[MT] (0: one workgroup per item, 1: persistent grid)
+ * and ms[2*MT + m] the best time of shape m, for MT = 0..LRX_MAX_ALPHA_TILES
+ * (host buffers, either may be NULL).  Returns LRX_MAX_ALPHA_TILES + 1. */
+#define LRX_MAX_ALPHA_TILES 8
+int lrx_batch_tuning(const lrx_ctx* ctx, int32_t* mode, float* ms);
 
 /* Message of the last failing call on this context ("" if none). */
 const char* lrx_last_error(const lrx_ctx* ctx);

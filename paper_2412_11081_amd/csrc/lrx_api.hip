@@ -11,10 +11,13 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <exception>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <tuple>
@@ -83,6 +86,8 @@ Pairs group_pairs(int N, int64_t n, const int32_t* first, const int32_t* second,
   return P;
 }
 
+std::atomic<uint64_t> g_gen{1};
+
 // CSR of blocks by atom (first or second), in caller order.
 void by_atom(int N, int64_t n, const int32_t* atom, std::vector<int>& row, std::vector<int64_t>& list) {
   row.assign(N + 1, 0);
@@ -124,6 +129,13 @@ struct lrx_ctx {
   std::vector<void*> allocs;
   double dev_bytes = 0;
   Dev dev{};
+  uint64_t gen = 0;                       // changes whenever dev changes (batch plans key on it)
+  std::vector<int> unitOrderHost;         // units sorted by alpha-tile group
+  std::array<int, lrx::kMaxAlphaTiles + 2> mtStartHost{};
+  lrx::TripleLaunch tl{};                 // this structure alone
+  // autotuner result of the last batch plan built with this context first
+  std::array<int, lrx::kMaxAlphaTiles + 1> tune_mode{};
+  std::array<float, 2 * (lrx::kMaxAlphaTiles + 1)> tune_ms{};
   double* h_out = nullptr;
   std::array<hipEvent_t, LRX_NSTAGES + 1> ev{};
   std::array<hipStream_t, lrx::kSideStreams> side{};
@@ -159,6 +171,8 @@ struct lrx_ctx {
 };
 
 namespace {
+
+void drop_plans_of(const lrx_ctx* c);   // batch plans that use c (defined with the batch code)
 
 template <class F>
 int guarded(lrx_ctx* ctx, F&& f) {
@@ -230,6 +244,7 @@ int lrx_set_structure(lrx_ctx* c, int32_t natom, const double* tau, const double
                       const int32_t* nabf) {
   return guarded(c, [&] {
     require(natom > 0 && tau && lattice && nao && nabf, "lrx_set_structure: bad arguments");
+    drop_plans_of(c);
     c->free_tensors();
     c->have_structure = false;
     c->N = natom;
@@ -255,6 +270,7 @@ int lrx_set_structure(lrx_ctx* c, int32_t natom, const double* tau, const double
 int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const double* D, int32_t on_device) {
   return guarded(c, [&] {
     require(c->have_structure, "lrx_set_tensors before lrx_set_structure");
+    drop_plans_of(c);
     c->free_tensors();
     check_blocks(c, C, true, "C");
     check_blocks(c, V, false, "V");
@@ -554,6 +570,19 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       for (int m = 0; m <= lrx::kMaxAlphaTiles; ++m) d.mtStart[m + 1] += d.mtStart[m];
     }
     d.unitOrder = c->upload(unitOrder);
+    c->unitOrderHost = unitOrder;
+    for (int m = 0; m <= lrx::kMaxAlphaTiles + 1; ++m) c->mtStartHost[m] = d.mtStart[m];
+    {
+      std::vector<int2> items(d.nUnit);
+      for (int k = 0; k < d.nUnit; ++k) items[k] = make_int2(0, unitOrder[k]);
+      int2* it = c->upload(items);
+      c->tl = lrx::TripleLaunch{};
+      for (int mt = 1; mt <= lrx::kMaxAlphaTiles; ++mt) {
+        c->tl.items[mt] = it + d.mtStart[mt];
+        c->tl.n[mt] = d.mtStart[mt + 1] - d.mtStart[mt];
+      }
+      c->tl.counters = c->dalloc<int>(8 * (lrx::kMaxAlphaTiles + 1));
+    }
     d.slotRow = c->upload(slotRow);
     d.nHB = (int)hbB.size();
     d.hbB = c->upload(hbB);
@@ -618,34 +647,51 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       throw Fail{LRX_EINVAL, m};
     }
     c->have_tensors = true;
+    c->gen = g_gen++;
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checks shared by lrx_evaluate and lrx_evaluate_batch; allocates the FP32
+// buffers of a reduced-precision form on first use.
+void prepare(lrx_ctx* c, const lrx_options* opts) {
+  require(opts != nullptr, "opts: NULL");
+  require(c->have_tensors, "evaluation before lrx_set_tensors");
+  require(opts->precision == LRX_FP64 || opts->precision == LRX_FP32 || opts->precision == LRX_BF16X3,
+          "unknown precision");
+  require(std::isfinite(opts->theta) && std::isfinite(opts->theta_cs), "non-finite threshold");
+  if (opts->precision != LRX_FP64 && !c->have_f32) {
+    Dev& d = c->dev;
+    const int64_t nt = c->ao[c->N];
+    d.Cf32 = c->dalloc<float>(c->n_cf);
+    d.Vf32 = c->dalloc<float>(c->n_vf);
+    d.D32 = c->dalloc<float>(nt * nt);
+    d.H32 = c->dalloc<float>(c->n_h);
+    HIPCHK(hipMemsetAsync(d.H32, 0, sizeof(float) * std::max<int64_t>(1, c->n_h), c->stream));
+    d.Zbuf32 = c->dalloc<float>(c->n_z);
+    d.Ybuf32 = c->dalloc<float>(c->n_y);
+    c->have_f32 = true;
+    c->gen = g_gen++;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
 int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, double* sigma) {
   return guarded(c, [&] {
-    require(opts != nullptr, "opts: NULL");
-    require(c->have_tensors, "lrx_evaluate before lrx_set_tensors");
-    require(opts->precision == LRX_FP64 || opts->precision == LRX_FP32 || opts->precision == LRX_BF16X3,
-            "unknown precision");
-    require(std::isfinite(opts->theta) && std::isfinite(opts->theta_cs), "non-finite threshold");
-    if (opts->precision != LRX_FP64 && !c->have_f32) {
-      Dev& d = c->dev;
-      const int64_t nt = c->ao[c->N];
-      d.Cf32 = c->dalloc<float>(c->n_cf);
-      d.Vf32 = c->dalloc<float>(c->n_vf);
-      d.D32 = c->dalloc<float>(nt * nt);
-      d.H32 = c->dalloc<float>(c->n_h);
-      HIPCHK(hipMemsetAsync(d.H32, 0, sizeof(float) * std::max<int64_t>(1, c->n_h), c->stream));
-      d.Zbuf32 = c->dalloc<float>(c->n_z);
-      d.Ybuf32 = c->dalloc<float>(c->n_y);
-      c->have_f32 = true;
-    }
+    prepare(c, opts);
     const lrx::Opts o{opts->theta, opts->theta_cs, opts->precision};
     const bool timing = opts->timing != 0;
     hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
     if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
     lrx::launch_screen(c->dev, o, c->stream, ev);
-    lrx::launch_contract(c->dev, opts->precision, c->stream, c->side.data(), c->fork.data(), ev);
+    c->tl.devs.s[0] = c->dev;
+    lrx::launch_contract(c->dev, c->tl, opts->precision, c->stream, c->side.data(), c->fork.data(), ev);
     HIPCHK(hipGetLastError());
     const int N = c->N;
     HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost,
@@ -755,17 +801,265 @@ const char* lrx_stage_name(int32_t i) {
   return (i >= 0 && i < LRX_NSTAGES) ? names[i] : "";
 }
 
+}  // extern "C"
+
+namespace {
+
+// A batch of structures evaluated together: the screening, folding, H-build
+// and gradient kernels of every structure and, per alpha-tile group, one
+// triple launch per kBatchDevs structures whose work items interleave the
+// structures' units.  Built once per (contexts, options); the launch shape of
+// every group is picked by timing (autotuner), and the whole kernel sequence
+// is captured in a HIP graph that later calls replay.
+struct BatchPlan {
+  int device = 0;
+  std::vector<lrx_ctx*> ctxs;
+  std::vector<uint64_t> gens;
+  int prec = 0, flags = 0;
+  double theta = 0, theta_cs = 0;
+  std::vector<lrx::TripleLaunch> launches;
+  std::vector<void*> allocs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::array<int, lrx::kMaxAlphaTiles + 1> mode{};
+  std::array<float, 2 * (lrx::kMaxAlphaTiles + 1)> tune_ms{};
+
+  ~BatchPlan() {
+    (void)hipSetDevice(device);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  bool matches(lrx_ctx* const* c, int n, const lrx_options* o) const {
+    if ((int)ctxs.size() != n || prec != o->precision || theta != o->theta || theta_cs != o->theta_cs ||
+        (flags & LRX_BATCH_NO_TUNE) != (o->flags & LRX_BATCH_NO_TUNE))
+      return false;
+    for (int i = 0; i < n; ++i)
+      if (ctxs[i] != c[i] || gens[i] != c[i]->gen) return false;
+    return true;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<size_t>(1, v.size() * sizeof(T))));
+    allocs.push_back(p);
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return (T*)p;
+  }
+};
+
+std::mutex g_plan_mu;
+std::vector<std::shared_ptr<BatchPlan>> g_plans;   // most recently used last
+constexpr size_t kMaxPlans = 8;
+
+void drop_plans_of(const lrx_ctx* c) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans.erase(std::remove_if(g_plans.begin(), g_plans.end(),
+                               [&](const std::shared_ptr<BatchPlan>& p) {
+                                 return std::find(p->ctxs.begin(), p->ctxs.end(), c) != p->ctxs.end();
+                               }),
+                g_plans.end());
+}
+
+// Alpha-tile groups of a plan, largest first.
+std::vector<int> group_order(const BatchPlan& P) {
+  std::vector<int> order;
+  std::array<long, lrx::kMaxAlphaTiles + 1> tot{};
+  for (const auto& L : P.launches)
+    for (int mt = 1; mt <= lrx::kMaxAlphaTiles; ++mt) tot[mt] += L.n[mt];
+  for (int mt = 1; mt <= lrx::kMaxAlphaTiles; ++mt)
+    if (tot[mt] > 0) order.push_back(mt);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return tot[a] > tot[b]; });
+  return order;
+}
+
+// Every kernel of one batched evaluation, on stream s (side streams carry the
+// smaller alpha-tile groups and join back before the gradients).
+void run_batch(const BatchPlan& P, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork) {
+  const lrx::Opts o{P.theta, P.theta_cs, P.prec};
+  for (lrx_ctx* c : P.ctxs) lrx::launch_screen(c->dev, o, s, nullptr);
+  for (lrx_ctx* c : P.ctxs) lrx::launch_hbuild(c->dev, P.prec, s);
+  const std::vector<int> order = group_order(P);
+  (void)hipEventRecord(fork[0], s);
+  for (size_t i = 0; i < order.size(); ++i) {
+    const hipStream_t st = i == 0 ? s : side[(i - 1) % lrx::kSideStreams];
+    if (i > 0 && i <= (size_t)lrx::kSideStreams) (void)hipStreamWaitEvent(st, fork[0], 0);
+    for (const auto& L : P.launches) lrx::launch_triple_group(L, order[i], P.prec, st);
+  }
+  for (size_t i = 1; i <= (size_t)lrx::kSideStreams && i < order.size(); ++i) {
+    (void)hipEventRecord(fork[i], side[i - 1]);
+    (void)hipStreamWaitEvent(s, fork[i], 0);
+  }
+  for (lrx_ctx* c : P.ctxs) lrx::launch_grads(c->dev, P.prec, s, nullptr);
+}
+
+std::shared_ptr<BatchPlan> build_plan(lrx_ctx* const* ctxs, int n, const lrx_options* opts) {
+  lrx_ctx* c0 = ctxs[0];
+  auto P = std::make_shared<BatchPlan>();
+  P->device = c0->device;
+  P->ctxs.assign(ctxs, ctxs + n);
+  for (int i = 0; i < n; ++i) P->gens.push_back(ctxs[i]->gen);
+  P->prec = opts->precision;
+  P->flags = opts->flags;
+  P->theta = opts->theta;
+  P->theta_cs = opts->theta_cs;
+  for (int g0 = 0; g0 < n; g0 += lrx::kBatchDevs) {
+    lrx::TripleLaunch L{};
+    const int ng = std::min(lrx::kBatchDevs, n - g0);
+    for (int j = 0; j < ng; ++j) L.devs.s[j] = ctxs[g0 + j]->dev;
+    std::vector<int2> items;
+    std::array<int, lrx::kMaxAlphaTiles + 2> start{};
+    for (int mt = 1; mt <= lrx::kMaxAlphaTiles; ++mt) {
+      start[mt] = (int)items.size();
+      // the structures' units of this group, interleaved in blocks so each
+      // structure's neighbouring units still land on the same XCD
+      std::vector<size_t> pos(ng, 0);
+      bool more = true;
+      while (more) {
+        more = false;
+        for (int j = 0; j < ng; ++j) {
+          const lrx_ctx* c = ctxs[g0 + j];
+          const int a = c->mtStartHost[mt], b = c->mtStartHost[mt + 1];
+          for (int k = 0; k < 64 && a + (int)pos[j] < b; ++k, ++pos[j])
+            items.push_back(make_int2(j, c->unitOrderHost[a + pos[j]]));
+          if (a + (int)pos[j] < b) more = true;
+        }
+      }
+      start[mt + 1] = (int)items.size();
+    }
+    int2* it = P->upload(items, c0->stream);
+    for (int mt = 1; mt <= lrx::kMaxAlphaTiles; ++mt) {
+      L.items[mt] = it + start[mt];
+      L.n[mt] = start[mt + 1] - start[mt];
+    }
+    L.counters = P->upload(std::vector<int>(8 * (lrx::kMaxAlphaTiles + 1), 0), c0->stream);
+    P->launches.push_back(L);
+  }
+  hipStream_t s = c0->stream;
+  // warm-up run: fills every intermediate buffer and sets kernel attributes
+  run_batch(*P, s, c0->side.data(), c0->fork.data());
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  if (!(opts->flags & LRX_BATCH_NO_TUNE)) {
+    // autotuner: per alpha-tile group, one workgroup per item (mode 0) or a
+    // persistent grid (mode 1), best of two timed launches of the group alone
+    // (the triple kernels only overwrite their own partial sums, so repeating
+    // them is harmless)
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int mt : group_order(*P)) {
+      float best[2] = {1e30f, 1e30f};
+      for (int mode = 0; mode < 2; ++mode) {
+        for (auto& L : P->launches) L.mode[mt] = mode;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIPCHK(hipEventRecord(e0, s));
+          for (const auto& L : P->launches) lrx::launch_triple_group(L, mt, P->prec, s);
+          HIPCHK(hipEventRecord(e1, s));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          best[mode] = std::min(best[mode], ms);
+        }
+      }
+      P->mode[mt] = best[1] < best[0] ? 1 : 0;
+      P->tune_ms[2 * mt] = best[0];
+      P->tune_ms[2 * mt + 1] = best[1];
+      for (auto& L : P->launches) L.mode[mt] = P->mode[mt];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  c0->tune_mode = P->mode;
+  c0->tune_ms = P->tune_ms;
+  // capture the whole sequence; replays launch it as one graph
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  run_batch(*P, s, c0->side.data(), c0->fork.data());
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(s, &g);
+  HIPCHK(ce);
+  P->graph = g;
+  HIPCHK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+  return P;
+}
+
+}  // namespace
+
+extern "C" {
+
 int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts, double* E, double* F,
                        double* sigma) {
-  if (!ctxs || n <= 0) return LRX_EINVAL;
-  ctxs[0]->err = "batched evaluation not available in this build";
-  return LRX_ESTATE;
+  if (!ctxs || n <= 0 || !ctxs[0]) return LRX_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return LRX_EINVAL;
+  lrx_ctx* c0 = ctxs[0];
+  return guarded(c0, [&] {
+    for (int i = 0; i < n; ++i) {
+      require(ctxs[i]->device == c0->device, "batch: contexts on different devices");
+      for (int j = 0; j < i; ++j) require(ctxs[i] != ctxs[j], "batch: a context appears twice");
+      prepare(ctxs[i], opts);
+    }
+    for (int i = 0; i < n; ++i)
+      if (ctxs[i]->stream != c0->stream) HIPCHK(hipStreamSynchronize(ctxs[i]->stream));
+    std::shared_ptr<BatchPlan> P;
+    {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      for (size_t k = 0; k < g_plans.size(); ++k)
+        if (g_plans[k]->matches(ctxs, n, opts)) {
+          P = g_plans[k];
+          g_plans.erase(g_plans.begin() + k);
+          g_plans.push_back(P);
+          break;
+        }
+    }
+    hipStream_t s = c0->stream;
+    if (!P) {
+      P = build_plan(ctxs, n, opts);
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      g_plans.push_back(P);
+      if (g_plans.size() > kMaxPlans) g_plans.erase(g_plans.begin());
+    }
+    if (opts->flags & LRX_BATCH_EAGER)
+      run_batch(*P, s, c0->side.data(), c0->fork.data());
+    else
+      HIPCHK(hipGraphLaunch(P->exec, s));
+    HIPCHK(hipGetLastError());
+    for (int i = 0; i < n; ++i) {
+      lrx_ctx* c = ctxs[i];
+      HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * c->N + 9 + 1), hipMemcpyDeviceToHost,
+                            s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t fo = 0;
+    for (int i = 0; i < n; ++i) {
+      lrx_ctx* c = ctxs[i];
+      c->evaluated = true;
+      c->timed = false;
+      if (E) E[i] = c->h_out[0];
+      if (F) std::memcpy(F + fo, c->h_out + 1, sizeof(double) * 3 * c->N);
+      if (sigma) std::memcpy(sigma + 9 * i, c->h_out + 1 + 3 * c->N, sizeof(double) * 9);
+      fo += 3 * c->N;
+    }
+  });
+}
+
+int lrx_batch_tuning(const lrx_ctx* c, int32_t* mode, float* ms) {
+  if (!c) return LRX_EINVAL;
+  for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) {
+    if (mode) mode[mt] = c->tune_mode[mt];
+    if (ms) {
+      ms[2 * mt] = c->tune_ms[2 * mt];
+      ms[2 * mt + 1] = c->tune_ms[2 * mt + 1];
+    }
+  }
+  return lrx::kMaxAlphaTiles + 1;
 }
 
 const char* lrx_last_error(const lrx_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
 
 void lrx_destroy(lrx_ctx* c) {
   if (!c) return;
+  drop_plans_of(c);
   (void)hipSetDevice(c->device);
   c->free_tensors();
   if (c->h_out) (void)hipHostFree(c->h_out);

@@ -256,12 +256,12 @@ struct TripleCfg {
   static constexpr int kXW = 8;                                              // waves taking part
   static constexpr int kNUZ = 2;                                             // tiles in flight: Z waves
   static constexpr int kNUY = (P == kP64 && MT >= 5) ? 1 : 2;                 // Y waves
-  static constexpr int kLds = 163840;
+  static constexpr int kLds = 163840 - 256;     // the last 256 bytes hold the persistent item slot
   static constexpr int kE = 16 / sizeof(T);
   static constexpr int kStage =
       (kLds - (int)sizeof(T) * 2 * 16 * kXS - (int)sizeof(A) * 3 * MT * 256) / (int)sizeof(T) / kE * kE;
   static_assert(2 * kMaxNao * kMaxNao + 16 * 16 * MT + kE <= kStage, "stage holds D and V of any chunk");
-  static constexpr size_t lds_bytes() { return kLds; }
+  static constexpr size_t lds_bytes() { return kLds + 256; }
 };
 
 constexpr int kTNT = 512;
@@ -793,12 +793,11 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
   }
 }
 
+// One work unit of structure d: geometry, X cleared, then the two roles.
 template <int MT, int P>
-__global__ void __launch_bounds__(kTNT, 1) k_triple(Dev d, const int* __restrict__ ulist) {
+__device__ __forceinline__ void triple_unit(const Dev& d, int u, unsigned char* ldsb) {
   using Cfg = TripleCfg<MT, P>;
   using T = typename Cfg::T;
-  extern __shared__ __attribute__((aligned(32))) unsigned char ldsb[];
-  const int u = ulist[xcd_remap(blockIdx.x, gridDim.x)];
   UnitGeo U;
   U.cp = d.unitCp[u];
   if (!d.aliveC[U.cp]) return;
@@ -840,6 +839,38 @@ __global__ void __launch_bounds__(kTNT, 1) k_triple(Dev d, const int* __restrict
     triple_role<MT, P, true>(d, U, ldsb, w, lane, q, g);
   else
     triple_role<MT, P, false>(d, U, ldsb, w, lane, q, g);
+}
+
+// items[i] = (structure index into devs, unit index of that structure).
+// PERSIST = false: one workgroup per item.  PERSIST = true: kPersistentGrid
+// workgroups; workgroup b first drains segment (b mod 8) of the item list,
+// then the other seven, taking items through one counter per segment (the
+// counters start at zero).  Every workgroup leaves once all eight segments
+// report exhausted.
+template <int MT, int P, bool PERSIST>
+__global__ void __launch_bounds__(kTNT, 1)
+    k_triple(DevBatch devs, const int2* __restrict__ items, int n, int* __restrict__ counters) {
+  extern __shared__ __attribute__((aligned(32))) unsigned char ldsb[];
+  if constexpr (!PERSIST) {
+    const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    triple_unit<MT, P>(devs.s[it.x], it.y, ldsb);
+  } else {
+    int& s_next = *(int*)(ldsb + TripleCfg<MT, P>::kLds);
+    const int q = (n + 7) >> 3;
+    for (int k = 0; k < 8; ++k) {
+      const int seg = (blockIdx.x + k) & 7;
+      const int s0 = seg * q, s1 = min(n, s0 + q);
+      for (;;) {
+        if (threadIdx.x == 0) s_next = s0 + atomicAdd(&counters[seg], 1);
+        __syncthreads();
+        const int i = s_next;
+        __syncthreads();
+        if (i >= s1) break;
+        const int2 it = items[i];
+        triple_unit<MT, P>(devs.s[it.x], it.y, ldsb);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,48 +1061,75 @@ __global__ void __launch_bounds__(kFinalNT) k_final(Dev d) {
 
 static inline unsigned grid1(int64_t n, int64_t b) { return (unsigned)(n > 0 ? (n + b - 1) / b : 1); }
 
+__global__ void k_fill_i32(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 template <int MT, int P>
-static void launch_triple(const Dev& d, hipStream_t s) {
-  const int n = d.mtStart[MT + 1] - d.mtStart[MT];
+static void launch_triple(const TripleLaunch& tl, hipStream_t s) {
+  const int n = tl.n[MT];
   if (n <= 0) return;
   const size_t lds = TripleCfg<MT, P>::lds_bytes();
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_triple<MT, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_triple<MT, P, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_triple<MT, P, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_triple<MT, P>), dim3(n), dim3(kTNT), lds, s, d, d.unitOrder + d.mtStart[MT]);
-}
-
-template <int P>
-static void launch_triple_mt(const Dev& d, int mt, hipStream_t st) {
-  switch (mt) {
-    case 1: launch_triple<1, P>(d, st); break;
-    case 2: launch_triple<2, P>(d, st); break;
-    case 3: launch_triple<3, P>(d, st); break;
-    case 4: launch_triple<4, P>(d, st); break;
-    case 5: launch_triple<5, P>(d, st); break;
-    case 6: launch_triple<6, P>(d, st); break;
-    case 7: launch_triple<7, P>(d, st); break;
-    default: launch_triple<8, P>(d, st); break;
+  if (tl.mode[MT] == 1) {
+    int* cnt = tl.counters + 8 * MT;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, cnt, 8, 0);
+    hipLaunchKernelGGL((k_triple<MT, P, true>), dim3(kPersistentGrid), dim3(kTNT), lds, s, tl.devs, tl.items[MT], n,
+                       cnt);
+  } else {
+    hipLaunchKernelGGL((k_triple<MT, P, false>), dim3(n), dim3(kTNT), lds, s, tl.devs, tl.items[MT], n,
+                       (int*)nullptr);
   }
 }
 
 template <int P>
-static void launch_contract_p(const Dev& d, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork,
-                              hipEvent_t* ev) {
-  using T = typename std::conditional<P == kP64, double, float>::type;
-  if (d.nHB) hipLaunchKernelGGL(k_hbuild<T>, dim3(d.nHB), dim3(kNT), 0, s, d);
-  if (ev) (void)hipEventRecord(ev[4], s);
+static void launch_triple_mt(const TripleLaunch& tl, int mt, hipStream_t st) {
+  switch (mt) {
+    case 1: launch_triple<1, P>(tl, st); break;
+    case 2: launch_triple<2, P>(tl, st); break;
+    case 3: launch_triple<3, P>(tl, st); break;
+    case 4: launch_triple<4, P>(tl, st); break;
+    case 5: launch_triple<5, P>(tl, st); break;
+    case 6: launch_triple<6, P>(tl, st); break;
+    case 7: launch_triple<7, P>(tl, st); break;
+    default: launch_triple<8, P>(tl, st); break;
+  }
+}
+
+void launch_triple_group(const TripleLaunch& tl, int mt, int prec, hipStream_t s) {
+  if (prec == kP64)
+    launch_triple_mt<kP64>(tl, mt, s);
+  else if (prec == kP32)
+    launch_triple_mt<kP32>(tl, mt, s);
+  else
+    launch_triple_mt<kPB3>(tl, mt, s);
+}
+
+void launch_hbuild(const Dev& d, int prec, hipStream_t s) {
+  if (!d.nHB) return;
+  if (prec == kP64)
+    hipLaunchKernelGGL(k_hbuild<double>, dim3(d.nHB), dim3(kNT), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_hbuild<float>, dim3(d.nHB), dim3(kNT), 0, s, d);
+}
+
+void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork) {
   // The alpha-tile groups are independent: the largest runs on the main
-  // stream, the others on side streams that join before the gradients.
+  // stream, the others on side streams that join back before the gradients.
   int order[kMaxAlphaTiles];
   int ng = 0;
   for (int mt = 1; mt <= kMaxAlphaTiles; ++mt)
-    if (d.mtStart[mt + 1] > d.mtStart[mt]) order[ng++] = mt;
+    if (tl.n[mt] > 0) order[ng++] = mt;
   for (int i = 1; i < ng; ++i)
-    for (int j = i; j > 0 && d.mtStart[order[j] + 1] - d.mtStart[order[j]] >
-                                 d.mtStart[order[j - 1] + 1] - d.mtStart[order[j - 1]]; --j) {
+    for (int j = i; j > 0 && tl.n[order[j]] > tl.n[order[j - 1]]; --j) {
       const int t = order[j];
       order[j] = order[j - 1];
       order[j - 1] = t;
@@ -1080,13 +1138,16 @@ static void launch_contract_p(const Dev& d, hipStream_t s, const hipStream_t* si
   for (int i = 0; i < ng; ++i) {
     const hipStream_t st = i == 0 ? s : side[(i - 1) % kSideStreams];
     if (i > 0 && i <= kSideStreams) (void)hipStreamWaitEvent(st, fork[0], 0);
-    launch_triple_mt<P>(d, order[i], st);
+    launch_triple_group(tl, order[i], prec, st);
   }
   for (int i = 1; i <= kSideStreams && i < ng; ++i) {
     (void)hipEventRecord(fork[i], side[i - 1]);
     (void)hipStreamWaitEvent(s, fork[i], 0);
   }
-  if (ev) (void)hipEventRecord(ev[5], s);
+}
+
+template <class T>
+static void launch_grads_t(const Dev& d, hipStream_t s, hipEvent_t* ev) {
   if (d.nVp) hipLaunchKernelGGL(k_zgrad<T>, dim3(d.nVp), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[6], s);
   if (d.nCp) hipLaunchKernelGGL(k_cgrad<T>, dim3(d.nCp), dim3(kNT), 0, s, d);
@@ -1096,14 +1157,20 @@ static void launch_contract_p(const Dev& d, hipStream_t s, const hipStream_t* si
   if (ev) (void)hipEventRecord(ev[8], s);
 }
 
-void launch_contract(const Dev& d, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork,
-                     hipEvent_t* ev) {
+void launch_grads(const Dev& d, int prec, hipStream_t s, hipEvent_t* ev) {
   if (prec == kP64)
-    launch_contract_p<kP64>(d, s, side, fork, ev);
-  else if (prec == kP32)
-    launch_contract_p<kP32>(d, s, side, fork, ev);
+    launch_grads_t<double>(d, s, ev);
   else
-    launch_contract_p<kPB3>(d, s, side, fork, ev);
+    launch_grads_t<float>(d, s, ev);
+}
+
+void launch_contract(const Dev& d, const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side,
+                     const hipEvent_t* fork, hipEvent_t* ev) {
+  launch_hbuild(d, prec, s);
+  if (ev) (void)hipEventRecord(ev[4], s);
+  launch_triples(tl, prec, s, side, fork);
+  if (ev) (void)hipEventRecord(ev[5], s);
+  launch_grads(d, prec, s, ev);
 }
 
 }  // namespace lrx

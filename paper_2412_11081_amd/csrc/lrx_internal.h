@@ -7,7 +7,8 @@
 //            (A,F) and a "V pair" (A,B), each with the sorted list of its
 //            image blocks (R lexicographic);
 //   folded   Cf(A,F) = sum of kept C images [mA][nA][nF];
-//            Vf(A,B) = sum of kept V images [mA][mB]  (Gamma point: the density
+//            Vf(A,B) = sum of kept V images [mA][mB rounded up to 16, zero
+//            padding]  (Gamma point: the density
 //            matrix is the same for every image pair, so the images of a pair
 //            meet the same D blocks and can be summed first);
 //   H        H(B,X)[b][beta][x] = sum_G Cf(B,G)[beta][b][g] D(G,X)[g][x] for
@@ -140,8 +141,38 @@ struct Opts {
 void launch_validate(const Dev& d, hipStream_t s);
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev);
 // kernels (lrx_contract.hip)
-void launch_contract(const Dev& d, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork,
-                     hipEvent_t* ev);
+
+// Work of the triple-product kernels: per alpha-tile group MT, a list of
+// (structure, unit) items over an array of structures on the device.  One
+// structure for lrx_evaluate; several for lrx_evaluate_batch.
+// mode 0: one workgroup per item (block order remapped for XCD locality);
+// mode 1: a persistent grid of one workgroup per CU pulling items from eight
+//         per-XCD segments (then from the other segments) through counters.
+// Up to kBatchDevs structures travel by value in the kernel arguments of
+// one triple launch (kernel arguments are limited to 4 KiB).
+constexpr int kBatchDevs = 4;
+struct DevBatch {
+  Dev s[kBatchDevs];
+};
+struct TripleLaunch {
+  DevBatch devs;                             // the structures of the launch
+  int* counters = nullptr;                   // device, 8 per group (mode 1)
+  const int2* items[kMaxAlphaTiles + 1] = {};
+  int n[kMaxAlphaTiles + 1] = {};
+  int mode[kMaxAlphaTiles + 1] = {};
+};
+constexpr int kPersistentGrid = 256;         // workgroups of a mode-1 launch (one per CU)
+
+void launch_hbuild(const Dev& d, int prec, hipStream_t s);
+// triple groups of tl: the largest on s, the others on the side streams, joined back into s
+void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork);
+// one group on s (the tuner times groups one at a time)
+void launch_triple_group(const TripleLaunch& tl, int mt, int prec, hipStream_t s);
+void launch_grads(const Dev& d, int prec, hipStream_t s, hipEvent_t* ev);
+// the whole contraction of one structure: hbuild, triples, gradients, forces;
+// ev (optional) receives stage marks ev[4..8]
+void launch_contract(const Dev& d, const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side,
+                     const hipEvent_t* fork, hipEvent_t* ev);
 void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipStream_t s);
 
 }  // namespace lrx

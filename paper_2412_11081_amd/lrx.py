@@ -34,9 +34,15 @@ class LrxError(RuntimeError):
         self.code = code
 
 
+BATCH_EAGER = 1
+BATCH_NO_TUNE = 2
+MAX_ALPHA_TILES = 8
+
+
 class Options(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("theta_cs", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Blocks(ctypes.Structure):
@@ -59,7 +65,7 @@ _lib = None
 
 EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
-           "lrx_last_error", "lrx_destroy"]
+           "lrx_batch_tuning", "lrx_last_error", "lrx_destroy"]
 
 
 def load(path: Optional[str] = None):
@@ -83,12 +89,13 @@ def load(path: Optional[str] = None):
     lib.lrx_stage_name.argtypes = [ctypes.c_int32]
     lib.lrx_stage_name.restype = ctypes.c_char_p
     lib.lrx_evaluate_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Options), _f64p, _f64p, _f64p]
+    lib.lrx_batch_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
     lib.lrx_last_error.argtypes = [vp]
     lib.lrx_last_error.restype = ctypes.c_char_p
     lib.lrx_destroy.argtypes = [vp]
     lib.lrx_destroy.restype = None
     for f in ("lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
-              "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch"):
+              "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -166,7 +173,7 @@ class Context:
         self.nC, self.nV = int(bc.nblk), int(bv.nblk)
 
     def evaluate(self, theta=0.0, theta_cs=0.0, precision="fp64", timing=False):
-        o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), int(bool(timing)))
+        o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), int(bool(timing)), 0, 0)
         E = ctypes.c_double()
         F = np.zeros((self.natom, 3))
         S = np.zeros((3, 3))
@@ -215,3 +222,36 @@ def context_for(structure, mats, device: int = 0, stream=None) -> Context:
     ctx.set_structure(structure.tau, structure.lat, structure.nao, structure.nabf)
     ctx.set_tensors(mats["C"], mats["V"], mats["D"])
     return ctx
+
+
+def evaluate_batch(contexts, theta=0.0, theta_cs=0.0, precision="fp64", eager=False, tune=True):
+    """lrx_evaluate_batch over ``contexts`` (distinct, one device): returns
+    lists of E, F [natom][3] and sigma [3][3], one entry per context."""
+    if not contexts:
+        return [], [], []
+    lib = contexts[0].lib
+    n = len(contexts)
+    handles = (ctypes.c_void_p * n)(*[c.h.value for c in contexts])
+    flags = (BATCH_EAGER if eager else 0) | (0 if tune else BATCH_NO_TUNE)
+    o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), 0, flags, 0)
+    E = np.zeros(n)
+    nat = [c.natom for c in contexts]
+    F = np.zeros((sum(nat), 3))
+    S = np.zeros((n, 3, 3))
+    contexts[0]._check(lib.lrx_evaluate_batch(handles, n, ctypes.byref(o), _ptr(E, _f64p), _ptr(F, _f64p),
+                                              _ptr(S, _f64p)))
+    out_f, k = [], 0
+    for a in nat:
+        out_f.append(F[k:k + a].copy())
+        k += a
+    return list(E), out_f, [S[i].copy() for i in range(n)]
+
+
+def batch_tuning(context):
+    """Launch shapes chosen by the autotuner of the last plan built with
+    ``context`` first: {MT: (mode, ms_mode0, ms_mode1)} for the tuned groups."""
+    mode = (ctypes.c_int32 * (MAX_ALPHA_TILES + 1))()
+    ms = (ctypes.c_float * (2 * (MAX_ALPHA_TILES + 1)))()
+    context.lib.lrx_batch_tuning(context.h, mode, ms)
+    return {mt: (int(mode[mt]), float(ms[2 * mt]), float(ms[2 * mt + 1]))
+            for mt in range(1, MAX_ALPHA_TILES + 1) if ms[2 * mt] > 0}
