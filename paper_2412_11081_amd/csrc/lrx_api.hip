@@ -682,32 +682,6 @@ void prepare(lrx_ctx* c, const lrx_options* opts) {
 
 extern "C" {
 
-int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, double* sigma) {
-  return guarded(c, [&] {
-    prepare(c, opts);
-    const lrx::Opts o{opts->theta, opts->theta_cs, opts->precision};
-    const bool timing = opts->timing != 0;
-    hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
-    if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
-    lrx::launch_screen(c->dev, o, c->stream, ev);
-    c->tl.devs.s[0] = c->dev;
-    lrx::launch_contract(c->dev, c->tl, opts->precision, c->stream, c->side.data(), c->fork.data(), ev);
-    HIPCHK(hipGetLastError());
-    const int N = c->N;
-    HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost,
-                          c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (timing) {
-      for (int i = 0; i < LRX_NSTAGES; ++i) HIPCHK(hipEventElapsedTime(&c->stage_ms[i], c->ev[i], c->ev[i + 1]));
-      c->timed = true;
-    }
-    c->evaluated = true;
-    if (E) *E = c->h_out[0];
-    if (F) std::memcpy(F, c->h_out + 1, sizeof(double) * 3 * N);
-    if (sigma) std::memcpy(sigma, c->h_out + 1 + 3 * N, sizeof(double) * 9);
-  });
-}
-
 int lrx_block_gradients(lrx_ctx* c, double* gC, double* gV) {
   return guarded(c, [&] {
     require(c->evaluated, "no evaluation yet");
@@ -972,7 +946,9 @@ std::shared_ptr<BatchPlan> build_plan(lrx_ctx* const* ctxs, int n, const lrx_opt
   }
   c0->tune_mode = P->mode;
   c0->tune_ms = P->tune_ms;
-  // capture the whole sequence; replays launch it as one graph
+  // capture the whole sequence; replays launch it as one graph (the legacy
+  // default stream cannot be captured: such contexts run eagerly)
+  if (s == nullptr) return P;
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   run_batch(*P, s, c0->side.data(), c0->fork.data());
   hipGraph_t g = nullptr;
@@ -983,9 +959,63 @@ std::shared_ptr<BatchPlan> build_plan(lrx_ctx* const* ctxs, int n, const lrx_opt
   return P;
 }
 
+// The plan of (contexts, options): from the cache, or built (and cached).
+std::shared_ptr<BatchPlan> get_plan(lrx_ctx* const* ctxs, int n, const lrx_options* opts) {
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (size_t k = 0; k < g_plans.size(); ++k)
+      if (g_plans[k]->matches(ctxs, n, opts)) {
+        std::shared_ptr<BatchPlan> P = g_plans[k];
+        g_plans.erase(g_plans.begin() + k);
+        g_plans.push_back(P);
+        return P;
+      }
+  }
+  std::shared_ptr<BatchPlan> P = build_plan(ctxs, n, opts);
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans.push_back(P);
+  if (g_plans.size() > kMaxPlans) g_plans.erase(g_plans.begin());
+  return P;
+}
+
 }  // namespace
 
 extern "C" {
+
+int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, double* sigma) {
+  return guarded(c, [&] {
+    prepare(c, opts);
+    lrx_ctx* one[1] = {c};
+    // launch shapes from the autotuner; the captured graph unless stage
+    // times are requested
+    std::shared_ptr<BatchPlan> P = get_plan(one, 1, opts);
+    const bool timing = opts->timing != 0;
+    if (timing || !P->exec) {
+      const lrx::Opts o{opts->theta, opts->theta_cs, opts->precision};
+      hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
+      if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
+      lrx::launch_screen(c->dev, o, c->stream, ev);
+      c->tl.devs.s[0] = c->dev;
+      for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) c->tl.mode[mt] = P->mode[mt];
+      lrx::launch_contract(c->dev, c->tl, opts->precision, c->stream, c->side.data(), c->fork.data(), ev);
+    } else {
+      HIPCHK(hipGraphLaunch(P->exec, c->stream));
+    }
+    HIPCHK(hipGetLastError());
+    const int N = c->N;
+    HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (timing) {
+      for (int i = 0; i < LRX_NSTAGES; ++i) HIPCHK(hipEventElapsedTime(&c->stage_ms[i], c->ev[i], c->ev[i + 1]));
+    }
+    c->timed = timing;
+    c->evaluated = true;
+    if (E) *E = c->h_out[0];
+    if (F) std::memcpy(F, c->h_out + 1, sizeof(double) * 3 * N);
+    if (sigma) std::memcpy(sigma, c->h_out + 1 + 3 * N, sizeof(double) * 9);
+  });
+}
 
 int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts, double* E, double* F,
                        double* sigma) {
@@ -1001,25 +1031,9 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
     }
     for (int i = 0; i < n; ++i)
       if (ctxs[i]->stream != c0->stream) HIPCHK(hipStreamSynchronize(ctxs[i]->stream));
-    std::shared_ptr<BatchPlan> P;
-    {
-      std::lock_guard<std::mutex> lk(g_plan_mu);
-      for (size_t k = 0; k < g_plans.size(); ++k)
-        if (g_plans[k]->matches(ctxs, n, opts)) {
-          P = g_plans[k];
-          g_plans.erase(g_plans.begin() + k);
-          g_plans.push_back(P);
-          break;
-        }
-    }
+    std::shared_ptr<BatchPlan> P = get_plan(ctxs, n, opts);
     hipStream_t s = c0->stream;
-    if (!P) {
-      P = build_plan(ctxs, n, opts);
-      std::lock_guard<std::mutex> lk(g_plan_mu);
-      g_plans.push_back(P);
-      if (g_plans.size() > kMaxPlans) g_plans.erase(g_plans.begin());
-    }
-    if (opts->flags & LRX_BATCH_EAGER)
+    if ((opts->flags & LRX_BATCH_EAGER) || !P->exec)
       run_batch(*P, s, c0->side.data(), c0->fork.data());
     else
       HIPCHK(hipGraphLaunch(P->exec, s));
