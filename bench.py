@@ -96,6 +96,76 @@ def cpu_baseline(st, mats, target_s=40.0, threads=None):
     return spent, n, order[:k], threads
 
 
+def serving_benchmark(n, precision="bf16x3", budget_gib=160, max_batch=8, workers=2, admitters=4):
+    """The serving stream: n requests of 20..500 atoms (three species, random
+    cubic or orthorhombic cells), each admitted (blocks materialised on the
+    device, context set up), evaluated and released.  Measures, after one
+    warm-up pass: (1) the one-at-a-time loop in arrival order, in the serving
+    precision and in plain FP64, (2) the capacity of the continuous-batching
+    server (all requests at once) and (3) the server under Poisson arrivals
+    at 0.8 x that capacity.  One server serves (2) and (3), as in a running
+    service."""
+    import numpy as np
+
+    from paper_2412_11081_amd import lrx, synth
+    from paper_2412_11081_amd.serve import LrxEngine, Server, poisson_arrivals, replay
+
+    t0 = time.time()
+    structs = [synth.serving_request(i).build() for i in range(n)]
+    print(f"# serving: {n} requests built in {time.time() - t0:.1f}s "
+          f"({min(s.natom for s in structs)}..{max(s.natom for s in structs)} atoms)", file=sys.stderr, flush=True)
+
+    def one_at_a_time(prec):
+        lat = []
+        t1 = time.perf_counter()
+        for st in structs:
+            ts = time.perf_counter()
+            mats = st.materialize("cuda")
+            ctx = lrx.context_for(st, mats)
+            ctx.evaluate(st.theta, st.theta_cs, precision=prec)
+            ctx.close()
+            del mats
+            lat.append(time.perf_counter() - ts)
+        return n / (time.perf_counter() - t1), lat
+
+    one_at_a_time(precision)      # warm-up: kernels loaded, launch shapes tuned, memory mapped
+    base, lat = one_at_a_time(precision)
+    base64, lat64 = one_at_a_time("fp64")
+    print(f"# serving: one-at-a-time {precision} {base:.2f} evals/s, fp64 {base64:.2f} evals/s",
+          file=sys.stderr, flush=True)
+
+    srv = Server(LrxEngine(precision=precision), hbm_budget=budget_gib << 30, max_batch=max_batch,
+                 workers=workers, admitters=admitters)
+
+    def run(arrivals):
+        srv.reset_stats()
+        replay(srv, structs, arrivals)
+        assert srv.drain(timeout=600), "serving run did not drain"
+        return srv.stats()
+
+    run(np.zeros(n))              # warm-up of the server's threads and streams
+    burst = run(np.zeros(n))
+    cap = burst["evals_per_s"]
+    print(f"# serving: burst capacity {cap:.2f} evals/s (mean batch {burst['mean_batch']:.2f})",
+          file=sys.stderr, flush=True)
+    rate = 0.8 * cap
+    st = run(poisson_arrivals(n, rate, seed=11081))
+    srv.close()
+    print(f"# serving: poisson {st['evals_per_s']:.2f} evals/s p50 {st['p50_s']*1e3:.0f} ms "
+          f"p99 {st['p99_s']*1e3:.0f} ms", file=sys.stderr, flush=True)
+    pct = lambda v, q: 1e3 * float(np.percentile(v, q))
+    return {"requests": n, "precision": precision, "arrivals": "poisson", "rate_per_s": rate,
+            "evals_per_s": st["evals_per_s"], "p50_ms": 1e3 * st["p50_s"], "p99_ms": 1e3 * st["p99_s"],
+            "mean_batch": st["mean_batch"], "failed": st["failed"] + burst["failed"],
+            "burst_evals_per_s": cap, "burst_mean_batch": burst["mean_batch"],
+            "one_at_a_time_evals_per_s": base, "one_at_a_time_p50_ms": pct(lat, 50),
+            "one_at_a_time_p99_ms": pct(lat, 99),
+            "one_at_a_time_fp64_evals_per_s": base64, "one_at_a_time_fp64_p50_ms": pct(lat64, 50),
+            "one_at_a_time_fp64_p99_ms": pct(lat64, 99),
+            "hbm_budget_gib": budget_gib, "max_batch": max_batch, "workers": workers, "admitters": admitters,
+            "max_bytes_held_gib": burst["max_bytes_held"] / 2**30}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +174,8 @@ def main():
     ap.add_argument("--workload", type=int, default=4)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="also run the serving stream with this many requests (p50/p99 latency)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -176,6 +248,10 @@ def main():
                      "flop_per_launch": stats["flop_triple"], "launch_ms": stage_avg["triple"]},
     }
     ctx.close()
+    del mats
+    torch.cuda.empty_cache()
+    if args.serving > 0:
+        out["serving"] = serving_benchmark(args.serving)
     if not args.no_cpu_baseline:
         spent, nsample, picked, threads = cpu_baseline(st, mats)
         total_kept = stats["kept_v_blocks"]

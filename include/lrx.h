@@ -64,8 +64,8 @@ typedef enum {
 } lrx_precision;
 
 /* lrx_options.flags (lrx_evaluate_batch only) */
-#define LRX_BATCH_EAGER 1     /* launch the kernels one by one instead of replaying the captured graph */
-#define LRX_BATCH_NO_TUNE 2   /* skip the launch-shape autotuner (one workgroup per work item)        */
+#define LRX_BATCH_EAGER 1     /* launch the kernels one by one; no graph is captured                  */
+#define LRX_BATCH_NO_TUNE 2   /* skip the launch-shape autotuner (every group takes the persistent grid) */
 
 typedef struct {
   double theta;        /* S1 threshold; <= 0 disables S1                  */
@@ -105,8 +105,12 @@ typedef struct {
 typedef struct lrx_ctx lrx_ctx;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
- * to run on (e.g. the caller's current stream), or NULL for a stream the
- * context creates and owns.  *out is set only on success. */
+ * to run on (e.g. the caller's current stream; it must outlive the
+ * context), or NULL for a stream the context owns.  Owned streams, and the
+ * context's side streams, come from a per-device pool of non-blocking
+ * streams that lrx_destroy refills, so creating and destroying contexts does
+ * not create and destroy streams once the pool is warm.  *out is set only on
+ * success. */
 int lrx_create(lrx_ctx** out, int32_t device, void* hip_stream);
 
 /* Geometry and basis sizes.  tau [natom][3], lattice [3][3] with rows
@@ -154,7 +158,8 @@ typedef struct {
   double device_bytes;          /* device memory held by the context         */
 } lrx_stats;
 
-/* Counts of the last evaluation (computed on the host from its masks). */
+/* Counts of the last evaluation (computed on the host from its masks); before
+ * the first evaluation only device_bytes is set. */
 int lrx_get_stats(lrx_ctx* ctx, lrx_stats* out);
 
 /* Stage durations (ms) of the last evaluation run with opts.timing != 0,
@@ -171,12 +176,15 @@ const char* lrx_stage_name(int32_t i);
  * of atoms with ceil(n_abf/16) = MT) one triple-product launch serves up to 4
  * structures, their units interleaved as work items; the other kernels run
  * per structure in the same sequence.  The first call for a given list of
- * contexts and options builds a plan: one eager run, a timing of each
- * group's launch shapes (one workgroup per item, or a persistent grid that
- * pulls items through counters), then the capture of the whole kernel
- * sequence in a HIP graph; later calls replay the graph (LRX_BATCH_EAGER
- * launches kernel by kernel instead).  A plan is dropped when one of its
- * contexts gets new tensors, a new structure or is destroyed.
+ * contexts and options builds a plan; the first plan that meets an alpha
+ * group (per precision, per process) times the group's launch shapes (one
+ * workgroup per item, or a persistent grid that pulls items through
+ * counters) after one eager run, and later plans reuse the choice.  A plan
+ * runs eagerly on its first use; its second use captures the whole kernel
+ * sequence in a HIP graph, which later calls replay (LRX_BATCH_EAGER keeps
+ * it eager).  lrx_evaluate goes through the same plans, with one context.
+ * A plan is dropped when one of its contexts gets new tensors, a new
+ * structure or is destroyed.
  * Results are written per context: E[i], F + 3*sum_{j<i} natom_j,
  * sigma + 9*i (host buffers); every context's block gradients and masks are
  * then available as after lrx_evaluate.  The contexts must not be used by
@@ -184,18 +192,30 @@ const char* lrx_stage_name(int32_t i);
 int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts, double* E, double* F,
                        double* sigma);
 
-/* Launch shapes the autotuner chose for the last plan built with this
- * context first: mode[MT] (0: one workgroup per item, 1: persistent grid)
- * and ms[2*MT + m] the best time of shape m, for MT = 0..LRX_MAX_ALPHA_TILES
- * (host buffers, either may be NULL).  Returns LRX_MAX_ALPHA_TILES + 1. */
+/* Launch shapes of the last plan built with this context first: mode[MT]
+ * (0: one workgroup per item, 1: persistent grid) and, for the groups that
+ * plan timed, ms[2*MT + m] the best time of shape m (0 if not timed there),
+ * for MT = 0..LRX_MAX_ALPHA_TILES (host buffers, either may be NULL).
+ * Returns LRX_MAX_ALPHA_TILES + 1. */
 #define LRX_MAX_ALPHA_TILES 8
 int lrx_batch_tuning(const lrx_ctx* ctx, int32_t* mode, float* ms);
 
 /* Message of the last failing call on this context ("" if none). */
 const char* lrx_last_error(const lrx_ctx* ctx);
 
-/* Release the context and every device buffer it owns.  NULL is allowed. */
+/* Release the context and every device buffer it owns.  NULL is allowed.
+ * Device buffers go back to the library's per-device memory cache, which
+ * serves later contexts from the memory it has already mapped (memory handed
+ * back to the driver has to be cleared before it is mapped again, which
+ * holds up the whole device); see lrx_pool_trim. */
 void lrx_destroy(lrx_ctx* ctx);
+
+/* Unmap segments of the library's device memory cache that no context uses,
+ * largest first, until at most keep_bytes stay mapped, after the device has
+ * finished its queued work.  For processes that need the memory for
+ * something else (e.g. another allocator).  Returns LRX_OK, or LRX_EINVAL
+ * for a device that does not exist. */
+int lrx_pool_trim(int32_t device, uint64_t keep_bytes);
 
 #ifdef __cplusplus
 }

@@ -88,6 +88,69 @@ Pairs group_pairs(int N, int64_t n, const int32_t* first, const int32_t* second,
 
 std::atomic<uint64_t> g_gen{1};
 
+// Pinned host buffers for results, by power-of-two size class (4 KiB and up),
+// kept for reuse: contexts that come and go (a serving stream) would otherwise
+// pin and unpin host memory, and unpinning waits for the whole device.
+struct PinnedPool {
+  std::mutex mu;
+  std::vector<std::vector<void*>> free_by_class = std::vector<std::vector<void*>>(40);
+  static int size_class(size_t bytes) {
+    int k = 12;
+    while (((size_t)1 << k) < bytes) ++k;
+    return k;
+  }
+  void* get(size_t bytes) {
+    const int k = size_class(bytes);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!free_by_class[k].empty()) {
+        void* p = free_by_class[k].back();
+        free_by_class[k].pop_back();
+        return p;
+      }
+    }
+    void* p = nullptr;
+    HIPCHK(hipHostMalloc(&p, (size_t)1 << k, hipHostMallocDefault));
+    return p;
+  }
+  void put(void* p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu);
+    free_by_class[size_class(bytes)].push_back(p);
+  }
+};
+PinnedPool g_pinned;
+
+// Non-blocking streams kept per device for reuse: contexts take theirs from
+// here and give them back, synchronised, when destroyed, so contexts that come
+// and go neither create nor destroy streams once the pool is warm, and memory
+// a context frees stream-ordered is always ordered on a stream that lives on.
+struct StreamPool {
+  std::mutex mu;
+  std::vector<std::pair<int, hipStream_t>> idle;
+  hipStream_t get(int device) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (size_t k = idle.size(); k-- > 0;)
+        if (idle[k].first == device) {
+          hipStream_t s = idle[k].second;
+          idle.erase(idle.begin() + k);
+          return s;
+        }
+    }
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+  }
+  void put(int device, hipStream_t s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s);
+    std::lock_guard<std::mutex> lk(mu);
+    idle.emplace_back(device, s);
+  }
+};
+StreamPool g_streams;
+
 // CSR of blocks by atom (first or second), in caller order.
 void by_atom(int N, int64_t n, const int32_t* atom, std::vector<int>& row, std::vector<int64_t>& list) {
   row.assign(N + 1, 0);
@@ -123,7 +186,7 @@ struct lrx_ctx {
   int max_mm = 1, max_depth = 4;
   // sizes of the FP32 buffers of the reduced-precision forms
   int64_t n_cf = 0, n_vf = 0, n_h = 0, n_z = 0, n_y = 0;
-  bool have_f32 = false;
+  bool have_f32 = false, have_f64 = false;
 
   // device memory
   std::vector<void*> allocs;
@@ -136,7 +199,8 @@ struct lrx_ctx {
   // autotuner result of the last batch plan built with this context first
   std::array<int, lrx::kMaxAlphaTiles + 1> tune_mode{};
   std::array<float, 2 * (lrx::kMaxAlphaTiles + 1)> tune_ms{};
-  double* h_out = nullptr;
+  double* h_out = nullptr;   // pinned, from g_pinned
+  size_t h_out_bytes = 0;
   std::array<hipEvent_t, LRX_NSTAGES + 1> ev{};
   std::array<hipStream_t, lrx::kSideStreams> side{};
   std::array<hipEvent_t, lrx::kSideStreams + 1> fork{};
@@ -149,7 +213,10 @@ struct lrx_ctx {
   T* dalloc(int64_t count) {
     void* p = nullptr;
     const size_t bytes = std::max<size_t>(1, (size_t)count * sizeof(T));
-    HIPCHK(hipMalloc(&p, bytes));
+    // from the library's device memory cache: contexts that come and go (a
+    // serving stream) reuse its memory instead of mapping fresh memory
+    p = lrx::dev_alloc(device, bytes);
+    if (!p) throw Fail{LRX_ENOMEM, "device memory exhausted (" + std::to_string(bytes) + " bytes requested)"};
     allocs.push_back(p);
     dev_bytes += (double)bytes;
     return (T*)p;
@@ -161,11 +228,15 @@ struct lrx_ctx {
     return p;
   }
   void free_tensors() {
-    if (stream) (void)hipStreamSynchronize(stream);
-    for (void* p : allocs) (void)hipFree(p);
+    // back to the cache once the work queued on this stream is done (every
+    // call that uses the buffers on another stream has synchronised that
+    // stream before returning)
+    (void)hipStreamSynchronize(stream);
+    for (void* p : allocs) lrx::dev_free(device, p);
     allocs.clear();
     dev_bytes = 0;
     have_tensors = false;
+    have_f32 = have_f64 = false;
     evaluated = false;
   }
 };
@@ -224,13 +295,13 @@ int lrx_create(lrx_ctx** out, int32_t device, void* hip_stream) {
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
     } else {
-      HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->stream = g_streams.get(device);
       c->own_stream = true;
     }
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
     for (auto& e : c->fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    for (auto& st : c->side) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     c->events = true;
+    for (auto& st : c->side) st = g_streams.get(device);
   });
   if (rc != LRX_OK) {
     lrx_destroy(c);
@@ -554,11 +625,11 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.slotB = c->upload(c->slotB); d.slotX = c->upload(c->slotX); d.hOff = c->upload(hOff);
     d.hSlotMap = c->upload(slotmap);
     d.need = c->dalloc<uint8_t>(nSlot);
-    d.H = c->dalloc<double>(hOff[nSlot]);
+    d.H = nullptr;   // work buffers of a precision are allocated on its first evaluation
     c->n_cf = cfOff[nCp];
     c->n_vf = vfOff[nVp];
     c->n_h = hOff[nSlot];
-    HIPCHK(hipMemsetAsync(d.H, 0, sizeof(double) * std::max<int64_t>(1, hOff[nSlot]), c->stream));
+
     d.nUnit = (int)c->unitCp.size();
     std::vector<int> unitOrder(d.nUnit);
     {
@@ -601,14 +672,14 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.triHF = c->upload(triHF); d.triHA = c->upload(triHA);
     d.hdRow = c->upload(hdRow); d.hdRowD = c->upload(hdRowD); d.hdG = c->upload(hdG); d.hdCp = c->upload(hdCp);
     d.hdCf = c->upload(hdCf); d.hdStride = c->upload(hdStride);
-    d.Zbuf = c->dalloc<double>(zOff[ntri]);
+    d.Zbuf = nullptr;
     c->n_z = zOff[ntri];
     std::vector<int64_t> yOff(nCp + 1, 0);
     for (int i = 0; i < nCp; ++i) yOff[i + 1] = yOff[i] + (cfOff[i + 1] - cfOff[i]) * c->nsplit[i];
     d.yOff = c->upload(yOff);
-    d.Ybuf = c->dalloc<double>(yOff[nCp]);
+    d.Ybuf = nullptr;
     c->n_y = yOff[nCp];
-    c->have_f32 = false;
+    c->have_f32 = c->have_f64 = false;
     d.Cf32 = nullptr; d.Vf32 = nullptr; d.D32 = nullptr; d.H32 = nullptr; d.Zbuf32 = nullptr; d.Ybuf32 = nullptr;
     d.gC = c->dalloc<double>(3 * c->nC);
     d.gV = c->dalloc<double>(3 * c->nV);
@@ -620,8 +691,10 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.atVsRow = c->upload(atVsRow); d.atVs = c->upload(atVs);
     d.out = c->dalloc<double>(1 + 3 * N + 9 + 1);
     d.err = c->dalloc<int>(1);
-    if (c->h_out) { (void)hipHostFree(c->h_out); c->h_out = nullptr; }
-    HIPCHK(hipHostMalloc((void**)&c->h_out, sizeof(double) * (1 + 3 * N + 9 + 1), hipHostMallocDefault));
+    g_pinned.put(c->h_out, c->h_out_bytes);
+    c->h_out = nullptr;
+    c->h_out_bytes = sizeof(double) * (1 + 3 * N + 9 + 1);
+    c->h_out = (double*)g_pinned.get(c->h_out_bytes);
 
     // ---- value validation on the device ------------------------------------
     HIPCHK(hipMemsetAsync(d.err, 0, sizeof(int), c->stream));
@@ -663,6 +736,15 @@ void prepare(lrx_ctx* c, const lrx_options* opts) {
   require(opts->precision == LRX_FP64 || opts->precision == LRX_FP32 || opts->precision == LRX_BF16X3,
           "unknown precision");
   require(std::isfinite(opts->theta) && std::isfinite(opts->theta_cs), "non-finite threshold");
+  if (opts->precision == LRX_FP64 && !c->have_f64) {
+    Dev& d = c->dev;
+    d.H = c->dalloc<double>(c->n_h);
+    HIPCHK(hipMemsetAsync(d.H, 0, sizeof(double) * std::max<int64_t>(1, c->n_h), c->stream));   // zero padding rows
+    d.Zbuf = c->dalloc<double>(c->n_z);
+    d.Ybuf = c->dalloc<double>(c->n_y);
+    c->have_f64 = true;
+    c->gen = g_gen++;
+  }
   if (opts->precision != LRX_FP64 && !c->have_f32) {
     Dev& d = c->dev;
     const int64_t nt = c->ao[c->N];
@@ -704,7 +786,12 @@ int lrx_keep_masks(lrx_ctx* c, uint8_t* keepC, uint8_t* keepV, uint8_t* keepD) {
 int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
   return guarded(c, [&] {
     require(s != nullptr, "NULL stats");
-    require(c->evaluated, "no evaluation yet");
+    require(c->have_tensors, "no tensors yet");
+    if (!c->evaluated) {   // before the first evaluation only the memory held is known
+      *s = lrx_stats{};
+      s->device_bytes = c->dev_bytes;
+      return;
+    }
     const Dev& d = c->dev;
     std::vector<uint8_t> kC(c->nC), kV(c->nV), aC(d.nCp), aV(d.nVp), need(d.nSlot);
     if (c->nC) HIPCHK(hipMemcpyAsync(kC.data(), d.keepC, c->nC, hipMemcpyDeviceToHost, c->stream));
@@ -793,8 +880,10 @@ struct BatchPlan {
   double theta = 0, theta_cs = 0;
   std::vector<lrx::TripleLaunch> launches;
   std::vector<void*> allocs;
+  hipStream_t stream = nullptr;   // the first context's stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int uses = 0;
   std::array<int, lrx::kMaxAlphaTiles + 1> mode{};
   std::array<float, 2 * (lrx::kMaxAlphaTiles + 1)> tune_ms{};
 
@@ -802,11 +891,14 @@ struct BatchPlan {
     (void)hipSetDevice(device);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (void* p : allocs) (void)hipFree(p);
+    // after the plan's last launch on its stream (every context of a plan,
+    // and so its stream, outlives the plan)
+    (void)hipStreamSynchronize(stream);
+    for (void* p : allocs) lrx::dev_free(device, p);
   }
   bool matches(lrx_ctx* const* c, int n, const lrx_options* o) const {
     if ((int)ctxs.size() != n || prec != o->precision || theta != o->theta || theta_cs != o->theta_cs ||
-        (flags & LRX_BATCH_NO_TUNE) != (o->flags & LRX_BATCH_NO_TUNE))
+        flags != o->flags)
       return false;
     for (int i = 0; i < n; ++i)
       if (ctxs[i] != c[i] || gens[i] != c[i]->gen) return false;
@@ -815,7 +907,9 @@ struct BatchPlan {
   template <class T>
   T* upload(const std::vector<T>& v, hipStream_t s) {
     void* p = nullptr;
-    HIPCHK(hipMalloc(&p, std::max<size_t>(1, v.size() * sizeof(T))));
+    p = lrx::dev_alloc(device, std::max<size_t>(1, v.size() * sizeof(T)));
+    if (!p) throw Fail{LRX_ENOMEM, "device memory exhausted (batch plan)"};
+    stream = s;
     allocs.push_back(p);
     if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return (T*)p;
@@ -825,6 +919,13 @@ struct BatchPlan {
 std::mutex g_plan_mu;
 std::vector<std::shared_ptr<BatchPlan>> g_plans;   // most recently used last
 constexpr size_t kMaxPlans = 8;
+// launch shape chosen by the autotuner per (precision, alpha group), -1 until
+// a plan has timed that group; later plans take it without timing again
+std::array<std::array<int, lrx::kMaxAlphaTiles + 1>, 3> g_tuned = [] {
+  std::array<std::array<int, lrx::kMaxAlphaTiles + 1>, 3> t{};
+  for (auto& r : t) r.fill(-1);
+  return t;
+}();
 
 void drop_plans_of(const lrx_ctx* c) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -910,11 +1011,26 @@ std::shared_ptr<BatchPlan> build_plan(lrx_ctx* const* ctxs, int n, const lrx_opt
     P->launches.push_back(L);
   }
   hipStream_t s = c0->stream;
-  // warm-up run: fills every intermediate buffer and sets kernel attributes
-  run_batch(*P, s, c0->side.data(), c0->fork.data());
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(s));
-  if (!(opts->flags & LRX_BATCH_NO_TUNE)) {
+  // shapes already tuned in this process are reused; without the tuner a
+  // group takes the persistent grid, the shape the tuner has preferred on
+  // every workload measured so far
+  std::vector<int> to_tune;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) {
+      const int t = g_tuned[P->prec][mt];
+      P->mode[mt] = t >= 0 ? t : 1;
+    }
+    for (int mt : group_order(*P))
+      if (g_tuned[P->prec][mt] < 0) to_tune.push_back(mt);
+  }
+  for (auto& L : P->launches)
+    for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) L.mode[mt] = P->mode[mt];
+  if (!(opts->flags & LRX_BATCH_NO_TUNE) && !to_tune.empty()) {
+    // warm-up run: fills every intermediate buffer and sets kernel attributes
+    run_batch(*P, s, c0->side.data(), c0->fork.data());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
     // autotuner: per alpha-tile group, one workgroup per item (mode 0) or a
     // persistent grid (mode 1), best of two timed launches of the group alone
     // (the triple kernels only overwrite their own partial sums, so repeating
@@ -922,7 +1038,7 @@ std::shared_ptr<BatchPlan> build_plan(lrx_ctx* const* ctxs, int n, const lrx_opt
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    for (int mt : group_order(*P)) {
+    for (int mt : to_tune) {
       float best[2] = {1e30f, 1e30f};
       for (int mode = 0; mode < 2; ++mode) {
         for (auto& L : P->launches) L.mode[mt] = mode;
@@ -940,23 +1056,38 @@ std::shared_ptr<BatchPlan> build_plan(lrx_ctx* const* ctxs, int n, const lrx_opt
       P->tune_ms[2 * mt] = best[0];
       P->tune_ms[2 * mt + 1] = best[1];
       for (auto& L : P->launches) L.mode[mt] = P->mode[mt];
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      g_tuned[P->prec][mt] = P->mode[mt];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
   c0->tune_mode = P->mode;
   c0->tune_ms = P->tune_ms;
-  // capture the whole sequence; replays launch it as one graph (the legacy
-  // default stream cannot be captured: such contexts run eagerly)
-  if (s == nullptr) return P;
-  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  run_batch(*P, s, c0->side.data(), c0->fork.data());
-  hipGraph_t g = nullptr;
-  const hipError_t ce = hipStreamEndCapture(s, &g);
-  HIPCHK(ce);
-  P->graph = g;
-  HIPCHK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
   return P;
+}
+
+// Run a plan on the first context's stream: eagerly on its first use, then
+// from the HIP graph captured on its second use (a plan used once, e.g. a
+// one-off batch, never pays for a capture).  The legacy default stream cannot
+// be captured: such contexts, and plans asked to run eagerly, stay eager.
+void launch_plan(BatchPlan& P, const lrx_options* opts) {
+  lrx_ctx* c0 = P.ctxs[0];
+  hipStream_t s = c0->stream;
+  ++P.uses;
+  const bool capturable = s != nullptr && !(opts->flags & LRX_BATCH_EAGER);
+  if (capturable && !P.exec && P.uses >= 2) {
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    run_batch(P, s, c0->side.data(), c0->fork.data());
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture(s, &g));
+    P.graph = g;
+    HIPCHK(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+  }
+  if (capturable && P.exec)
+    HIPCHK(hipGraphLaunch(P.exec, s));
+  else
+    run_batch(P, s, c0->side.data(), c0->fork.data());
 }
 
 // The plan of (contexts, options): from the cache, or built (and cached).
@@ -990,7 +1121,7 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
     // times are requested
     std::shared_ptr<BatchPlan> P = get_plan(one, 1, opts);
     const bool timing = opts->timing != 0;
-    if (timing || !P->exec) {
+    if (timing) {
       const lrx::Opts o{opts->theta, opts->theta_cs, opts->precision};
       hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
       if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
@@ -999,7 +1130,7 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
       for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) c->tl.mode[mt] = P->mode[mt];
       lrx::launch_contract(c->dev, c->tl, opts->precision, c->stream, c->side.data(), c->fork.data(), ev);
     } else {
-      HIPCHK(hipGraphLaunch(P->exec, c->stream));
+      launch_plan(*P, opts);
     }
     HIPCHK(hipGetLastError());
     const int N = c->N;
@@ -1033,10 +1164,7 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
       if (ctxs[i]->stream != c0->stream) HIPCHK(hipStreamSynchronize(ctxs[i]->stream));
     std::shared_ptr<BatchPlan> P = get_plan(ctxs, n, opts);
     hipStream_t s = c0->stream;
-    if ((opts->flags & LRX_BATCH_EAGER) || !P->exec)
-      run_batch(*P, s, c0->side.data(), c0->fork.data());
-    else
-      HIPCHK(hipGraphLaunch(P->exec, s));
+    launch_plan(*P, opts);
     HIPCHK(hipGetLastError());
     for (int i = 0; i < n; ++i) {
       lrx_ctx* c = ctxs[i];
@@ -1071,18 +1199,27 @@ int lrx_batch_tuning(const lrx_ctx* c, int32_t* mode, float* ms) {
 
 const char* lrx_last_error(const lrx_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
 
+int lrx_pool_trim(int32_t device, uint64_t keep_bytes) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LRX_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return LRX_EHIP;
+  if (hipDeviceSynchronize() != hipSuccess) return LRX_EHIP;
+  (void)lrx::dev_trim(device, (size_t)keep_bytes);
+  return LRX_OK;
+}
+
 void lrx_destroy(lrx_ctx* c) {
   if (!c) return;
   drop_plans_of(c);
   (void)hipSetDevice(c->device);
   c->free_tensors();
-  if (c->h_out) (void)hipHostFree(c->h_out);
+  g_pinned.put(c->h_out, c->h_out_bytes);
   if (c->events) {
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     for (auto& e : c->fork) (void)hipEventDestroy(e);
-    for (auto& st : c->side) (void)hipStreamDestroy(st);
   }
-  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  for (auto& st : c->side) g_streams.put(c->device, st);
+  if (c->own_stream) g_streams.put(c->device, c->stream);
   delete c;
 }
 

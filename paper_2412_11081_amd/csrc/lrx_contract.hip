@@ -1071,14 +1071,15 @@ static void launch_triple(const TripleLaunch& tl, hipStream_t s) {
   const int n = tl.n[MT];
   if (n <= 0) return;
   const size_t lds = TripleCfg<MT, P>::lds_bytes();
-  static bool attr = false;
-  if (!attr) {
+  // once per process (thread-safe initialisation of a function-local static)
+  static const bool attr = [lds] {
     (void)hipFuncSetAttribute((const void*)k_triple<MT, P, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     (void)hipFuncSetAttribute((const void*)k_triple<MT, P, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   if (tl.mode[MT] == 1) {
     int* cnt = tl.counters + 8 * MT;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, cnt, 8, 0);

@@ -44,6 +44,16 @@ constexpr int kHPass = 64;         // depth of one H-build pass
 
 enum Prec : int { kP64 = 0, kP32 = 1, kPB3 = 2 };
 
+// Device memory cache (lrx_mem.hip), per device and process-wide: blocks are
+// served from memory the cache has mapped and come back to it on dev_free;
+// nullptr when the device is out of memory.  dev_free only after the work
+// that uses the block has finished.  dev_trim unmaps idle segments until at
+// most `keep` bytes stay mapped (device idle) and returns the bytes mapped.
+void* dev_alloc(int device, size_t bytes);
+void dev_free(int device, void* p);
+size_t dev_trim(int device, size_t keep);
+void dev_cache_bytes(int device, size_t* mapped, size_t* used);
+
 // Everything the kernels read or write for one structure.  Passed by value.
 struct Dev {
   int N;

@@ -65,7 +65,7 @@ _lib = None
 
 EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
-           "lrx_batch_tuning", "lrx_last_error", "lrx_destroy"]
+           "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim"]
 
 
 def load(path: Optional[str] = None):
@@ -94,8 +94,10 @@ def load(path: Optional[str] = None):
     lib.lrx_last_error.restype = ctypes.c_char_p
     lib.lrx_destroy.argtypes = [vp]
     lib.lrx_destroy.restype = None
+    lib.lrx_pool_trim.argtypes = [ctypes.c_int32, ctypes.c_uint64]
     for f in ("lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
-              "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning"):
+              "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning",
+              "lrx_pool_trim"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -168,6 +170,12 @@ class Context:
             dptr, dd = Dm.ctypes.data, False
         if not (dc == dv == dd):
             raise ValueError("C, V and D must all be on the device or all on the host")
+        if dc:
+            # the library reads the tensors on its own stream: finish the work
+            # that produced them on the caller's streams first
+            import torch
+
+            torch.cuda.current_stream().synchronize()
         self._check(self.lib.lrx_set_tensors(self.h, ctypes.byref(bc), ctypes.byref(bv), ctypes.c_void_p(dptr), int(dc)))
         self._keep = keep
         self.nC, self.nV = int(bc.nblk), int(bv.nblk)
@@ -248,10 +256,17 @@ def evaluate_batch(contexts, theta=0.0, theta_cs=0.0, precision="fp64", eager=Fa
 
 
 def batch_tuning(context):
-    """Launch shapes chosen by the autotuner of the last plan built with
-    ``context`` first: {MT: (mode, ms_mode0, ms_mode1)} for the tuned groups."""
+    """Launch shapes of the last plan built with ``context`` first:
+    {MT: (mode, ms_mode0, ms_mode1)}; the times are 0 for groups that plan did
+    not time (shapes already chosen earlier in the process)."""
     mode = (ctypes.c_int32 * (MAX_ALPHA_TILES + 1))()
     ms = (ctypes.c_float * (2 * (MAX_ALPHA_TILES + 1)))()
     context.lib.lrx_batch_tuning(context.h, mode, ms)
-    return {mt: (int(mode[mt]), float(ms[2 * mt]), float(ms[2 * mt + 1]))
-            for mt in range(1, MAX_ALPHA_TILES + 1) if ms[2 * mt] > 0}
+    return {mt: (int(mode[mt]), float(ms[2 * mt]), float(ms[2 * mt + 1])) for mt in range(1, MAX_ALPHA_TILES + 1)}
+
+
+def pool_trim(device: int = 0, keep_bytes: int = 0):
+    """lrx_pool_trim: hand the device pool's unused memory back to the driver."""
+    rc = load().lrx_pool_trim(int(device), int(keep_bytes))
+    if rc != 0:
+        raise LrxError(rc, f"lrx_pool_trim(device={device}) failed")

@@ -122,7 +122,7 @@ class Structure:
     theta: float               # block screening threshold
     theta_cs: float            # Schwarz threshold
     seed: int
-    d_kind: str = "haar"       # "haar" (Q diag(U[0,2]) Q^T) or "goe" (I + S/rho)
+    d_kind: str = "haar"       # "haar" (Q diag(U[0,2]) Q^T), "goe" (I + S/rho) or "gersh" (drawn on the device)
 
     # filled by build()
     nao: np.ndarray = None
@@ -187,7 +187,7 @@ class Structure:
             self.keysV = enumerate_pairs(self.tau, self.lat, self.rv)
         else:
             self.keysC, self.keysV = keys
-        if with_d:
+        if with_d and self.d_kind != "gersh":
             self.D = make_density(self.n_tot, self.d_kind, rng)
         return self
 
@@ -246,12 +246,16 @@ class Structure:
                 fi = torch.from_numpy(f[idx]).to(device)
                 fpi = torch.from_numpy(np.ascontiguousarray(fpx[idx])).to(device)
                 nb = idx.size
-                val[start:start + nb * size].view(nb, size).copy_(fi[:, None] * b[None, :])
-                dval[3 * start:3 * (start + nb * size)].view(nb, 3, size).copy_(
-                    fpi[:, :, None] * b[None, None, :])
+                # written in place: no temporaries the size of the blocks
+                torch.mul(fi[:, None], b[None, :], out=val[start:start + nb * size].view(nb, size))
+                torch.mul(fpi[:, :, None], b[None, None, :],
+                          out=dval[3 * start:3 * (start + nb * size)].view(nb, 3, size))
             first, second, R = self.keysC if kind == "C" else self.keysV
             out[kind] = dict(first=first, second=second, R=R, off=off, val=val, dval=dval, disp=disp)
-        out["D"] = torch.from_numpy(self.D).to(device)
+        if self.d_kind == "gersh" and self.D is None:
+            out["D"] = gersh_density(self.n_tot, self.seed + 104729, device)
+        else:
+            out["D"] = torch.from_numpy(self.D).to(device)
         return out
 
 
@@ -285,6 +289,24 @@ def make_density(n: int, kind: str, rng: np.random.Generator) -> np.ndarray:
         raise ValueError(kind)
     d = 0.5 * (d + d.T)
     return np.ascontiguousarray(d)
+
+
+def gersh_density(n: int, seed: int, device: str = "cpu"):
+    """Symmetric n x n torch matrix with eigenvalues in (0, 2), drawn on ``device``:
+    I + S / rho with S = (G + G^T)/sqrt(2), G Gaussian from a seeded torch
+    generator, and rho = 1.001 * max_i sum_j |S_ij| (Gershgorin: every
+    eigenvalue of S lies in [-rho, rho]).  Cheap for the serving stream."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    G = torch.randn(n, n, generator=g, device=device, dtype=torch.float64)
+    S = (G + G.T) * (1.0 / math.sqrt(2.0))
+    del G
+    rho = 1.001 * float(S.abs().sum(dim=1).max())
+    S /= rho
+    S.diagonal().add_(1.0)
+    return S.contiguous()
 
 
 # ----------------------------------------------------------------------------
@@ -385,7 +407,7 @@ def serving_request(i: int, rng_seed: Optional[int] = None) -> Structure:
     lat = np.diag(side)
     species = rng.permutation(np.array([0] * (n // 5) + [1] * (n // 5) + [2] * (n - 2 * (n // 5)), np.int32))
     return Structure(f"req{i}", frac @ lat, lat, species, [SPECIES_A, SPECIES_B, SPECIES_X],
-                     rc=8.0, rv=20.0, theta=1e-4, theta_cs=1e-7, seed=seed, d_kind="goe")
+                     rc=8.0, rv=20.0, theta=1e-4, theta_cs=1e-7, seed=seed, d_kind="gersh")
 
 
 def workload(k: int) -> Structure:
