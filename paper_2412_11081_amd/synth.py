@@ -193,23 +193,27 @@ class Structure:
 
     # ------------------------------------------------------------------
     def _layout(self, kind: str):
-        """Group blocks by value template; return offsets and group list."""
+        """Group blocks by value template; return offsets and group list.
+
+        Groups are laid out in the order of str(template key), the blocks of
+        a group in key order."""
         first, second, R = self.keysC if kind == "C" else self.keysV
-        sp = self.species
+        first, second = np.asarray(first), np.asarray(second)
+        sp = np.asarray(self.species, np.int64)
+        sa, sb = sp[first], sp[second]
         if kind == "C":
-            onsite = (first == second) & np.all(R == 0, axis=1)
-            tkey = [("on", int(sp[a])) if o else (int(sp[a]), int(sp[b]))
-                    for a, b, o in zip(first, second, onsite)]
+            onsite = (first == second) & np.all(np.asarray(R) == 0, axis=1)
         else:
-            tkey = [(int(sp[a]), int(sp[b])) for a, b in zip(first, second)]
-        groups: Dict = {}
-        for i, k in enumerate(tkey):
-            groups.setdefault(k, []).append(i)
-        off = np.zeros(len(tkey), np.int64)
+            onsite = np.zeros(first.shape[0], bool)
+        code = np.where(onsite, -1 - sa, sa * 4096 + sb)
+        uniq, inv = np.unique(code, return_inverse=True)
+        keys = [("on", int(-1 - c)) if c < 0 else (int(c // 4096), int(c % 4096)) for c in uniq]
+        off = np.zeros(first.shape[0], np.int64)
         glist = []
         cur = 0
-        for k in sorted(groups, key=str):
-            idx = np.array(groups[k], np.int64)
+        for g in sorted(range(len(keys)), key=lambda g: str(keys[g])):
+            k = keys[g]
+            idx = np.nonzero(inv == g)[0].astype(np.int64)
             base = self.base_c[k] if kind == "C" else self.base_v[k]
             size = base.size
             off[idx] = cur + np.arange(idx.size, dtype=np.int64) * size
