@@ -35,3 +35,26 @@ def test_results_same_alone_and_in_the_mix():
         assert np.max(np.abs(F - ref[1])) <= 1e-4
         assert np.max(np.abs(S - ref[2])) <= 1e-5
         assert abs(E - ref[0]) <= 1e-4 * abs(ref[0]) + 1e-8 * s.natom
+
+
+def test_memory_cache_trim_and_reuse():
+    """Contexts come and go: the second pass reuses the library's cached
+    device memory; after lrx_pool_trim the next context maps fresh memory and
+    still gives the same results."""
+    H.require_gpu()
+    structs = [synth.serving_request(i).build() for i in REQUESTS[:3]]
+    first = []
+    for s in structs:
+        mats = s.materialize("cuda")
+        ctx = lrx.context_for(s, mats)
+        first.append(ctx.evaluate(s.theta, s.theta_cs, precision="bf16x3"))
+        ctx.close()
+    lrx.pool_trim(0, 0)
+    for s, ref in zip(structs, first):
+        mats = s.materialize("cuda")
+        ctx = lrx.context_for(s, mats)
+        got = ctx.evaluate(s.theta, s.theta_cs, precision="bf16x3")
+        ctx.close()
+        assert got[0] == ref[0] and np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+    with pytest.raises(lrx.LrxError):
+        lrx.pool_trim(999, 0)
