@@ -452,7 +452,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       hColRow[B + 1] = (int)hColSlot.size();
       const int rows = c->nabf[B] * c->nao[B], cols = hColRow[B + 1] - hColRow[B];
       for (int r0 = 0; r0 < rows; r0 += lrx::kHRows)
-        for (int c0 = 0; c0 < cols; c0 += 64) {
+        for (int c0 = 0; c0 < cols; c0 += lrx::kHItemCols) {
           hbB.push_back(B);
           hbR0.push_back(r0);
           hbC0.push_back(c0);

@@ -125,33 +125,39 @@ __device__ inline int xcd_remap(int b, int G) {
 
 // ---------------------------------------------------------------------------
 // H(B,X)[b][beta][x] = sum_{G alive} sum_g Cf(B,G)[beta][b][g] D(G,X)[g][x].
-// One workgroup per (B, 64 rows of (beta,b), 64 columns): the columns are
-// the (X, x) pairs of every H slot of B concatenated, so one D tile staged in
-// LDS serves four 16-column tiles per wave, and the Cf(B, .) fragments of the
-// wave's row tile are requested once per pass.  The depth (every g of every
-// live C pair (B,G)) runs in passes of at most kHPass.
+// Per atom B this is one dense product: rows (beta,b), depth (G,g) over the
+// live C pairs (B,G), columns (X,x) over the H slots of B concatenated, with
+// D(G,X) dropped for screened D pairs.  One workgroup of 8 waves per (B, 128
+// rows, kHItemCols columns): each wave keeps the Cf fragments of its 16 rows
+// in registers and walks the item's 64-column blocks (4 tiles of 16 per
+// wave) and depth passes of at most kHPass; the D tile of the next step is
+// loaded into registers while the current one is contracted from LDS
+// (double buffer, one barrier per step).
 // ---------------------------------------------------------------------------
-constexpr int kHCols = 64;
+constexpr int kHT = 512;
+constexpr int kHCB = 64;                         // columns of one block: 4 tiles of 16
+constexpr int kHPre = kHPass * kHCB / kHT;       // D elements each thread stages per step
+static_assert(kHRows == 16 * (kHT / 64), "one 16-row tile per wave");
 template <class T>
-__global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
+__global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIMD: two workgroups per CU
   using M = M4<T>;
   __shared__ int krow[kHMaxDepth];   // D row (ao[G] + g) of depth index k
   __shared__ int kG[kHMaxDepth];     // atom G, or -1 (padding or screened pair)
   __shared__ int64_t kcf[kHMaxDepth];
   __shared__ int kst[kHMaxDepth];
-  __shared__ int cD[kHCols], cAt[kHCols], cSl[kHCols], cX[kHCols];
+  __shared__ int cD[kHItemCols], cAt[kHItemCols], cSl[kHItemCols];
   __shared__ int kdepth;
-  __shared__ T Ds[kHPass * kHCols];
+  __shared__ T Ds[2][kHPass * kHCB];
   const T* Cf = Buf<T>::Cf(d);
   const T* Dm = Buf<T>::D(d);
   const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x], c0 = d.hbC0[blockIdx.x];
   const int mB = d.nabf[B], nB = d.nao[B], rows = mB * nB;
-  const int ncols = d.hColRow[B + 1] - d.hColRow[B];
+  const int ncols = min(kHItemCols, d.hColRow[B + 1] - d.hColRow[B] - c0);
   const int tid = threadIdx.x, lane = tid & 63, q = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
   {
     const int h0 = d.hdRow[B], hn = d.hdRow[B + 1] - h0;
-    for (int k = tid; k < hn; k += kNT) {
+    for (int k = tid; k < hn; k += kHT) {
       const int t = d.hdCp[h0 + k];
       const bool live = t >= 0 && d.aliveC[t >> 6];
       krow[k] = d.hdRowD[h0 + k];
@@ -159,63 +165,90 @@ __global__ void __launch_bounds__(kNT) k_hbuild(Dev d) {
       kcf[k] = d.hdCf[h0 + k];
       kst[k] = d.hdStride[h0 + k];
     }
-    for (int cl = tid; cl < kHCols; cl += kNT) {
-      const int c = c0 + cl;
-      const bool in = c < ncols;
-      const int s = in ? d.hColSlot[d.hColRow[B] + c] : 0;
-      cSl[cl] = in && d.need[s] ? s : -1;
-      cD[cl] = in ? d.hColD[d.hColRow[B] + c] : 0;
-      cAt[cl] = in ? d.hColAtom[d.hColRow[B] + c] : 0;
-      cX[cl] = in ? d.hColX[d.hColRow[B] + c] : 0;
+    for (int cl = tid; cl < kHItemCols; cl += kHT) {
+      const bool in = cl < ncols;
+      const int c = d.hColRow[B] + c0 + (in ? cl : 0);
+      const int sl = d.hColSlot[c];
+      cSl[cl] = in && d.need[sl] ? sl : -1;
+      cD[cl] = d.hColD[c];           // a valid D column also past the item's end
+      cAt[cl] = d.hColAtom[c];
     }
     if (tid == 0) kdepth = hn;
   }
   __syncthreads();
-  const int Kall = kdepth;
+  const int K = kdepth, N = d.N;
+  const int npass = (K + kHPass - 1) / kHPass;
+  const int nblk = (ncols + kHCB - 1) / kHCB;
+  const int steps = nblk * npass;
   const int mBp = (mB + 15) & ~15;
   const int row = r0 + 16 * w + q;    // A-operand row of this lane
-  typename M::acc acc[kHCols / 16];
+  // output rows of this lane: (b, beta) -> b * mBp + beta, or -1
+  int orow[4];
 #pragma unroll
-  for (int j = 0; j < kHCols / 16; ++j) acc[j] = typename M::acc{0, 0, 0, 0};
-  for (int kb = 0; kb < Kall; kb += kHPass) {
-    const int K = min(kHPass, Kall - kb);
-    T af[kHPass / 4];
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + 16 * w + M::row(g, i);
+    const int be = r / nB, bb = r - be * nB;
+    orow[i] = r < rows ? bb * mBp + be : -1;
+  }
+  // D tile of step s into registers: element e = tid + kHT i is (k, cl) =
+  // (e / kHCB, e mod kHCB); screened pairs, dead C pairs and padding give 0
+  T pv[kHPre];
+  auto fetch = [&](int st) {
+    const int blk = st / npass, p = st - blk * npass, kb = p * kHPass;
 #pragma unroll
-    for (int s = 0; s < kHPass / 4; ++s) {
-      const int k = kb + 4 * s + g;
-      af[s] = (4 * s < K && row < rows && kG[k] >= 0) ? Cf[kcf[k] + (int64_t)row * kst[k]] : T(0);
+    for (int i = 0; i < kHPre; ++i) {
+      const int e = tid + kHT * i, k = kb + (e >> 6), cl = blk * kHCB + (e & (kHCB - 1));
+      const int kk = k < K ? k : kb;
+      const int G = k < K ? kG[kk] : -1;
+      const T v = Dm[(int64_t)krow[kk] * d.ntot + cD[cl]];
+      const bool keep = G >= 0 && cSl[cl] >= 0 && d.keepD[(int64_t)G * N + cAt[cl]];
+      pv[i] = keep ? v : T(0);
     }
-    for (int e = tid; e < K * kHCols; e += kNT) {
-      const int k = e / kHCols, cl = e - k * kHCols;
-      const int G = kG[kb + k];
-      T v = 0;
-      if (G >= 0 && cSl[cl] >= 0 && d.keepD[(int64_t)G * d.N + cAt[cl]])
-        v = Dm[(int64_t)krow[kb + k] * d.ntot + cD[cl]];
-      Ds[k * kHCols + cl] = v;
+  };
+  T af[kHPass / 4];
+  auto load_a = [&](int p) {
+    const int kb = p * kHPass;
+#pragma unroll
+    for (int t = 0; t < kHPass / 4; ++t) {
+      const int k = kb + 4 * t + g;
+      af[t] = (k < K && row < rows && kG[k] >= 0) ? Cf[kcf[k] + (int64_t)row * kst[k]] : T(0);
     }
+  };
+  typename M::acc acc[kHCB / 16];
+#pragma unroll
+  for (int j = 0; j < kHCB / 16; ++j) acc[j] = typename M::acc{0, 0, 0, 0};
+  T* H = Buf<T>::H(d);
+  if (steps > 0) fetch(0);
+  load_a(0);
+  for (int st = 0; st < steps; ++st) {
+    const int blk = st / npass, p = st - blk * npass;
+    T* D2 = Ds[st & 1];
+#pragma unroll
+    for (int i = 0; i < kHPre; ++i) D2[tid + kHT * i] = pv[i];
+    if (st + 1 < steps) fetch(st + 1);
+    if (npass > 1 && st > 0) load_a(p);
     __syncthreads();
+    const int Kp = min(kHPass, K - p * kHPass);
 #pragma unroll
-    for (int s = 0; s < kHPass / 4; ++s) {
-      if (4 * s < K) {
+    for (int t = 0; t < kHPass / 4; ++t) {
+      if (4 * t < Kp) {
 #pragma unroll
-        for (int j = 0; j < kHCols / 16; ++j) acc[j] = M::mma(af[s], Ds[(4 * s + g) * kHCols + 16 * j + q], acc[j]);
+        for (int j = 0; j < kHCB / 16; ++j) acc[j] = M::mma(af[t], D2[(4 * t + g) * kHCB + 16 * j + q], acc[j]);
       }
     }
-    __syncthreads();
-  }
-  T* H = Buf<T>::H(d);
+    if (p == npass - 1) {
 #pragma unroll
-  for (int j = 0; j < kHCols / 16; ++j) {
-    const int cl = 16 * j + q;
-    const int s = cSl[cl];
-    if (s < 0) continue;
-    const int nX = d.nao[d.slotX[s]], x = cX[cl];
-    T* Hout = H + d.hOff[s];
-    for (int i = 0; i < 4; ++i) {
-      const int r = r0 + 16 * w + M::row(g, i);
-      if (r < rows) {
-        const int be = r / nB, bb = r - be * nB;
-        Hout[((int64_t)bb * mBp + be) * nX + x] = acc[j][i];
+      for (int j = 0; j < kHCB / 16; ++j) {
+        const int cl = blk * kHCB + 16 * j + q;
+        const int sl = cSl[cl];
+        if (sl >= 0) {
+          const int X = cAt[cl], nX = d.nao[X], x = cD[cl] - (int)d.ao[X];
+          T* Hout = H + d.hOff[sl] + x;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (orow[i] >= 0) Hout[(int64_t)orow[i] * nX] = acc[j][i];
+        }
+        acc[j] = typename M::acc{0, 0, 0, 0};
       }
     }
   }
@@ -1117,9 +1150,9 @@ void launch_triple_group(const TripleLaunch& tl, int mt, int prec, hipStream_t s
 void launch_hbuild(const Dev& d, int prec, hipStream_t s) {
   if (!d.nHB) return;
   if (prec == kP64)
-    hipLaunchKernelGGL(k_hbuild<double>, dim3(d.nHB), dim3(kNT), 0, s, d);
+    hipLaunchKernelGGL(k_hbuild<double>, dim3(d.nHB), dim3(kHT), 0, s, d);
   else
-    hipLaunchKernelGGL(k_hbuild<float>, dim3(d.nHB), dim3(kNT), 0, s, d);
+    hipLaunchKernelGGL(k_hbuild<float>, dim3(d.nHB), dim3(kHT), 0, s, d);
 }
 
 void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork) {

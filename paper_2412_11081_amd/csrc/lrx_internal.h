@@ -38,7 +38,8 @@ constexpr int kMaxAlphaTiles = (kMaxNabf + 15) / 16;
 // these columns and the Y tiles of these columns in registers).
 __host__ __device__ constexpr int unit_cols(int alpha_tiles) { return alpha_tiles <= 5 ? 176 : 128; }
 constexpr int kSideStreams = 3;    // extra streams: alpha-tile groups of the triple kernel run concurrently
-constexpr int kHRows = 64;         // rows (beta,b) of H one H-build workgroup owns
+constexpr int kHRows = 128;        // rows (beta,b) of H one H-build workgroup owns
+constexpr int kHItemCols = 256;    // columns (X,x) of H one H-build workgroup owns
 constexpr int kHMaxDepth = 512;    // max sum of NAOs over the C partners of one atom
 constexpr int kHPass = 64;         // depth of one H-build pass
 
