@@ -123,6 +123,14 @@ __device__ inline int xcd_remap(int b, int G) {
   return x < r ? x * q + pos : r * q + (x - r) * (q - 1) + pos;
 }
 
+// Entry i of a table that the reading kernel does not write, read through the
+// constant address space: at a uniform index the compiler can then use a
+// scalar load (scalar cache, scalar registers) instead of a vector load.
+template <class T>
+__device__ __forceinline__ T ldu(const T* p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
 // ---------------------------------------------------------------------------
 // H(B,X)[b][beta][x] = sum_{G alive} sum_g Cf(B,G)[beta][b][g] D(G,X)[g][x].
 // Per atom B this is one dense product: rows (beta,b), depth (G,g) over the
@@ -260,7 +268,8 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
 // "chunks" = (live V pair (A,B), 16 rows beta0..beta0+15 of B's ABFs):
 //   X-build (all waves, matrix cores, operands in LDS):
 //       X1[beta][a f] = sum_b D_AB[a][b] H(B,F)[b][beta][f]
-//           tiles of 16 rows a x 16 columns of the flattened (beta, f) index
+//           tiles of 16 rows a (from the unit's first a) x 16 columns of the
+//           flattened (beta, f) index
 //       X2[beta][a f] = sum_b H(B,A)[b][beta][a] D_FB[f][b]
 //           tiles of one a: 16 rows beta x 16 columns f
 //       Only the tiles that reach the unit's column chunk are formed; each
@@ -289,12 +298,11 @@ struct TripleCfg {
   static constexpr int kXW = 8;                                              // waves taking part
   static constexpr int kNUZ = 2;                                             // tiles in flight: Z waves
   static constexpr int kNUY = (P == kP64 && MT >= 5) ? 1 : 2;                 // Y waves
-  static constexpr int kLds = 163840 - 256;     // the last 256 bytes hold the persistent item slot
+  static constexpr int kLds = 163840 - 256;     // X, Z partials and the stage; the rest holds the item slot
   static constexpr int kE = 16 / sizeof(T);
   static constexpr int kStage =
       (kLds - (int)sizeof(T) * 2 * 16 * kXS - (int)sizeof(A) * 3 * MT * 256) / (int)sizeof(T) / kE * kE;
   static_assert(2 * kMaxNao * kMaxNao + 16 * 16 * MT + kE <= kStage, "stage holds D and V of any chunk");
-  static constexpr size_t lds_bytes() { return kLds + 256; }
 };
 
 constexpr int kTNT = 512;
@@ -313,7 +321,7 @@ struct Div {
 
 struct UnitGeo {
   int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, fpos, vp0, nVpA, vb, ve, split;
-  int a0, tr0, N1, N2, TF;   // X-build tiles: rows a0.. of term 1, a's of term 2
+  int a0, N1, N2, TF;        // X-build tiles: term 1 rows from a0 (16 per tile), term 2 one a per tile
   int pF, pA;                // 16-byte pieces per staged H row (F and A slices)
   Div dnF, dpF, dpA;
 };
@@ -324,14 +332,14 @@ struct Chunk {
 
 __device__ inline Chunk chunk_at(const Dev& d, const UnitGeo& U, int p, int b0) {
   Chunk c;
-  for (; p < U.ve && !d.aliveV[p]; ++p) {
+  for (; p < U.ve && !ldu(d.aliveV, p); ++p) {
   }
   c.p = p < U.ve ? p : -1;
   c.b0 = b0;
   if (c.p >= 0) {
-    c.B = d.vpB[c.p];
-    c.mB = d.nabf[c.B];
-    c.nB = d.nao[c.B];
+    c.B = ldu(d.vpB, c.p);
+    c.mB = ldu(d.nabf, c.B);
+    c.nB = ldu(d.nao, c.B);
   } else {
     c.B = c.mB = c.nB = 0;
   }
@@ -347,7 +355,7 @@ __device__ inline Chunk chunk_next(const Dev& d, const UnitGeo& U, const Chunk& 
   return chunk_at(d, U, c.p + 1, 0);
 }
 __device__ inline int64_t chunk_tri(const Dev& d, const UnitGeo& U, const Chunk& c) {
-  return d.tBase[U.A] + (int64_t)U.fpos * U.nVpA + (c.p - U.vp0);
+  return ldu(d.tBase, U.A) + (int64_t)U.fpos * U.nVpA + (c.p - U.vp0);
 }
 
 // Chunk stage in LDS (elements of T):
@@ -399,23 +407,21 @@ struct Stager {
   char* sH;
 
   __device__ void init(const Dev& d, const UnitGeo& U, const Chunk& c, const StageGeo& sg, bool with_d, bool with_h,
-                       T* S) {
-    const T* Dm = Buf<T>::D(d);
+                       T* S, const T* Dm, const T* Vfg, const T* H) {
     nB = c.nB;
     dRow = (unsigned)(d.ntot * sizeof(T));
-    dA = (const char*)(Dm + d.ao[U.A] * d.ntot + d.ao[c.B]);
-    dF = (const char*)(Dm + d.ao[U.F] * d.ntot + d.ao[c.B]);
+    dA = (const char*)(Dm + ldu(d.ao, U.A) * d.ntot + ldu(d.ao, c.B));
+    dF = (const char*)(Dm + ldu(d.ao, U.F) * d.ntot + ldu(d.ao, c.B));
     dB.init(nB);
     PA = W * U.nA * nB;
     PD = with_d ? PA + W * U.nF * nB : 0;
     const int mBp = (c.mB + 15) & ~15;
-    v0 = (const char*)(Buf<T>::Vf(d) + d.vfOff[c.p] + c.b0);
+    v0 = (const char*)(Vfg + ldu(d.vfOff, c.p) + c.b0);
     vRow = (unsigned)(mBp * sizeof(T));
     PV = PR * U.mA;
     const int64_t t = chunk_tri(d, U, c);
-    const T* H = Buf<T>::H(d);
-    hF = (const char*)(H + d.triHF[t] + (int64_t)c.b0 * U.nF);
-    hA = (const char*)(H + d.triHA[t] + (int64_t)c.b0 * U.nA);
+    hF = (const char*)(H + ldu(d.triHF, t) + (int64_t)c.b0 * U.nF);
+    hA = (const char*)(H + ldu(d.triHA, t) + (int64_t)c.b0 * U.nA);
     hRowF = (unsigned)(mBp * U.nF * sizeof(T));
     hRowA = (unsigned)(mBp * U.nA * sizeof(T));
     PF = c.nB * U.pF;
@@ -485,7 +491,8 @@ __device__ inline void lds_sync() {
 // X-build of one chunk: this wave's tiles t = w, w+XW, ... of the N1 term-1
 // tiles followed by the N2 term-2 tiles (XW waves take part), NU at a time
 // (NU independent accumulation chains on the matrix core).  The b index runs in
-// k-steps of 4, two steps per pass (a step past nB has zero operands).
+// k-steps of 4 (the part of a step past nB has zero operands), two steps per
+// pass and one in an odd last pass.
 // DIRECT: the H slices are read from global memory (chunks whose slices
 // exceed the LDS stage); otherwise from the stage.
 template <class T, bool DIRECT, int NU, int XW>
@@ -507,17 +514,17 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
       on[u] = t < NT;
       const int tt = on[u] ? t : t0;
       if (tt < U.N1) {
-        const int rt = U.dnF(tt), tr = U.tr0 + rt, tc = tt - rt * U.nF;
-        ap[u] = Dab + __umul24((unsigned)min(16 * tr + q, U.nA - 1), (unsigned)nB);
+        const int rt = U.dnF(tt), ar = U.a0 + 16 * rt, tc = tt - rt * U.nF;
+        ap[u] = Dab + __umul24((unsigned)min(ar + q, U.nA - 1), (unsigned)nB);
         as[u] = 1;
         const int c = 16 * tc + q, be = U.dnF(c), f = c - be * U.nF;
         bp[u] = HF + c;
         bs[u] = hsF;
         xb[u] = X1 + __umul24((unsigned)be, (unsigned)U.XS);
-        kb[u] = 16 * tr * U.nF + f - U.k0;
+        kb[u] = ar * U.nF + f - U.k0;
         ks[u] = U.nF;
         rs[u] = 0;
-        rl[u] = U.nA - 16 * tr;
+        rl[u] = U.nA - ar;
         lok[u] = true;
         kp[u] = kAB;
       } else {
@@ -560,9 +567,11 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
       T an[NU][2], bn[NU][2];
       load(s0 + 2, an, bn);
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
+      for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][0], bv[u][0], acc[u]);
+      if (s0 + 1 < SB) {   // an odd last pass has one k-step
 #pragma unroll
-        for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][s], bv[u][s], acc[u]);
+        for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][1], bv[u][1], acc[u]);
+      }
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
@@ -585,7 +594,11 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
 }
 
 template <int MT, int P, bool ZROLE>
-__device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb, int w, int lane, int q, int g) {
+__device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<MT, P>::T* __restrict__ X1,
+                            typename TripleCfg<MT, P>::A* __restrict__ Zred, typename TripleCfg<MT, P>::T* __restrict__ S,
+                            const typename TripleCfg<MT, P>::T* __restrict__ Dg,
+                            const typename TripleCfg<MT, P>::T* __restrict__ Vg,
+                            const typename TripleCfg<MT, P>::T* __restrict__ Hg, int w, int lane, int q, int g) {
   using Cfg = TripleCfg<MT, P>;
   using T = typename Cfg::T;
   using M = M4<T>;
@@ -593,15 +606,13 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
   using A = typename Cfg::A;
   constexpr bool B3 = P == kPB3;
   constexpr int NU = ZROLE ? Cfg::kNUZ : Cfg::kNUY;
-  T* X1 = (T*)ldsb;
+  // X1 and X2 (X), Zred (partial Z tiles on their way to the owning wave) and
+  // S (the chunk stage) are distinct LDS objects
   T* X2 = X1 + 16 * Cfg::kXS;
-  A* Zred = (A*)(X2 + 16 * Cfg::kXS);   // partial Z tiles on their way to the owning wave
-  T* S = (T*)(Zred + 3 * MT * 256);     // chunk stage
   const int ww = w & 3;
   const int N = d.N;
   const int mA = U.mA, XS = U.XS;
   const T* Cf = Buf<T>::Cf(d);
-  const T* Hg = Buf<T>::H(d);
 
   // ---- resident operands / accumulators of the role ----------------------
   constexpr int ZI = ZROLE ? MT : 1, ZT = ZROLE ? Cfg::kKSW : 1;
@@ -610,7 +621,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
   s4 cfh[B3 ? ZI : 1][B3 ? ZT : 1], cfl[B3 ? ZI : 1][B3 ? ZT : 1];
   Acc yacc[YI][YJ];
   if constexpr (ZROLE) {
-    const T* Cfp = Cf + d.cfOff[U.cp];
+    const T* Cfp = Cf + ldu(d.cfOff, U.cp);
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -644,14 +655,14 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
   StageGeo sg = stage_geo<T>(U, ch.nB);
   if (ch.p >= 0) {
     Stager<T> st;
-    st.init(d, U, ch, sg, true, sg.hend <= Cfg::kStage, S);
+    st.init(d, U, ch, sg, true, sg.hend <= Cfg::kStage, S, Dg, Vg, Hg);
     for (int J = w; J < st.n; J += 8) st.issue(J, lane, U);
   }
   __builtin_amdgcn_s_waitcnt(0);
   lds_sync();
   while (ch.p >= 0) {
     const Chunk nx = chunk_next(d, U, ch);
-    const bool kAB = d.keepD[(int64_t)U.A * N + ch.B], kFB = d.keepD[(int64_t)U.F * N + ch.B];
+    const bool kAB = ldu(d.keepD, (int64_t)U.A * N + ch.B), kFB = ldu(d.keepD, (int64_t)U.F * N + ch.B);
     const int64_t tri = chunk_tri(d, U, ch);
     // V fragments of this chunk (Y waves), read before the stage is reused
     T avn[(ZROLE || B3) ? 1 : 4][(ZROLE || B3) ? 1 : MT];
@@ -684,18 +695,23 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
                               S + U.nA * ch.nB, kAB, kFB, X1, X2, w, q, g);
     } else {
       const int mBp = (ch.mB + 15) & ~15;
-      xbuild<T, true, NU, Cfg::kXW>(U, ch.nB, Hg + d.triHF[tri] + (int64_t)ch.b0 * U.nF, mBp * U.nF,
-                             Hg + d.triHA[tri] + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * ch.nB, kAB, kFB,
+      xbuild<T, true, NU, Cfg::kXW>(U, ch.nB, Hg + ldu(d.triHF, tri) + (int64_t)ch.b0 * U.nF, mBp * U.nF,
+                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * ch.nB, kAB, kFB,
                              X1, X2, w, q, g);
     }
     lds_sync();
     // ---- stage the next chunk while this one is contracted --------------
+    // Each role reads its X operands first and only then issues the loads of
+    // the next chunk: an LDS read placed after those loads would wait for
+    // them to land (the compiler cannot tell the stage from X).
     const StageGeo sn = stage_geo<T>(U, nx.nB);
-    if (nx.p >= 0) {
-      Stager<T> st;
-      st.init(d, U, nx, sn, nx.p != ch.p, sn.hend <= Cfg::kStage, S);
-      for (int J = w; J < st.n; J += 8) st.issue(J, lane, U);
-    }
+    auto stage_next = [&] {
+      if (nx.p >= 0) {
+        Stager<T> st;
+        st.init(d, U, nx, sn, nx.p != ch.p, sn.hend <= Cfg::kStage, S, Dg, Vg, Hg);
+        for (int J = w; J < st.n; J += 8) st.issue(J, lane, U);
+      }
+    };
     if constexpr (ZROLE) {
       Acc zp[MT];
 #pragma unroll
@@ -703,6 +719,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
       if constexpr (B3) {
         // k-steps past the chunk's columns meet zero Cf fragments; their X
         // reads may leave the row, so the values are dropped as well
+        s4 bh[Cfg::kKSW], bl[Cfg::kKSW];
 #pragma unroll
         for (int t = 0; t < Cfg::kKSW; ++t) {
           const int ks = ww + 4 * t;
@@ -712,10 +729,15 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
             const int c = min(16 * ks + 4 * g + j, XS - 1);
             v[j] = ks < U.NTc ? X1[q * XS + c] + X2[q * XS + c] : 0.f;
           }
-          s4 bh, bl;
-          split4(v, bh, bl);
+          split4(v, bh[t], bl[t]);
+        }
+        stage_next();
+        // k-steps past the chunk's columns are skipped (uniform per wave)
 #pragma unroll
-          for (int i = 0; i < MT; ++i) zp[i] = mma_bf16x3(cfh[i][t], cfl[i][t], bh, bl, zp[i]);
+        for (int t = 0; t < Cfg::kKSW; ++t) {
+          if (ww + 4 * t >= U.NTc) break;
+#pragma unroll
+          for (int i = 0; i < MT; ++i) zp[i] = mma_bf16x3(cfh[i][t], cfl[i][t], bh[t], bl[t], zp[i]);
         }
       } else {
         // columns 4 ks + g < kCols < XS; past the chunk's columns X and the
@@ -726,10 +748,14 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
           const int c = (int)__umul24((unsigned)q, (unsigned)XS) + 4 * (ww + 4 * t) + g;
           xb[t] = X1[c] + X2[c];
         }
+        stage_next();
+        // k-steps past the chunk's columns are skipped (uniform per wave)
 #pragma unroll
-        for (int t = 0; t < Cfg::kKSW; ++t)
+        for (int t = 0; t < Cfg::kKSW; ++t) {
+          if (ww + 4 * t >= U.KS) break;
 #pragma unroll
           for (int i = 0; i < MT; ++i) zp[i] = M::mma(cfr[i][t], xb[t], zp[i]);
+        }
       }
       // tile i is owned by Z wave (i mod 4); the other three park their partials
 #pragma unroll
@@ -739,7 +765,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
       }
       __builtin_amdgcn_s_waitcnt(0);
       lds_sync();
-      T* Zdst = Buf<T>::Z(d) + d.zOff[tri] + (int64_t)U.kc * mA * ch.mB;
+      T* Zdst = Buf<T>::Z(d) + ldu(d.zOff, tri) + (int64_t)U.kc * mA * ch.mB;
       const int be = ch.b0 + q;
 #pragma unroll
       for (int i = 0; i < MT; ++i) {
@@ -756,6 +782,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
     } else {
       if constexpr (B3) {
         // column tiles j >= NTc accumulate values that are never stored
+        s4 bh[Cfg::kJW], blo[Cfg::kJW];
 #pragma unroll
         for (int jj = 0; jj < Cfg::kJW; ++jj) {
           if (jj == Cfg::kJW - 1 && jj >= nYJ) break;
@@ -766,10 +793,14 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
             const int bl = 4 * g + k, c = min(16 * j + q, XS - 1);
             v[k] = X1[bl * XS + c] + X2[bl * XS + c];
           }
-          s4 bh, blo;
-          split4(v, bh, blo);
+          split4(v, bh[jj], blo[jj]);
+        }
+        stage_next();
 #pragma unroll
-          for (int i = 0; i < MT; ++i) yacc[i][jj] = mma_bf16x3(avh[i], avl[i], bh, blo, yacc[i][jj]);
+        for (int jj = 0; jj < Cfg::kJW; ++jj) {
+          if (jj == Cfg::kJW - 1 && jj >= nYJ) break;
+#pragma unroll
+          for (int i = 0; i < MT; ++i) yacc[i][jj] = mma_bf16x3(avh[i], avl[i], bh[jj], blo[jj], yacc[i][jj]);
         }
       } else {
         // column tiles j >= NTc accumulate values that are never stored; the
@@ -784,6 +815,14 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
             const int e = (int)__umul24((unsigned)bl, (unsigned)XS) + c;
             xb[s][jj] = X1[e] + X2[e];
           }
+        if (JF < nYJ) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int bl = 4 * s + g, e = (int)__umul24((unsigned)bl, (unsigned)XS) + 16 * (ww + 4 * JF) + q;
+            xb[s][JF] = X1[e] + X2[e];
+          }
+        }
+        stage_next();
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -791,11 +830,6 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
 #pragma unroll
             for (int i = 0; i < MT; ++i) yacc[i][jj] = M::mma(avn[s][i], xb[s][jj], yacc[i][jj]);
         if (JF < nYJ) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int bl = 4 * s + g, e = (int)__umul24((unsigned)bl, (unsigned)XS) + 16 * (ww + 4 * JF) + q;
-            xb[s][JF] = X1[e] + X2[e];
-          }
 #pragma unroll
           for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -809,7 +843,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
     sg = sn;
   }
   if constexpr (!ZROLE) {
-    T* Y = Buf<T>::Y(d) + d.yOff[U.cp] + (int64_t)U.split * mA * U.K1;
+    T* Y = Buf<T>::Y(d) + ldu(d.yOff, U.cp) + (int64_t)U.split * mA * U.K1;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -828,35 +862,35 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, unsigned char* ldsb,
 
 // One work unit of structure d: geometry, X cleared, then the two roles.
 template <int MT, int P>
-__device__ __forceinline__ void triple_unit(const Dev& d, int u, unsigned char* ldsb) {
+__device__ __forceinline__ void triple_unit(const Dev& d, int u, typename TripleCfg<MT, P>::T* X,
+                                            typename TripleCfg<MT, P>::A* Zred, typename TripleCfg<MT, P>::T* S) {
   using Cfg = TripleCfg<MT, P>;
   using T = typename Cfg::T;
   UnitGeo U;
-  U.cp = d.unitCp[u];
-  if (!d.aliveC[U.cp]) return;
-  U.A = d.cpA[U.cp];
-  U.F = d.cpF[U.cp];
-  U.mA = d.nabf[U.A];
-  U.nA = d.nao[U.A];
-  U.nF = d.nao[U.F];
+  U.cp = ldu(d.unitCp, u);
+  if (!ldu(d.aliveC, U.cp)) return;
+  U.A = ldu(d.cpA, U.cp);
+  U.F = ldu(d.cpF, U.cp);
+  U.mA = ldu(d.nabf, U.A);
+  U.nA = ldu(d.nao, U.A);
+  U.nF = ldu(d.nao, U.F);
   U.K1 = U.nA * U.nF;
-  U.k0 = d.unitK0[u];
-  U.Kc = d.unitK1[u] - U.k0;
-  U.kc = d.unitKc[u];
+  U.k0 = ldu(d.unitK0, u);
+  U.Kc = ldu(d.unitK1, u) - U.k0;
+  U.kc = ldu(d.unitKc, u);
   U.NTc = (U.Kc + 15) >> 4;
   U.KS = U.NTc * 4;
   U.XS = U.NTc * 16 + 1;
-  U.fpos = U.cp - d.cpRow[U.A];
-  U.vp0 = d.vpRow[U.A];
-  U.nVpA = d.vpRow[U.A + 1] - U.vp0;
-  U.vb = d.unitV0[u];
-  U.ve = d.unitV1[u];
-  U.split = d.unitS[u];
+  U.fpos = U.cp - ldu(d.cpRow, U.A);
+  U.vp0 = ldu(d.vpRow, U.A);
+  U.nVpA = ldu(d.vpRow, U.A + 1) - U.vp0;
+  U.vb = ldu(d.unitV0, u);
+  U.ve = ldu(d.unitV1, u);
+  U.split = ldu(d.unitS, u);
   U.dnF.init(U.nF);
   U.a0 = U.dnF(U.k0);
   const int a1 = U.dnF(U.k0 + U.Kc - 1);
-  U.tr0 = U.a0 >> 4;
-  U.N1 = ((a1 >> 4) - U.tr0 + 1) * U.nF;
+  U.N1 = ((a1 - U.a0) / 16 + 1) * U.nF;
   U.TF = (U.nF + 15) >> 4;
   U.N2 = (a1 - U.a0 + 1) * U.TF;
   U.pF = 16 * U.nF * (int)sizeof(T) / 16;
@@ -865,13 +899,12 @@ __device__ __forceinline__ void triple_unit(const Dev& d, int u, unsigned char* 
   U.dpA.init(U.pA);
   const int tid = threadIdx.x, lane = tid & 63, q = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
-  T* X = (T*)ldsb;
   for (int e = tid; e < 32 * Cfg::kXS; e += kTNT) X[e] = T(0);
   __syncthreads();
   if (w < 4)
-    triple_role<MT, P, true>(d, U, ldsb, w, lane, q, g);
+    triple_role<MT, P, true>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
   else
-    triple_role<MT, P, false>(d, U, ldsb, w, lane, q, g);
+    triple_role<MT, P, false>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
 }
 
 // items[i] = (structure index into devs, unit index of that structure).
@@ -883,12 +916,18 @@ __device__ __forceinline__ void triple_unit(const Dev& d, int u, unsigned char* 
 template <int MT, int P, bool PERSIST>
 __global__ void __launch_bounds__(kTNT, 1)
     k_triple(DevBatch devs, const int2* __restrict__ items, int n, int* __restrict__ counters) {
-  extern __shared__ __attribute__((aligned(32))) unsigned char ldsb[];
+  using Cfg = TripleCfg<MT, P>;
+  // three LDS objects: the compiler tells the stage (written by direct
+  // global->LDS loads) apart from X and the Z partials, so the products read
+  // those without waiting for the next chunk's loads to land
+  __shared__ __attribute__((aligned(16))) typename Cfg::T sX[2 * 16 * Cfg::kXS];
+  __shared__ __attribute__((aligned(16))) typename Cfg::A sZ[3 * MT * 256];
+  __shared__ __attribute__((aligned(16))) typename Cfg::T sS[Cfg::kStage];
+  __shared__ int s_next;
   if constexpr (!PERSIST) {
     const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    triple_unit<MT, P>(devs.s[it.x], it.y, ldsb);
+    triple_unit<MT, P>(devs.s[it.x], it.y, sX, sZ, sS);
   } else {
-    int& s_next = *(int*)(ldsb + TripleCfg<MT, P>::kLds);
     const int q = (n + 7) >> 3;
     for (int k = 0; k < 8; ++k) {
       const int seg = (blockIdx.x + k) & 7;
@@ -896,11 +935,13 @@ __global__ void __launch_bounds__(kTNT, 1)
       for (;;) {
         if (threadIdx.x == 0) s_next = s0 + atomicAdd(&counters[seg], 1);
         __syncthreads();
-        const int i = s_next;
+        // every lane read the same slot: made uniform, so the item, its
+        // structure and everything derived from them live in scalar registers
+        const int i = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
         if (i >= s1) break;
-        const int2 it = items[i];
-        triple_unit<MT, P>(devs.s[it.x], it.y, ldsb);
+        const int* it = (const int*)items + 2 * i;
+        triple_unit<MT, P>(devs.s[ldu(it, 0)], ldu(it, 1), sX, sZ, sS);
       }
     }
   }
@@ -1103,23 +1144,13 @@ template <int MT, int P>
 static void launch_triple(const TripleLaunch& tl, hipStream_t s) {
   const int n = tl.n[MT];
   if (n <= 0) return;
-  const size_t lds = TripleCfg<MT, P>::lds_bytes();
-  // once per process (thread-safe initialisation of a function-local static)
-  static const bool attr = [lds] {
-    (void)hipFuncSetAttribute((const void*)k_triple<MT, P, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_triple<MT, P, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    return true;
-  }();
-  (void)attr;
   if (tl.mode[MT] == 1) {
     int* cnt = tl.counters + 8 * MT;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, cnt, 8, 0);
-    hipLaunchKernelGGL((k_triple<MT, P, true>), dim3(kPersistentGrid), dim3(kTNT), lds, s, tl.devs, tl.items[MT], n,
+    hipLaunchKernelGGL((k_triple<MT, P, true>), dim3(kPersistentGrid), dim3(kTNT), 0, s, tl.devs, tl.items[MT], n,
                        cnt);
   } else {
-    hipLaunchKernelGGL((k_triple<MT, P, false>), dim3(n), dim3(kTNT), lds, s, tl.devs, tl.items[MT], n,
+    hipLaunchKernelGGL((k_triple<MT, P, false>), dim3(n), dim3(kTNT), 0, s, tl.devs, tl.items[MT], n,
                        (int*)nullptr);
   }
 }
