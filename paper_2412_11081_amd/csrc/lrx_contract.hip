@@ -156,6 +156,10 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
   __shared__ int cD[kHItemCols], cAt[kHItemCols], cSl[kHItemCols];
   __shared__ int kdepth;
   __shared__ T Ds[2][kHPass * kHCB];
+  // D-pair keep flags of the item as a local table [C pair of B][slot],
+  // when B has at most 32 C pairs and the item spans at most 64 slots
+  __shared__ unsigned char keepL[32 * 64];
+  __shared__ signed char kgi[kHMaxDepth], cxi[kHItemCols];
   const T* Cf = Buf<T>::Cf(d);
   const T* Dm = Buf<T>::D(d);
   const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x], c0 = d.hbC0[blockIdx.x];
@@ -163,6 +167,9 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
   const int ncols = min(kHItemCols, d.hColRow[B + 1] - d.hColRow[B] - c0);
   const int tid = threadIdx.x, lane = tid & 63, q = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
+  const int cp0 = d.cpRow[B], ncp = d.cpRow[B + 1] - cp0;
+  const int s0 = d.hColSlot[d.hColRow[B] + c0], nsl = d.hColSlot[d.hColRow[B] + c0 + ncols - 1] - s0 + 1;
+  const bool local = ncp <= 32 && nsl <= 64;
   {
     const int h0 = d.hdRow[B], hn = d.hdRow[B + 1] - h0;
     for (int k = tid; k < hn; k += kHT) {
@@ -172,6 +179,7 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
       kG[k] = live ? d.hdG[h0 + k] : -1;
       kcf[k] = d.hdCf[h0 + k];
       kst[k] = d.hdStride[h0 + k];
+      kgi[k] = (signed char)(t >= 0 && local ? (t >> 6) - cp0 : 0);
     }
     for (int cl = tid; cl < kHItemCols; cl += kHT) {
       const bool in = cl < ncols;
@@ -180,7 +188,13 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
       cSl[cl] = in && d.need[sl] ? sl : -1;
       cD[cl] = d.hColD[c];           // a valid D column also past the item's end
       cAt[cl] = d.hColAtom[c];
+      cxi[cl] = (signed char)(local ? sl - s0 : 0);
     }
+    if (local)
+      for (int e = tid; e < ncp * nsl; e += kHT) {
+        const int gi = e / nsl, xi = e - gi * nsl;
+        keepL[gi * 64 + xi] = d.keepD[(int64_t)d.cpF[cp0 + gi] * d.N + d.slotX[s0 + xi]];
+      }
     if (tid == 0) kdepth = hn;
   }
   __syncthreads();
@@ -209,7 +223,8 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
       const int kk = k < K ? k : kb;
       const int G = k < K ? kG[kk] : -1;
       const T v = Dm[(int64_t)krow[kk] * d.ntot + cD[cl]];
-      const bool keep = G >= 0 && cSl[cl] >= 0 && d.keepD[(int64_t)G * N + cAt[cl]];
+      const bool keep = G >= 0 && cSl[cl] >= 0 &&
+                        (local ? keepL[kgi[kk] * 64 + cxi[cl]] != 0 : d.keepD[(int64_t)G * N + cAt[cl]] != 0);
       pv[i] = keep ? v : T(0);
     }
   };
