@@ -148,12 +148,17 @@ int lrx_block_gradients(lrx_ctx* ctx, double* gC, double* gV);
  * keepD [natom][natom]); any pointer may be NULL. */
 int lrx_keep_masks(lrx_ctx* ctx, uint8_t* keepC, uint8_t* keepV, uint8_t* keepD);
 
+#define LRX_MAX_ALPHA_TILES 8
+
 typedef struct {
   int64_t kept_c_blocks, kept_v_blocks, alive_c_pairs, alive_v_pairs;
   int64_t alive_triples;        /* (A,F,B) with (A,F) and (A,B) alive      */
   int64_t h_slots;              /* H(B,X) blocks computed                   */
   double flop_alg;              /* algorithmic FLOPs of one evaluation       */
   double flop_triple;           /* ... of the triple-product kernel alone    */
+  double flop_triple_group[LRX_MAX_ALPHA_TILES + 1];
+                                /* ... of its launch for the atoms A with
+                                 * ceil(n_abf(A) / 16) = MT, by MT          */
   double bytes_alg;             /* algorithmic HBM bytes of one evaluation   */
   double device_bytes;          /* device memory held by the context         */
 } lrx_stats;
@@ -170,6 +175,14 @@ int lrx_get_stats(lrx_ctx* ctx, lrx_stats* out);
 #define LRX_NSTAGES 9
 int lrx_stage_times(lrx_ctx* ctx, float* ms, int32_t n);
 const char* lrx_stage_name(int32_t i);
+
+/* Duration (ms) of each alpha-tile group's triple-product launch in the last
+ * timed evaluation, by MT = 0..LRX_MAX_ALPHA_TILES (0 for empty groups),
+ * from HIP events recorded around the launch on the stream it runs on (the
+ * largest group on the context's stream, the others on side streams, where
+ * the time includes waiting for compute units the largest group holds).
+ * Writes up to n values; returns LRX_MAX_ALPHA_TILES + 1 or a negative code. */
+int lrx_group_times(lrx_ctx* ctx, float* ms, int32_t n);
 
 /* Evaluate several contexts (distinct, all on one device) in one batched
  * pass on the first context's stream.  Per alpha-tile group (the work units
@@ -197,7 +210,6 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
  * plan timed, ms[2*MT + m] the best time of shape m (0 if not timed there),
  * for MT = 0..LRX_MAX_ALPHA_TILES (host buffers, either may be NULL).
  * Returns LRX_MAX_ALPHA_TILES + 1. */
-#define LRX_MAX_ALPHA_TILES 8
 int lrx_batch_tuning(const lrx_ctx* ctx, int32_t* mode, float* ms);
 
 /* Message of the last failing call on this context ("" if none). */

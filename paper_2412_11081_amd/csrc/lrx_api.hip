@@ -206,6 +206,8 @@ struct lrx_ctx {
   std::array<hipEvent_t, lrx::kSideStreams + 1> fork{};
   bool events = false;
   std::array<float, LRX_NSTAGES> stage_ms{};
+  std::array<hipEvent_t, 2 * (lrx::kMaxAlphaTiles + 1)> gev{};   // around each triple group's launch
+  std::array<float, lrx::kMaxAlphaTiles + 1> group_ms{};
   bool timed = false;
   bool evaluated = false;
 
@@ -299,6 +301,7 @@ int lrx_create(lrx_ctx** out, int32_t device, void* hip_stream) {
       c->own_stream = true;
     }
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    for (auto& e : c->gev) HIPCHK(hipEventCreate(&e));
     for (auto& e : c->fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     c->events = true;
     for (auto& st : c->side) st = g_streams.get(device);
@@ -828,6 +831,7 @@ int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
         s->alive_triples++;
         const double t = 4.0 * nb[A] * nb[B] * na[A] * na[Fa] + 4.0 * nb[B] * na[A] * na[B] * na[Fa];
         ft += t;
+        s->flop_triple_group[(nb[A] + 15) / 16] += t;
       }
     }
     for (int sl = 0; sl < d.nSlot; ++sl) {
@@ -844,6 +848,16 @@ int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
     s->bytes_alg = by;
     s->device_bytes = c->dev_bytes;
   });
+}
+
+int lrx_group_times(lrx_ctx* c, float* ms, int32_t n) {
+  if (!c) return LRX_EINVAL;
+  if (!c->timed) {
+    c->err = "no timed evaluation yet";
+    return LRX_ESTATE;
+  }
+  for (int i = 0; i < n && i <= lrx::kMaxAlphaTiles; ++i) ms[i] = c->group_ms[i];
+  return lrx::kMaxAlphaTiles + 1;
 }
 
 int lrx_stage_times(lrx_ctx* c, float* ms, int32_t n) {
@@ -1128,7 +1142,8 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
       lrx::launch_screen(c->dev, o, c->stream, ev);
       c->tl.devs.s[0] = c->dev;
       for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) c->tl.mode[mt] = P->mode[mt];
-      lrx::launch_contract(c->dev, c->tl, opts->precision, c->stream, c->side.data(), c->fork.data(), ev);
+      lrx::launch_contract(c->dev, c->tl, opts->precision, c->stream, c->side.data(), c->fork.data(), ev,
+                           c->gev.data());
     } else {
       launch_plan(*P, opts);
     }
@@ -1139,6 +1154,10 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
     HIPCHK(hipStreamSynchronize(c->stream));
     if (timing) {
       for (int i = 0; i < LRX_NSTAGES; ++i) HIPCHK(hipEventElapsedTime(&c->stage_ms[i], c->ev[i], c->ev[i + 1]));
+      for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) {
+        c->group_ms[mt] = 0.f;
+        if (c->tl.n[mt] > 0) HIPCHK(hipEventElapsedTime(&c->group_ms[mt], c->gev[2 * mt], c->gev[2 * mt + 1]));
+      }
     }
     c->timed = timing;
     c->evaluated = true;
@@ -1216,6 +1235,7 @@ void lrx_destroy(lrx_ctx* c) {
   g_pinned.put(c->h_out, c->h_out_bytes);
   if (c->events) {
     for (auto& e : c->ev) (void)hipEventDestroy(e);
+    for (auto& e : c->gev) (void)hipEventDestroy(e);
     for (auto& e : c->fork) (void)hipEventDestroy(e);
   }
   for (auto& st : c->side) g_streams.put(c->device, st);

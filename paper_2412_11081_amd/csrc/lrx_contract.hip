@@ -1201,7 +1201,8 @@ void launch_hbuild(const Dev& d, int prec, hipStream_t s) {
     hipLaunchKernelGGL(k_hbuild<float>, dim3(d.nHB), dim3(kHT), 0, s, d);
 }
 
-void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork) {
+void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork,
+                    hipEvent_t* gev) {
   // The alpha-tile groups are independent: the largest runs on the main
   // stream, the others on side streams that join back before the gradients.
   int order[kMaxAlphaTiles];
@@ -1218,7 +1219,9 @@ void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipSt
   for (int i = 0; i < ng; ++i) {
     const hipStream_t st = i == 0 ? s : side[(i - 1) % kSideStreams];
     if (i > 0 && i <= kSideStreams) (void)hipStreamWaitEvent(st, fork[0], 0);
+    if (gev) (void)hipEventRecord(gev[2 * order[i]], st);
     launch_triple_group(tl, order[i], prec, st);
+    if (gev) (void)hipEventRecord(gev[2 * order[i] + 1], st);
   }
   for (int i = 1; i <= kSideStreams && i < ng; ++i) {
     (void)hipEventRecord(fork[i], side[i - 1]);
@@ -1245,10 +1248,10 @@ void launch_grads(const Dev& d, int prec, hipStream_t s, hipEvent_t* ev) {
 }
 
 void launch_contract(const Dev& d, const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side,
-                     const hipEvent_t* fork, hipEvent_t* ev) {
+                     const hipEvent_t* fork, hipEvent_t* ev, hipEvent_t* gev) {
   launch_hbuild(d, prec, s);
   if (ev) (void)hipEventRecord(ev[4], s);
-  launch_triples(tl, prec, s, side, fork);
+  launch_triples(tl, prec, s, side, fork, gev);
   if (ev) (void)hipEventRecord(ev[5], s);
   launch_grads(d, prec, s, ev);
 }

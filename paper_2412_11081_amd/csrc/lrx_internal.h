@@ -176,14 +176,17 @@ constexpr int kPersistentGrid = 256;         // workgroups of a mode-1 launch (o
 
 void launch_hbuild(const Dev& d, int prec, hipStream_t s);
 // triple groups of tl: the largest on s, the others on the side streams, joined back into s
-void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork);
+// gev (optional): events recorded around each group's launch on its stream,
+// gev[2 MT] before and gev[2 MT + 1] after
+void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork,
+                    hipEvent_t* gev = nullptr);
 // one group on s (the tuner times groups one at a time)
 void launch_triple_group(const TripleLaunch& tl, int mt, int prec, hipStream_t s);
 void launch_grads(const Dev& d, int prec, hipStream_t s, hipEvent_t* ev);
 // the whole contraction of one structure: hbuild, triples, gradients, forces;
 // ev (optional) receives stage marks ev[4..8]
 void launch_contract(const Dev& d, const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side,
-                     const hipEvent_t* fork, hipEvent_t* ev);
+                     const hipEvent_t* fork, hipEvent_t* ev, hipEvent_t* gev = nullptr);
 void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipStream_t s);
 
 }  // namespace lrx

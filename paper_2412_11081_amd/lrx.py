@@ -55,17 +55,20 @@ class Stats(ctypes.Structure):
                 ("alive_c_pairs", ctypes.c_int64), ("alive_v_pairs", ctypes.c_int64),
                 ("alive_triples", ctypes.c_int64), ("h_slots", ctypes.c_int64),
                 ("flop_alg", ctypes.c_double), ("flop_triple", ctypes.c_double),
+                ("flop_triple_group", ctypes.c_double * 9),
                 ("bytes_alg", ctypes.c_double), ("device_bytes", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {k: getattr(self, k) for k, _ in self._fields_}
+        out["flop_triple_group"] = list(out["flop_triple_group"])
+        return out
 
 
 _lib = None
 
 EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
-           "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim"]
+           "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim", "lrx_group_times"]
 
 
 def load(path: Optional[str] = None):
@@ -95,9 +98,10 @@ def load(path: Optional[str] = None):
     lib.lrx_destroy.argtypes = [vp]
     lib.lrx_destroy.restype = None
     lib.lrx_pool_trim.argtypes = [ctypes.c_int32, ctypes.c_uint64]
+    lib.lrx_group_times.argtypes = [vp, _f32p, ctypes.c_int32]
     for f in ("lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
               "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning",
-              "lrx_pool_trim"):
+              "lrx_pool_trim", "lrx_group_times"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -210,6 +214,14 @@ class Context:
         if rc < 0:
             self._check(rc)
         return {self.lib.lrx_stage_name(i).decode(): float(ms[i]) for i in range(NSTAGES)}
+
+    def group_times(self):
+        """lrx_group_times: {MT: ms} of the triple launches of the last timed evaluation."""
+        ms = (ctypes.c_float * (MAX_ALPHA_TILES + 1))()
+        rc = self.lib.lrx_group_times(self.h, ms, MAX_ALPHA_TILES + 1)
+        if rc < 0:
+            self._check(rc)
+        return {mt: float(ms[mt]) for mt in range(MAX_ALPHA_TILES + 1) if ms[mt] > 0}
 
     def close(self):
         if self.h:
