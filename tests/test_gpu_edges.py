@@ -1,0 +1,139 @@
+"""Edge cases of the HIP path, through the C-ABI, against the CPU oracle:
+everything screened away, a cell of one atom (only its own images), the
+largest block sizes the kernels take (32 NAOs and 128 ABFs per atom: eight
+alpha tiles, H slices too large for the LDS stage), and inputs the library
+must reject with an error instead of computing."""
+import numpy as np
+import pytest
+
+from paper_2412_11081_amd import lrx, synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(oracle_lib, st, theta, theta_cs):
+    mats = st.materialize("cuda")
+    ctx = H.gpu_context(st, mats)
+    E, F, S = ctx.evaluate(theta, theta_cs)
+    gC, gV = ctx.block_gradients()
+    keep = ctx.keep_masks()
+    ctx.close()
+    r = oracle_lib.Problem.from_structure(st, mats).evaluate(theta, theta_cs, nthreads=H.nthreads())
+    return (E, F, S, gC, gV, keep), r
+
+
+def _check(st, got, r):
+    E, F, S, gC, gV, keep = got
+    np.testing.assert_array_equal(keep[0], r["keepC"])
+    np.testing.assert_array_equal(keep[1], r["keepV"])
+    np.testing.assert_array_equal(keep[2], r["keepD"])
+    H.assert_close_fp64("E", E, r["E"], H.TOL_E_PER_ATOM * st.natom)
+    H.assert_close_fp64("F", F, r["F"], H.TOL_F)
+    H.assert_close_fp64("sigma", S, r["sigma"], H.TOL_SIGMA)
+    H.assert_close_fp64("gC", gC, r["gC"], H.TOL_F)
+    H.assert_close_fp64("gV", gV, r["gV"], H.TOL_F)
+
+
+def test_everything_screened(oracle_lib):
+    """A threshold above every block: no block, pair or triple survives; E, F,
+    sigma and every gradient are exactly zero, as in the oracle."""
+    H.require_gpu()
+    st = synth.small_case(natom=3, nspecies=2, n_ao=5, n_abf=17, box=6.5, rc=5.0, rv=8.0, seed=41,
+                          jitter=0.5).build()
+    got, r = _both(oracle_lib, st, 1e6, 1e3)
+    E, F, S, gC, gV, keep = got
+    assert E == 0.0 and not F.any() and not S.any() and not gC.any() and not gV.any()
+    assert not keep[0].any() and not keep[1].any() and not keep[2].any()
+    _check(st, got, r)
+
+
+def test_single_atom_cell(oracle_lib):
+    """One atom: every block is an image of the atom itself (force-free by
+    symmetry up to rounding, stress from the image displacements)."""
+    H.require_gpu()
+    st = synth.small_case(natom=1, nspecies=1, n_ao=7, n_abf=23, box=4.0, rc=5.0, rv=7.5, seed=42,
+                          jitter=0.0).build()
+    print("blocks", len(st.keysC[0]), len(st.keysV[0]), flush=True)
+    got, r = _both(oracle_lib, st, 0.0, 0.0)
+    _check(st, got, r)
+    assert np.max(np.abs(got[1])) <= 1e-10 * max(1.0, np.abs(got[2]).max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_largest_blocks(oracle_lib, prec):
+    """32 NAOs and 128 ABFs on every atom: eight alpha tiles, the widest
+    column chunks, and H slices that exceed the LDS stage (read from HBM)."""
+    H.require_gpu()
+    st = synth.small_case(natom=2, nspecies=1, n_ao=32, n_abf=128, box=7.0, rc=4.5, rv=6.0, seed=43,
+                          jitter=0.5).build()
+    print("blocks", len(st.keysC[0]), len(st.keysV[0]), flush=True)
+    mats = st.materialize("cuda")
+    ctx = H.gpu_context(st, mats)
+    E, F, S = ctx.evaluate(0.0, 0.0, precision=prec)
+    gC, gV = ctx.block_gradients()
+    keep = ctx.keep_masks()
+    ctx.close()
+    r = oracle_lib.Problem.from_structure(st, mats).evaluate(0.0, 0.0, nthreads=H.nthreads())
+    if prec == "fp64":
+        _check(st, (E, F, S, gC, gV, keep), r)
+    else:
+        # the BF16x3 bounds of tests/test_gpu_precision.py
+        assert abs(E - r["E"]) <= 1e-4 * abs(r["E"]) + 1e-8 * st.natom
+        assert np.max(np.abs(F - r["F"])) <= 1e-4
+        assert np.max(np.abs(S - r["sigma"])) <= 1e-5
+
+
+def _fresh(seed=44):
+    st = synth.small_case(natom=2, nspecies=1, n_ao=3, n_abf=5, box=6.0, rc=4.5, rv=7.0, seed=seed,
+                          jitter=0.5).build()
+    return st, st.materialize("cuda")
+
+
+def _expect_rejected(st, C, V, D, words):
+    ctx = lrx.Context(0)
+    ctx.set_structure(st.tau, st.lat, st.nao, st.nabf)
+    with pytest.raises(lrx.LrxError) as e:
+        ctx.set_tensors(C, V, D)
+    msg = str(e.value)
+    print("rejected:", msg, flush=True)
+    assert any(w in msg for w in words), msg
+    ctx.close()
+
+
+def test_non_finite_values_are_rejected():
+    H.require_gpu()
+    st, m = _fresh()
+    C = dict(m["C"])
+    C["val"] = m["C"]["val"].clone()
+    C["val"][3] = float("nan")
+    _expect_rejected(st, C, m["V"], m["D"], ["finite", "NaN", "nan"])
+
+
+def test_asymmetric_density_matrix_is_rejected():
+    H.require_gpu()
+    st, m = _fresh()
+    D = m["D"].clone()
+    D[0, 1] += 1e-3
+    _expect_rejected(st, m["C"], m["V"], D, ["D", "symmetric"])
+
+
+def test_broken_v_mirror_is_rejected():
+    H.require_gpu()
+    st, m = _fresh()
+    V = dict(m["V"])
+    V["val"] = m["V"]["val"].clone()
+    # an off-diagonal element of the first block: its mirror block no longer matches
+    V["val"][1] += 1e-3
+    _expect_rejected(st, m["C"], V, m["D"], ["mirror", "V"])
+
+
+def test_block_sizes_beyond_the_kernels_are_rejected():
+    H.require_gpu()
+    ctx = lrx.Context(0)
+    tau = np.zeros((1, 3))
+    with pytest.raises(lrx.LrxError):
+        ctx.set_structure(tau, np.eye(3) * 5.0, np.array([33], np.int32), np.array([10], np.int32))
+    with pytest.raises(lrx.LrxError):
+        ctx.set_structure(tau, np.eye(3) * 5.0, np.array([10], np.int32), np.array([129], np.int32))
+    ctx.close()
