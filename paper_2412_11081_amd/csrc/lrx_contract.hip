@@ -373,25 +373,43 @@ __device__ inline int64_t chunk_tri(const Dev& d, const UnitGeo& U, const Chunk&
   return ldu(d.tBase, U.A) + (int64_t)U.fpos * U.nVpA + (c.p - U.vp0);
 }
 
-// Chunk stage in LDS (elements of T):
-//   [0, nA nB)            D(A,B)[a][b]       (rewritten only when B changes)
-//   [nA nB, (nA+nF) nB)   D(F,B)[f][b]
-//   [vo, vo + 16 mA)      Vf(A,B)[alpha][beta0 .. beta0+15], 16-byte pieces of a
-//                         row stored in XOR-swizzled order (conflict-free reads)
-//   [ho, ...)             H(B,F)[b][beta][f] then H(B,A)[b][beta][a], 16 rows beta
-// vo = (nA+nF) nB rounded up to 16 bytes, ho = vo + 16 mA.  Everything is
-// brought in with direct global->LDS loads; H only when it fits.
+// Chunk stage in LDS (elements of T), with nBp = nB rounded up to 4 (one
+// k-step of the X-build):
+//   [0, nA nBp)             D(A,B)[a][b], b < nBp, zero for b >= nB
+//   [nA nBp, (nA+nF) nBp)   D(F,B)[f][b]        (both rewritten only when B changes)
+//   [vo, vo + 16 mA)        Vf(A,B)[alpha][beta0 .. beta0+15], 16-byte pieces of a
+//                           row stored in XOR-swizzled order (conflict-free reads)
+//   [ho, ...)               H(B,F)[b][beta][f] then H(B,A)[b][beta][a], 16 rows
+//                           beta, with room for nBp rows of H(B,A)
+// vo = (nA+nF) nBp rounded up to 16 bytes, ho = vo + 16 mA.  Everything but
+// the zero columns of D is brought in with direct global->LDS loads; H only
+// when it fits.  The X-build reads nBp rows b: past nB the D operand is zero
+// and the H operand is finite (H(B,A) rows, or stale stage contents, which
+// start zeroed), so those k-steps add nothing.
 struct StageGeo {
-  int vo, ho, hend;
+  int nBp, vo, ho, hend;
 };
 template <class T>
 __device__ inline StageGeo stage_geo(const UnitGeo& U, int nB) {
   constexpr int E = 16 / sizeof(T);
   StageGeo s;
-  s.vo = ((U.nA + U.nF) * nB + E - 1) / E * E;
+  s.nBp = (nB + 3) & ~3;
+  s.vo = ((U.nA + U.nF) * s.nBp + E - 1) / E * E;
   s.ho = s.vo + 16 * U.mA;
-  s.hend = s.ho + nB * 16 * (U.nF + U.nA);
+  s.hend = s.ho + 16 * (nB * U.nF + s.nBp * U.nA);
   return s;
+}
+
+// Zero columns nB .. nBp-1 of the staged D rows (all threads of the
+// workgroup; issued before any of the stage's direct loads).
+template <class T>
+__device__ inline void zero_d_padding(const UnitGeo& U, int nB, T* S) {
+  const int nBp = (nB + 3) & ~3, pad = nBp - nB;
+  if (pad == 0) return;
+  for (int e = threadIdx.x; e < (U.nA + U.nF) * pad; e += kTNT) {
+    const int r = e / pad;
+    S[r * nBp + nB + (e - r * pad)] = T(0);
+  }
 }
 
 // The direct global->LDS loads that stage one chunk, as a list of 64-lane
@@ -408,7 +426,7 @@ struct Stager {
   const char* dA;                                   // D rows of A at column ao[B]
   const char* dF;
   unsigned dRow;                                    // bytes per D row
-  int nB, PA, PD;
+  int nB, nBp, PA, PD;
   Div dB;
   const char* v0;
   unsigned vRow;                                    // bytes per folded V row
@@ -427,9 +445,10 @@ struct Stager {
     dRow = (unsigned)(d.ntot * sizeof(T));
     dA = (const char*)(Dm + ldu(d.ao, U.A) * d.ntot + ldu(d.ao, c.B));
     dF = (const char*)(Dm + ldu(d.ao, U.F) * d.ntot + ldu(d.ao, c.B));
-    dB.init(nB);
-    PA = W * U.nA * nB;
-    PD = with_d ? PA + W * U.nF * nB : 0;
+    nBp = (nB + 3) & ~3;
+    dB.init(nBp);
+    PA = W * U.nA * nBp;
+    PD = with_d ? PA + W * U.nF * nBp : 0;
     const int mBp = (c.mB + 15) & ~15;
     v0 = (const char*)(Vfg + ldu(d.vfOff, c.p) + c.b0);
     vRow = (unsigned)(mBp * sizeof(T));
@@ -458,10 +477,12 @@ struct Stager {
         const bool ab = pc < PA;
         const int pp = ab ? pc : pc - PA;
         const int e = W == 2 ? pp >> 1 : pp, part = pp - e * W;
-        const int r = dB(e), b = e - r * nB;
+        const int r = dB(e), b = e - r * nBp;
         const unsigned off = __umul24((unsigned)r, dRow) + (unsigned)(b * (int)sizeof(T) + 4 * part);
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((ab ? dA : dF) + off),
-                                         (__attribute__((address_space(3))) void*)(sD + 256 * J), 4, 0, 0);
+        // columns b >= nB are zeroed separately (zero_d_padding)
+        if (b < nB)
+          __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((ab ? dA : dF) + off),
+                                           (__attribute__((address_space(3))) void*)(sD + 256 * J), 4, 0, 0);
       }
     } else if (J < nV) {
       const int j = J - nD, pc = j * 64 + lane;
@@ -514,7 +535,8 @@ template <class T, bool DIRECT, int NU, int XW>
 __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, int hsF, const T* HA, int hsA,
                                        const T* Dab, const T* Dfb, bool kAB, bool kFB, T* X1, T* X2, int w, int q,
                                        int g) {
-  const int SB = (nB + 3) >> 2;
+  const int nBp = (nB + 3) & ~3;   // row stride of the staged D blocks
+  const int SB = nBp >> 2;
   using M = M4<T>;
   const int NT = U.N1 + U.N2;
   for (int t0 = w; t0 < NT; t0 += XW * NU) {
@@ -530,7 +552,7 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
       const int tt = on[u] ? t : t0;
       if (tt < U.N1) {
         const int rt = U.dnF(tt), ar = U.a0 + 16 * rt, tc = tt - rt * U.nF;
-        ap[u] = Dab + __umul24((unsigned)min(ar + q, U.nA - 1), (unsigned)nB);
+        ap[u] = Dab + __umul24((unsigned)min(ar + q, U.nA - 1), (unsigned)nBp);
         as[u] = 1;
         const int c = 16 * tc + q, be = U.dnF(c), f = c - be * U.nF;
         bp[u] = HF + c;
@@ -547,7 +569,7 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
         const int f = 16 * tf + q;
         ap[u] = HA + __umul24((unsigned)q, (unsigned)U.nA) + a;
         as[u] = hsA;
-        bp[u] = Dfb + __umul24((unsigned)min(f, U.nF - 1), (unsigned)nB);
+        bp[u] = Dfb + __umul24((unsigned)min(f, U.nF - 1), (unsigned)nBp);
         bs[u] = 1;
         xb[u] = X2;
         kb[u] = a * U.nF + f - U.k0;
@@ -561,6 +583,45 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
     typename M::acc acc[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
+    if constexpr (!DIRECT) {
+      // every operand is in the stage for b < nBp (zero D columns past nB):
+      // plain loads one k-step ahead, addresses advanced by a fixed stride
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        ap[u] += __umul24((unsigned)g, (unsigned)as[u]);
+        bp[u] += __umul24((unsigned)g, (unsigned)bs[u]);
+      }
+      // two register sets in turn: the loads of step st+1 are in flight
+      // while the product of step st is issued
+      T a0[NU], b0[NU], a1[NU], b1[NU];
+      auto next = [&](T (&av)[NU], T (&bv)[NU]) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          av[u] = *ap[u];
+          bv[u] = *bp[u];
+          ap[u] += 4 * as[u];
+          bp[u] += 4 * bs[u];
+        }
+      };
+      next(a0, b0);
+      int st = 0;
+#pragma unroll 1
+      for (; st + 2 < SB; st += 2) {   // steps st, st+1; the loads run one step ahead
+        next(a1, b1);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[u] = M::mma(a0[u], b0[u], acc[u]);
+        next(a0, b0);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[u] = M::mma(a1[u], b1[u], acc[u]);
+      }
+      if (st + 1 < SB) next(a1, b1);   // the last one or two steps
+#pragma unroll
+      for (int u = 0; u < NU; ++u) acc[u] = M::mma(a0[u], b0[u], acc[u]);
+      if (st + 1 < SB) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[u] = M::mma(a1[u], b1[u], acc[u]);
+      }
+    } else {
     // operands of the next pass are requested before the products of the
     // current one (addresses clamped into the slices; b >= nB gives zero)
     T av[NU][2], bv[NU][2];
@@ -594,6 +655,7 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
           av[u][s] = an[u][s];
           bv[u][s] = bn[u][s];
         }
+    }
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -707,11 +769,11 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
     if (!ZROLE && Cfg::kXW == 4) {
     } else if (sg.hend <= Cfg::kStage) {
       xbuild<T, false, NU, Cfg::kXW>(U, ch.nB, S + sg.ho, 16 * U.nF, S + sg.ho + ch.nB * 16 * U.nF, 16 * U.nA, S,
-                              S + U.nA * ch.nB, kAB, kFB, X1, X2, w, q, g);
+                              S + U.nA * sg.nBp, kAB, kFB, X1, X2, w, q, g);
     } else {
       const int mBp = (ch.mB + 15) & ~15;
       xbuild<T, true, NU, Cfg::kXW>(U, ch.nB, Hg + ldu(d.triHF, tri) + (int64_t)ch.b0 * U.nF, mBp * U.nF,
-                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * ch.nB, kAB, kFB,
+                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * sg.nBp, kAB, kFB,
                              X1, X2, w, q, g);
     }
     lds_sync();
@@ -720,6 +782,9 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
     // the next chunk: an LDS read placed after those loads would wait for
     // them to land (the compiler cannot tell the stage from X).
     const StageGeo sn = stage_geo<T>(U, nx.nB);
+    // a new B: zero the padding columns of its D blocks before any wave
+    // issues the loads that stage them
+    if (nx.p >= 0 && nx.p != ch.p) zero_d_padding(U, nx.nB, S);
     auto stage_next = [&] {
       if (nx.p >= 0) {
         Stager<T> st;
@@ -915,6 +980,8 @@ __device__ __forceinline__ void triple_unit(const Dev& d, int u, typename Triple
   const int tid = threadIdx.x, lane = tid & 63, q = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
   for (int e = tid; e < 32 * Cfg::kXS; e += kTNT) X[e] = T(0);
+  // the stage starts zeroed: padding rows the X-build reads past nB are finite
+  for (int e = tid; e < Cfg::kStage; e += kTNT) S[e] = T(0);
   __syncthreads();
   if (w < 4)
     triple_role<MT, P, true>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
