@@ -745,24 +745,23 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
     T avn[(ZROLE || B3) ? 1 : 4][(ZROLE || B3) ? 1 : MT];
     s4 avh[(!ZROLE && B3) ? MT : 1], avl[(!ZROLE && B3) ? MT : 1];
     if constexpr (!ZROLE) {
+      // element (16 i + q, be) of the staged V is 256 i + vs_index(q, be);
+      // rows past mA read other (finite) stage contents and only feed
+      // accumulator rows that are never stored
       const T* Vs = S + sg.vo;
       if constexpr (B3) {
 #pragma unroll
         for (int i = 0; i < MT; ++i) {
-          const int al = 16 * i + q;
           float v[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) v[j] = al < mA ? Vs[vs_index<T>(al, 4 * g + j)] : 0.f;
+          for (int j = 0; j < 4; ++j) v[j] = Vs[256 * i + vs_index<T>(q, 4 * g + j)];
           split4(v, avh[i], avl[i]);
         }
       } else {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int i = 0; i < MT; ++i) {
-            const int al = 16 * i + q;
-            avn[s][i] = al < mA ? Vs[vs_index<T>(al, 4 * s + g)] : T(0);
-          }
+          for (int i = 0; i < MT; ++i) avn[s][i] = Vs[256 * i + vs_index<T>(q, 4 * s + g)];
       }
     }
     // ---- X-build of this chunk (all waves) ------------------------------
