@@ -317,7 +317,7 @@ struct TripleCfg {
   static constexpr int kE = 16 / sizeof(T);
   static constexpr int kStage =
       (kLds - (int)sizeof(T) * 2 * 16 * kXS - (int)sizeof(A) * 3 * MT * 256) / (int)sizeof(T) / kE * kE;
-  static_assert(2 * kMaxNao * kMaxNao + 16 * 16 * MT + kE <= kStage, "stage holds D and V of any chunk");
+  static_assert(2 * kMaxNao * (kMaxNao + 1) + 16 * 16 * MT + kE <= kStage, "stage holds D and V of any chunk");
 };
 
 constexpr int kTNT = 512;
@@ -374,27 +374,30 @@ __device__ inline int64_t chunk_tri(const Dev& d, const UnitGeo& U, const Chunk&
 }
 
 // Chunk stage in LDS (elements of T), with nBp = nB rounded up to 4 (one
-// k-step of the X-build):
-//   [0, nA nBp)             D(A,B)[a][b], b < nBp, zero for b >= nB
-//   [nA nBp, (nA+nF) nBp)   D(F,B)[f][b]        (both rewritten only when B changes)
+// k-step of the X-build) and D rows ldD = nBp + 1 elements apart (an odd
+// stride: the 16 rows that 16 lanes read at once fall in distinct banks):
+//   [0, nA ldD)             D(A,B)[a][b], b < nBp, zero for nB <= b < nBp
+//   [nA ldD, (nA+nF) ldD)   D(F,B)[f][b]        (both rewritten only when B changes)
 //   [vo, vo + 16 mA)        Vf(A,B)[alpha][beta0 .. beta0+15], 16-byte pieces of a
 //                           row stored in XOR-swizzled order (conflict-free reads)
 //   [ho, ...)               H(B,F)[b][beta][f] then H(B,A)[b][beta][a], 16 rows
 //                           beta, with room for nBp rows of H(B,A)
-// vo = (nA+nF) nBp rounded up to 16 bytes, ho = vo + 16 mA.  Everything but
+// vo = (nA+nF) ldD rounded up to 16 bytes, ho = vo + 16 mA.  Everything but
 // the zero columns of D is brought in with direct global->LDS loads; H only
 // when it fits.  The X-build reads nBp rows b: past nB the D operand is zero
 // and the H operand is finite (H(B,A) rows, or stale stage contents, which
 // start zeroed), so those k-steps add nothing.
 struct StageGeo {
-  int nBp, vo, ho, hend;
+  int nBp, ldD, vo, ho, hend;
 };
+__device__ inline int d_stride(int nB) { return ((nB + 3) & ~3) + 1; }
 template <class T>
 __device__ inline StageGeo stage_geo(const UnitGeo& U, int nB) {
   constexpr int E = 16 / sizeof(T);
   StageGeo s;
   s.nBp = (nB + 3) & ~3;
-  s.vo = ((U.nA + U.nF) * s.nBp + E - 1) / E * E;
+  s.ldD = d_stride(nB);
+  s.vo = ((U.nA + U.nF) * s.ldD + E - 1) / E * E;
   s.ho = s.vo + 16 * U.mA;
   s.hend = s.ho + 16 * (nB * U.nF + s.nBp * U.nA);
   return s;
@@ -404,11 +407,11 @@ __device__ inline StageGeo stage_geo(const UnitGeo& U, int nB) {
 // workgroup; issued before any of the stage's direct loads).
 template <class T>
 __device__ inline void zero_d_padding(const UnitGeo& U, int nB, T* S) {
-  const int nBp = (nB + 3) & ~3, pad = nBp - nB;
+  const int nBp = (nB + 3) & ~3, pad = nBp - nB, ld = d_stride(nB);
   if (pad == 0) return;
   for (int e = threadIdx.x; e < (U.nA + U.nF) * pad; e += kTNT) {
     const int r = e / pad;
-    S[r * nBp + nB + (e - r * pad)] = T(0);
+    S[r * ld + nB + (e - r * pad)] = T(0);
   }
 }
 
@@ -426,7 +429,7 @@ struct Stager {
   const char* dA;                                   // D rows of A at column ao[B]
   const char* dF;
   unsigned dRow;                                    // bytes per D row
-  int nB, nBp, PA, PD;
+  int nB, ldD, PA, PD;
   Div dB;
   const char* v0;
   unsigned vRow;                                    // bytes per folded V row
@@ -445,10 +448,10 @@ struct Stager {
     dRow = (unsigned)(d.ntot * sizeof(T));
     dA = (const char*)(Dm + ldu(d.ao, U.A) * d.ntot + ldu(d.ao, c.B));
     dF = (const char*)(Dm + ldu(d.ao, U.F) * d.ntot + ldu(d.ao, c.B));
-    nBp = (nB + 3) & ~3;
-    dB.init(nBp);
-    PA = W * U.nA * nBp;
-    PD = with_d ? PA + W * U.nF * nBp : 0;
+    ldD = sg.ldD;
+    dB.init(ldD);
+    PA = W * U.nA * ldD;
+    PD = with_d ? PA + W * U.nF * ldD : 0;
     const int mBp = (c.mB + 15) & ~15;
     v0 = (const char*)(Vfg + ldu(d.vfOff, c.p) + c.b0);
     vRow = (unsigned)(mBp * sizeof(T));
@@ -477,7 +480,7 @@ struct Stager {
         const bool ab = pc < PA;
         const int pp = ab ? pc : pc - PA;
         const int e = W == 2 ? pp >> 1 : pp, part = pp - e * W;
-        const int r = dB(e), b = e - r * nBp;
+        const int r = dB(e), b = e - r * ldD;
         const unsigned off = __umul24((unsigned)r, dRow) + (unsigned)(b * (int)sizeof(T) + 4 * part);
         // columns b >= nB are zeroed separately (zero_d_padding)
         if (b < nB)
@@ -535,7 +538,8 @@ template <class T, bool DIRECT, int NU, int XW>
 __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, int hsF, const T* HA, int hsA,
                                        const T* Dab, const T* Dfb, bool kAB, bool kFB, T* X1, T* X2, int w, int q,
                                        int g) {
-  const int nBp = (nB + 3) & ~3;   // row stride of the staged D blocks
+  const int nBp = (nB + 3) & ~3;   // b extent of the k-steps
+  const int ldD = d_stride(nB);    // row stride of the staged D blocks
   const int SB = nBp >> 2;
   using M = M4<T>;
   const int NT = U.N1 + U.N2;
@@ -552,7 +556,7 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
       const int tt = on[u] ? t : t0;
       if (tt < U.N1) {
         const int rt = U.dnF(tt), ar = U.a0 + 16 * rt, tc = tt - rt * U.nF;
-        ap[u] = Dab + __umul24((unsigned)min(ar + q, U.nA - 1), (unsigned)nBp);
+        ap[u] = Dab + __umul24((unsigned)min(ar + q, U.nA - 1), (unsigned)ldD);
         as[u] = 1;
         const int c = 16 * tc + q, be = U.dnF(c), f = c - be * U.nF;
         bp[u] = HF + c;
@@ -569,7 +573,7 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
         const int f = 16 * tf + q;
         ap[u] = HA + __umul24((unsigned)q, (unsigned)U.nA) + a;
         as[u] = hsA;
-        bp[u] = Dfb + __umul24((unsigned)min(f, U.nF - 1), (unsigned)nBp);
+        bp[u] = Dfb + __umul24((unsigned)min(f, U.nF - 1), (unsigned)ldD);
         bs[u] = 1;
         xb[u] = X2;
         kb[u] = a * U.nF + f - U.k0;
@@ -768,11 +772,11 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
     if (!ZROLE && Cfg::kXW == 4) {
     } else if (sg.hend <= Cfg::kStage) {
       xbuild<T, false, NU, Cfg::kXW>(U, ch.nB, S + sg.ho, 16 * U.nF, S + sg.ho + ch.nB * 16 * U.nF, 16 * U.nA, S,
-                              S + U.nA * sg.nBp, kAB, kFB, X1, X2, w, q, g);
+                              S + U.nA * sg.ldD, kAB, kFB, X1, X2, w, q, g);
     } else {
       const int mBp = (ch.mB + 15) & ~15;
       xbuild<T, true, NU, Cfg::kXW>(U, ch.nB, Hg + ldu(d.triHF, tri) + (int64_t)ch.b0 * U.nF, mBp * U.nF,
-                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * sg.nBp, kAB, kFB,
+                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * sg.ldD, kAB, kFB,
                              X1, X2, w, q, g);
     }
     lds_sync();
