@@ -527,73 +527,63 @@ __device__ inline void lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// X-build of one chunk: this wave's tiles t = w, w+XW, ... of the N1 term-1
-// tiles followed by the N2 term-2 tiles (XW waves take part), NU at a time
-// (NU independent accumulation chains on the matrix core).  The b index runs in
-// k-steps of 4 (the part of a step past nB has zero operands), two steps per
-// pass and one in an odd last pass.
+// X-build of one chunk, one term at a time: this wave's tiles of the term,
+// t = first, first + XW, ... below Nt (the two terms continue one round-robin
+// over the XW waves that take part), NU at a time (NU independent
+// accumulation chains on the matrix core).  The b index runs in k-steps of 4
+// up to nBp; past nB the staged D operand is zero.
+//   term 1 (TERM2 false): rows a of D(A,B) times H(B,F) columns c = (beta, f),
+//     16 rows a and 16 columns c per tile; element (a, c) goes to
+//     X1[beta][a nF + f - k0].
+//   term 2 (TERM2 true): rows beta of H(B,A) at one a times D(F,B) columns f,
+//     16 f per tile; element (beta, f) goes to X2[beta][a nF + f - k0].
 // DIRECT: the H slices are read from global memory (chunks whose slices
 // exceed the LDS stage); otherwise from the stage.
-template <class T, bool DIRECT, int NU, int XW>
-__device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, int hsF, const T* HA, int hsA,
-                                       const T* Dab, const T* Dfb, bool kAB, bool kFB, T* X1, T* X2, int w, int q,
-                                       int g) {
+template <class T, bool DIRECT, int NU, int XW, bool TERM2>
+__device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int hs, const T* Dm, bool keep, T* X,
+                                      int first, int Nt, int q, int g) {
   const int nBp = (nB + 3) & ~3;   // b extent of the k-steps
   const int ldD = d_stride(nB);    // row stride of the staged D blocks
   const int SB = nBp >> 2;
+  // b strides of the A and B operands
+  const int as = TERM2 ? hs : 1, bs = TERM2 ? 1 : hs;
   using M = M4<T>;
-  const int NT = U.N1 + U.N2;
-  for (int t0 = w; t0 < NT; t0 += XW * NU) {
+  for (int t0 = first; t0 < Nt; t0 += XW * NU) {
     const T* ap[NU];
     const T* bp[NU];
     T* xb[NU];
-    int as[NU], bs[NU], kb[NU], ks[NU], rs[NU], rl[NU];
-    bool on[NU], lok[NU], kp[NU];
+    int kb[NU], ar[NU];
+    bool on[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      const int t = t0 + XW * u;
-      on[u] = t < NT;
-      const int tt = on[u] ? t : t0;
-      if (tt < U.N1) {
-        const int rt = U.dnF(tt), ar = U.a0 + 16 * rt, tc = tt - rt * U.nF;
-        ap[u] = Dab + __umul24((unsigned)min(ar + q, U.nA - 1), (unsigned)ldD);
-        as[u] = 1;
-        const int c = 16 * tc + q, be = U.dnF(c), f = c - be * U.nF;
-        bp[u] = HF + c;
-        bs[u] = hsF;
-        xb[u] = X1 + __umul24((unsigned)be, (unsigned)U.XS);
-        kb[u] = ar * U.nF + f - U.k0;
-        ks[u] = U.nF;
-        rs[u] = 0;
-        rl[u] = U.nA - ar;
-        lok[u] = true;
-        kp[u] = kAB;
+      on[u] = t0 + XW * u < Nt;                 // uniform
+      const int t = on[u] ? t0 + XW * u : t0;   // a tile past the end repeats t0, unstored
+      if constexpr (!TERM2) {
+        const int rt = U.dnF(t), tc = t - rt * U.nF, c = 16 * tc + q, be = U.dnF(c), f = c - be * U.nF;
+        ar[u] = U.a0 + 16 * rt;
+        ap[u] = Dm + __umul24((unsigned)min(ar[u] + q, U.nA - 1), (unsigned)ldD);
+        bp[u] = H + c;
+        xb[u] = X + __umul24((unsigned)be, (unsigned)U.XS);
+        kb[u] = ar[u] * U.nF + f - U.k0;
       } else {
-        const int t2 = tt - U.N1, ai = U.TF == 2 ? t2 >> 1 : t2, tf = t2 - ai * U.TF, a = U.a0 + ai;
-        const int f = 16 * tf + q;
-        ap[u] = HA + __umul24((unsigned)q, (unsigned)U.nA) + a;
-        as[u] = hsA;
-        bp[u] = Dfb + __umul24((unsigned)min(f, U.nF - 1), (unsigned)ldD);
-        bs[u] = 1;
-        xb[u] = X2;
-        kb[u] = a * U.nF + f - U.k0;
-        ks[u] = 0;
-        rs[u] = U.XS;
-        rl[u] = 16;
-        lok[u] = f < U.nF;
-        kp[u] = kFB;
+        const int ai = U.TF == 2 ? t >> 1 : t, tf = t - ai * U.TF, a = U.a0 + ai, f = 16 * tf + q;
+        ap[u] = H + __umul24((unsigned)q, (unsigned)U.nA) + a;
+        bp[u] = Dm + __umul24((unsigned)min(f, U.nF - 1), (unsigned)ldD);
+        xb[u] = X;
+        kb[u] = f < U.nF ? a * U.nF + f - U.k0 : -1;   // -1: the lane's column is not stored
+        ar[u] = 0;
       }
     }
     typename M::acc acc[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
     if constexpr (!DIRECT) {
-      // every operand is in the stage for b < nBp (zero D columns past nB):
-      // plain loads one k-step ahead, addresses advanced by a fixed stride
+      // every operand is in the stage for b < nBp: plain loads one k-step
+      // ahead, addresses advanced by a fixed stride
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
-        ap[u] += __umul24((unsigned)g, (unsigned)as[u]);
-        bp[u] += __umul24((unsigned)g, (unsigned)bs[u]);
+        ap[u] += __umul24((unsigned)g, (unsigned)as);
+        bp[u] += __umul24((unsigned)g, (unsigned)bs);
       }
       // two register sets in turn: the loads of step st+1 are in flight
       // while the product of step st is issued
@@ -603,8 +593,8 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
         for (int u = 0; u < NU; ++u) {
           av[u] = *ap[u];
           bv[u] = *bp[u];
-          ap[u] += 4 * as[u];
-          bp[u] += 4 * bs[u];
+          ap[u] += 4 * as;
+          bp[u] += 4 * bs;
         }
       };
       next(a0, b0);
@@ -626,52 +616,78 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
         for (int u = 0; u < NU; ++u) acc[u] = M::mma(a1[u], b1[u], acc[u]);
       }
     } else {
-    // operands of the next pass are requested before the products of the
-    // current one (addresses clamped into the slices; b >= nB gives zero)
-    T av[NU][2], bv[NU][2];
-    auto load = [&](int s0, T (&a2)[NU][2], T (&b2)[NU][2]) {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int b = 4 * (s0 + s) + g, bc = min(b, nB - 1);
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const T a = ap[u][__umul24((unsigned)bc, (unsigned)as[u])];
-          a2[u][s] = b < nB ? a : T(0);
-          b2[u][s] = bp[u][__umul24((unsigned)bc, (unsigned)bs[u])];
-        }
-      }
-    };
-    load(0, av, bv);
-#pragma unroll 1
-    for (int s0 = 0; s0 < SB; s0 += 2) {
-      T an[NU][2], bn[NU][2];
-      load(s0 + 2, an, bn);
-#pragma unroll
-      for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][0], bv[u][0], acc[u]);
-      if (s0 + 1 < SB) {   // an odd last pass has one k-step
-#pragma unroll
-        for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][1], bv[u][1], acc[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < NU; ++u)
+      // the D operand (stage) is read at b < nBp, zero past nB; the H operand
+      // (global) at min(b, nB - 1), finite.  The operands of the next pass
+      // are requested before the products of the current one.
+      T av[NU][2], bv[NU][2];
+      auto load = [&](int s0, T (&a2)[NU][2], T (&b2)[NU][2]) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-          av[u][s] = an[u][s];
-          bv[u][s] = bn[u][s];
+          const int b = min(4 * (s0 + s) + g, nBp - 1), bc = min(b, nB - 1);
+          const int ba = TERM2 ? bc : b, bb = TERM2 ? b : bc;
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            a2[u][s] = ap[u][__umul24((unsigned)ba, (unsigned)as)];
+            b2[u][s] = bp[u][__umul24((unsigned)bb, (unsigned)bs)];
+          }
         }
+      };
+      load(0, av, bv);
+#pragma unroll 1
+      for (int s0 = 0; s0 < SB; s0 += 2) {
+        T an[NU][2], bn[NU][2];
+        load(s0 + 2, an, bn);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][0], bv[u][0], acc[u]);
+        if (s0 + 1 < SB) {   // an odd last pass has one k-step
+#pragma unroll
+          for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][1], bv[u][1], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            av[u][s] = an[u][s];
+            bv[u][s] = bn[u][s];
+          }
+      }
     }
+    if (!keep) {   // screened D block: the term is zero
+#pragma unroll
+      for (int u = 0; u < NU; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       if (!on[u]) continue;
+      if constexpr (!TERM2) {
+        // rows r < rfull lie wholly inside the unit's columns [k0, k0 + Kc)
+        // (uniform); other rows are checked per element (rows past nA fall
+        // past the unit's columns)
+        const int rfull = ar[u] * U.nF >= U.k0 ? min(16, (U.k0 + U.Kc) / U.nF - ar[u]) : 0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = M::row(g, i), k = kb[u] + (int)__umul24((unsigned)r, (unsigned)ks[u]);
-        if (lok[u] && r < rl[u] && k >= 0 && k < U.Kc)
-          xb[u][k + (int)__umul24((unsigned)r, (unsigned)rs[u])] = kp[u] ? acc[u][i] : T(0);
+        for (int i = 0; i < 4; ++i) {
+          const int k = kb[u] + M::row(g, i) * U.nF;
+          if (M::row(3, i) < rfull)
+            xb[u][k] = acc[u][i];
+          else if ((unsigned)k < (unsigned)U.Kc)
+            xb[u][k] = acc[u][i];
+        }
+      } else {
+        if ((unsigned)kb[u] < (unsigned)U.Kc) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) xb[u][(int)__umul24((unsigned)M::row(g, i), (unsigned)U.XS) + kb[u]] = acc[u][i];
+        }
       }
     }
   }
+}
+
+template <class T, bool DIRECT, int NU, int XW>
+__device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, int hsF, const T* HA, int hsA,
+                                       const T* Dab, const T* Dfb, bool kAB, bool kFB, T* X1, T* X2, int w, int q,
+                                       int g) {
+  xterm<T, DIRECT, NU, XW, false>(U, nB, HF, hsF, Dab, kAB, X1, w, U.N1, q, g);
+  xterm<T, DIRECT, NU, XW, true>(U, nB, HA, hsA, Dfb, kFB, X2, ((w - U.N1) % XW + XW) % XW, U.N2, q, g);
 }
 
 template <int MT, int P, bool ZROLE>
