@@ -449,7 +449,7 @@ struct Stager {
     dA = (const char*)(Dm + ldu(d.ao, U.A) * d.ntot + ldu(d.ao, c.B));
     dF = (const char*)(Dm + ldu(d.ao, U.F) * d.ntot + ldu(d.ao, c.B));
     ldD = sg.ldD;
-    dB.init(ldD);
+    if (with_d) dB.init(ldD);   // a division: only for chunks that stage D
     PA = W * U.nA * ldD;
     PD = with_d ? PA + W * U.nF * ldD : 0;
     const int mBp = (c.mB + 15) & ~15;
@@ -529,7 +529,7 @@ __device__ inline void lds_sync() {
 
 // X-build of one chunk, one term at a time: this wave's tiles of the term,
 // t = first, first + XW, ... below Nt (the two terms continue one round-robin
-// over the XW waves that take part), NU at a time (NU independent
+// over the XW waves that take part), up to NU at a time (independent
 // accumulation chains on the matrix core).  The b index runs in k-steps of 4
 // up to nBp; past nB the staged D operand is zero.
 //   term 1 (TERM2 false): rows a of D(A,B) times H(B,F) columns c = (beta, f),
@@ -548,16 +548,16 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
   // b strides of the A and B operands
   const int as = TERM2 ? hs : 1, bs = TERM2 ? 1 : hs;
   using M = M4<T>;
-  for (int t0 = first; t0 < Nt; t0 += XW * NU) {
-    const T* ap[NU];
-    const T* bp[NU];
-    T* xb[NU];
-    int kb[NU], ar[NU];
-    bool on[NU];
+  // NUx tiles t0, t0 + XW, ... in flight
+  auto tiles = [&](auto nu, int t0) {
+    constexpr int NUx = decltype(nu)::value;
+    const T* ap[NUx];
+    const T* bp[NUx];
+    T* xb[NUx];
+    int kb[NUx], ar[NUx];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      on[u] = t0 + XW * u < Nt;                 // uniform
-      const int t = on[u] ? t0 + XW * u : t0;   // a tile past the end repeats t0, unstored
+    for (int u = 0; u < NUx; ++u) {
+      const int t = t0 + XW * u;
       if constexpr (!TERM2) {
         const int rt = U.dnF(t), tc = t - rt * U.nF, c = 16 * tc + q, be = U.dnF(c), f = c - be * U.nF;
         ar[u] = U.a0 + 16 * rt;
@@ -574,23 +574,23 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
         ar[u] = 0;
       }
     }
-    typename M::acc acc[NU];
+    typename M::acc acc[NUx];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
+    for (int u = 0; u < NUx; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
     if constexpr (!DIRECT) {
       // every operand is in the stage for b < nBp: plain loads one k-step
       // ahead, addresses advanced by a fixed stride
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
+      for (int u = 0; u < NUx; ++u) {
         ap[u] += __umul24((unsigned)g, (unsigned)as);
         bp[u] += __umul24((unsigned)g, (unsigned)bs);
       }
       // two register sets in turn: the loads of step st+1 are in flight
       // while the product of step st is issued
-      T a0[NU], b0[NU], a1[NU], b1[NU];
-      auto next = [&](T (&av)[NU], T (&bv)[NU]) {
+      T a0[NUx], b0[NUx], a1[NUx], b1[NUx];
+      auto next = [&](T (&av)[NUx], T (&bv)[NUx]) {
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
+        for (int u = 0; u < NUx; ++u) {
           av[u] = *ap[u];
           bv[u] = *bp[u];
           ap[u] += 4 * as;
@@ -603,30 +603,30 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
       for (; st + 2 < SB; st += 2) {   // steps st, st+1; the loads run one step ahead
         next(a1, b1);
 #pragma unroll
-        for (int u = 0; u < NU; ++u) acc[u] = M::mma(a0[u], b0[u], acc[u]);
+        for (int u = 0; u < NUx; ++u) acc[u] = M::mma(a0[u], b0[u], acc[u]);
         next(a0, b0);
 #pragma unroll
-        for (int u = 0; u < NU; ++u) acc[u] = M::mma(a1[u], b1[u], acc[u]);
+        for (int u = 0; u < NUx; ++u) acc[u] = M::mma(a1[u], b1[u], acc[u]);
       }
       if (st + 1 < SB) next(a1, b1);   // the last one or two steps
 #pragma unroll
-      for (int u = 0; u < NU; ++u) acc[u] = M::mma(a0[u], b0[u], acc[u]);
+      for (int u = 0; u < NUx; ++u) acc[u] = M::mma(a0[u], b0[u], acc[u]);
       if (st + 1 < SB) {
 #pragma unroll
-        for (int u = 0; u < NU; ++u) acc[u] = M::mma(a1[u], b1[u], acc[u]);
+        for (int u = 0; u < NUx; ++u) acc[u] = M::mma(a1[u], b1[u], acc[u]);
       }
     } else {
       // the D operand (stage) is read at b < nBp, zero past nB; the H operand
       // (global) at min(b, nB - 1), finite.  The operands of the next pass
       // are requested before the products of the current one.
-      T av[NU][2], bv[NU][2];
-      auto load = [&](int s0, T (&a2)[NU][2], T (&b2)[NU][2]) {
+      T av[NUx][2], bv[NUx][2];
+      auto load = [&](int s0, T (&a2)[NUx][2], T (&b2)[NUx][2]) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           const int b = min(4 * (s0 + s) + g, nBp - 1), bc = min(b, nB - 1);
           const int ba = TERM2 ? bc : b, bb = TERM2 ? b : bc;
 #pragma unroll
-          for (int u = 0; u < NU; ++u) {
+          for (int u = 0; u < NUx; ++u) {
             a2[u][s] = ap[u][__umul24((unsigned)ba, (unsigned)as)];
             b2[u][s] = bp[u][__umul24((unsigned)bb, (unsigned)bs)];
           }
@@ -635,16 +635,16 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
       load(0, av, bv);
 #pragma unroll 1
       for (int s0 = 0; s0 < SB; s0 += 2) {
-        T an[NU][2], bn[NU][2];
+        T an[NUx][2], bn[NUx][2];
         load(s0 + 2, an, bn);
 #pragma unroll
-        for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][0], bv[u][0], acc[u]);
+        for (int u = 0; u < NUx; ++u) acc[u] = M::mma(av[u][0], bv[u][0], acc[u]);
         if (s0 + 1 < SB) {   // an odd last pass has one k-step
 #pragma unroll
-          for (int u = 0; u < NU; ++u) acc[u] = M::mma(av[u][1], bv[u][1], acc[u]);
+          for (int u = 0; u < NUx; ++u) acc[u] = M::mma(av[u][1], bv[u][1], acc[u]);
         }
 #pragma unroll
-        for (int u = 0; u < NU; ++u)
+        for (int u = 0; u < NUx; ++u)
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
             av[u][s] = an[u][s];
@@ -654,11 +654,10 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
     }
     if (!keep) {   // screened D block: the term is zero
 #pragma unroll
-      for (int u = 0; u < NU; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
+      for (int u = 0; u < NUx; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      if (!on[u]) continue;
+    for (int u = 0; u < NUx; ++u) {
       if constexpr (!TERM2) {
         // rows r < rfull lie wholly inside the unit's columns [k0, k0 + Kc)
         // (uniform); other rows are checked per element (rows past nA fall
@@ -679,6 +678,12 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
         }
       }
     }
+  };
+  // groups of NU tiles, then the wave's last tile alone when NU does not divide its share
+  int t0 = first;
+  for (; t0 + XW * (NU - 1) < Nt; t0 += XW * NU) tiles(std::integral_constant<int, NU>{}, t0);
+  if constexpr (NU > 1) {
+    for (; t0 < Nt; t0 += XW) tiles(std::integral_constant<int, 1>{}, t0);
   }
 }
 
