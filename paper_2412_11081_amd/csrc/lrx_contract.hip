@@ -132,7 +132,9 @@ __device__ __forceinline__ T ldu(const T* p, int64_t i) {
 }
 
 // ---------------------------------------------------------------------------
-// H(B,X)[b][beta][x] = sum_{G alive} sum_g Cf(B,G)[beta][b][g] D(G,X)[g][x].
+// H(B,X)[b][beta][x] = sum_{G alive} sum_g Cf(B,G)[beta][b][g] D(G,X)[g][x],
+// stored in blocks of 16 beta: [beta / 16][b][beta mod 16][x], so the slice
+// of one block of 16 beta (what one triple-product chunk reads) is contiguous.
 // Per atom B this is one dense product: rows (beta,b), depth (G,g) over the
 // live C pairs (B,G), columns (X,x) over the H slots of B concatenated, with
 // D(G,X) dropped for screened D pairs.  One workgroup of 8 waves per (B, 128
@@ -202,15 +204,14 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
   const int npass = (K + kHPass - 1) / kHPass;
   const int nblk = (ncols + kHCB - 1) / kHCB;
   const int steps = nblk * npass;
-  const int mBp = (mB + 15) & ~15;
   const int row = r0 + 16 * w + q;    // A-operand row of this lane
-  // output rows of this lane: (b, beta) -> b * mBp + beta, or -1
+  // output rows of this lane: (b, beta) -> (beta / 16) 16 nB + 16 b + beta mod 16, or -1
   int orow[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = r0 + 16 * w + M::row(g, i);
     const int be = r / nB, bb = r - be * nB;
-    orow[i] = r < rows ? bb * mBp + be : -1;
+    orow[i] = r < rows ? (be >> 4) * 16 * nB + 16 * bb + (be & 15) : -1;
   }
   // D tile of step s into registers: element e = tid + kHT i is (k, cl) =
   // (e / kHCB, e mod kHCB); screened pairs, dead C pairs and padding give 0
@@ -337,8 +338,8 @@ struct Div {
 struct UnitGeo {
   int cp, A, F, mA, nA, nF, K1, k0, Kc, kc, NTc, KS, XS, fpos, vp0, nVpA, vb, ve, split;
   int a0, N1, N2, TF;        // X-build tiles: term 1 rows from a0 (16 per tile), term 2 one a per tile
-  int pF, pA;                // 16-byte pieces per staged H row (F and A slices)
-  Div dnF, dpF, dpA;
+  int pF, pA;                // 16-byte pieces per b row of the H slices (F and A)
+  Div dnF;
 };
 
 struct Chunk {
@@ -436,7 +437,6 @@ struct Stager {
   int PV;
   const char* hF;
   const char* hA;
-  unsigned hRowF, hRowA;                            // bytes between b rows of the H slots
   int PF, PH;
   char* sD;
   char* sV;
@@ -457,10 +457,9 @@ struct Stager {
     vRow = (unsigned)(mBp * sizeof(T));
     PV = PR * U.mA;
     const int64_t t = chunk_tri(d, U, c);
-    hF = (const char*)(H + ldu(d.triHF, t) + (int64_t)c.b0 * U.nF);
-    hA = (const char*)(H + ldu(d.triHA, t) + (int64_t)c.b0 * U.nA);
-    hRowF = (unsigned)(mBp * U.nF * sizeof(T));
-    hRowA = (unsigned)(mBp * U.nA * sizeof(T));
+    // the chunk's block of 16 beta in the H slots: contiguous [b][beta][x]
+    hF = (const char*)(H + ldu(d.triHF, t) + (int64_t)c.b0 * c.nB * U.nF);
+    hA = (const char*)(H + ldu(d.triHA, t) + (int64_t)c.b0 * c.nB * U.nA);
     PF = c.nB * U.pF;
     PH = with_h ? PF + c.nB * U.pA : 0;
     sD = (char*)S;
@@ -498,14 +497,7 @@ struct Stager {
     } else {
       const int j = J - nV, pc = j * 64 + lane;
       if (pc < PH) {
-        const char* src;
-        if (pc < PF) {
-          const int b = U.dpF(pc);
-          src = hF + (__umul24((unsigned)b, hRowF) + 16u * (unsigned)(pc - b * U.pF));
-        } else {
-          const int pp = pc - PF, b = U.dpA(pp);
-          src = hA + (__umul24((unsigned)b, hRowA) + 16u * (unsigned)(pp - b * U.pA));
-        }
+        const char* src = pc < PF ? hF + 16u * (unsigned)pc : hA + 16u * (unsigned)(pc - PF);
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                          (__attribute__((address_space(3))) void*)(sH + 1024 * j), 16, 0, 0);
       }
@@ -795,9 +787,8 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
       xbuild<T, false, NU, Cfg::kXW>(U, ch.nB, S + sg.ho, 16 * U.nF, S + sg.ho + ch.nB * 16 * U.nF, 16 * U.nA, S,
                               S + U.nA * sg.ldD, kAB, kFB, X1, X2, w, q, g);
     } else {
-      const int mBp = (ch.mB + 15) & ~15;
-      xbuild<T, true, NU, Cfg::kXW>(U, ch.nB, Hg + ldu(d.triHF, tri) + (int64_t)ch.b0 * U.nF, mBp * U.nF,
-                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * U.nA, mBp * U.nA, S, S + U.nA * sg.ldD, kAB, kFB,
+      xbuild<T, true, NU, Cfg::kXW>(U, ch.nB, Hg + ldu(d.triHF, tri) + (int64_t)ch.b0 * ch.nB * U.nF, 16 * U.nF,
+                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * ch.nB * U.nA, 16 * U.nA, S, S + U.nA * sg.ldD, kAB, kFB,
                              X1, X2, w, q, g);
     }
     lds_sync();
@@ -999,8 +990,6 @@ __device__ __forceinline__ void triple_unit(const Dev& d, int u, typename Triple
   U.N2 = (a1 - U.a0 + 1) * U.TF;
   U.pF = 16 * U.nF * (int)sizeof(T) / 16;
   U.pA = 16 * U.nA * (int)sizeof(T) / 16;
-  U.dpF.init(U.pF);
-  U.dpA.init(U.pA);
   const int tid = threadIdx.x, lane = tid & 63, q = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
   for (int e = tid; e < 32 * Cfg::kXS; e += kTNT) X[e] = T(0);
