@@ -378,6 +378,7 @@ __device__ inline int64_t chunk_tri(const Dev& d, const UnitGeo& U, const Chunk&
 // k-step of the X-build) and D rows ldD = nBp + 1 elements apart (an odd
 // stride: the 16 rows that 16 lanes read at once fall in distinct banks):
 //   [0, nA ldD)             D(A,B)[a][b], b < nBp, zero for nB <= b < nBp
+//                           (and everywhere when the block is screened)
 //   [nA ldD, (nA+nF) ldD)   D(F,B)[f][b]        (both rewritten only when B changes)
 //   [vo, vo + 16 mA)        Vf(A,B)[alpha][beta0 .. beta0+15], 16-byte pieces of a
 //                           row stored in XOR-swizzled order (conflict-free reads)
@@ -404,15 +405,19 @@ __device__ inline StageGeo stage_geo(const UnitGeo& U, int nB) {
   return s;
 }
 
-// Zero columns nB .. nBp-1 of the staged D rows (all threads of the
-// workgroup; issued before any of the stage's direct loads).
+// Zero columns nB .. nBp-1 of the staged D rows, and every column of the
+// rows of a screened block (kAB: D(A,B) kept, kFB: D(F,B) kept), which the
+// direct loads skip (all threads of the workgroup; issued before any of the
+// stage's direct loads).
 template <class T>
-__device__ inline void zero_d_padding(const UnitGeo& U, int nB, T* S) {
-  const int nBp = (nB + 3) & ~3, pad = nBp - nB, ld = d_stride(nB);
-  if (pad == 0) return;
-  for (int e = threadIdx.x; e < (U.nA + U.nF) * pad; e += kTNT) {
-    const int r = e / pad;
-    S[r * ld + nB + (e - r * pad)] = T(0);
+__device__ inline void zero_d_padding(const UnitGeo& U, int nB, bool kAB, bool kFB, T* S) {
+  const int nBp = (nB + 3) & ~3, ld = d_stride(nB);
+  const int pA = kAB ? nBp - nB : nBp, pF = kFB ? nBp - nB : nBp;   // zeroed columns per row, the last ones
+  const int nzA = U.nA * pA, nz = nzA + U.nF * pF;
+  for (int e = threadIdx.x; e < nz; e += kTNT) {
+    const bool a = e < nzA;
+    const int p = a ? pA : pF, e2 = a ? e : e - nzA, r = e2 / p;
+    S[(a ? r : U.nA + r) * ld + (nBp - p) + (e2 - r * p)] = T(0);
   }
 }
 
@@ -442,9 +447,12 @@ struct Stager {
   char* sV;
   char* sH;
 
+  bool kAB, kFB;                                    // D blocks kept (screened ones stay zero)
   __device__ void init(const Dev& d, const UnitGeo& U, const Chunk& c, const StageGeo& sg, bool with_d, bool with_h,
                        T* S, const T* Dm, const T* Vfg, const T* H) {
     nB = c.nB;
+    kAB = with_d && ldu(d.keepD, (int64_t)U.A * d.N + c.B) != 0;
+    kFB = with_d && ldu(d.keepD, (int64_t)U.F * d.N + c.B) != 0;
     dRow = (unsigned)(d.ntot * sizeof(T));
     dA = (const char*)(Dm + ldu(d.ao, U.A) * d.ntot + ldu(d.ao, c.B));
     dF = (const char*)(Dm + ldu(d.ao, U.F) * d.ntot + ldu(d.ao, c.B));
@@ -481,8 +489,8 @@ struct Stager {
         const int e = W == 2 ? pp >> 1 : pp, part = pp - e * W;
         const int r = dB(e), b = e - r * ldD;
         const unsigned off = __umul24((unsigned)r, dRow) + (unsigned)(b * (int)sizeof(T) + 4 * part);
-        // columns b >= nB are zeroed separately (zero_d_padding)
-        if (b < nB)
+        // columns b >= nB and screened blocks are zeroed separately (zero_d_padding)
+        if (b < nB && (ab ? kAB : kFB))
           __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((ab ? dA : dF) + off),
                                            (__attribute__((address_space(3))) void*)(sD + 256 * J), 4, 0, 0);
       }
@@ -523,7 +531,8 @@ __device__ inline void lds_sync() {
 // t = first, first + XW, ... below Nt (the two terms continue one round-robin
 // over the XW waves that take part), up to NU at a time (independent
 // accumulation chains on the matrix core).  The b index runs in k-steps of 4
-// up to nBp; past nB the staged D operand is zero.
+// up to nBp; past nB the staged D operand is zero, and so is all of a
+// screened D block, which makes its term zero.
 //   term 1 (TERM2 false): rows a of D(A,B) times H(B,F) columns c = (beta, f),
 //     16 rows a and 16 columns c per tile; element (a, c) goes to
 //     X1[beta][a nF + f - k0].
@@ -532,7 +541,7 @@ __device__ inline void lds_sync() {
 // DIRECT: the H slices are read from global memory (chunks whose slices
 // exceed the LDS stage); otherwise from the stage.
 template <class T, bool DIRECT, int NU, int XW, bool TERM2>
-__device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int hs, const T* Dm, bool keep, T* X,
+__device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int hs, const T* Dm, T* X,
                                       int first, int Nt, int q, int g) {
   const int nBp = (nB + 3) & ~3;   // b extent of the k-steps
   const int ldD = d_stride(nB);    // row stride of the staged D blocks
@@ -644,10 +653,6 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
           }
       }
     }
-    if (!keep) {   // screened D block: the term is zero
-#pragma unroll
-      for (int u = 0; u < NUx; ++u) acc[u] = typename M::acc{0, 0, 0, 0};
-    }
 #pragma unroll
     for (int u = 0; u < NUx; ++u) {
       if constexpr (!TERM2) {
@@ -681,10 +686,10 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
 
 template <class T, bool DIRECT, int NU, int XW>
 __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, int hsF, const T* HA, int hsA,
-                                       const T* Dab, const T* Dfb, bool kAB, bool kFB, T* X1, T* X2, int w, int q,
+                                       const T* Dab, const T* Dfb, T* X1, T* X2, int w, int q,
                                        int g) {
-  xterm<T, DIRECT, NU, XW, false>(U, nB, HF, hsF, Dab, kAB, X1, w, U.N1, q, g);
-  xterm<T, DIRECT, NU, XW, true>(U, nB, HA, hsA, Dfb, kFB, X2, ((w - U.N1) % XW + XW) % XW, U.N2, q, g);
+  xterm<T, DIRECT, NU, XW, false>(U, nB, HF, hsF, Dab, X1, w, U.N1, q, g);
+  xterm<T, DIRECT, NU, XW, true>(U, nB, HA, hsA, Dfb, X2, ((w - U.N1) % XW + XW) % XW, U.N2, q, g);
 }
 
 template <int MT, int P, bool ZROLE>
@@ -756,7 +761,6 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
   lds_sync();
   while (ch.p >= 0) {
     const Chunk nx = chunk_next(d, U, ch);
-    const bool kAB = ldu(d.keepD, (int64_t)U.A * N + ch.B), kFB = ldu(d.keepD, (int64_t)U.F * N + ch.B);
     const int64_t tri = chunk_tri(d, U, ch);
     // V fragments of this chunk (Y waves), read before the stage is reused
     T avn[(ZROLE || B3) ? 1 : 4][(ZROLE || B3) ? 1 : MT];
@@ -785,10 +789,10 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
     if (!ZROLE && Cfg::kXW == 4) {
     } else if (sg.hend <= Cfg::kStage) {
       xbuild<T, false, NU, Cfg::kXW>(U, ch.nB, S + sg.ho, 16 * U.nF, S + sg.ho + ch.nB * 16 * U.nF, 16 * U.nA, S,
-                              S + U.nA * sg.ldD, kAB, kFB, X1, X2, w, q, g);
+                              S + U.nA * sg.ldD, X1, X2, w, q, g);
     } else {
       xbuild<T, true, NU, Cfg::kXW>(U, ch.nB, Hg + ldu(d.triHF, tri) + (int64_t)ch.b0 * ch.nB * U.nF, 16 * U.nF,
-                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * ch.nB * U.nA, 16 * U.nA, S, S + U.nA * sg.ldD, kAB, kFB,
+                             Hg + ldu(d.triHA, tri) + (int64_t)ch.b0 * ch.nB * U.nA, 16 * U.nA, S, S + U.nA * sg.ldD,
                              X1, X2, w, q, g);
     }
     lds_sync();
@@ -799,7 +803,8 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
     const StageGeo sn = stage_geo<T>(U, nx.nB);
     // a new B: zero the padding columns of its D blocks before any wave
     // issues the loads that stage them
-    if (nx.p >= 0 && nx.p != ch.p) zero_d_padding(U, nx.nB, S);
+    if (nx.p >= 0 && nx.p != ch.p)
+      zero_d_padding(U, nx.nB, ldu(d.keepD, (int64_t)U.A * N + nx.B) != 0, ldu(d.keepD, (int64_t)U.F * N + nx.B) != 0, S);
     auto stage_next = [&] {
       if (nx.p >= 0) {
         Stager<T> st;
@@ -871,7 +876,9 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           const int al = 16 * i + M::row(g, rr);
-          if (al < mA && be < ch.mB) Zdst[(int64_t)al * ch.mB + be] = z[rr];
+          // 32-bit byte offset from the uniform block base (a Z block is far below 4 GiB)
+          if (al < mA && be < ch.mB)
+            *(T*)((char*)Zdst + (unsigned)(al * ch.mB + be) * (unsigned)sizeof(T)) = z[rr];
         }
       }
     } else {

@@ -1,8 +1,9 @@
 """Edge cases of the HIP path, through the C-ABI, against the CPU oracle:
-everything screened away, a cell of one atom (only its own images), the
-largest block sizes the kernels take (32 NAOs and 128 ABFs per atom: eight
-alpha tiles, H slices too large for the LDS stage), and inputs the library
-must reject with an error instead of computing."""
+everything screened away, D blocks screened under live triples, a cell of
+one atom (only its own images), the largest block sizes the kernels take
+(32 NAOs and 128 ABFs per atom: eight alpha tiles, H slices too large for
+the LDS stage), and inputs the library must reject with an error instead of
+computing."""
 import numpy as np
 import pytest
 
@@ -45,6 +46,27 @@ def test_everything_screened(oracle_lib):
     E, F, S, gC, gV, keep = got
     assert E == 0.0 and not F.any() and not S.any() and not gC.any() and not gV.any()
     assert not keep[0].any() and not keep[1].any() and not keep[2].any()
+    _check(st, got, r)
+
+
+@pytest.mark.parametrize("case", [(4, 2, 3, 9, 6.0, 51, 0.3), (5, 2, 4, 11, 6.5, 52, 0.2)],
+                         ids=["n4ao3th0.3", "n5ao4th0.2"])
+def test_partially_screened_density_blocks(oracle_lib, case):
+    """A threshold that screens some D blocks while C and V blocks survive:
+    live triples whose D(A,B) or D(F,B) is screened take that term as zero."""
+    H.require_gpu()
+    natom, nsp, nao, nabf, box, seed, theta = case
+    st = synth.small_case(natom=natom, nspecies=nsp, n_ao=nao, n_abf=nabf, box=box, rc=4.5, rv=7.0, seed=seed,
+                          theta=theta, theta_cs=0.0, jitter=0.5).build()
+    got, r = _both(oracle_lib, st, theta, 0.0)
+    kD = np.asarray(r["keepD"]).reshape(natom, natom)
+    cA, cF, _ = st.keysC
+    vA, vB, _ = st.keysV
+    live_c = {(int(a), int(f)) for a, f, k in zip(cA, cF, r["keepC"]) if k}
+    live_v = {(int(a), int(b)) for a, b, k in zip(vA, vB, r["keepV"]) if k}
+    touched = sum(1 for a, f in live_c for a2, b in live_v if a2 == a and not (kD[a, b] and kD[f, b]))
+    print("live triples with a screened D block:", touched, flush=True)
+    assert touched > 0 and r["E"] != 0.0
     _check(st, got, r)
 
 
