@@ -314,10 +314,15 @@ struct TripleCfg {
   static constexpr int kXW = 8;                                              // waves taking part
   static constexpr int kNUZ = 2;                                             // tiles in flight: Z waves
   static constexpr int kNUY = (P == kP64 && MT >= 5) ? 1 : 2;                 // Y waves
+  // Z reduction: alpha tiles below kMF are owned by Z wave (i mod 4), which
+  // adds the three partials the other Z waves park; a single remaining tile
+  // (MT = 1 mod 4) is parked by all four and reduced a quarter per wave
+  static constexpr int kMF = MT % 4 == 1 ? MT - 1 : MT;
+  static constexpr int kZSlots = 3 * kMF + 4 * (MT - kMF);                  // parked 16x16 tiles
   static constexpr int kLds = 163840 - 256;     // X, Z partials and the stage; the rest holds the item slot
   static constexpr int kE = 16 / sizeof(T);
   static constexpr int kStage =
-      (kLds - (int)sizeof(T) * 2 * 16 * kXS - (int)sizeof(A) * 3 * MT * 256) / (int)sizeof(T) / kE * kE;
+      (kLds - (int)sizeof(T) * 2 * 16 * kXS - (int)sizeof(A) * kZSlots * 256) / (int)sizeof(T) / kE * kE;
   static_assert(2 * kMaxNao * (kMaxNao + 1) + 16 * 16 * MT + kE <= kStage, "stage holds D and V of any chunk");
 };
 
@@ -857,29 +862,43 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
           for (int i = 0; i < MT; ++i) zp[i] = M::mma(cfr[i][t], xb[t], zp[i]);
         }
       }
-      // tile i is owned by Z wave (i mod 4); the other three park their partials
+      // tile i < MF is owned by Z wave (i mod 4): the other three park their
+      // partials; a remaining tile is parked by all four Z waves, and wave ww
+      // adds accumulator component ww of the four
+      constexpr int MF = Cfg::kMF;
 #pragma unroll
       for (int i = 0; i < MT; ++i) {
-        const int own = i & 3;
-        if (own != ww) *(Acc*)&Zred[((((ww - own - 1) & 3) * MT) + i) * 256 + lane * 4] = zp[i];
+        if (i < MF) {
+          const int own = i & 3;
+          if (own != ww) *(Acc*)&Zred[(((ww - own - 1) & 3) * MF + i) * 256 + lane * 4] = zp[i];
+        } else {
+          *(Acc*)&Zred[(3 * MF + 4 * (i - MF) + ww) * 256 + lane * 4] = zp[i];
+        }
       }
       __builtin_amdgcn_s_waitcnt(0);
       lds_sync();
       T* Zdst = Buf<T>::Z(d) + ldu(d.zOff, tri) + (int64_t)U.kc * mA * ch.mB;
       const int be = ch.b0 + q;
+      // 32-bit byte offsets from the uniform block base (a Z block is far below 4 GiB)
+      auto zstore = [&](int al, T v) {
+        if (al < mA && be < ch.mB) *(T*)((char*)Zdst + (unsigned)(al * ch.mB + be) * (unsigned)sizeof(T)) = v;
+      };
 #pragma unroll
-      for (int i = 0; i < MT; ++i) {
+      for (int i = 0; i < MF; ++i) {
         if ((i & 3) != ww) continue;
         Acc z = zp[i];
 #pragma unroll
-        for (int v = 0; v < 3; ++v) z += *(const Acc*)&Zred[(v * MT + i) * 256 + lane * 4];
+        for (int v = 0; v < 3; ++v) z += *(const Acc*)&Zred[(v * MF + i) * 256 + lane * 4];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int al = 16 * i + M::row(g, rr);
-          // 32-bit byte offset from the uniform block base (a Z block is far below 4 GiB)
-          if (al < mA && be < ch.mB)
-            *(T*)((char*)Zdst + (unsigned)(al * ch.mB + be) * (unsigned)sizeof(T)) = z[rr];
-        }
+        for (int rr = 0; rr < 4; ++rr) zstore(16 * i + M::row(g, rr), z[rr]);
+      }
+#pragma unroll
+      for (int i = MF; i < MT; ++i) {
+        const A* zr = Zred + (3 * MF + 4 * (i - MF)) * 256 + lane * 4 + ww;
+        T z = zr[0];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) z += zr[256 * v];
+        zstore(16 * i + M::row(g, ww), z);
       }
     } else {
       if constexpr (B3) {
@@ -1023,7 +1042,7 @@ __global__ void __launch_bounds__(kTNT, 1)
   // global->LDS loads) apart from X and the Z partials, so the products read
   // those without waiting for the next chunk's loads to land
   __shared__ __attribute__((aligned(16))) typename Cfg::T sX[2 * 16 * Cfg::kXS];
-  __shared__ __attribute__((aligned(16))) typename Cfg::A sZ[3 * MT * 256];
+  __shared__ __attribute__((aligned(16))) typename Cfg::A sZ[Cfg::kZSlots * 256];
   __shared__ __attribute__((aligned(16))) typename Cfg::T sS[Cfg::kStage];
   __shared__ int s_next;
   if constexpr (!PERSIST) {
