@@ -213,19 +213,25 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
     const int be = r / nB, bb = r - be * nB;
     orow[i] = r < rows ? (be >> 4) * 16 * nB + 16 * bb + (be & 15) : -1;
   }
-  // D tile of step s into registers: element e = tid + kHT i is (k, cl) =
-  // (e / kHCB, e mod kHCB); screened pairs, dead C pairs and padding give 0
+  // D tile of (column block blk, pass p) into registers: element
+  // e = tid + kHT i is (k, cl) = (e / kHCB, e mod kHCB), so a thread keeps
+  // one column cl over its kHPre depth indices; screened pairs, dead C pairs
+  // and padding give 0
+  static_assert(kHT % kHCB == 0, "a thread's column is the same for every i");
   T pv[kHPre];
-  auto fetch = [&](int st) {
-    const int blk = st / npass, p = st - blk * npass, kb = p * kHPass;
+  auto fetch = [&](int blk, int p) {
+    const int kb = p * kHPass, cl = blk * kHCB + (tid & (kHCB - 1));
+    const T* Dc = Dm + cD[cl];
+    const bool cok = cSl[cl] >= 0;
+    const int cx = cxi[cl], ca = cAt[cl];
 #pragma unroll
     for (int i = 0; i < kHPre; ++i) {
-      const int e = tid + kHT * i, k = kb + (e >> 6), cl = blk * kHCB + (e & (kHCB - 1));
+      const int k = kb + (tid >> 6) + (kHT >> 6) * i;
       const int kk = k < K ? k : kb;
       const int G = k < K ? kG[kk] : -1;
-      const T v = Dm[(int64_t)krow[kk] * d.ntot + cD[cl]];
-      const bool keep = G >= 0 && cSl[cl] >= 0 &&
-                        (local ? keepL[kgi[kk] * 64 + cxi[cl]] != 0 : d.keepD[(int64_t)G * N + cAt[cl]] != 0);
+      const T v = Dc[(int64_t)krow[kk] * d.ntot];
+      const bool keep = G >= 0 && cok &&
+                        (local ? keepL[kgi[kk] * 64 + cx] != 0 : d.keepD[(int64_t)G * N + ca] != 0);
       pv[i] = keep ? v : T(0);
     }
   };
@@ -242,14 +248,15 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
 #pragma unroll
   for (int j = 0; j < kHCB / 16; ++j) acc[j] = typename M::acc{0, 0, 0, 0};
   T* H = Buf<T>::H(d);
-  if (steps > 0) fetch(0);
+  if (steps > 0) fetch(0, 0);
   load_a(0);
-  for (int st = 0; st < steps; ++st) {
-    const int blk = st / npass, p = st - blk * npass;
+  // step st = (column block blk, depth pass p), p fastest
+  for (int st = 0, blk = 0, p = 0; st < steps; ++st) {
     T* D2 = Ds[st & 1];
 #pragma unroll
     for (int i = 0; i < kHPre; ++i) D2[tid + kHT * i] = pv[i];
-    if (st + 1 < steps) fetch(st + 1);
+    const bool wrap = p + 1 == npass;
+    if (st + 1 < steps) fetch(wrap ? blk + 1 : blk, wrap ? 0 : p + 1);
     if (npass > 1 && st > 0) load_a(p);
     __syncthreads();
     const int Kp = min(kHPass, K - p * kHPass);
@@ -260,7 +267,7 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
         for (int j = 0; j < kHCB / 16; ++j) acc[j] = M::mma(af[t], D2[(4 * t + g) * kHCB + 16 * j + q], acc[j]);
       }
     }
-    if (p == npass - 1) {
+    if (wrap) {
 #pragma unroll
       for (int j = 0; j < kHCB / 16; ++j) {
         const int cl = blk * kHCB + 16 * j + q;
@@ -274,6 +281,10 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
         }
         acc[j] = typename M::acc{0, 0, 0, 0};
       }
+      ++blk;
+      p = 0;
+    } else {
+      ++p;
     }
   }
 }
