@@ -299,11 +299,13 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
 //           flattened (beta, f) index
 //       X2[beta][a f] = sum_b H(B,A)[b][beta][a] D_FB[f][b]
 //           tiles of one a: 16 rows beta x 16 columns f
-//       Only the tiles that reach the unit's column chunk are formed; each
-//       wave keeps two tiles in flight.
+//       Only the tiles that reach the unit's column chunk are formed, one
+//       term after the other; a Z wave keeps two tiles in flight (a Y wave
+//       one or two, as its registers allow).
 //   Z waves 0-3 (K split four ways, Cf(A,F) fragments in registers):
 //       Z(A,B)[alpha][beta] over (a,f) in the chunk; the four partial sums
-//       of alpha tile i meet in LDS and are added by Z wave (i mod 4)
+//       of alpha tile i meet in LDS and are added by Z wave (i mod 4), except
+//       that a single last tile (MT = 1 mod 4) is added a quarter per wave
 //   Y waves 4-7 (accumulators resident for the whole unit):
 //       Y(A,F)[alpha][a f] += Vf(A,B)[alpha][beta] X[beta][a f]
 // The V slice and the H slices (and, when B changes, the D blocks) of the
