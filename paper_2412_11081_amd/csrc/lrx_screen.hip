@@ -280,14 +280,29 @@ __global__ void __launch_bounds__(kNT) k_fold_v(Dev d, int prec) {
   double* out = d.Vf + d.vfOff[p];
   float* out32 = prec != kP64 ? d.Vf32 + d.vfOff[p] : nullptr;
   const int k0 = d.vpB0[p], k1 = d.vpB1[p];
+  // the kept image blocks, in order (uniform; a pair has few images)
+  constexpr int kImg = 4;
+  const double* src[kImg];
+  int ns = 0, k = k0;
+  for (; k < k1 && ns < kImg; ++k) {
+    const int64_t b = d.vpBlk[k];
+    if (d.keepV[b]) src[ns++] = d.Vval + d.Voff[b];
+  }
+  // e / mBp exactly for e < 2^16 (mA, mBp <= 128): ceil(2^32 / mBp) times e, high word
+  const unsigned mdiv = 0xFFFFFFFFu / (unsigned)mBp + 1u;
   for (int e = threadIdx.x; e < mA * mBp; e += kNT) {
-    const int al = e / mBp, be = e - al * mBp;
+    const int al = (int)__umulhi((unsigned)e, mdiv), be = e - al * mBp;
     double s = 0;
-    if (be < mB)
-      for (int k = k0; k < k1; ++k) {
-        const int64_t b = d.vpBlk[k];
-        if (d.keepV[b]) s += d.Vval[d.Voff[b] + al * mB + be];
+    if (be < mB) {
+      const int o = al * mB + be;
+#pragma unroll
+      for (int j = 0; j < kImg; ++j)
+        if (j < ns) s += src[j][o];
+      for (int kk = k; kk < k1; ++kk) {   // images past the first kImg kept ones
+        const int64_t b = d.vpBlk[kk];
+        if (d.keepV[b]) s += d.Vval[d.Voff[b] + o];
       }
+    }
     out[e] = s;
     if (out32) out32[e] = (float)s;
   }
