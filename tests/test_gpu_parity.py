@@ -39,6 +39,8 @@ SMALL = [
     (2, 1, 22, 40, 9.0, 5.0, 8.0, 0.0, 35),
     (3, 1, 18, 100, 12.0, 5.0, 7.0, 0.0, 36),
     (2, 2, 16, 64, 3.6, 4.0, 5.0, 0.0, 37),
+    (2, 1, 9, 75, 7.5, 5.0, 8.0, 0.0, 38),      # five alpha tiles: the last one reduced a quarter per Z wave
+    (2, 2, 11, 90, 8.0, 5.0, 8.0, 1e-4, 39),    # six alpha tiles
 ]
 
 
