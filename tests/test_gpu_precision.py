@@ -31,6 +31,8 @@ CASES = [
     (4, 3, 7, 20, 5.5, 4.5, 7.5, 2e-3, 34),
     (3, 1, 18, 100, 12.0, 5.0, 7.0, 0.0, 36),
     (2, 2, 16, 64, 3.6, 4.0, 5.0, 0.0, 37),
+    (2, 1, 3, 5, 6.0, 4.5, 7.0, 0.0, 31),       # one alpha tile: reduced a quarter per Z wave
+    (2, 1, 9, 75, 7.5, 5.0, 8.0, 0.0, 38),      # five alpha tiles
 ]
 
 
