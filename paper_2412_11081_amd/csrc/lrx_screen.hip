@@ -68,22 +68,38 @@ __global__ void k_val_finite(const double* p, int64_t n, int* err, int code) {
     if (!isfinite(p[i])) atomicOr(err, code);
 }
 
-__global__ void k_val_vmirror(Dev d) {
+// V(B,A,-R) = V(A,B,R)^T and dV(B,A,-R) = -dV(A,B,R)^T: block b is [mA][mB],
+// its mirror [mB][mA].  The mirror is read in 32 x 32 tiles through LDS so
+// that both blocks are read along their rows.
+__global__ void __launch_bounds__(kNT) k_val_vmirror(Dev d) {
+  constexpr int kT = 32;
+  __shared__ double tile[kT][kT + 1];
   const int64_t b = blockIdx.x;
   const int64_t m = d.Vmir[b];
   const int mA = d.nabf[d.Vfirst[b]], mB = d.nabf[d.Vsecond[b]];
   const int n = mA * mB;
-  const double* vb = d.Vval + d.Voff[b];
-  const double* vm = d.Vval + d.Voff[m];
-  const double* db = d.Vdval + 3 * d.Voff[b];
-  const double* dm = d.Vdval + 3 * d.Voff[m];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int al = e / mB, be = e % mB;
-    const int et = be * mA + al;
-    if (!close_rel(vb[e], vm[et])) atomicOr(d.err, kErrVMirror);
-    for (int x = 0; x < 3; ++x)
-      if (!close_rel(db[x * n + e], -dm[x * n + et])) atomicOr(d.err, kErrDVMirror);
+  int bad = 0;
+  for (int x = 0; x < 4; ++x) {   // the value, then the three derivatives
+    const double* vb = x == 0 ? d.Vval + d.Voff[b] : d.Vdval + 3 * d.Voff[b] + (int64_t)(x - 1) * n;
+    const double* vm = x == 0 ? d.Vval + d.Voff[m] : d.Vdval + 3 * d.Voff[m] + (int64_t)(x - 1) * n;
+    const double sgn = x == 0 ? 1.0 : -1.0;
+    for (int r0 = 0; r0 < mA; r0 += kT)
+      for (int c0 = 0; c0 < mB; c0 += kT) {
+        // mirror rows be in [c0, c0+kT), columns al in [r0, r0+kT)
+        for (int e = threadIdx.x; e < kT * kT; e += kNT) {
+          const int i = e / kT, j = e % kT;
+          if (c0 + i < mB && r0 + j < mA) tile[i][j] = vm[(c0 + i) * mA + r0 + j];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kT * kT; e += kNT) {
+          const int i = e / kT, j = e % kT;
+          if (r0 + i < mA && c0 + j < mB && !close_rel(vb[(r0 + i) * mB + c0 + j], sgn * tile[j][i])) bad |= 1 << x;
+        }
+        __syncthreads();
+      }
   }
+  if (bad & 1) atomicOr(d.err, kErrVMirror);
+  if (bad & 14) atomicOr(d.err, kErrDVMirror);
 }
 
 __global__ void k_val_onsite(Dev d) {
