@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(kNT) k_val_vmirror(Dev d) {
   __shared__ double tile[kT][kT + 1];
   const int64_t b = blockIdx.x;
   const int64_t m = d.Vmir[b];
+  if (m < b) return;   // the pair (m, b) compares the same elements
   const int mA = d.nabf[d.Vfirst[b]], mB = d.nabf[d.Vsecond[b]];
   const int n = mA * mB;
   int bad = 0;
@@ -113,12 +114,33 @@ __global__ void k_val_onsite(Dev d) {
   }
 }
 
-__global__ void k_val_dsym(Dev d) {
+// D = D^T, checked on the 32 x 32 tiles (tr, tc) with tr <= tc: tile (tc, tr)
+// is read along its rows into LDS and compared transposed.  Workgroup w
+// takes tiles w, w + gridDim.x, ... of the T x T tiles and skips those
+// below the diagonal (the skip is uniform over the workgroup).
+__global__ void __launch_bounds__(kNT) k_val_dsym(Dev d) {
+  constexpr int kT = 32;
+  __shared__ double tile[kT][kT + 1];
   const int64_t nt = d.ntot;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt * nt; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / nt, c = i % nt;
-    if (c > r && !close_rel(d.D[i], d.D[c * nt + r])) atomicOr(d.err, kErrDSym);
+  const int64_t T = (nt + kT - 1) / kT;
+  int bad = 0;
+  for (int64_t w = blockIdx.x; w < T * T; w += gridDim.x) {
+    const int64_t tr = w / T, tc = w - tr * T;
+    if (tr > tc) continue;
+    const int64_t r0 = tr * kT, c0 = tc * kT;
+    for (int e = threadIdx.x; e < kT * kT; e += kNT) {
+      const int i = e / kT, j = e % kT;
+      if (c0 + i < nt && r0 + j < nt) tile[i][j] = d.D[(c0 + i) * nt + r0 + j];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kT * kT; e += kNT) {
+      const int i = e / kT, j = e % kT;
+      const int64_t r = r0 + i, c = c0 + j;
+      if (c > r && c < nt && !close_rel(d.D[r * nt + c], tile[j][i])) bad = 1;
+    }
+    __syncthreads();
   }
+  if (bad) atomicOr(d.err, kErrDSym);
 }
 
 void launch_validate(const Dev& d, hipStream_t s) {
