@@ -703,8 +703,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     HIPCHK(hipMemsetAsync(d.err, 0, sizeof(int), c->stream));
     lrx::launch_validate_finite(d.Cval, C->nval, d.err, 1, c->stream);
     lrx::launch_validate_finite(d.Cdval, 3 * C->nval, d.err, 1, c->stream);
-    lrx::launch_validate_finite(d.Vval, V->nval, d.err, 2, c->stream);
-    lrx::launch_validate_finite(d.Vdval, 3 * V->nval, d.err, 2, c->stream);
+    // V and dV: finiteness is checked by the mirror pass of launch_validate
     lrx::launch_validate(d, c->stream);
     HIPCHK(hipGetLastError());
     int herr = 0;

@@ -70,7 +70,9 @@ __global__ void k_val_finite(const double* p, int64_t n, int* err, int code) {
 
 // V(B,A,-R) = V(A,B,R)^T and dV(B,A,-R) = -dV(A,B,R)^T: block b is [mA][mB],
 // its mirror [mB][mA].  The mirror is read in 32 x 32 tiles through LDS so
-// that both blocks are read along their rows.
+// that both blocks are read along their rows.  Every pair is checked once,
+// and as every V block is in a pair, this pass also checks that V and dV
+// are finite.
 __global__ void __launch_bounds__(kNT) k_val_vmirror(Dev d) {
   constexpr int kT = 32;
   __shared__ double tile[kT][kT + 1];
@@ -94,13 +96,18 @@ __global__ void __launch_bounds__(kNT) k_val_vmirror(Dev d) {
         __syncthreads();
         for (int e = threadIdx.x; e < kT * kT; e += kNT) {
           const int i = e / kT, j = e % kT;
-          if (r0 + i < mA && c0 + j < mB && !close_rel(vb[(r0 + i) * mB + c0 + j], sgn * tile[j][i])) bad |= 1 << x;
+          if (r0 + i < mA && c0 + j < mB) {
+            const double u = vb[(r0 + i) * mB + c0 + j], v = tile[j][i];
+            if (!isfinite(u) || !isfinite(v)) bad |= 16;
+            if (!close_rel(u, sgn * v)) bad |= 1 << x;
+          }
         }
         __syncthreads();
       }
   }
   if (bad & 1) atomicOr(d.err, kErrVMirror);
   if (bad & 14) atomicOr(d.err, kErrDVMirror);
+  if (bad & 16) atomicOr(d.err, kErrNonfiniteV);
 }
 
 __global__ void k_val_onsite(Dev d) {

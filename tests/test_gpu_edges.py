@@ -132,6 +132,20 @@ def test_non_finite_values_are_rejected():
     _expect_rejected(st, C, m["V"], m["D"], ["finite", "NaN", "nan"])
 
 
+def test_non_finite_v_values_are_rejected():
+    """V and dV are checked for finiteness in the mirror pass."""
+    H.require_gpu()
+    st, m = _fresh()
+    V = dict(m["V"])
+    V["val"] = m["V"]["val"].clone()
+    V["val"][-1] = float("nan")
+    _expect_rejected(st, m["C"], V, m["D"], ["non-finite V"])
+    V = dict(m["V"])
+    V["dval"] = m["V"]["dval"].clone()
+    V["dval"][2] = float("inf")
+    _expect_rejected(st, m["C"], V, m["D"], ["non-finite V"])
+
+
 def test_asymmetric_density_matrix_is_rejected():
     H.require_gpu()
     st, m = _fresh()
