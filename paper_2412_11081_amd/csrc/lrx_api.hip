@@ -66,7 +66,22 @@ Pairs group_pairs(int N, int64_t n, const int32_t* first, const int32_t* second,
   P.order.resize(n);
   std::iota(P.order.begin(), P.order.end(), 0);
   auto key = [&](int64_t b) { return Key{first[b], second[b], R[3 * b], R[3 * b + 1], R[3 * b + 2]}; };
-  std::sort(P.order.begin(), P.order.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+  // the key packed into 64 bits with the same order (atoms below 2^20, image
+  // indices in [-128, 127]), sorted with the block index; else the general sort
+  bool packable = N <= (1 << 20);
+  for (int64_t b = 0; b < n && packable; ++b)
+    for (int x = 0; x < 3; ++x) packable = packable && R[3 * b + x] >= -128 && R[3 * b + x] <= 127;
+  if (packable) {
+    std::vector<std::pair<uint64_t, int64_t>> kv(n);
+    for (int64_t b = 0; b < n; ++b)
+      kv[b] = {(uint64_t)first[b] << 44 | (uint64_t)second[b] << 24 | (uint64_t)(R[3 * b] + 128) << 16 |
+                   (uint64_t)(R[3 * b + 1] + 128) << 8 | (uint64_t)(R[3 * b + 2] + 128),
+               b};
+    std::sort(kv.begin(), kv.end());
+    for (int64_t k = 0; k < n; ++k) P.order[k] = kv[k].second;
+  } else {
+    std::sort(P.order.begin(), P.order.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+  }
   for (int64_t k = 1; k < n; ++k)
     require(!(key(P.order[k - 1]) == key(P.order[k])), "duplicate block key");
   P.row.assign(N + 1, 0);
@@ -374,24 +389,26 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
         if (C->first[b] == C->second[b] && !C->R[3 * b] && !C->R[3 * b + 1] && !C->R[3 * b + 2]) on[C->first[b]] = 1;
       for (int i = 0; i < N; ++i) require(on[i], "C: atom " + std::to_string(i) + " has no on-site block (A,A,0)");
     }
+    // mirror of every V block: (B, A, -R) for (A, B, R).  The blocks of a pair
+    // are sorted by R, so the mirrors of pair (A,B)'s blocks are pair (B,A)'s
+    // blocks in reverse order; every pairing is checked.
     std::vector<int64_t> vmir(c->nV);
     std::vector<int> vpmir(nVp);
-    {
-      std::vector<Key> sk(c->nV);
-      for (int64_t k = 0; k < c->nV; ++k) {
-        const int64_t b = vp.order[k];
-        sk[k] = Key{V->first[b], V->second[b], V->R[3 * b], V->R[3 * b + 1], V->R[3 * b + 2]};
-      }
-      std::vector<int> pos_pair(c->nV);
-      for (int p = 0; p < nVp; ++p)
-        for (int k = vp.b0[p]; k < vp.b1[p]; ++k) pos_pair[k] = p;
-      for (int64_t k = 0; k < c->nV; ++k) {
-        const Key m{sk[k].s, sk[k].f, -sk[k].r0, -sk[k].r1, -sk[k].r2};
-        auto it = std::lower_bound(sk.begin(), sk.end(), m);
-        require(it != sk.end() && *it == m, "V: block without its mirror (second, first, -R)");
-        const int64_t km = it - sk.begin();
-        vmir[vp.order[k]] = vp.order[km];
-        vpmir[pos_pair[k]] = pos_pair[km];
+    for (int p = 0; p < nVp; ++p) {
+      const int A = vp.pA[p], B = vp.pB[p];
+      const auto beg = vp.pB.begin() + vp.row[B], end = vp.pB.begin() + vp.row[B + 1];
+      const auto it = std::lower_bound(beg, end, A);
+      require(it != end && *it == A, "V: block without its mirror (second, first, -R)");
+      const int pm = (int)(it - vp.pB.begin());
+      const int n = vp.b1[p] - vp.b0[p];
+      require(vp.b1[pm] - vp.b0[pm] == n, "V: block without its mirror (second, first, -R)");
+      vpmir[p] = pm;
+      for (int j = 0; j < n; ++j) {
+        const int64_t b = vp.order[vp.b0[p] + j], bm = vp.order[vp.b1[pm] - 1 - j];
+        require(V->first[bm] == B && V->second[bm] == A && V->R[3 * bm] == -V->R[3 * b] &&
+                    V->R[3 * bm + 1] == -V->R[3 * b + 1] && V->R[3 * bm + 2] == -V->R[3 * b + 2],
+                "V: block without its mirror (second, first, -R)");
+        vmir[b] = bm;
       }
     }
     // ---- per-pair sizes and offsets --------------------------------------
@@ -443,6 +460,14 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       require(k + 3 <= lrx::kHMaxDepth,
               "atom " + std::to_string(B) + ": its C partners have more than 508 NAOs in total");
       c->max_depth = std::max(c->max_depth, (k + 3) & ~3);
+    }
+    {
+      int64_t ncol = 0;
+      for (int s = 0; s < nSlot; ++s) ncol += c->nao[c->slotX[s]];
+      hColSlot.reserve(ncol);
+      hColX.reserve(ncol);
+      hColD.reserve(ncol);
+      hColAtom.reserve(ncol);
     }
     for (int B = 0; B < N; ++B) {
       for (int s = slotRow[B]; s < slotRow[B + 1]; ++s)

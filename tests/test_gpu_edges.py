@@ -146,6 +146,18 @@ def test_non_finite_v_values_are_rejected():
     _expect_rejected(st, m["C"], V, m["D"], ["non-finite V"])
 
 
+def test_v_block_without_mirror_is_rejected():
+    """A V block whose (second, first, -R) partner is missing: one block moved
+    to a far image breaks the pairing in both directions."""
+    H.require_gpu()
+    st, m = _fresh()
+    V = dict(m["V"])
+    R = np.array(V["R"], dtype=np.int32).reshape(-1, 3).copy()
+    R[0, 0] += 1000
+    V["R"] = R
+    _expect_rejected(st, m["C"], V, m["D"], ["mirror"])
+
+
 def test_asymmetric_density_matrix_is_rejected():
     H.require_gpu()
     st, m = _fresh()
