@@ -139,6 +139,22 @@ int lrx_set_tensors(lrx_ctx* ctx, const lrx_blocks* C, const lrx_blocks* V, cons
  * reductions) runs in this library's kernels on the context's stream. */
 int lrx_evaluate(lrx_ctx* ctx, const lrx_options* opts, double* E, double* F, double* sigma);
 
+/* Asynchronous form of lrx_evaluate (the same evaluation, Eqs. for E_X, the
+ * forces and the stress): queues it on the context's stream and returns at
+ * once with *ticket, without waiting for the GPU.  opts->timing must be 0.
+ * Several submissions may be outstanding on one context; they run in order,
+ * each result going to its own pinned host buffer (owned by the library).
+ * Block gradients, masks and stats read after a submission describe the
+ * latest submitted evaluation (those calls wait for it).  Errors found while
+ * queueing are returned here; the ticket is then not issued. */
+int lrx_submit(lrx_ctx* ctx, const lrx_options* opts, int64_t* ticket);
+
+/* Wait for a submitted evaluation and write E, F [natom][3] and sigma [3][3]
+ * (host buffers; any may be NULL).  Each ticket is waited for once; an
+ * unknown or already-used ticket returns LRX_EINVAL.  Tickets still
+ * outstanding at lrx_destroy are waited for and released there. */
+int lrx_wait(lrx_ctx* ctx, int64_t ticket, double* E, double* F, double* sigma);
+
 /* Per-block gradients dE/dr_b of the last evaluation, in the caller's block
  * order: gC [C.nblk][3], gV [V.nblk][3] (host buffers; either may be NULL).
  * Screened blocks report 0. */

@@ -225,6 +225,20 @@ struct lrx_ctx {
   std::array<float, lrx::kMaxAlphaTiles + 1> group_ms{};
   bool timed = false;
   bool evaluated = false;
+  // evaluations queued by lrx_submit: results land in their own pinned buffer
+  struct Ticket {
+    hipEvent_t done = nullptr;
+    double* h = nullptr;
+    size_t bytes = 0;
+    int N = 0;
+  };
+  std::map<int64_t, Ticket> tickets;
+  int64_t next_ticket = 1;
+  void release(Ticket& t) {
+    if (t.done) (void)hipEventDestroy(t.done);
+    g_pinned.put(t.h, t.bytes);
+    t = Ticket{};
+  }
 
   template <class T>
   T* dalloc(int64_t count) {
@@ -1191,6 +1205,54 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
   });
 }
 
+int lrx_submit(lrx_ctx* c, const lrx_options* opts, int64_t* ticket) {
+  return guarded(c, [&] {
+    require(ticket != nullptr, "ticket: NULL");
+    require(opts != nullptr, "opts: NULL");
+    require(opts->timing == 0, "lrx_submit: stage times need lrx_evaluate");
+    prepare(c, opts);
+    lrx_ctx* one[1] = {c};
+    std::shared_ptr<BatchPlan> P = get_plan(one, 1, opts);
+    launch_plan(*P, opts);
+    HIPCHK(hipGetLastError());
+    lrx_ctx::Ticket t;
+    t.N = c->N;
+    t.bytes = sizeof(double) * (1 + 3 * c->N + 9 + 1);
+    HIPCHK(hipEventCreateWithFlags(&t.done, hipEventDisableTiming));
+    try {
+      t.h = (double*)g_pinned.get(t.bytes);
+      // the next evaluation on this stream overwrites dev.out only after this copy
+      HIPCHK(hipMemcpyAsync(t.h, c->dev.out, t.bytes, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipEventRecord(t.done, c->stream));
+    } catch (...) {
+      c->release(t);
+      throw;
+    }
+    c->timed = false;
+    c->evaluated = true;
+    const int64_t id = c->next_ticket++;
+    c->tickets[id] = t;
+    *ticket = id;
+  });
+}
+
+int lrx_wait(lrx_ctx* c, int64_t ticket, double* E, double* F, double* sigma) {
+  return guarded(c, [&] {
+    auto it = c->tickets.find(ticket);
+    require(it != c->tickets.end(), "lrx_wait: unknown ticket (not submitted on this context, or already waited for)");
+    lrx_ctx::Ticket t = it->second;
+    c->tickets.erase(it);
+    const hipError_t e = hipEventSynchronize(t.done);
+    if (e == hipSuccess) {
+      if (E) *E = t.h[0];
+      if (F) std::memcpy(F, t.h + 1, sizeof(double) * 3 * t.N);
+      if (sigma) std::memcpy(sigma, t.h + 1 + 3 * t.N, sizeof(double) * 9);
+    }
+    c->release(t);
+    HIPCHK(e);
+  });
+}
+
 int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts, double* E, double* F,
                        double* sigma) {
   if (!ctxs || n <= 0 || !ctxs[0]) return LRX_EINVAL;
@@ -1255,6 +1317,11 @@ void lrx_destroy(lrx_ctx* c) {
   if (!c) return;
   drop_plans_of(c);
   (void)hipSetDevice(c->device);
+  for (auto& kv : c->tickets) {   // submitted and never waited for
+    if (kv.second.done) (void)hipEventSynchronize(kv.second.done);
+    c->release(kv.second);
+  }
+  c->tickets.clear();
   c->free_tensors();
   g_pinned.put(c->h_out, c->h_out_bytes);
   if (c->events) {

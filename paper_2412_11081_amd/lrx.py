@@ -68,7 +68,8 @@ _lib = None
 
 EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
-           "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim", "lrx_group_times"]
+           "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim", "lrx_group_times",
+           "lrx_submit", "lrx_wait"]
 
 
 def load(path: Optional[str] = None):
@@ -99,9 +100,11 @@ def load(path: Optional[str] = None):
     lib.lrx_destroy.restype = None
     lib.lrx_pool_trim.argtypes = [ctypes.c_int32, ctypes.c_uint64]
     lib.lrx_group_times.argtypes = [vp, _f32p, ctypes.c_int32]
+    lib.lrx_submit.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int64)]
+    lib.lrx_wait.argtypes = [vp, ctypes.c_int64, _f64p, _f64p, _f64p]
     for f in ("lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
               "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning",
-              "lrx_pool_trim", "lrx_group_times"):
+              "lrx_pool_trim", "lrx_group_times", "lrx_submit", "lrx_wait"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -190,6 +193,21 @@ class Context:
         F = np.zeros((self.natom, 3))
         S = np.zeros((3, 3))
         self._check(self.lib.lrx_evaluate(self.h, ctypes.byref(o), ctypes.byref(E), _ptr(F, _f64p), _ptr(S, _f64p)))
+        return E.value, F, S
+
+    def submit(self, theta=0.0, theta_cs=0.0, precision="fp64"):
+        """lrx_submit: queue an evaluation on the context's stream; returns its ticket."""
+        o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), 0, 0, 0)
+        t = ctypes.c_int64()
+        self._check(self.lib.lrx_submit(self.h, ctypes.byref(o), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket):
+        """lrx_wait: (E, F, sigma) of a submitted evaluation."""
+        E = ctypes.c_double()
+        F = np.zeros((self.natom, 3))
+        S = np.zeros((3, 3))
+        self._check(self.lib.lrx_wait(self.h, int(ticket), ctypes.byref(E), _ptr(F, _f64p), _ptr(S, _f64p)))
         return E.value, F, S
 
     def block_gradients(self):
