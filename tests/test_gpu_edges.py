@@ -70,6 +70,26 @@ def test_partially_screened_density_blocks(oracle_lib, case):
     _check(st, got, r)
 
 
+def test_empty_v_list():
+    """No V blocks at all (an empty list is valid input): no triple exists,
+    so E, F, sigma and every C-block gradient are exactly zero."""
+    H.require_gpu()
+    import torch
+
+    st, m = _fresh(45)
+    V = dict(first=np.zeros(0, np.int32), second=np.zeros(0, np.int32), R=np.zeros((0, 3), np.int32),
+              off=np.zeros(0, np.int64), val=torch.zeros(0, dtype=torch.float64, device="cuda"),
+              dval=torch.zeros(0, dtype=torch.float64, device="cuda"))
+    ctx = lrx.Context(0)
+    ctx.set_structure(st.tau, st.lat, st.nao, st.nabf)
+    ctx.set_tensors(m["C"], V, m["D"])
+    for prec in ("fp64", "bf16x3"):
+        E, F, S = ctx.evaluate(0.0, 0.0, precision=prec)
+        gC, gV = ctx.block_gradients()
+        assert E == 0.0 and not F.any() and not S.any() and not gC.any() and gV.size == 0, prec
+    ctx.close()
+
+
 def test_single_atom_cell(oracle_lib):
     """One atom: every block is an image of the atom itself (force-free by
     symmetry up to rounding, stress from the image displacements)."""
