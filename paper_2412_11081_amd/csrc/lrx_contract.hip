@@ -1051,9 +1051,9 @@ template <int MT, int P, bool PERSIST>
 __global__ void __launch_bounds__(kTNT, 1)
     k_triple(DevBatch devs, const int2* __restrict__ items, int n, int* __restrict__ counters) {
   using Cfg = TripleCfg<MT, P>;
-  // three LDS objects: the compiler tells the stage (written by direct
-  // global->LDS loads) apart from X and the Z partials, so the products read
-  // those without waiting for the next chunk's loads to land
+  // LDS: X, the parked Z partials and the chunk stage (the compiler does not
+  // tell them apart for the direct global->LDS loads, so every wave reads its
+  // X operands before it issues the next chunk's loads), and the item slot
   __shared__ __attribute__((aligned(16))) typename Cfg::T sX[2 * 16 * Cfg::kXS];
   __shared__ __attribute__((aligned(16))) typename Cfg::A sZ[Cfg::kZSlots * 256];
   __shared__ __attribute__((aligned(16))) typename Cfg::T sS[Cfg::kStage];
