@@ -422,8 +422,10 @@ def workload(k: int) -> Structure:
 
 def small_case(natom: int = 3, n_ao: int = 3, n_abf: int = 5, box: float = 6.0, rc: float = 4.5,
                rv: float = 7.0, seed: int = 5, theta: float = 0.0, theta_cs: float = 0.0,
-               nspecies: int = 1, jitter: float = 0.6) -> Structure:
-    """Tiny random periodic cell for pins (finite differences, brute force)."""
+               nspecies: int = 1) -> Structure:
+    """Tiny random periodic cell for pins (finite differences, brute force):
+    a lattice within 0.3 Bohr of a cube of side ``box`` and atoms at uniform
+    random fractional positions."""
     rng = np.random.default_rng(seed)
     lat = np.eye(3) * box + rng.uniform(-0.3, 0.3, size=(3, 3))
     frac = rng.uniform(0, 1, size=(natom, 3))

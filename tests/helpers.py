@@ -17,6 +17,22 @@ TOL_SIGMA = 1e-6           # Ha/Bohr^3
 REL_FP64 = 1e-9
 
 
+def golden(case):
+    """Stored oracle result of a workload (tests/golden/make_golden_big.py)."""
+    from tests.golden import make_golden_big
+
+    return make_golden_big.load(case)
+
+
+def check_fingerprint(mats, ref):
+    """The generated inputs are the ones the stored result was computed from."""
+    from tests.golden import make_golden_big
+
+    fp = make_golden_big.fingerprint(mats)
+    assert np.allclose(fp, ref["fingerprint"], rtol=1e-10, atol=0), \
+        f"inputs differ from the stored ones: {fp} vs {ref['fingerprint']}"
+
+
 def nthreads():
     return int(os.environ.get("LRX_ORACLE_THREADS", min(16, os.cpu_count() or 1)))
 

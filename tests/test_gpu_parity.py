@@ -1,10 +1,9 @@
 """HIP path (through the C-ABI) against the CPU oracle.
 
 Small cells: every output element (E, F, sigma, per-block gradients, keep
-masks) against the oracle run live.  The 8-atom workload: against the stored
-oracle result.  The 64-, 320- and 1080-atom workloads: per-block gradients of
-sampled blocks against the oracle restricted to the quartets that contain
-them, the keep masks of those blocks, and properties that hold at any size.
+masks) against the oracle run live, with and without a binding Cauchy-Schwarz
+step.  The 8-, 64-, 320- and 1080-atom workloads: every output element
+against the oracle results stored by tests/golden/make_golden*.py.
 """
 import json
 import os
@@ -49,7 +48,7 @@ def test_small_cells_every_element(oracle_lib, case):
     H.require_gpu()
     natom, nsp, nao, nabf, box, rc, rv, theta, seed = case
     st = synth.small_case(natom=natom, nspecies=nsp, n_ao=nao, n_abf=nabf, box=box, rc=rc, rv=rv,
-                          seed=seed, theta=theta, theta_cs=1e-3 * theta, jitter=0.5).build()
+                          seed=seed, theta=theta, theta_cs=1e-3 * theta).build()
     print(f"case {case}: nC={len(st.keysC[0])} nV={len(st.keysV[0])}", flush=True)
     mats = st.materialize("cuda")
     g = _gpu(st, mats, st.theta, st.theta_cs)
@@ -91,51 +90,88 @@ def test_repeat_is_bitwise_identical():
     assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
-def _sampled(st, mats, nsample, seed):
-    g = _gpu(st, mats, st.theta, st.theta_cs)
-    rng = np.random.default_rng(seed)
-    nC, nV = g["gC"].shape[0], g["gV"].shape[0]
-    # properties that hold at any size
-    assert np.max(np.abs(g["F"].sum(axis=0))) <= 1e-10 * max(1.0, np.abs(g["F"]).max())
-    assert np.max(np.abs(g["sigma"] - g["sigma"].T)) <= 1e-10 * np.abs(g["sigma"]).max()
-    # forces and stress are the scatter of the block gradients
-    Fh = np.zeros_like(g["F"])
-    W = np.zeros((3, 3))
-    for kind, gr in (("C", g["gC"]), ("V", g["gV"])):
-        blk = mats[kind]
-        f, s = np.asarray(blk["first"]), np.asarray(blk["second"])
-        np.add.at(Fh, f, gr)
-        np.add.at(Fh, s, -gr)
-        W += gr.T @ blk["disp"]
-    H.assert_close_fp64("F from gradients", g["F"], Fh, H.TOL_F)
-    H.assert_close_fp64("sigma from gradients", g["sigma"], -W / st.volume, H.TOL_SIGMA)
-    picks = [("C", int(b)) for b in rng.choice(nC, size=min(nsample, nC), replace=False)]
-    picks += [("V", int(b)) for b in rng.choice(nV, size=min(nsample, nV), replace=False)]
-    for kind, b in picks:
-        ref, kept = H.oracle_block_gradient(st, mats, kind, b, st.theta, st.theta_cs)
-        got = (g["gC"] if kind == "C" else g["gV"])[b]
-        assert bool((g["keepC"] if kind == "C" else g["keepV"])[b]) == kept, (kind, b)
-        H.assert_close_fp64(f"g{kind}[{b}]", got, ref, H.TOL_F)
-    return g
+def _s2_threshold(pr, theta):
+    """A theta_cs at which step 2 removes between a fifth and four fifths of
+    the V blocks that step 1 keeps, chosen from the oracle's decisions on a
+    geometric grid (so the case cannot quietly stop exercising step 2)."""
+    base = int(pr.screen(theta, 0.0)[1].sum())
+    best, best_gap = None, None
+    for tcs in np.geomspace(1e-8, 1e4, 49):
+        drop = base - int(pr.screen(theta, float(tcs))[1].sum())
+        gap = abs(drop - 0.5 * base)
+        if drop > 0 and (best is None or gap < best_gap):
+            best, best_gap = float(tcs), gap
+    return best, base
 
 
-def test_diamond64_sampled_blocks():
+# cells where the Cauchy-Schwarz step (S2) removes V blocks that step 1 keeps
+S2_CASES = [
+    (3, 2, 13, 33, 7.0, 5.0, 8.0, 1e-4, 33),
+    (4, 3, 7, 20, 5.5, 4.5, 7.5, 2e-3, 34),
+    (3, 2, 5, 17, 6.5, 5.0, 8.0, 0.0, 32),      # step 2 alone (theta = 0)
+    (2, 2, 11, 90, 8.0, 5.0, 8.0, 1e-4, 39),
+]
+
+
+@pytest.mark.parametrize("case", S2_CASES, ids=[f"s2_n{c[0]}s{c[1]}ao{c[2]}abf{c[3]}th{c[7]}" for c in S2_CASES])
+def test_small_cells_schwarz_step_drops_blocks(oracle_lib, case):
+    """Step 2 of the screening (Cauchy-Schwarz bound, Sec. Sparsity
+    exploitation) with a threshold that binds: the keep masks and every
+    output element against the oracle, and a nonzero count of V blocks that
+    step 2 removed."""
     H.require_gpu()
-    st = H.workload(2)
+    natom, nsp, nao, nabf, box, rc, rv, theta, seed = case
+    st = synth.small_case(natom=natom, nspecies=nsp, n_ao=nao, n_abf=nabf, box=box, rc=rc, rv=rv,
+                          seed=seed, theta=theta).build()
     mats = st.materialize("cuda")
-    _sampled(st, mats, 3, 2)
+    pr = oracle_lib.Problem.from_structure(st, mats)
+    tcs, base = _s2_threshold(pr, theta)
+    assert tcs is not None, "no threshold makes step 2 bind"
+    r = pr.evaluate(theta, tcs, nthreads=H.nthreads())
+    dropped = base - int(r["keepV"].sum())
+    print(f"case {case}: theta_cs {tcs:.3e}, step 1 keeps {base} V blocks, step 2 drops {dropped}", flush=True)
+    assert dropped > 0
+    g = _gpu(st, mats, theta, tcs)
+    np.testing.assert_array_equal(g["keepC"], r["keepC"])
+    np.testing.assert_array_equal(g["keepV"], r["keepV"])
+    np.testing.assert_array_equal(g["keepD"], r["keepD"])
+    H.assert_close_fp64("E", g["E"], r["E"], H.TOL_E_PER_ATOM * st.natom)
+    H.assert_close_fp64("F", g["F"], r["F"], H.TOL_F)
+    H.assert_close_fp64("sigma", g["sigma"], r["sigma"], H.TOL_SIGMA)
+    H.assert_close_fp64("gC", g["gC"], r["gC"], H.TOL_F)
+    H.assert_close_fp64("gV", g["gV"], r["gV"], H.TOL_F)
 
 
-def test_perovskite320_sampled_blocks():
+# The 64-, 320- and 1080-atom workloads (the 1080-atom one in the
+# configuration the benchmark times) against the oracle results stored by
+# tests/golden/make_golden_big.py; diamond64_s2 is the 64-atom cell with a
+# Cauchy-Schwarz threshold that removes V blocks step 1 keeps.
+BIG = ["diamond64", "diamond64_s2", "abx3_320", "abx3_1080"]
+
+
+@pytest.mark.parametrize("case", BIG)
+def test_workload_every_element_against_stored_oracle(case):
     H.require_gpu()
-    st = H.workload(3)
+    ref = H.golden(case)
+    st = H.workload(int(ref["workload"]))
+    theta, theta_cs = float(ref["theta"]), float(ref["theta_cs"])
+    print(f"{case}: natom {st.natom}, theta {theta:g}, theta_cs {theta_cs:g}", flush=True)
     mats = st.materialize("cuda")
-    _sampled(st, mats, 3, 3)
-
-
-def test_perovskite1080_sampled_blocks():
-    """The 1080-atom workload in the configuration the benchmark times."""
-    H.require_gpu()
-    st = H.workload(4)
-    mats = st.materialize("cuda")
-    _sampled(st, mats, 2, 4)
+    H.check_fingerprint(mats, ref)
+    g = _gpu(st, mats, theta, theta_cs)
+    assert g["gC"].shape[0] == int(ref["nC"]) and g["gV"].shape[0] == int(ref["nV"])
+    np.testing.assert_array_equal(g["keepC"], ref["keepC"])
+    np.testing.assert_array_equal(g["keepV"], ref["keepV"])
+    np.testing.assert_array_equal(g["keepD"], ref["keepD"])
+    dropped = int(ref["kept_v_step1"]) - int(ref["keepV"].sum())
+    print(f"  kept C {int(ref['keepC'].sum())}, kept V {int(ref['keepV'].sum())} (step 2 dropped {dropped})", flush=True)
+    if case.endswith("_s2"):
+        assert dropped > 0
+    for name in ("E", "F", "sigma", "gC", "gV"):
+        err = np.max(np.abs(np.asarray(g[name]) - ref[name]))
+        print(f"  {name}: max abs error {err:.3e} (scale {np.max(np.abs(ref[name])):.3e})", flush=True)
+    H.assert_close_fp64("E", g["E"], ref["E"], H.TOL_E_PER_ATOM * st.natom)
+    H.assert_close_fp64("F", g["F"], ref["F"], H.TOL_F)
+    H.assert_close_fp64("sigma", g["sigma"], ref["sigma"], H.TOL_SIGMA)
+    H.assert_close_fp64("gC", g["gC"], ref["gC"], H.TOL_F)
+    H.assert_close_fp64("gV", g["gV"], ref["gV"], H.TOL_F)

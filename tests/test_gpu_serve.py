@@ -1,6 +1,7 @@
 """The serving loop on the GPU: each request's result is the same alone and
 in the mix (bit for bit: a request's work units and kernels do not depend on
-its batch), and within the BF16x3 bounds of the FP64 result."""
+its batch), and within the BF16x3 bounds (relative to each result's
+magnitude) of the FP64 result of the same request."""
 import numpy as np
 import pytest
 
@@ -32,9 +33,12 @@ def test_results_same_alone_and_in_the_mix():
         ctx.close()
         E, F, S = r.result
         assert E == alone[0] and np.array_equal(F, alone[1]) and np.array_equal(S, alone[2]), r.rid
-        assert np.max(np.abs(F - ref[1])) <= 1e-4
-        assert np.max(np.abs(S - ref[2])) <= 1e-5
-        assert abs(E - ref[0]) <= 1e-4 * abs(ref[0]) + 1e-8 * s.natom
+        dF, dS, dE = np.max(np.abs(F - ref[1])), np.max(np.abs(S - ref[2])), abs(E - ref[0])
+        print(f"request {r.rid} ({s.natom} atoms): |dE| {dE:.2e} max|dF| {dF:.2e} (max|F| "
+              f"{np.abs(ref[1]).max():.2e}) max|dsigma| {dS:.2e}", flush=True)
+        assert dF <= 1e-4 * np.abs(ref[1]).max() + 1e-12
+        assert dS <= 1e-4 * np.abs(ref[2]).max() + 1e-12
+        assert dE <= 1e-6 * abs(ref[0])
 
 
 def test_memory_cache_trim_and_reuse():

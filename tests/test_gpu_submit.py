@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 def _structure():
     return synth.small_case(natom=3, nspecies=2, n_ao=6, n_abf=21, box=6.5, rc=5.0, rv=8.0, seed=61,
-                            theta=1e-4, theta_cs=1e-7, jitter=0.5).build()
+                            theta=1e-4, theta_cs=1e-7).build()
 
 
 def _same(a, b):

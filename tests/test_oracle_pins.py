@@ -275,3 +275,37 @@ def test_block_screen_decisions(oracle_lib):
     for (a, c, r), i in key.items():
         j = key[(c, a, tuple(-np.array(r)))]
         assert kV[i] == kV[j]
+
+
+def test_schwarz_bound_is_tight_for_positive_scalar_blocks(oracle_lib):
+    """P6, equality case: with one NAO and one ABF per atom, positive C and D
+    entries and derivatives too small to enter the norms, every term of the
+    Cauchy-Schwarz bound S(A,B) is exactly the matching term of the folded
+    Z(A,B) = sum_{F,G} C(A,F) C(B,G) [D_AB D_FG + D_AG D_FB] (the triangle
+    inequality is an equality for positive terms).  Z is read off the
+    oracle's V-block gradients, g_b = -dV_b Z(A,B) for 1 x 1 blocks, so the
+    bound's formula is pinned to the contraction itself: a dropped term, a
+    wrong index or a missing factor breaks the equality."""
+    st = synth.small_case(natom=3, seed=23, nspecies=1, n_ao=1, n_abf=1, box=5.0, rc=4.0, rv=6.0).build()
+    mats = st.materialize("cpu")
+    C = dict(mats["C"])
+    C["val"] = mats["C"]["val"].abs() + 0.05
+    C["dval"] = mats["C"]["dval"] * 1e-9
+    D = np.abs(st.D)
+    pr = oracle_lib.Problem(st.tau, st.lat, st.nao, st.nabf, C, mats["V"], D)
+    kC, kV, kD, S = pr.screen(0.0, 0.0)
+    _, _, gV = pr.contract((kC, kV, kD))
+    V = mats["V"]
+    dv = V["dval"].numpy()
+    checked = 0
+    for b in range(pr.nV):
+        o = 3 * int(V["off"][b])
+        d3 = dv[o:o + 3]
+        x = int(np.argmax(np.abs(d3)))
+        if abs(d3[x]) < 1e-6:
+            continue   # on-site V block: no derivative to read Z through
+        A, B = int(V["first"][b]), int(V["second"][b])
+        Z = -gV[b, x] / d3[x]
+        assert Z > 0 and abs(S[A, B] - Z) <= 1e-12 * Z, (A, B, S[A, B], Z)
+        checked += 1
+    assert checked >= 6
