@@ -128,7 +128,9 @@ int lrx_set_structure(lrx_ctx* ctx, int32_t natom, const double* tau, const doub
  * Keys are always host arrays and are copied.  Validates keys on the host
  * and values on the device (finite, mirror and swap symmetries, D
  * symmetric); returns LRX_EINVAL with a message on the first violation.
- * Allocates the device work buffers for the worst case (nothing screened). */
+ * Allocates the lists, folded blocks, norms, masks and gradients for the
+ * worst case (nothing screened); the work buffers of a precision (see
+ * lrx_stats.work_bytes) are allocated by its first evaluation. */
 int lrx_set_tensors(lrx_ctx* ctx, const lrx_blocks* C, const lrx_blocks* V, const double* D,
                     int32_t data_on_device);
 
@@ -176,11 +178,21 @@ typedef struct {
                                 /* ... of its launch for the atoms A with
                                  * ceil(n_abf(A) / 16) = MT, by MT          */
   double bytes_alg;             /* algorithmic HBM bytes of one evaluation   */
-  double device_bytes;          /* device memory held by the context         */
+  double device_bytes;          /* device memory held by the context now     */
+  double work_bytes[3];         /* device memory of the work buffers of each
+                                 * precision (index = lrx_precision): H, Z
+                                 * and Y partials, and for FP32/BF16X3 the
+                                 * FP32 copies of the folded blocks and D
+                                 * (FP32 and BF16X3 share theirs).  Allocated
+                                 * by the first evaluation in that precision,
+                                 * then held (and counted in device_bytes)
+                                 * until new tensors or lrx_destroy.        */
+  int32_t work_held[3];         /* 1 if those buffers are allocated          */
+  int32_t reserved;
 } lrx_stats;
 
 /* Counts of the last evaluation (computed on the host from its masks); before
- * the first evaluation only device_bytes is set. */
+ * the first evaluation only device_bytes, work_bytes and work_held are set. */
 int lrx_get_stats(lrx_ctx* ctx, lrx_stats* out);
 
 /* Stage durations (ms) of the last evaluation run with opts.timing != 0,

@@ -714,6 +714,16 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.triHF = c->upload(triHF); d.triHA = c->upload(triHA);
     d.hdRow = c->upload(hdRow); d.hdRowD = c->upload(hdRowD); d.hdG = c->upload(hdG); d.hdCp = c->upload(hdCp);
     d.hdCf = c->upload(hdCf); d.hdStride = c->upload(hdStride);
+    d.hcK = c->dalloc<int>(N);
+    d.hcNcol = c->dalloc<int>(N);
+    d.hcRowD = c->dalloc<int>((int64_t)hdRowD.size());
+    d.hcG = c->dalloc<int>((int64_t)hdRowD.size());
+    d.hcCp = c->dalloc<int>((int64_t)hdRowD.size());
+    d.hcCf = c->dalloc<int64_t>((int64_t)hdRowD.size());
+    d.hcStride = c->dalloc<int>((int64_t)hdRowD.size());
+    d.hcColSlot = c->dalloc<int>((int64_t)hColSlot.size());
+    d.hcColD = c->dalloc<int>((int64_t)hColSlot.size());
+    d.hcColAtom = c->dalloc<int>((int64_t)hColSlot.size());
     d.Zbuf = nullptr;
     c->n_z = zOff[ntri];
     std::vector<int64_t> yOff(nCp + 1, 0);
@@ -828,9 +838,18 @@ int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
   return guarded(c, [&] {
     require(s != nullptr, "NULL stats");
     require(c->have_tensors, "no tensors yet");
-    if (!c->evaluated) {   // before the first evaluation only the memory held is known
+    auto work = [&](lrx_stats* o) {
+      const int64_t nt = c->ao[c->N];
+      o->work_bytes[LRX_FP64] = 8.0 * (double)(c->n_h + c->n_z + c->n_y);
+      o->work_bytes[LRX_FP32] = 4.0 * (double)(c->n_cf + c->n_vf + nt * nt + c->n_h + c->n_z + c->n_y);
+      o->work_bytes[LRX_BF16X3] = o->work_bytes[LRX_FP32];
+      o->work_held[LRX_FP64] = c->have_f64;
+      o->work_held[LRX_FP32] = o->work_held[LRX_BF16X3] = c->have_f32;
+      o->device_bytes = c->dev_bytes;
+    };
+    if (!c->evaluated) {   // before the first evaluation only the memory is known
       *s = lrx_stats{};
-      s->device_bytes = c->dev_bytes;
+      work(s);
       return;
     }
     const Dev& d = c->dev;
@@ -884,7 +903,7 @@ int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
     s->flop_triple = ft;
     s->flop_alg = fl + ft;
     s->bytes_alg = by;
-    s->device_bytes = c->dev_bytes;
+    work(s);
   });
 }
 

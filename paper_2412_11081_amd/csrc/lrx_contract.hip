@@ -166,30 +166,34 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
   const T* Dm = Buf<T>::D(d);
   const int B = d.hbB[blockIdx.x], r0 = d.hbR0[blockIdx.x], c0 = d.hbC0[blockIdx.x];
   const int mB = d.nabf[B], nB = d.nao[B], rows = mB * nB;
-  const int ncols = min(kHItemCols, d.hColRow[B + 1] - d.hColRow[B] - c0);
+  // the item's columns among the needed ones (the grid covers every column
+  // of the static table; items past the needed columns have nothing to do)
+  const int ncols = min(kHItemCols, d.hcNcol[B] - c0);
+  if (ncols <= 0) return;
   const int tid = threadIdx.x, lane = tid & 63, q = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
   const int cp0 = d.cpRow[B], ncp = d.cpRow[B + 1] - cp0;
-  const int s0 = d.hColSlot[d.hColRow[B] + c0], nsl = d.hColSlot[d.hColRow[B] + c0 + ncols - 1] - s0 + 1;
+  const int cb = d.hColRow[B];   // first column of B in the (compacted) column table
+  const int s0 = d.hcColSlot[cb + c0], nsl = d.hcColSlot[cb + c0 + ncols - 1] - s0 + 1;
   const bool local = ncp <= 32 && nsl <= 64;
   {
-    const int h0 = d.hdRow[B], hn = d.hdRow[B + 1] - h0;
+    // depth entries of the live C pairs (B,G) only (compacted per evaluation)
+    const int h0 = d.hdRow[B], hn = d.hcK[B];
     for (int k = tid; k < hn; k += kHT) {
-      const int t = d.hdCp[h0 + k];
-      const bool live = t >= 0 && d.aliveC[t >> 6];
-      krow[k] = d.hdRowD[h0 + k];
-      kG[k] = live ? d.hdG[h0 + k] : -1;
-      kcf[k] = d.hdCf[h0 + k];
-      kst[k] = d.hdStride[h0 + k];
+      const int t = d.hcCp[h0 + k];
+      krow[k] = d.hcRowD[h0 + k];
+      kG[k] = d.hcG[h0 + k];
+      kcf[k] = d.hcCf[h0 + k];
+      kst[k] = d.hcStride[h0 + k];
       kgi[k] = (signed char)(t >= 0 && local ? (t >> 6) - cp0 : 0);
     }
     for (int cl = tid; cl < kHItemCols; cl += kHT) {
       const bool in = cl < ncols;
-      const int c = d.hColRow[B] + c0 + (in ? cl : 0);
-      const int sl = d.hColSlot[c];
-      cSl[cl] = in && d.need[sl] ? sl : -1;
-      cD[cl] = d.hColD[c];           // a valid D column also past the item's end
-      cAt[cl] = d.hColAtom[c];
+      const int c = cb + c0 + (in ? cl : 0);
+      const int sl = d.hcColSlot[c];
+      cSl[cl] = in ? sl : -1;
+      cD[cl] = d.hcColD[c];          // a valid D column also past the item's end
+      cAt[cl] = d.hcColAtom[c];
       cxi[cl] = (signed char)(local ? sl - s0 : 0);
     }
     if (local)

@@ -105,6 +105,13 @@ struct Dev {
   const int* hColRow;      // [N+1] columns of atom B: the (slot, x) of every H slot of B, concatenated
   const int* hColSlot; const int* hColX; const int* hColD; const int* hColAtom;
   uint8_t* need;
+  // per evaluation: the static depth and column tables of every atom B
+  // compacted to the live C pairs (B,G) and the needed slots (B,X), in the
+  // same regions and order (k_hcompact); hcK[B] depth entries (a multiple of
+  // 4, at least 4), hcNcol[B] columns
+  int* hcK; int* hcNcol;
+  int* hcRowD; int* hcG; int* hcCp; int64_t* hcCf; int* hcStride;
+  int* hcColSlot; int* hcColD; int* hcColAtom;
   double* H;
 
   // triple work units

@@ -377,6 +377,79 @@ __global__ void k_mark(Dev d) {
   }
 }
 
+// Compaction of the H-build tables of atom B (one workgroup per atom):
+// depth entries of live C pairs (B,G), in table order, padded with entries
+// of no atom to a multiple of 4 (at least 4, so a slot whose C pairs are all
+// screened is still written, as zeros); columns of the needed slots (B,X),
+// in table order.  Ordered prefix sums over the ballots of each 64-lane
+// wave: the result does not depend on scheduling.
+__device__ inline int block_exclusive_scan(bool flag, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int within = __popcll(m & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (lane == 0) sh[w] = __popcll(m);
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int i = 0; i < nw; ++i) {
+    before += i < w ? sh[i] : 0;
+    all += sh[i];
+  }
+  *total = all;
+  return before + within;
+}
+
+__global__ void __launch_bounds__(kNT) k_hcompact(Dev d) {
+  __shared__ int sh[kNT / 64];
+  const int B = blockIdx.x;
+  {
+    const int h0 = d.hdRow[B], hn = d.hdRow[B + 1] - h0;
+    int n = 0;
+    for (int k0 = 0; k0 < hn; k0 += kNT) {
+      const int k = k0 + threadIdx.x;
+      const int t = k < hn ? d.hdCp[h0 + k] : -1;
+      const bool live = t >= 0 && d.aliveC[t >> 6];
+      int tot;
+      const int pos = h0 + n + block_exclusive_scan(live, sh, &tot);
+      if (live) {
+        d.hcRowD[pos] = d.hdRowD[h0 + k];
+        d.hcG[pos] = d.hdG[h0 + k];
+        d.hcCp[pos] = t;
+        d.hcCf[pos] = d.hdCf[h0 + k];
+        d.hcStride[pos] = d.hdStride[h0 + k];
+      }
+      n += tot;
+    }
+    const int K = max(4, (n + 3) & ~3);   // <= hn: every atom has its on-site pair
+    for (int k = n + threadIdx.x; k < K; k += kNT) {
+      d.hcRowD[h0 + k] = 0;
+      d.hcG[h0 + k] = -1;
+      d.hcCp[h0 + k] = -1;
+      d.hcCf[h0 + k] = 0;
+      d.hcStride[h0 + k] = 0;
+    }
+    if (threadIdx.x == 0) d.hcK[B] = K;
+  }
+  {
+    const int c0 = d.hColRow[B], cn = d.hColRow[B + 1] - c0;
+    int n = 0;
+    for (int k0 = 0; k0 < cn; k0 += kNT) {
+      const int k = k0 + threadIdx.x;
+      const int sl = k < cn ? d.hColSlot[c0 + k] : -1;
+      const bool live = sl >= 0 && d.need[sl];
+      int tot;
+      const int pos = c0 + n + block_exclusive_scan(live, sh, &tot);
+      if (live) {
+        d.hcColSlot[pos] = sl;
+        d.hcColD[pos] = d.hColD[c0 + k];
+        d.hcColAtom[pos] = d.hColAtom[c0 + k];
+      }
+      n += tot;
+    }
+    if (threadIdx.x == 0) d.hcNcol[B] = n;
+  }
+}
+
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)(a > 0 ? (a + b - 1) / b : 1); }
 
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev) {
@@ -397,6 +470,7 @@ void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev) {
   hipLaunchKernelGGL(k_fill_u8, dim3(cdiv(d.nSlot, kNT)), dim3(kNT), 0, s, d.need,
                      (int64_t)d.nSlot);
   hipLaunchKernelGGL(k_mark, dim3(cdiv(d.nCp, kNT)), dim3(kNT), 0, s, d);
+  hipLaunchKernelGGL(k_hcompact, dim3((unsigned)d.N), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[3], s);
 }
 

@@ -56,11 +56,14 @@ class Stats(ctypes.Structure):
                 ("alive_triples", ctypes.c_int64), ("h_slots", ctypes.c_int64),
                 ("flop_alg", ctypes.c_double), ("flop_triple", ctypes.c_double),
                 ("flop_triple_group", ctypes.c_double * 9),
-                ("bytes_alg", ctypes.c_double), ("device_bytes", ctypes.c_double)]
+                ("bytes_alg", ctypes.c_double), ("device_bytes", ctypes.c_double),
+                ("work_bytes", ctypes.c_double * 3), ("work_held", ctypes.c_int32 * 3),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        out = {k: getattr(self, k) for k, _ in self._fields_}
-        out["flop_triple_group"] = list(out["flop_triple_group"])
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        for k in ("flop_triple_group", "work_bytes", "work_held"):
+            out[k] = list(out[k])
         return out
 
 

@@ -237,6 +237,9 @@ class Server:
                 self._lock.notify_all()
 
 
+_PRECISION_INDEX = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
 class LrxEngine(Engine):
     """The library as the server's engine: one context per admitted request,
     block tensors materialised on the device at admission, batches evaluated
@@ -272,7 +275,13 @@ class LrxEngine(Engine):
         with torch.cuda.stream(self._streams.s):
             mats = st.materialize(f"cuda:{self.device}")
             ctx = lrx.context_for(st, mats, device=self.device)
-        held = int(ctx.stats()["device_bytes"]) + self.input_bytes(st)
+        stats = ctx.stats()
+        p = _PRECISION_INDEX[self.precision]
+        # what the context holds now, plus the work buffers its first
+        # evaluation in the serving precision allocates
+        held = int(stats["device_bytes"]) + self.input_bytes(st)
+        if not stats["work_held"][p]:
+            held += int(stats["work_bytes"][p])
         with self._rlock:
             self.ratio = max(self.ratio, held / max(1, self.input_bytes(st)) - 1.0)
         return (ctx, mats, st), held
@@ -280,11 +289,18 @@ class LrxEngine(Engine):
     def run(self, handles):
         from . import lrx
 
-        ctxs = [h[0] for h in handles]
-        st = handles[0][2]
-        E, F, S = lrx.evaluate_batch(ctxs, st.theta, st.theta_cs, precision=self.precision, eager=True,
-                                     tune=False)
-        return list(zip(E, F, S))
+        # one batched pass per distinct (theta, theta_cs): the thresholds are
+        # options of the whole pass
+        out = [None] * len(handles)
+        groups = {}
+        for i, h in enumerate(handles):
+            groups.setdefault((h[2].theta, h[2].theta_cs), []).append(i)
+        for (theta, theta_cs), idx in groups.items():
+            E, F, S = lrx.evaluate_batch([handles[i][0] for i in idx], theta, theta_cs, precision=self.precision,
+                                         eager=True, tune=False)
+            for k, i in enumerate(idx):
+                out[i] = (E[k], F[k], S[k])
+        return out
 
     def release(self, handle):
         handle[0].close()
