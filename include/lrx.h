@@ -240,6 +240,28 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
  * Returns LRX_MAX_ALPHA_TILES + 1. */
 int lrx_batch_tuning(const lrx_ctx* ctx, int32_t* mode, float* ms);
 
+/* Size of the fixed device scratch of lrx_evaluate_noalloc (bytes per GPU). */
+#define LRX_SCRATCH_BYTES (128ull << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * evaluation as lrx_evaluate (same kernels, same results), but its work
+ * buffers (H slots, Z and Y partial sums, and for FP32/BF16X3 the FP32
+ * copies of the folded blocks and D) come from a fixed device array of
+ * LRX_SCRATCH_BYTES that each GPU holds from the library's load until the
+ * process ends, instead of the context's own buffers.  Calls no hipMalloc,
+ * hipFree or other allocating routine; kernels run eagerly on the context's
+ * stream (no batch plan, no graph).  The context must hold tensors
+ * (lrx_set_tensors, which allocates as documented there); inputs and outputs
+ * are as for lrx_evaluate; opts->timing must be 0.
+ * Returns LRX_EBUDGET, computing nothing, when the structure needs more
+ * scratch than LRX_SCRATCH_BYTES (small cells only: lrx_get_stats reports
+ * the size as work_bytes).  Every call on one GPU uses that GPU's one array
+ * and overwrites what the last call left there, so calls that overlap in
+ * time on one GPU (other threads, other contexts or streams) race: the
+ * caller must serialise them. */
+int lrx_evaluate_noalloc(lrx_ctx* ctx, const lrx_options* opts, double* E, double* F, double* sigma);
+
 /* Message of the last failing call on this context ("" if none). */
 const char* lrx_last_error(const lrx_ctx* ctx);
 

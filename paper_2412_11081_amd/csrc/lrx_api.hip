@@ -28,6 +28,12 @@
 
 using lrx::Dev;
 
+// The fixed device scratch of lrx_evaluate_noalloc: one array per GPU, held
+// from the module's load until the process ends.  Its name is only a
+// host-side handle; host code uses the per-device address that
+// hipGetSymbolAddress returns (scratch_on), never the name itself.
+static __device__ __align__(256) unsigned char scratch[LRX_SCRATCH_BYTES];
+
 namespace {
 
 struct Fail {
@@ -176,6 +182,27 @@ void by_atom(int N, int64_t n, const int32_t* atom, std::vector<int>& row, std::
   for (int64_t b = 0; b < n; ++b) list[fill[atom[b]]++] = b;
 }
 
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_addr;   // device -> address of its scratch
+
+// Address of this device's scratch, looked up once per device with that
+// device current (called from lrx_create).
+unsigned char* scratch_on(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Fail{LRX_EHIP, "hipGetSymbolAddress(scratch) returned NULL"};
+  g_scratch_addr[device] = (unsigned char*)p;
+  return (unsigned char*)p;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
 }  // namespace
 
 struct lrx_ctx {
@@ -214,6 +241,7 @@ struct lrx_ctx {
   // autotuner result of the last batch plan built with this context first
   std::array<int, lrx::kMaxAlphaTiles + 1> tune_mode{};
   std::array<float, 2 * (lrx::kMaxAlphaTiles + 1)> tune_ms{};
+  unsigned char* scratch = nullptr;   // this device's fixed scratch (lrx_evaluate_noalloc)
   double* h_out = nullptr;   // pinned, from g_pinned
   size_t h_out_bytes = 0;
   std::array<hipEvent_t, LRX_NSTAGES + 1> ev{};
@@ -334,6 +362,7 @@ int lrx_create(lrx_ctx** out, int32_t device, void* hip_stream) {
     for (auto& e : c->fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     c->events = true;
     for (auto& st : c->side) st = g_streams.get(device);
+    c->scratch = scratch_on(device);
   });
   if (rc != LRX_OK) {
     lrx_destroy(c);
@@ -1306,6 +1335,72 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
       if (sigma) std::memcpy(sigma + 9 * i, c->h_out + 1 + 3 * c->N, sizeof(double) * 9);
       fo += 3 * c->N;
     }
+  });
+}
+
+int lrx_evaluate_noalloc(lrx_ctx* c, const lrx_options* opts, double* E, double* F, double* sigma) {
+  return guarded(c, [&] {
+    require(opts != nullptr, "opts: NULL");
+    require(c->have_tensors, "evaluation before lrx_set_tensors");
+    const int prec = opts->precision;
+    require(prec == LRX_FP64 || prec == LRX_FP32 || prec == LRX_BF16X3, "unknown precision");
+    require(std::isfinite(opts->theta) && std::isfinite(opts->theta_cs), "non-finite threshold");
+    require(opts->timing == 0, "lrx_evaluate_noalloc: stage times need lrx_evaluate");
+    require(c->scratch != nullptr, "lrx_evaluate_noalloc: no scratch address for this device");
+    // the work buffers of this precision, carved from the scratch in 256-byte steps
+    const int64_t nt = c->ao[c->N];
+    auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255; };
+    size_t need = 0;
+    if (prec == LRX_FP64)
+      need = al(8 * c->n_h) + al(8 * c->n_z) + al(8 * c->n_y);
+    else
+      need = al(4 * c->n_cf) + al(4 * c->n_vf) + al(4 * nt * nt) + al(4 * c->n_h) + al(4 * c->n_z) + al(4 * c->n_y);
+    if (need > (size_t)LRX_SCRATCH_BYTES)
+      throw Fail{LRX_EBUDGET, "lrx_evaluate_noalloc: this structure needs " + std::to_string(need) +
+                                  " bytes of scratch, more than the fixed " + std::to_string((size_t)LRX_SCRATCH_BYTES)};
+    Dev d = c->dev;
+    size_t used = 0;
+    auto carve = [&](size_t bytes) {
+      unsigned char* p = c->scratch + used;
+      used += al(bytes);
+      return p;
+    };
+    unsigned char* hbase;
+    size_t hbytes;
+    if (prec == LRX_FP64) {
+      d.H = (double*)(hbase = carve(hbytes = 8 * c->n_h));
+      d.Zbuf = (double*)carve(8 * c->n_z);
+      d.Ybuf = (double*)carve(8 * c->n_y);
+    } else {
+      d.Cf32 = (float*)carve(4 * c->n_cf);
+      d.Vf32 = (float*)carve(4 * c->n_vf);
+      d.D32 = (float*)carve(4 * nt * nt);
+      d.H32 = (float*)(hbase = carve(hbytes = 4 * c->n_h));
+      d.Zbuf32 = (float*)carve(4 * c->n_z);
+      d.Ybuf32 = (float*)carve(4 * c->n_y);
+    }
+    // the scratch keeps whatever the last call on this GPU left: the padding
+    // rows of the H slots, which no kernel writes, must read zero
+    hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, c->stream, (unsigned long long*)hbase,
+                       (int64_t)(al(hbytes) / 8));
+    lrx::TripleLaunch tl = c->tl;
+    tl.devs.s[0] = d;
+    {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) tl.mode[mt] = g_tuned[prec][mt] >= 0 ? g_tuned[prec][mt] : 1;
+    }
+    const lrx::Opts o{opts->theta, opts->theta_cs, prec};
+    lrx::launch_screen(d, o, c->stream, nullptr);
+    lrx::launch_contract(d, tl, prec, c->stream, c->side.data(), c->fork.data(), nullptr, nullptr);
+    HIPCHK(hipGetLastError());
+    const int N = c->N;
+    HIPCHK(hipMemcpyAsync(c->h_out, d.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->timed = false;
+    c->evaluated = true;
+    if (E) *E = c->h_out[0];
+    if (F) std::memcpy(F, c->h_out + 1, sizeof(double) * 3 * N);
+    if (sigma) std::memcpy(sigma, c->h_out + 1 + 3 * N, sizeof(double) * 9);
   });
 }
 

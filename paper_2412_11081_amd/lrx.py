@@ -37,6 +37,7 @@ class LrxError(RuntimeError):
 BATCH_EAGER = 1
 BATCH_NO_TUNE = 2
 MAX_ALPHA_TILES = 8
+SCRATCH_BYTES = 128 << 20     # LRX_SCRATCH_BYTES of include/lrx.h
 
 
 class Options(ctypes.Structure):
@@ -72,7 +73,7 @@ _lib = None
 EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
            "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim", "lrx_group_times",
-           "lrx_submit", "lrx_wait"]
+           "lrx_submit", "lrx_wait", "lrx_evaluate_noalloc"]
 
 
 def load(path: Optional[str] = None):
@@ -105,7 +106,8 @@ def load(path: Optional[str] = None):
     lib.lrx_group_times.argtypes = [vp, _f32p, ctypes.c_int32]
     lib.lrx_submit.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int64)]
     lib.lrx_wait.argtypes = [vp, ctypes.c_int64, _f64p, _f64p, _f64p]
-    for f in ("lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
+    lib.lrx_evaluate_noalloc.argtypes = [vp, ctypes.POINTER(Options), _f64p, _f64p, _f64p]
+    for f in ("lrx_evaluate_noalloc", "lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
               "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning",
               "lrx_pool_trim", "lrx_group_times", "lrx_submit", "lrx_wait"):
         getattr(lib, f).restype = ctypes.c_int
@@ -196,6 +198,17 @@ class Context:
         F = np.zeros((self.natom, 3))
         S = np.zeros((3, 3))
         self._check(self.lib.lrx_evaluate(self.h, ctypes.byref(o), ctypes.byref(E), _ptr(F, _f64p), _ptr(S, _f64p)))
+        return E.value, F, S
+
+    def evaluate_noalloc(self, theta=0.0, theta_cs=0.0, precision="fp64"):
+        """lrx_evaluate_noalloc: the evaluation with the library's fixed device
+        scratch for its work buffers (no device allocation)."""
+        o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), 0, 0, 0)
+        E = ctypes.c_double()
+        F = np.zeros((self.natom, 3))
+        S = np.zeros((3, 3))
+        self._check(self.lib.lrx_evaluate_noalloc(self.h, ctypes.byref(o), ctypes.byref(E), _ptr(F, _f64p),
+                                                  _ptr(S, _f64p)))
         return E.value, F, S
 
     def submit(self, theta=0.0, theta_cs=0.0, precision="fp64"):
