@@ -224,6 +224,7 @@ struct lrx_ctx {
   std::vector<int32_t> Cf, Cs, CR, Vf, Vs, VR;
   Pairs cp, vp;
   std::vector<int> slotB, slotX, unitCp, unitK0, unitK1, unitKc, unitV0, unitV1, unitS, nkc, nsplit;
+  std::vector<uint8_t> unitYonly;
   std::vector<int64_t> tBase;
   int max_mm = 1, max_depth = 4;
   // sizes of the FP32 buffers of the reduced-precision forms
@@ -552,6 +553,11 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
         c->nsplit[i] = (int)std::max<int64_t>(1, std::min<int64_t>({want, (int64_t)nv, 16}));
       }
     }
+    // The V partners of A (sorted by B) fall in two ranges: B < A, where only
+    // Y is formed (Z(A,B) is the transpose of Z(B,A), formed by the units of
+    // atom B), and B >= A, where Z and Y are both formed.  Each range is
+    // divided into its share of the C pair's nsplit V ranges.
+    c->unitYonly.clear();
     for (int i = 0; i < nCp; ++i) {
       const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
       const int cols = lrx::unit_cols((c->nabf[cp.pA[i]] + 15) / 16);
@@ -560,18 +566,26 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       chunk = std::min(cols, (chunk + 15) / 16 * 16);
       int cnt = 0;
       const int A = cp.pA[i];
-      const int nv = vp.row[A + 1] - vp.row[A], ns = c->nsplit[i];
+      const int r0 = vp.row[A], r1 = vp.row[A + 1], nv = r1 - r0, ns = c->nsplit[i];
+      const int mid = (int)(std::lower_bound(vp.pB.begin() + r0, vp.pB.begin() + r1, A) - vp.pB.begin());
+      const int ny = mid - r0, nz = r1 - mid;
+      const int nsY = ny > 0 ? std::max(1, (int)(((int64_t)ns * ny + nv / 2) / std::max(1, nv))) : 0;
+      const int nsZ = nz > 0 ? std::max(1, ns - nsY) : 0;
       for (int k0 = 0; k0 < K1; k0 += chunk, ++cnt)
-        for (int sp = 0; sp < ns; ++sp) {
+        for (int sp = 0; sp < nsY + nsZ; ++sp) {
+          const bool yo = sp < nsY;
+          const int b0 = yo ? r0 : mid, len = yo ? ny : nz, m = yo ? nsY : nsZ, k = yo ? sp : sp - nsY;
           c->unitCp.push_back(i);
           c->unitK0.push_back(k0);
           c->unitK1.push_back(std::min(K1, k0 + chunk));
           c->unitKc.push_back(cnt);
-          c->unitV0.push_back(vp.row[A] + (int)((int64_t)nv * sp / ns));
-          c->unitV1.push_back(vp.row[A] + (int)((int64_t)nv * (sp + 1) / ns));
+          c->unitV0.push_back(b0 + (int)((int64_t)len * k / m));
+          c->unitV1.push_back(b0 + (int)((int64_t)len * (k + 1) / m));
           c->unitS.push_back(sp);
+          c->unitYonly.push_back(yo ? 1 : 0);
         }
       c->nkc[i] = cnt;
+      c->nsplit[i] = nsY + nsZ;
     }
     for (int A = 0; A < N; ++A) {
       int z = 0;
@@ -588,7 +602,8 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
       for (int i = cp.row[A]; i < cp.row[A + 1]; ++i)
         for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
           const int64_t t = c->tBase[A] + (int64_t)(i - cp.row[A]) * nvA + (p - vp.row[A]);
-          zOff[t + 1] = (int64_t)c->nkc[i] * c->nabf[A] * c->nabf[vp.pB[p]];
+          // Z partials only where Z(A,B) is formed (B >= A)
+          zOff[t + 1] = vp.pB[p] >= A ? (int64_t)c->nkc[i] * c->nabf[A] * c->nabf[vp.pB[p]] : 0;
         }
     }
     for (int64_t t = 0; t < ntri; ++t) zOff[t + 1] += zOff[t];
@@ -738,6 +753,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.unitCp = c->upload(c->unitCp); d.unitK0 = c->upload(c->unitK0); d.unitK1 = c->upload(c->unitK1);
     d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
     d.unitV0 = c->upload(c->unitV0); d.unitV1 = c->upload(c->unitV1); d.unitS = c->upload(c->unitS);
+    d.unitYonly = c->upload(c->unitYonly);
     d.nsplit = c->upload(c->nsplit);
     d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);
     d.triHF = c->upload(triHF); d.triHA = c->upload(triHA);
@@ -915,7 +931,8 @@ int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
         if (!aV[p]) continue;
         const int B = vp.pB[p];
         s->alive_triples++;
-        const double t = 4.0 * nb[A] * nb[B] * na[A] * na[Fa] + 4.0 * nb[B] * na[A] * na[B] * na[Fa];
+        // Y and (for B >= A; the other half is its transpose) Z, and the X-build
+        const double t = (B >= A ? 4.0 : 2.0) * nb[A] * nb[B] * na[A] * na[Fa] + 4.0 * nb[B] * na[A] * na[B] * na[Fa];
         ft += t;
         s->flop_triple_group[(nb[A] + 15) / 16] += t;
       }

@@ -324,13 +324,15 @@ struct TripleCfg {
   using A = T;                                                               // Z partial sums
   static constexpr int kCols = unit_cols(MT);
   static constexpr int kKSW = P == kPB3 ? (kCols / 16 + 3) / 4 : kCols / 16;   // Z k-steps per Z wave
-  static constexpr int kJW = (kCols / 16 + 3) / 4;                            // Y column tiles per Y wave
+  static constexpr int kJW = (kCols / 16 + 3) / 4;                            // Y column tiles per Y wave (4 Y waves)
+  static constexpr int kJW8 = (kCols / 16 + 7) / 8;                           // ... when all 8 waves are Y waves
   static constexpr int kXS = kCols + 1;
   // X-build by all eight waves; FP64 with many alpha tiles leaves the Y
   // waves registers for one tile in flight only
   static constexpr int kXW = 8;                                              // waves taking part
   static constexpr int kNUZ = 2;                                             // tiles in flight: Z waves
-  static constexpr int kNUY = (P == kP64 && MT >= 5) ? 1 : 2;                 // Y waves
+  static constexpr int kNUY = (P == kP64 && MT >= 5) ? 1 : 2;                 // Y waves (4 Y waves)
+  static constexpr int kNUY8 = 2;                                            // ... (8 Y waves)
   // Z reduction: alpha tiles below kMF are owned by Z wave (i mod 4), which
   // adds the three partials the other Z waves park; a single remaining tile
   // (MT = 1 mod 4) is parked by all four and reduced a quarter per wave
@@ -714,7 +716,13 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
   xterm<T, DIRECT, NU, XW, true>(U, nB, HA, hsA, Dfb, X2, ((w - U.N1) % XW + XW) % XW, U.N2, q, g);
 }
 
-template <int MT, int P, bool ZROLE>
+// Roles of a wave in a unit: a Z wave (units whose V partners B have B >= A:
+// Z and Y are both formed), a Y wave beside four Z waves, or one of eight Y
+// waves (units whose partners all have B < A: Z(A,B) is the transpose of
+// Z(B,A), which the units of atom B form, so only Y is formed).
+enum Role : int { kRoleZ = 0, kRoleY = 1, kRoleY8 = 2 };
+
+template <int MT, int P, int ROLE>
 __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<MT, P>::T* __restrict__ X1,
                             typename TripleCfg<MT, P>::A* __restrict__ Zred, typename TripleCfg<MT, P>::T* __restrict__ S,
                             const typename TripleCfg<MT, P>::T* __restrict__ Dg,
@@ -726,18 +734,21 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
   using Acc = typename M::acc;           // d4 (FP64) or f4 (FP32, BF16x3)
   using A = typename Cfg::A;
   constexpr bool B3 = P == kPB3;
-  constexpr int NU = ZROLE ? Cfg::kNUZ : Cfg::kNUY;
+  constexpr bool ZROLE = ROLE == kRoleZ;
+  constexpr int NYW = ROLE == kRoleY8 ? 8 : 4;                      // Y waves of the unit
+  constexpr int JW = ROLE == kRoleY8 ? Cfg::kJW8 : Cfg::kJW;          // Y column tiles per Y wave
+  constexpr int NU = ZROLE ? Cfg::kNUZ : (ROLE == kRoleY8 ? Cfg::kNUY8 : Cfg::kNUY);
   // X1 and X2 (X), Zred (partial Z tiles on their way to the owning wave) and
   // S (the chunk stage) are distinct LDS objects
   T* X2 = X1 + 16 * Cfg::kXS;
-  const int ww = w & 3;
+  const int ww = ROLE == kRoleY8 ? w : (w & 3);   // index among the waves of the role
   const int N = d.N;
   const int mA = U.mA, XS = U.XS;
   const T* Cf = Buf<T>::Cf(d);
 
   // ---- resident operands / accumulators of the role ----------------------
   constexpr int ZI = ZROLE ? MT : 1, ZT = ZROLE ? Cfg::kKSW : 1;
-  constexpr int YI = ZROLE ? 1 : MT, YJ = ZROLE ? 1 : Cfg::kJW;
+  constexpr int YI = ZROLE ? 1 : MT, YJ = ZROLE ? 1 : JW;
   T cfr[B3 ? 1 : ZI][B3 ? 1 : ZT];
   s4 cfh[B3 ? ZI : 1][B3 ? ZT : 1], cfl[B3 ? ZI : 1][B3 ? ZT : 1];
   Acc yacc[YI][YJ];
@@ -766,10 +777,10 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
-      for (int j = 0; j < Cfg::kJW; ++j) yacc[i][j] = Acc{0, 0, 0, 0};
+      for (int j = 0; j < JW; ++j) yacc[i][j] = Acc{0, 0, 0, 0};
   }
   // column tiles of this Y wave that reach the chunk's columns
-  const int nYJ = min(Cfg::kJW, (U.NTc - ww + 3) >> 2);
+  const int nYJ = min(JW, (U.NTc - ww + NYW - 1) / NYW);
 
   // prologue: stage the first chunk
   Chunk ch = chunk_at(d, U, U.vb, 0);
@@ -920,11 +931,11 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
     } else {
       if constexpr (B3) {
         // column tiles j >= NTc accumulate values that are never stored
-        s4 bh[Cfg::kJW], blo[Cfg::kJW];
+        s4 bh[JW], blo[JW];
 #pragma unroll
-        for (int jj = 0; jj < Cfg::kJW; ++jj) {
-          if (jj == Cfg::kJW - 1 && jj >= nYJ) break;
-          const int j = ww + 4 * jj;
+        for (int jj = 0; jj < JW; ++jj) {
+          if (jj == JW - 1 && jj >= nYJ) break;
+          const int j = ww + NYW * jj;
           float v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
@@ -935,28 +946,28 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
         }
         stage_next();
 #pragma unroll
-        for (int jj = 0; jj < Cfg::kJW; ++jj) {
-          if (jj == Cfg::kJW - 1 && jj >= nYJ) break;
+        for (int jj = 0; jj < JW; ++jj) {
+          if (jj == JW - 1 && jj >= nYJ) break;
 #pragma unroll
           for (int i = 0; i < MT; ++i) yacc[i][jj] = mma_bf16x3(avh[i], avl[i], bh[jj], blo[jj], yacc[i][jj]);
         }
       } else {
         // column tiles j >= NTc accumulate values that are never stored; the
         // last tile of a wave is skipped when it lies past the chunk
-        constexpr int JF = Cfg::kJW - 1;
-        T xb[4][Cfg::kJW];
+        constexpr int JF = JW - 1;
+        T xb[4][JW];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int jj = 0; jj < JF; ++jj) {
-            const int bl = 4 * s + g, c = min(16 * (ww + 4 * jj) + q, XS - 1);
+            const int bl = 4 * s + g, c = min(16 * (ww + NYW * jj) + q, XS - 1);
             const int e = (int)__umul24((unsigned)bl, (unsigned)XS) + c;
             xb[s][jj] = X1[e] + X2[e];
           }
         if (JF < nYJ) {
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            const int bl = 4 * s + g, e = (int)__umul24((unsigned)bl, (unsigned)XS) + 16 * (ww + 4 * JF) + q;
+            const int bl = 4 * s + g, e = (int)__umul24((unsigned)bl, (unsigned)XS) + 16 * (ww + NYW * JF) + q;
             xb[s][JF] = X1[e] + X2[e];
           }
         }
@@ -985,8 +996,8 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
-      for (int jj = 0; jj < Cfg::kJW; ++jj) {
-        const int j = ww + 4 * jj;
+      for (int jj = 0; jj < JW; ++jj) {
+        const int j = ww + NYW * jj;
         if (j < U.NTc) {
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
@@ -1039,10 +1050,12 @@ __device__ __forceinline__ void triple_unit(const Dev& d, int u, typename Triple
   // the stage starts zeroed: padding rows the X-build reads past nB are finite
   for (int e = tid; e < Cfg::kStage; e += kTNT) S[e] = T(0);
   __syncthreads();
-  if (w < 4)
-    triple_role<MT, P, true>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
+  if (ldu(d.unitYonly, u))
+    triple_role<MT, P, kRoleY8>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
+  else if (w < 4)
+    triple_role<MT, P, kRoleZ>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
   else
-    triple_role<MT, P, false>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
+    triple_role<MT, P, kRoleY>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
 }
 
 // items[i] = (structure index into devs, unit index of that structure).
@@ -1088,6 +1101,10 @@ __global__ void __launch_bounds__(kTNT, 1)
 // ---------------------------------------------------------------------------
 // Z(A,B) = sum over live (A,F) and column chunks of the Z partials; then, in
 // one pass over the pair's blocks, E = -<Vf, Z> and g_v = -<dV_v, Z> (FP64).
+// Only pairs with A <= B: the mirror pair (B,A) has Z(B,A) = Z(A,B)^T and
+// Vf(B,A) = Vf(A,B)^T, so its energy term is the same, and each mirror block
+// (B,A,-R) has dV = -dV(A,B,R)^T, so its gradient is -g_v (input checks hold
+// these symmetries to 1e-12 relative).
 // ---------------------------------------------------------------------------
 constexpr int kZB = 4;      // V image blocks contracted per pass over Z
 constexpr int kZMax = 64;   // Z partials (live C pairs x column chunks) of one V pair
@@ -1102,13 +1119,17 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
   const T* Zb = Buf<T>::Z(d);
   const int p = blockIdx.x;
   const int A = d.vpA[p], B = d.vpB[p];
+  if (A > B) return;   // written by the mirror pair (B,A)
+  const bool mirror = A < B;
+  const int pm = d.vpMir[p];
   const int mA = d.nabf[A], mB = d.nabf[B], n = mA * mB;
   if (!d.aliveV[p]) {
     for (int k = d.vpB0[p] + threadIdx.x; k < d.vpB1[p]; k += kNT) {
-      const int64_t b = d.vpBlk[k];
+      const int64_t b = d.vpBlk[k], bm = d.Vmir[b];
       d.gV[3 * b] = d.gV[3 * b + 1] = d.gV[3 * b + 2] = 0.0;
+      d.gV[3 * bm] = d.gV[3 * bm + 1] = d.gV[3 * bm + 2] = 0.0;
     }
-    if (threadIdx.x == 0) d.Ep[p] = 0.0;
+    if (threadIdx.x == 0) d.Ep[p] = d.Ep[pm] = 0.0;
     return;
   }
   {
@@ -1164,10 +1185,17 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
     }
     block_sum_n<1 + 3 * kZB>(acc, sh);
     if (threadIdx.x == 0) {
-      if (first) d.Ep[p] = -acc[0];
+      if (first) {
+        d.Ep[p] = -acc[0];
+        if (mirror) d.Ep[pm] = -acc[0];
+      }
       for (int j = 0; j < nb; ++j) {
         const int64_t b = d.vpBlk[k0 + j];
         for (int x = 0; x < 3; ++x) d.gV[3 * b + x] = kp[j] ? -acc[1 + 3 * j + x] : 0.0;
+        if (mirror) {
+          const int64_t bm = d.Vmir[b];
+          for (int x = 0; x < 3; ++x) d.gV[3 * bm + x] = kp[j] ? acc[1 + 3 * j + x] : 0.0;
+        }
       }
     }
     if (kb1 <= kb0) break;

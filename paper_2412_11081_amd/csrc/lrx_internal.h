@@ -14,8 +14,10 @@
 //   H        H(B,X)[b][beta][x] = sum_G Cf(B,G)[beta][b][g] D(G,X)[g][x] for
 //            every (B,X) a triple (A,F,B) needs (X = A or X = F); beta runs
 //            over the ABFs of B rounded up to 16 (padding rows stay zero);
-//   Zbuf     per triple (A,F,B) and column chunk: the F-partial of
-//            Z(A,B)[alpha][beta] = sum_{F,a,f} Cf(A,F)[alpha][a][f] X^{AFB}[beta][a][f],
+//   Zbuf     per triple (A,F,B) with A <= B and column chunk: the F-partial of
+//            Z(A,B)[alpha][beta] = sum_{F,a,f} Cf(A,F)[alpha][a][f] X^{AFB}[beta][a][f]
+//            (Z(B,A) = Z(A,B)^T: D is symmetric and the screening keeps
+//            mirror pairs together, so pairs with A > B take the transpose),
 //            X^{AFB}[beta][a][f] = sum_b D_AB[a][b] H(B,F)[beta][b][f]
 //                                + sum_b D_FB[f][b] H(B,A)[beta][b][a];
 //   Ybuf     per C pair and V-pair range s: Y_s(A,F)[alpha][a][f] = sum_{B in range s}
@@ -118,6 +120,7 @@ struct Dev {
   int nUnit;
   const int* unitCp; const int* unitK0; const int* unitK1; const int* unitKc;
   const int* unitV0; const int* unitV1; const int* unitS;   // V-pair range and split index of a unit
+  const uint8_t* unitYonly; // 1: every V partner B of the unit has B < A (only Y is formed)
   const int* nsplit;       // [nCp] number of V-pair ranges (Y partials) of a C pair
   const int* unitOrder;    // units grouped by the alpha-tile count of their atom A
   int mtStart[kMaxAlphaTiles + 2];
