@@ -240,6 +240,27 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
  * Returns LRX_MAX_ALPHA_TILES + 1. */
 int lrx_batch_tuning(const lrx_ctx* ctx, int32_t* mode, float* ms);
 
+/* Image pairs within a cutoff (Methods: the combined index of atom and
+ * lattice vector; every two-centre block -- C within the orbital cutoff, V
+ * within the Coulomb range -- depends on the displacement
+ * r = tau[second] + R.L - tau[first] of its two atoms).  Every key
+ * (first, second, R) with |r|^2 < rcut^2 is found on the device, where
+ *   R.L = (R_0 a1 + R_1 a2) + R_2 a3,  r = (tau[second] - tau[first]) + R.L,
+ *   |r|^2 = (r_x^2 + r_y^2) + r_z^2,
+ * each operation rounded to FP64 on its own (no fused multiply-add), so the
+ * decision is reproducible; R_i runs over |R_i| <= ceil(rcut / h_i) + 1, h_i
+ * the spacing of the lattice planes spanned by the other two vectors.  Keys
+ * are written sorted by (first, second, R_0, R_1, R_2); the list is closed
+ * under the mirror (second, first, -R) up to the rounding of that formula.
+ * tau [natom][3], lattice [3][3] (rows a1..a3), host arrays.  Outputs are
+ * host arrays first/second [capacity] and R [capacity][3]; *count receives
+ * the number of keys.  Returns LRX_EBUDGET (writing only *count) when
+ * capacity is too small, LRX_EINVAL for bad arguments (non-finite
+ * positions, a singular lattice, a cutoff more than 62 lattice spacings).
+ * Uses device memory of its own for the duration of the call. */
+int lrx_enumerate_pairs(int32_t device, int32_t natom, const double* tau, const double* lattice, double rcut,
+                        int64_t capacity, int32_t* first, int32_t* second, int32_t* R, int64_t* count);
+
 /* Size of the fixed device scratch of lrx_evaluate_noalloc (bytes per GPU). */
 #define LRX_SCRATCH_BYTES (128ull << 20)
 

@@ -73,7 +73,7 @@ _lib = None
 EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
            "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim", "lrx_group_times",
-           "lrx_submit", "lrx_wait", "lrx_evaluate_noalloc"]
+           "lrx_submit", "lrx_wait", "lrx_evaluate_noalloc", "lrx_enumerate_pairs"]
 
 
 def load(path: Optional[str] = None):
@@ -107,7 +107,9 @@ def load(path: Optional[str] = None):
     lib.lrx_submit.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int64)]
     lib.lrx_wait.argtypes = [vp, ctypes.c_int64, _f64p, _f64p, _f64p]
     lib.lrx_evaluate_noalloc.argtypes = [vp, ctypes.POINTER(Options), _f64p, _f64p, _f64p]
-    for f in ("lrx_evaluate_noalloc", "lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
+    lib.lrx_enumerate_pairs.argtypes = [ctypes.c_int32, ctypes.c_int32, _f64p, _f64p, ctypes.c_double, ctypes.c_int64,
+                                        _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_int64)]
+    for f in ("lrx_evaluate_noalloc", "lrx_enumerate_pairs", "lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
               "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning",
               "lrx_pool_trim", "lrx_group_times", "lrx_submit", "lrx_wait"):
         getattr(lib, f).restype = ctypes.c_int
@@ -309,6 +311,35 @@ def batch_tuning(context):
     ms = (ctypes.c_float * (2 * (MAX_ALPHA_TILES + 1)))()
     context.lib.lrx_batch_tuning(context.h, mode, ms)
     return {mt: (int(mode[mt]), float(ms[2 * mt]), float(ms[2 * mt + 1])) for mt in range(1, MAX_ALPHA_TILES + 1)}
+
+
+def enumerate_pairs(tau, lat, rcut, device: int = 0, capacity: int = 0):
+    """lrx_enumerate_pairs: keys (first, second, R[n][3]) of every image pair
+    within rcut, sorted by (first, second, R).  Calls the library again with
+    the exact size when the first buffer (``capacity``, default an estimate
+    from the cell's density) is too small."""
+    lib = load()
+    tau = _np(tau, np.float64)
+    lat = _np(lat, np.float64)
+    n = int(tau.shape[0])
+    if capacity <= 0:
+        vol = abs(float(np.linalg.det(lat)))
+        dens = n / vol if vol > 0 and np.isfinite(vol) else 0.0   # the library rejects a singular lattice
+        capacity = int(min(n * (1 + 1.5 * 4.19 * rcut ** 3 * dens), 1 << 30)) + 64
+    for _ in range(2):
+        f = np.zeros(capacity, np.int32)
+        s = np.zeros(capacity, np.int32)
+        R = np.zeros((capacity, 3), np.int32)
+        cnt = ctypes.c_int64()
+        rc = lib.lrx_enumerate_pairs(int(device), n, _ptr(tau, _f64p), _ptr(lat, _f64p), float(rcut), int(capacity),
+                                     _ptr(f, _i32p), _ptr(s, _i32p), _ptr(R, _i32p), ctypes.byref(cnt))
+        if rc == 0:
+            k = int(cnt.value)
+            return f[:k].copy(), s[:k].copy(), R[:k].copy()
+        if rc != -5:
+            raise LrxError(rc, "lrx_enumerate_pairs failed (bad arguments or device error)")
+        capacity = int(cnt.value)
+    raise LrxError(-5, "lrx_enumerate_pairs: capacity")
 
 
 def pool_trim(device: int = 0, keep_bytes: int = 0):
