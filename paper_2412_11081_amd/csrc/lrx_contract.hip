@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
   // and padding give 0
   static_assert(kHT % kHCB == 0, "a thread's column is the same for every i");
   T pv[kHPre];
-  auto fetch = [&](int blk, int p) {
+  auto fetch = [&](int blk, int p) __attribute__((always_inline)) {
     const int kb = p * kHPass, cl = blk * kHCB + (tid & (kHCB - 1));
     const T* Dc = Dm + cD[cl];
     const bool cok = cSl[cl] >= 0;
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
     }
   };
   T af[kHPass / 4];
-  auto load_a = [&](int p) {
+  auto load_a = [&](int p) __attribute__((always_inline)) {
     const int kb = p * kHPass;
 #pragma unroll
     for (int t = 0; t < kHPass / 4; ++t) {
@@ -574,7 +574,7 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
   const int as = TERM2 ? hs : 1, bs = TERM2 ? 1 : hs;
   using M = M4<T>;
   // NUx tiles t0, t0 + XW, ... in flight
-  auto tiles = [&](auto nu, int t0) {
+  auto tiles = [&](auto nu, int t0) __attribute__((always_inline)) {
     constexpr int NUx = decltype(nu)::value;
     const T* ap[NUx];
     const T* bp[NUx];
@@ -613,7 +613,7 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
       // two register sets in turn: the loads of step st+1 are in flight
       // while the product of step st is issued
       T a0[NUx], b0[NUx], a1[NUx], b1[NUx];
-      auto next = [&](T (&av)[NUx], T (&bv)[NUx]) {
+      auto next = [&](T (&av)[NUx], T (&bv)[NUx]) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < NUx; ++u) {
           av[u] = *ap[u];
@@ -645,7 +645,7 @@ __device__ __forceinline__ void xterm(const UnitGeo& U, int nB, const T* H, int 
       // (global) at min(b, nB - 1), finite.  The operands of the next pass
       // are requested before the products of the current one.
       T av[NUx][2], bv[NUx][2];
-      auto load = [&](int s0, T (&a2)[NUx][2], T (&b2)[NUx][2]) {
+      auto load = [&](int s0, T (&a2)[NUx][2], T (&b2)[NUx][2]) __attribute__((always_inline)) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           const int b = min(4 * (s0 + s) + g, nBp - 1), bc = min(b, nB - 1);
@@ -723,7 +723,7 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
 enum Role : int { kRoleZ = 0, kRoleY = 1, kRoleY8 = 2 };
 
 template <int MT, int P, int ROLE>
-__device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<MT, P>::T* __restrict__ X1,
+__device__ __forceinline__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<MT, P>::T* __restrict__ X1,
                             typename TripleCfg<MT, P>::A* __restrict__ Zred, typename TripleCfg<MT, P>::T* __restrict__ S,
                             const typename TripleCfg<MT, P>::T* __restrict__ Dg,
                             const typename TripleCfg<MT, P>::T* __restrict__ Vg,
@@ -838,7 +838,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
     // issues the loads that stage them
     if (nx.p >= 0 && nx.p != ch.p)
       zero_d_padding(U, nx.nB, ldu(d.keepD, (int64_t)U.A * N + nx.B) != 0, ldu(d.keepD, (int64_t)U.F * N + nx.B) != 0, S);
-    auto stage_next = [&] {
+    auto stage_next = [&]() __attribute__((always_inline)) {
       if (nx.p >= 0) {
         Stager<T> st;
         st.init(d, U, nx, sn, nx.p != ch.p, sn.hend <= Cfg::kStage, S, Dg, Vg, Hg);
@@ -908,7 +908,7 @@ __device__ void triple_role(const Dev& d, const UnitGeo& U, typename TripleCfg<M
       T* Zdst = Buf<T>::Z(d) + ldu(d.zOff, tri) + (int64_t)U.kc * mA * ch.mB;
       const int be = ch.b0 + q;
       // 32-bit byte offsets from the uniform block base (a Z block is far below 4 GiB)
-      auto zstore = [&](int al, T v) {
+      auto zstore = [&](int al, T v) __attribute__((always_inline)) {
         if (al < mA && be < ch.mB) *(T*)((char*)Zdst + (unsigned)(al * ch.mB + be) * (unsigned)sizeof(T)) = v;
       };
 #pragma unroll
