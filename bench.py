@@ -135,7 +135,7 @@ def cpu_full_small():
     return {"value": 1.0 / dt, "unit": "evals/s", "cores": 1, "workload": WORKLOADS[1], "seconds": dt}
 
 
-def serving_benchmark(n, precision="bf16x3", budget_gib=160, max_batch=8, workers=2, admitters=4):
+def serving_benchmark(n, precision="bf16x3", budget_gib=160, max_batch=8, workers=1, admitters=4, window=0.01):
     """The serving stream: n requests of 20..500 atoms (three species, random
     cubic or orthorhombic cells), each admitted (blocks materialised on the
     device, context set up), evaluated and released.  Measures, after one
@@ -174,7 +174,7 @@ def serving_benchmark(n, precision="bf16x3", budget_gib=160, max_batch=8, worker
           file=sys.stderr, flush=True)
 
     srv = Server(LrxEngine(precision=precision), hbm_budget=budget_gib << 30, max_batch=max_batch,
-                 workers=workers, admitters=admitters)
+                 workers=workers, admitters=admitters, window=window)
 
     def run(arrivals):
         srv.reset_stats()
@@ -202,6 +202,7 @@ def serving_benchmark(n, precision="bf16x3", budget_gib=160, max_batch=8, worker
             "one_at_a_time_fp64_evals_per_s": base64, "one_at_a_time_fp64_p50_ms": pct(lat64, 50),
             "one_at_a_time_fp64_p99_ms": pct(lat64, 99),
             "hbm_budget_gib": budget_gib, "max_batch": max_batch, "workers": workers, "admitters": admitters,
+            "window_s": window,
             "max_bytes_held_gib": burst["max_bytes_held"] / 2**30}
 
 

@@ -67,12 +67,18 @@ class Engine:
 class Server:
     """Continuous-batching request loop over an Engine."""
 
-    def __init__(self, engine: Engine, hbm_budget: int, max_batch: int = 8, workers: int = 2, admitters: int = 2):
-        assert hbm_budget > 0 and max_batch > 0 and workers > 0 and admitters > 0
+    def __init__(self, engine: Engine, hbm_budget: int, max_batch: int = 8, workers: int = 2, admitters: int = 2,
+                 window: float = 0.0):
+        assert hbm_budget > 0 and max_batch > 0 and workers > 0 and admitters > 0 and window >= 0
         self.engine = engine
         self.budget = int(hbm_budget)
         self.max_batch = int(max_batch)
         self.n_workers = int(workers)
+        # batching window: a free worker takes the admitted requests once
+        # max_batch of them are ready, once the oldest has waited `window`
+        # seconds, or once no other request is on its way (pending or being
+        # admitted); 0 dispatches whatever is ready at once
+        self.window = float(window)
         self._lock = threading.Condition()
         self._pending: collections.deque = collections.deque()      # submitted, not admitted
         self._ready: collections.deque = collections.deque()        # admitted, waiting for a worker
@@ -173,7 +179,7 @@ class Server:
                     self._used += take.footprint
                     self.max_used = max(self.max_used, self._used)
                 # dispatch: a free worker takes the admitted requests
-                if self._ready and self._busy + len(self._jobs) < self.n_workers:
+                if self._ready and self._busy + len(self._jobs) < self.n_workers and self._dispatch_now():
                     batch = [self._ready.popleft() for _ in range(min(self.max_batch, len(self._ready)))]
                     self._jobs.append(batch)
                     self._lock.notify_all()
@@ -182,6 +188,14 @@ class Server:
             else:
                 with self._lock:
                     self._lock.wait(0.002)
+
+    def _dispatch_now(self) -> bool:
+        """Whether the ready requests go out now (called with the lock held)."""
+        if self.window <= 0 or len(self._ready) >= self.max_batch:
+            return True
+        if not self._pending and not self._admitting:
+            return True
+        return time.perf_counter() - self._ready[0].t_admit >= self.window
 
     def _admit(self, req: Request):
         try:

@@ -119,3 +119,20 @@ def test_poisson_replay_and_latency_stats():
     assert st["completed"] == 40 and st["failed"] == 0
     assert 0 < st["p50_s"] <= st["p99_s"]
     assert all(r.t_submit <= r.t_done for r in reqs)
+
+
+def test_batching_window_gathers_requests_admitted_close_together():
+    """With a window, a free worker waits for the requests being admitted
+    (up to max_batch or the window) instead of taking the first one alone;
+    without one it takes whatever is ready."""
+    sizes = {}
+    for window in (0.0, 0.05):
+        eng = FakeEngine()
+        srv = Server(eng, hbm_budget=1000, max_batch=6, workers=1, admitters=4, window=window)
+        reqs = [srv.submit(Request(i, dict(bytes=10, secs=0.02, value=i))) for i in range(12)]
+        assert srv.drain(timeout=30)
+        srv.close()
+        assert all(r.error is None for r in reqs)
+        sizes[window] = list(srv.batches)
+    assert sizes[0.05] == [6, 6], sizes
+    assert len(sizes[0.0]) > 2, sizes
