@@ -57,6 +57,12 @@ def _load():
         lib.orc_contract.argtypes = [ctypes.POINTER(OrcInput), _u8p, _u8p, _u8p, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.c_int, ctypes.c_int64, ctypes.c_int, _f64p, _f64p, _f64p]
         lib.orc_contract.restype = ctypes.c_int
+        lib.orc_contract2.argtypes = [ctypes.POINTER(OrcInput), _u8p, _u8p, _u8p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _f64p, _f64p,
+                                      _f64p, _f64p]
+        lib.orc_contract2.restype = ctypes.c_int
+        lib.orc_screen5.argtypes = [ctypes.POINTER(OrcInput), _f64p, ctypes.c_double, _u8p, _u8p, _u8p, _f64p]
+        lib.orc_screen5.restype = ctypes.c_int
         lib.orc_forces_stress.argtypes = [ctypes.POINTER(OrcInput), _f64p, _f64p, _f64p, _f64p]
         lib.orc_has_openmp.restype = ctypes.c_int
         _lib = lib
@@ -120,17 +126,47 @@ class Problem:
             raise ValueError("V block without mirror (second, first, -R)")
         return kC, kV, kD, S.reshape(self.natom, self.natom)
 
-    def contract(self, keep, v_begin=0, v_end=None, focus=None, nthreads=1):
-        """E and block gradients from the quartets of V blocks [v_begin, v_end)."""
+    def screen5(self, thr, theta_cs):
+        """Per-tensor screening, thr = (theta_C, theta_V, theta_D, theta_dC,
+        theta_dV): bit masks (bit 0 value kept, bit 1 derivative kept) for C
+        and V blocks, 0/1 for D pairs, and S(A,B)."""
+        lib = _load()
+        t = np.ascontiguousarray(thr, np.float64)
+        assert t.shape == (5,)
+        kC = np.zeros(self.nC, np.uint8)
+        kV = np.zeros(self.nV, np.uint8)
+        kD = np.zeros(self.natom * self.natom, np.uint8)
+        S = np.zeros(self.natom * self.natom, np.float64)
+        rc = lib.orc_screen5(ctypes.byref(self.s), _p(t, _f64p), theta_cs, _p(kC, _u8p), _p(kV, _u8p), _p(kD, _u8p),
+                             _p(S, _f64p))
+        if rc != 0:
+            raise ValueError("V block without mirror (second, first, -R)")
+        return kC, kV, kD, S.reshape(self.natom, self.natom)
+
+    def contract(self, keep, v_begin=0, v_end=None, focus=None, nthreads=1, bits=False, theta_item=0.0):
+        """E and block gradients from the quartets of V blocks [v_begin, v_end).
+
+        keep = (keepC, keepV, keepD): 0/1 masks from screen() (a kept block in
+        both lists), or with bits=True the bit masks of screen5().
+        theta_item > 0 adds the item-level Cauchy-Schwarz test; the sum of the
+        bounds of the skipped energy items is then in self.skipped_bound."""
         lib = _load()
         kC, kV, kD = keep[:3]
+        if not bits:
+            kC = np.where(np.asarray(kC) != 0, 3, 0).astype(np.uint8)
+            kV = np.where(np.asarray(kV) != 0, 3, 0).astype(np.uint8)
+        kC = np.ascontiguousarray(kC, np.uint8)
+        kV = np.ascontiguousarray(kV, np.uint8)
+        kD = np.ascontiguousarray(kD, np.uint8)
         E = np.zeros(1)
+        sk = np.zeros(1)
         gC = np.zeros((self.nC, 3))
         gV = np.zeros((self.nV, 3))
         fk, fi = (0, 0) if focus is None else ({"C": 1, "V": 2}[focus[0]], int(focus[1]))
-        lib.orc_contract(ctypes.byref(self.s), _p(kC, _u8p), _p(kV, _u8p), _p(kD, _u8p), int(v_begin),
-                         int(self.nV if v_end is None else v_end), fk, fi, int(nthreads),
-                         _p(E, _f64p), _p(gC, _f64p), _p(gV, _f64p))
+        lib.orc_contract2(ctypes.byref(self.s), _p(kC, _u8p), _p(kV, _u8p), _p(kD, _u8p), int(v_begin),
+                          int(self.nV if v_end is None else v_end), fk, fi, int(nthreads), float(theta_item),
+                          _p(E, _f64p), _p(gC, _f64p), _p(gV, _f64p), _p(sk, _f64p))
+        self.skipped_bound = float(sk[0])
         return float(E[0]), gC, gV
 
     def forces_stress(self, gC, gV):
@@ -148,6 +184,16 @@ class Problem:
         E, gC, gV = self.contract(keep, nthreads=nthreads)
         F, sig = self.forces_stress(gC, gV)
         return dict(E=E, F=F, sigma=sig, gC=gC, gV=gV, keepC=keep[0], keepV=keep[1], keepD=keep[2])
+
+
+    def evaluate5(self, thr, theta_cs, theta_item=0.0, nthreads=1):
+        """E, F, sigma with per-tensor thresholds (screen5) and, for
+        theta_item > 0, the item-level Cauchy-Schwarz test."""
+        keep = self.screen5(thr, theta_cs)
+        E, gC, gV = self.contract(keep, nthreads=nthreads, bits=True, theta_item=theta_item)
+        F, sig = self.forces_stress(gC, gV)
+        return dict(E=E, F=F, sigma=sig, gC=gC, gV=gV, keepC=keep[0], keepV=keep[1], keepD=keep[2],
+                    skipped_bound=self.skipped_bound)
 
 
 def evaluate_structure(st, theta=None, theta_cs=None, nthreads=1, mats=None):

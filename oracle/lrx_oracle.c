@@ -218,6 +218,86 @@ int orc_screen(const orc_input* in, double theta, double theta_cs,
   return rc;
 }
 
+/*
+ * Screening with one threshold per tensor (Table thr_default: C, V, D, dC,
+ * dV), thr = {theta_C, theta_V, theta_D, theta_dC, theta_dV}; a threshold
+ * <= 0 keeps that whole tensor.  keepC / keepV get bit masks: bit 0 when the
+ * block's value passes its threshold (max|C| > theta_C; for V the larger of
+ * max|V| over the block and its mirror > theta_V), bit 1 when its derivative
+ * passes (max|dC| > theta_dC; max|dV| over the block and its mirror >
+ * theta_dV); keepD 0/1 (max|D_XY| > theta_D on the block with X <= Y).
+ * Step 2 (theta_cs > 0) then drops a V block (both bits) iff
+ * nv * S(A,B) <= theta_cs, with c(A,F) summing, over the images with any
+ * bit, the larger Frobenius norm of the kept parts, and nv the larger
+ * Frobenius norm of the kept parts of the block and its mirror.
+ * Returns 0, or -1 if a V block has no mirror.
+ */
+int orc_screen5(const orc_input* in, const double* thr, double theta_cs,
+                uint8_t* keepC, uint8_t* keepV, uint8_t* keepD, double* S_out) {
+  const int N = in->natom;
+  const double tC = thr[0], tV = thr[1], tD = thr[2], tdC = thr[3], tdV = thr[4];
+  int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+  const int64_t nt = ntot_of(in, ao);
+  double* d = (double*)calloc((size_t)N * N, sizeof(double));
+  double* c = (double*)calloc((size_t)N * N, sizeof(double));
+  double* S = (double*)calloc((size_t)N * N, sizeof(double));
+  uint8_t* have = (uint8_t*)calloc((size_t)N * N, 1);
+  for (int X = 0; X < N; ++X)
+    for (int Y = X; Y < N; ++Y) {
+      double mx = 0, ss = 0;
+      for (int i = 0; i < in->nao[X]; ++i)
+        for (int j = 0; j < in->nao[Y]; ++j) {
+          double v = in->D[(ao[X] + i) * nt + ao[Y] + j];
+          if (fabs(v) > mx) mx = fabs(v);
+          ss += v * v;
+        }
+      int keep = !(tD > 0) || mx > tD;
+      keepD[(int64_t)X * N + Y] = keepD[(int64_t)Y * N + X] = (uint8_t)keep;
+      d[(int64_t)X * N + Y] = d[(int64_t)Y * N + X] = keep ? sqrt(ss) : 0.0;
+    }
+  for (int64_t b = 0; b < in->nC; ++b) {
+    double nr[4];
+    block_norms(in->C_val + in->C_off[b], in->C_dval + 3 * in->C_off[b], c_size(in, b), nr);
+    const int bits = ((!(tC > 0) || nr[0] > tC) ? 1 : 0) | ((!(tdC > 0) || nr[1] > tdC) ? 2 : 0);
+    keepC[b] = (uint8_t)bits;
+    const double a = (bits & 1) ? nr[2] : 0.0, da = (bits & 2) ? nr[3] : 0.0;
+    if (bits) c[(int64_t)in->C_first[b] * N + in->C_second[b]] += (a > da ? a : da);
+  }
+  int* prow = (int*)calloc(N + 1, sizeof(int));
+  for (int A = 0; A < N; ++A)
+    for (int F = 0; F < N; ++F) if (c[(int64_t)A * N + F] != 0) prow[A + 1]++;
+  for (int A = 0; A < N; ++A) prow[A + 1] += prow[A];
+  int* plist = (int*)malloc(sizeof(int) * (prow[N] + 1));
+  for (int A = 0, k = 0; A < N; ++A)
+    for (int F = 0; F < N; ++F) if (c[(int64_t)A * N + F] != 0) plist[k++] = F;
+  int64_t* mir = v_mirrors(in);
+  int rc = 0;
+  for (int64_t b = 0; b < in->nV; ++b) {
+    int64_t m = mir[b];
+    if (m < 0) { rc = -1; keepV[b] = 0; continue; }
+    double n1[4], n2[4];
+    int64_t n = v_size(in, b);
+    block_norms(in->V_val + in->V_off[b], in->V_dval + 3 * in->V_off[b], n, n1);
+    block_norms(in->V_val + in->V_off[m], in->V_dval + 3 * in->V_off[m], n, n2);
+    const int bits = ((!(tV > 0) || fmax(n1[0], n2[0]) > tV) ? 1 : 0) |
+                     ((!(tdV > 0) || fmax(n1[1], n2[1]) > tdV) ? 2 : 0);
+    const double nv = fmax((bits & 1) ? fmax(n1[2], n2[2]) : 0.0, (bits & 2) ? fmax(n1[3], n2[3]) : 0.0);
+    const int A = in->V_first[b], B = in->V_second[b];
+    const int lo = A < B ? A : B, hi = A < B ? B : A;
+    if (!have[(int64_t)lo * N + hi]) {
+      double s = s_pair(N, c, d, prow, plist, lo, hi);
+      S[(int64_t)lo * N + hi] = S[(int64_t)hi * N + lo] = s;
+      have[(int64_t)lo * N + hi] = 1;
+    }
+    int keep = bits;
+    if (keep && theta_cs > 0 && !(nv * S[(int64_t)A * N + B] > theta_cs)) keep = 0;
+    keepV[b] = (uint8_t)keep;
+  }
+  if (S_out) memcpy(S_out, S, sizeof(double) * N * N);
+  free(ao); free(d); free(c); free(S); free(have); free(prow); free(plist); free(mir);
+  return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* D block (X,Y) as a pointer into the dense matrix (row stride nt), or NULL */
 typedef struct { const double* p; int64_t ld; } dblk;
@@ -236,7 +316,7 @@ typedef struct { double* w; } scratch;
 static void quartet(int mA, int mB, int nA, int nF, int nB, int nG,
                     const double* C1, const double* dC1, const double* V, const double* dV,
                     const double* C2, const double* dC2,
-                    dblk DAB, dblk DFG, dblk DAG, dblk DFB, double* ws,
+                    dblk DAB, dblk DFG, dblk DAG, dblk DFB, double* ws, int want,
                     double* E, double g1[3], double gv[3], double g2[3]) {
   /* workspace: What[mB][nA][nF], Wtil[mA][nB][nG], T[nB][nF], U[nG][nF], P[nA][nG], Q[nF][nG] */
   double* What = ws;
@@ -327,14 +407,35 @@ static void quartet(int mA, int mB, int nA, int nF, int nB, int nG,
       const int64_t e = (int64_t)be * k2 + k;
       for (int x = 0; x < 3; ++x) s2[x] += dC2[(int64_t)x * mB * k2 + e] * r;
     }
-  *E -= item;
-  for (int x = 0; x < 3; ++x) { gv[x] -= sv[x]; g1[x] -= s1[x]; g2[x] -= s2[x]; }
+  /* want: bit 0 the item (energy), bit 1 the C1 slot, bit 2 the V slot,
+   * bit 3 the C2 slot */
+  if (want & 1) *E -= item;
+  for (int x = 0; x < 3; ++x) {
+    if (want & 2) g1[x] -= s1[x];
+    if (want & 4) gv[x] -= sv[x];
+    if (want & 8) g2[x] -= s2[x];
+  }
 }
 
 /*
- * Quartet loop over V blocks [v_begin, v_end) in key order; for each, the kept
- * C blocks of A, then the kept C blocks of B (Algorithm 1's loop nest,
- * extended to every term as the text after it describes).
+ * Quartet loop over V blocks [v_begin, v_end) in key order; for each, the
+ * listed C blocks of A, then the listed C blocks of B (Algorithm 1's loop
+ * nest, extended to every term as the text after it describes).
+ *
+ * keepC / keepV are bit masks per block: bit 0 puts the block in the list of
+ * values (C or V), bit 1 in the list of derivatives (dC or dV); keepD 0/1
+ * per atom pair.  Each term of a quartet uses its own lists, as the paper's
+ * per-tensor thresholds do (Table thr_default): the item (energy) needs C1,
+ * V and C2 in the value lists; the C1 slot needs dC1 in the derivative list
+ * and V, C2 in the value lists; likewise the V and C2 slots.
+ *
+ * theta_item > 0: the item-level Cauchy-Schwarz test of Algorithm 1 (Sec.
+ * Sparsity exploitation): a term is skipped when the product of the
+ * Frobenius norms of its three blocks times |D_AB||D_FG| + |D_AG||D_FB|
+ * (Frobenius norms, 0 for a screened D pair) -- a bound on the term --
+ * is at most theta_item.  *skipped (optional) receives the sum of the
+ * bounds of the skipped energy items, so |E - E(theta_item = 0)| is at most
+ * that sum.
  *
  * focus_kind: 0 = all quartets; 1 = only quartets that contain C block
  * focus_idx; 2 = only quartets that contain V block focus_idx.
@@ -342,21 +443,28 @@ static void quartet(int mA, int mB, int nA, int nF, int nB, int nG,
  * nthreads > 1 splits the V blocks over OpenMP threads with private
  * accumulators, summed in thread order afterwards.
  */
-int orc_contract(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV,
-                 const uint8_t* keepD, int64_t v_begin, int64_t v_end, int focus_kind,
-                 int64_t focus_idx, int nthreads, double* E, double* gC, double* gV) {
+static double frob(const double* p, int64_t n) {
+  double s = 0;
+  for (int64_t i = 0; i < n; ++i) s += p[i] * p[i];
+  return sqrt(s);
+}
+
+int orc_contract2(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV,
+                  const uint8_t* keepD, int64_t v_begin, int64_t v_end, int focus_kind,
+                  int64_t focus_idx, int nthreads, double theta_item, double* E, double* gC, double* gV,
+                  double* skipped) {
   const int N = in->natom;
   int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
   const int64_t nt = ntot_of(in, ao);
   /* kept C blocks grouped by first atom, in key order */
   int64_t* crow = (int64_t*)calloc(N + 1, sizeof(int64_t));
   int64_t* clist = (int64_t*)malloc(sizeof(int64_t) * (in->nC + 1));
-  for (int64_t b = 0; b < in->nC; ++b) if (keepC[b]) crow[in->C_first[b] + 1]++;
+  for (int64_t b = 0; b < in->nC; ++b) if (keepC[b] & 3) crow[in->C_first[b] + 1]++;
   for (int i = 0; i < N; ++i) crow[i + 1] += crow[i];
   {
     int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * N);
     for (int i = 0; i < N; ++i) fill[i] = crow[i];
-    for (int64_t b = 0; b < in->nC; ++b) if (keepC[b]) clist[fill[in->C_first[b]]++] = b;
+    for (int64_t b = 0; b < in->nC; ++b) if (keepC[b] & 3) clist[fill[in->C_first[b]]++] = b;
     free(fill);
   }
   int mmax = 0, nmax = 0;
@@ -369,6 +477,35 @@ int orc_contract(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV
   nth = 1;
 #endif
   double* accE = (double*)calloc(nth, sizeof(double));
+  double* accS = (double*)calloc(nth, sizeof(double));
+  /* Frobenius norms for the item-level test: [2] per block (value, derivative), D pairs */
+  double* nC = NULL; double* nV = NULL; double* nD = NULL;
+  if (theta_item > 0) {
+    nC = (double*)malloc(sizeof(double) * 2 * (in->nC + 1));
+    nV = (double*)malloc(sizeof(double) * 2 * (in->nV + 1));
+    nD = (double*)calloc((size_t)N * N, sizeof(double));
+    for (int64_t b = 0; b < in->nC; ++b) {
+      const int64_t n = c_size(in, b);
+      nC[2 * b] = frob(in->C_val + in->C_off[b], n);
+      nC[2 * b + 1] = frob(in->C_dval + 3 * in->C_off[b], 3 * n);
+    }
+    for (int64_t b = 0; b < in->nV; ++b) {
+      const int64_t n = v_size(in, b);
+      nV[2 * b] = frob(in->V_val + in->V_off[b], n);
+      nV[2 * b + 1] = frob(in->V_dval + 3 * in->V_off[b], 3 * n);
+    }
+    for (int X = 0; X < N; ++X)
+      for (int Y = 0; Y < N; ++Y) {
+        if (!keepD[X * N + Y]) continue;
+        double ss = 0;
+        for (int i = 0; i < in->nao[X]; ++i)
+          for (int j = 0; j < in->nao[Y]; ++j) {
+            const double v = in->D[(ao[X] + i) * nt + ao[Y] + j];
+            ss += v * v;
+          }
+        nD[(int64_t)X * N + Y] = sqrt(ss);
+      }
+  }
   double* accC = (double*)calloc((size_t)nth * in->nC * 3, sizeof(double));
   double* accV = (double*)calloc((size_t)nth * in->nV * 3, sizeof(double));
   double** wsv = (double**)malloc(sizeof(double*) * nth);
@@ -382,7 +519,7 @@ int orc_contract(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV
 #ifdef _OPENMP
     t = omp_get_thread_num();
 #endif
-    if (!keepV[v]) continue;
+    if (!(keepV[v] & 3)) continue;
     const int A = in->V_first[v], B = in->V_second[v];
     const int mA = in->nabf[A], mB = in->nabf[B], nA = in->nao[A], nB = in->nao[B];
     const double* V = in->V_val + in->V_off[v];
@@ -399,10 +536,27 @@ int orc_contract(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV
         const int G = in->C_second[c2], nG = in->nao[G];
         dblk DFG = {keepD[F * N + G] ? in->D + ao[F] * nt + ao[G] : NULL, nt};
         dblk DAG = {keepD[A * N + G] ? in->D + ao[A] * nt + ao[G] : NULL, nt};
+        /* the terms this quartet takes: by the lists of its blocks, then by
+         * the item-level bound */
+        const int e1 = keepC[c1] & 1, d1 = keepC[c1] & 2, ev = keepV[v] & 1, dv = keepV[v] & 2;
+        const int e2 = keepC[c2] & 1, d2 = keepC[c2] & 2;
+        int want = (e1 && ev && e2 ? 1 : 0) | (d1 && ev && e2 ? 2 : 0) | (e1 && dv && e2 ? 4 : 0) |
+                   (e1 && ev && d2 ? 8 : 0);
+        if (theta_item > 0 && want) {
+          const double kd = nD[(int64_t)A * N + B] * nD[(int64_t)F * N + G] +
+                            nD[(int64_t)A * N + G] * nD[(int64_t)F * N + B];
+          const double a1 = nC[2 * c1], ad1 = nC[2 * c1 + 1], av = nV[2 * v], adv = nV[2 * v + 1];
+          const double a2 = nC[2 * c2], ad2 = nC[2 * c2 + 1];
+          if ((want & 1) && a1 * av * a2 * kd <= theta_item) { want &= ~1; accS[t] += a1 * av * a2 * kd; }
+          if ((want & 2) && ad1 * av * a2 * kd <= theta_item) want &= ~2;
+          if ((want & 4) && a1 * adv * a2 * kd <= theta_item) want &= ~4;
+          if ((want & 8) && a1 * av * ad2 * kd <= theta_item) want &= ~8;
+        }
+        if (!want) continue;
         quartet(mA, mB, nA, nF, nB, nG,
                 in->C_val + in->C_off[c1], in->C_dval + 3 * in->C_off[c1], V, dV,
                 in->C_val + in->C_off[c2], in->C_dval + 3 * in->C_off[c2],
-                DAB, DFG, DAG, DFB, wsv[t], &accE[t],
+                DAB, DFG, DAG, DFB, wsv[t], want, &accE[t],
                 accC + ((size_t)t * in->nC + c1) * 3, accV + ((size_t)t * in->nV + v) * 3,
                 accC + ((size_t)t * in->nC + c2) * 3);
       }
@@ -410,12 +564,29 @@ int orc_contract(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV
   }
   for (int t = 0; t < nth; ++t) {
     *E += accE[t];
+    if (skipped) *skipped += accS[t];
     for (int64_t i = 0; i < 3 * in->nC; ++i) gC[i] += accC[(size_t)t * in->nC * 3 + i];
     for (int64_t i = 0; i < 3 * in->nV; ++i) gV[i] += accV[(size_t)t * in->nV * 3 + i];
     free(wsv[t]);
   }
-  free(wsv); free(accE); free(accC); free(accV); free(ao); free(crow); free(clist);
+  free(wsv); free(accE); free(accS); free(accC); free(accV); free(ao); free(crow); free(clist);
+  free(nC); free(nV); free(nD);
   return 0;
+}
+
+/* The joint lists of orc_screen (a kept block in both lists), no item test. */
+int orc_contract(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV,
+                 const uint8_t* keepD, int64_t v_begin, int64_t v_end, int focus_kind,
+                 int64_t focus_idx, int nthreads, double* E, double* gC, double* gV) {
+  uint8_t* kc = (uint8_t*)malloc(in->nC + 1);
+  uint8_t* kv = (uint8_t*)malloc(in->nV + 1);
+  for (int64_t b = 0; b < in->nC; ++b) kc[b] = keepC[b] ? 3 : 0;
+  for (int64_t b = 0; b < in->nV; ++b) kv[b] = keepV[b] ? 3 : 0;
+  const int rc = orc_contract2(in, kc, kv, keepD, v_begin, v_end, focus_kind, focus_idx, nthreads, 0.0, E, gC, gV,
+                               NULL);
+  free(kc);
+  free(kv);
+  return rc;
 }
 
 /*
