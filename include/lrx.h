@@ -63,17 +63,30 @@ typedef enum {
                           reductions                                                          */
 } lrx_precision;
 
-/* lrx_options.flags (lrx_evaluate_batch only) */
-#define LRX_BATCH_EAGER 1     /* launch the kernels one by one; no graph is captured                  */
-#define LRX_BATCH_NO_TUNE 2   /* skip the launch-shape autotuner (every group takes the persistent grid) */
+/* lrx_options.flags */
+#define LRX_BATCH_EAGER 1     /* lrx_evaluate_batch: launch the kernels one by one; no graph is captured */
+#define LRX_BATCH_NO_TUNE 2   /* lrx_evaluate_batch: skip the launch-shape autotuner                     */
+#define LRX_SCREEN_PER_TENSOR 4
+/* Step 1 with one threshold per tensor (Sec. Sparsity exploitation, Table
+ * thr_default): theta_tensor = {C, V, D, dC, dV} replaces theta.  A C block
+ * enters the value list (folded into the energy's C) iff max|C| > theta_C and
+ * the derivative list (its gradient is formed) iff max|dC| > theta_dC; V
+ * blocks likewise over the block and its mirror; D pairs iff max|D| >
+ * theta_D.  Every term then uses its own lists: the energy the value lists,
+ * the gradient of a block its derivative and the other blocks' values.  A
+ * threshold <= 0 keeps that whole list.  Step 2 (theta_cs) drops a V block
+ * from both lists, with c(A,F) and nv taken over the kept parts.  Without
+ * the flag, theta keeps a block in both lists when its value or its
+ * derivative passes. */
 
 typedef struct {
   double theta;        /* S1 threshold; <= 0 disables S1                  */
   double theta_cs;     /* S2 threshold; <= 0 disables S2                  */
   int32_t precision;   /* lrx_precision                                    */
   int32_t timing;      /* nonzero: time every stage with HIP events (lrx_evaluate) */
-  int32_t flags;       /* LRX_BATCH_* bits; 0 for the defaults             */
+  int32_t flags;       /* LRX_BATCH_* and LRX_SCREEN_* bits; 0 for the defaults */
   int32_t reserved;    /* set to 0                                         */
+  double theta_tensor[5];  /* with LRX_SCREEN_PER_TENSOR: C, V, D, dC, dV thresholds */
 } lrx_options;
 
 /*
@@ -162,8 +175,10 @@ int lrx_wait(lrx_ctx* ctx, int64_t ticket, double* E, double* F, double* sigma);
  * Screened blocks report 0. */
 int lrx_block_gradients(lrx_ctx* ctx, double* gC, double* gV);
 
-/* Screening decisions of the last evaluation (host buffers, 0/1 per block;
- * keepD [natom][natom]); any pointer may be NULL. */
+/* Screening decisions of the last evaluation (host buffers; keepD
+ * [natom][natom] 0/1); any pointer may be NULL.  keepC / keepV: 0/1 per
+ * block, or with LRX_SCREEN_PER_TENSOR the bits 1 (value list) and 2
+ * (derivative list). */
 int lrx_keep_masks(lrx_ctx* ctx, uint8_t* keepC, uint8_t* keepV, uint8_t* keepD);
 
 #define LRX_MAX_ALPHA_TILES 8

@@ -254,6 +254,7 @@ struct lrx_ctx {
   std::array<float, lrx::kMaxAlphaTiles + 1> group_ms{};
   bool timed = false;
   bool evaluated = false;
+  bool per_tensor = false;   // screening mode of the last evaluation
   // evaluations queued by lrx_submit: results land in their own pinned buffer
   struct Ticket {
     hipEvent_t done = nullptr;
@@ -824,6 +825,14 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
 
 namespace {
 
+// The screening options of a call.
+lrx::Opts make_opts(const lrx_options* o) {
+  lrx::Opts r{o->theta, o->theta_cs, o->precision};
+  r.per_tensor = (o->flags & LRX_SCREEN_PER_TENSOR) != 0;
+  for (int k = 0; k < 5; ++k) r.th[k] = o->theta_tensor[k];
+  return r;
+}
+
 // Checks shared by lrx_evaluate and lrx_evaluate_batch; allocates the FP32
 // buffers of a reduced-precision form on first use.
 void prepare(lrx_ctx* c, const lrx_options* opts) {
@@ -832,6 +841,9 @@ void prepare(lrx_ctx* c, const lrx_options* opts) {
   require(opts->precision == LRX_FP64 || opts->precision == LRX_FP32 || opts->precision == LRX_BF16X3,
           "unknown precision");
   require(std::isfinite(opts->theta) && std::isfinite(opts->theta_cs), "non-finite threshold");
+  if (opts->flags & LRX_SCREEN_PER_TENSOR)
+    for (int k = 0; k < 5; ++k) require(std::isfinite(opts->theta_tensor[k]), "non-finite threshold");
+  c->per_tensor = (opts->flags & LRX_SCREEN_PER_TENSOR) != 0;
   if (opts->precision == LRX_FP64 && !c->have_f64) {
     Dev& d = c->dev;
     d.H = c->dalloc<double>(c->n_h);
@@ -876,6 +888,12 @@ int lrx_keep_masks(lrx_ctx* c, uint8_t* keepC, uint8_t* keepV, uint8_t* keepD) {
     if (keepV && c->nV) HIPCHK(hipMemcpyAsync(keepV, c->dev.keepV, c->nV, hipMemcpyDeviceToHost, c->stream));
     if (keepD) HIPCHK(hipMemcpyAsync(keepD, c->dev.keepD, (size_t)c->N * c->N, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (!c->per_tensor) {   // the joint lists: 0/1 per block
+      if (keepC)
+        for (int64_t b = 0; b < c->nC; ++b) keepC[b] = keepC[b] != 0;
+      if (keepV)
+        for (int64_t b = 0; b < c->nV; ++b) keepV[b] = keepV[b] != 0;
+    }
   });
 }
 
@@ -995,6 +1013,7 @@ struct BatchPlan {
   std::vector<uint64_t> gens;
   int prec = 0, flags = 0;
   double theta = 0, theta_cs = 0;
+  lrx::Opts opts{};
   std::vector<lrx::TripleLaunch> launches;
   std::vector<void*> allocs;
   hipStream_t stream = nullptr;   // the first context's stream
@@ -1017,6 +1036,8 @@ struct BatchPlan {
     if ((int)ctxs.size() != n || prec != o->precision || theta != o->theta || theta_cs != o->theta_cs ||
         flags != o->flags)
       return false;
+    for (int k = 0; k < 5; ++k)
+      if ((flags & LRX_SCREEN_PER_TENSOR) && opts.th[k] != o->theta_tensor[k]) return false;
     for (int i = 0; i < n; ++i)
       if (ctxs[i] != c[i] || gens[i] != c[i]->gen) return false;
     return true;
@@ -1068,7 +1089,7 @@ std::vector<int> group_order(const BatchPlan& P) {
 // Every kernel of one batched evaluation, on stream s (side streams carry the
 // smaller alpha-tile groups and join back before the gradients).
 void run_batch(const BatchPlan& P, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork) {
-  const lrx::Opts o{P.theta, P.theta_cs, P.prec};
+  const lrx::Opts o = P.opts;
   for (lrx_ctx* c : P.ctxs) lrx::launch_screen(c->dev, o, s, nullptr);
   for (lrx_ctx* c : P.ctxs) lrx::launch_hbuild(c->dev, P.prec, s);
   const std::vector<int> order = group_order(P);
@@ -1095,6 +1116,7 @@ std::shared_ptr<BatchPlan> build_plan(lrx_ctx* const* ctxs, int n, const lrx_opt
   P->flags = opts->flags;
   P->theta = opts->theta;
   P->theta_cs = opts->theta_cs;
+  P->opts = make_opts(opts);
   for (int g0 = 0; g0 < n; g0 += lrx::kBatchDevs) {
     lrx::TripleLaunch L{};
     const int ng = std::min(lrx::kBatchDevs, n - g0);
@@ -1239,7 +1261,7 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
     std::shared_ptr<BatchPlan> P = get_plan(one, 1, opts);
     const bool timing = opts->timing != 0;
     if (timing) {
-      const lrx::Opts o{opts->theta, opts->theta_cs, opts->precision};
+      const lrx::Opts o = make_opts(opts);
       hipEvent_t* ev = timing ? c->ev.data() + 1 : nullptr;
       if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
       lrx::launch_screen(c->dev, o, c->stream, ev);
@@ -1362,6 +1384,9 @@ int lrx_evaluate_noalloc(lrx_ctx* c, const lrx_options* opts, double* E, double*
     const int prec = opts->precision;
     require(prec == LRX_FP64 || prec == LRX_FP32 || prec == LRX_BF16X3, "unknown precision");
     require(std::isfinite(opts->theta) && std::isfinite(opts->theta_cs), "non-finite threshold");
+    if (opts->flags & LRX_SCREEN_PER_TENSOR)
+      for (int k = 0; k < 5; ++k) require(std::isfinite(opts->theta_tensor[k]), "non-finite threshold");
+    c->per_tensor = (opts->flags & LRX_SCREEN_PER_TENSOR) != 0;
     require(opts->timing == 0, "lrx_evaluate_noalloc: stage times need lrx_evaluate");
     require(c->scratch != nullptr, "lrx_evaluate_noalloc: no scratch address for this device");
     // the work buffers of this precision, carved from the scratch in 256-byte steps
@@ -1406,7 +1431,7 @@ int lrx_evaluate_noalloc(lrx_ctx* c, const lrx_options* opts, double* E, double*
       std::lock_guard<std::mutex> lk(g_plan_mu);
       for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) tl.mode[mt] = g_tuned[prec][mt] >= 0 ? g_tuned[prec][mt] : 1;
     }
-    const lrx::Opts o{opts->theta, opts->theta_cs, prec};
+    const lrx::Opts o = make_opts(opts);
     lrx::launch_screen(d, o, c->stream, nullptr);
     lrx::launch_contract(d, tl, prec, c->stream, c->side.data(), c->fork.data(), nullptr, nullptr);
     HIPCHK(hipGetLastError());

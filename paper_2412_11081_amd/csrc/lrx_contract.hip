@@ -1161,7 +1161,7 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
 #pragma unroll
     for (int j = 0; j < kZB; ++j) {
       const int64_t b = d.vpBlk[j < nb ? k0 + j : kb0];
-      kp[j] = j < nb && d.keepV[b];
+      kp[j] = j < nb && (d.keepV[b] & 2);   // in the derivative list
       dv[j] = d.Vdval + 3 * d.Voff[b];
     }
     double acc[1 + 3 * kZB];
@@ -1232,7 +1232,7 @@ __global__ void __launch_bounds__(kNT) k_cgrad(Dev d) {
   if (threadIdx.x == 0) d.Ecp[cp] = -s[0];
   for (int k = d.cpB0[cp]; k < d.cpB1[cp]; ++k) {
     const int64_t b = d.cpBlk[k];
-    if (!d.keepC[b]) {
+    if (!(d.keepC[b] & 2)) {   // not in the derivative list
       if (threadIdx.x == 0) d.gC[3 * b] = d.gC[3 * b + 1] = d.gC[3 * b + 2] = 0.0;
       continue;
     }

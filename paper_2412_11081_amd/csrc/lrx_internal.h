@@ -152,10 +152,17 @@ struct Dev {
   int* err;      // validation error code (0 = ok)
 };
 
+// Screening options of one evaluation.  Joint mode (per_tensor == 0): one
+// theta for every tensor, a block kept in both its lists.  Per-tensor mode:
+// th = {C, V, D, dC, dV}; keep masks are bits: 1 = value in the value list
+// (folded into Cf / Vf), 2 = derivative in the derivative list (its
+// gradient is formed); the joint mode stores 3 for a kept block.
 struct Opts {
   double theta;
   double theta_cs;
   int prec;
+  int per_tensor = 0;
+  double th[5] = {0, 0, 0, 0, 0};
 };
 
 // kernels (lrx_screen.hip)

@@ -227,10 +227,14 @@ __global__ void k_screen_c(Dev d, Opts o) {
   for (int k = d.cpB0[cp]; k < d.cpB1[cp]; ++k) {
     const int64_t b = d.cpBlk[k];
     const double* nr = d.nrmC + 4 * b;
-    const bool keep = !(o.theta > 0) || nr[0] > o.theta || nr[1] > o.theta;
-    d.keepC[b] = keep;
-    if (keep) {
-      c += fmax(sqrt(nr[2]), sqrt(nr[3]));
+    int bits;
+    if (o.per_tensor)
+      bits = ((!(o.th[0] > 0) || nr[0] > o.th[0]) ? 1 : 0) | ((!(o.th[3] > 0) || nr[1] > o.th[3]) ? 2 : 0);
+    else
+      bits = (!(o.theta > 0) || nr[0] > o.theta || nr[1] > o.theta) ? 3 : 0;
+    d.keepC[b] = (uint8_t)bits;
+    if (bits) {
+      c += fmax((bits & 1) ? sqrt(nr[2]) : 0.0, (bits & 2) ? sqrt(nr[3]) : 0.0);
       alive = 1;
     }
   }
@@ -243,7 +247,8 @@ __global__ void k_screen_d(Dev d, Opts o) {
   if (t >= (int64_t)d.N * d.N) return;
   const int X = (int)(t / d.N), Y = (int)(t % d.N);
   const int64_t c = X <= Y ? t : (int64_t)Y * d.N + X;
-  const bool keep = !(o.theta > 0) || d.dmax[c] > o.theta;
+  const double tD = o.per_tensor ? o.th[2] : o.theta;
+  const bool keep = !(tD > 0) || d.dmax[c] > tD;
   d.keepD[t] = keep;
   d.dnrm[t] = keep ? sqrt(d.dss[c]) : 0.0;
 }
@@ -286,12 +291,17 @@ __global__ void k_screen_v(Dev d, Opts o) {
     const int64_t m = d.Vmir[b];
     const double* n1 = d.nrmV + 4 * b;
     const double* n2 = d.nrmV + 4 * m;
-    const double mx = fmax(fmax(n1[0], n1[1]), fmax(n2[0], n2[1]));
-    const double nv = fmax(fmax(sqrt(n1[2]), sqrt(n1[3])), fmax(sqrt(n2[2]), sqrt(n2[3])));
-    bool keep = !(o.theta > 0) || mx > o.theta;
-    if (keep && o.theta_cs > 0) keep = nv * S > o.theta_cs;
-    d.keepV[b] = keep;
-    alive |= keep;
+    const double mv = fmax(n1[0], n2[0]), md = fmax(n1[1], n2[1]);
+    int bits;
+    if (o.per_tensor)
+      bits = ((!(o.th[1] > 0) || mv > o.th[1]) ? 1 : 0) | ((!(o.th[4] > 0) || md > o.th[4]) ? 2 : 0);
+    else
+      bits = (!(o.theta > 0) || fmax(mv, md) > o.theta) ? 3 : 0;
+    const double nv = fmax((bits & 1) ? fmax(sqrt(n1[2]), sqrt(n2[2])) : 0.0,
+                           (bits & 2) ? fmax(sqrt(n1[3]), sqrt(n2[3])) : 0.0);
+    if (bits && o.theta_cs > 0 && !(nv * S > o.theta_cs)) bits = 0;
+    d.keepV[b] = (uint8_t)bits;
+    alive |= bits != 0;
   }
   d.aliveV[p] = alive;
 }
@@ -310,7 +320,7 @@ __global__ void __launch_bounds__(kNT) k_fold_c(Dev d, int prec) {
     double s = 0;
     for (int k = k0; k < k1; ++k) {
       const int64_t b = d.cpBlk[k];
-      if (d.keepC[b]) s += d.Cval[d.Coff[b] + e];
+      if (d.keepC[b] & 1) s += d.Cval[d.Coff[b] + e];
     }
     out[e] = s;
     if (out32) out32[e] = (float)s;
@@ -331,7 +341,7 @@ __global__ void __launch_bounds__(kNT) k_fold_v(Dev d, int prec) {
   int ns = 0, k = k0;
   for (; k < k1 && ns < kImg; ++k) {
     const int64_t b = d.vpBlk[k];
-    if (d.keepV[b]) src[ns++] = d.Vval + d.Voff[b];
+    if (d.keepV[b] & 1) src[ns++] = d.Vval + d.Voff[b];
   }
   // e / mBp exactly for e < 2^16 (mA, mBp <= 128): ceil(2^32 / mBp) times e, high word
   const unsigned mdiv = 0xFFFFFFFFu / (unsigned)mBp + 1u;
@@ -345,7 +355,7 @@ __global__ void __launch_bounds__(kNT) k_fold_v(Dev d, int prec) {
         if (j < ns) s += src[j][o];
       for (int kk = k; kk < k1; ++kk) {   // images past the first kImg kept ones
         const int64_t b = d.vpBlk[kk];
-        if (d.keepV[b]) s += d.Vval[d.Voff[b] + o];
+        if (d.keepV[b] & 1) s += d.Vval[d.Voff[b] + o];
       }
     }
     out[e] = s;

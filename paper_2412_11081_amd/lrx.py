@@ -43,7 +43,23 @@ SCRATCH_BYTES = 128 << 20     # LRX_SCRATCH_BYTES of include/lrx.h
 class Options(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("theta_cs", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("theta_tensor", ctypes.c_double * 5)]
+
+
+SCREEN_PER_TENSOR = 4
+
+
+def _options(theta, theta_cs, precision, timing=0, flags=0, thresholds=None):
+    """lrx_options; thresholds = (C, V, D, dC, dV) selects per-tensor screening."""
+    o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), int(bool(timing)), int(flags), 0)
+    if thresholds is not None:
+        t = [float(x) for x in thresholds]
+        assert len(t) == 5
+        o.flags |= SCREEN_PER_TENSOR
+        for k in range(5):
+            o.theta_tensor[k] = t[k]
+    return o
 
 
 class Blocks(ctypes.Structure):
@@ -194,18 +210,19 @@ class Context:
         self._keep = keep
         self.nC, self.nV = int(bc.nblk), int(bv.nblk)
 
-    def evaluate(self, theta=0.0, theta_cs=0.0, precision="fp64", timing=False):
-        o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), int(bool(timing)), 0, 0)
+    def evaluate(self, theta=0.0, theta_cs=0.0, precision="fp64", timing=False, thresholds=None):
+        """lrx_evaluate; thresholds = (C, V, D, dC, dV) for per-tensor screening."""
+        o = _options(theta, theta_cs, precision, timing, thresholds=thresholds)
         E = ctypes.c_double()
         F = np.zeros((self.natom, 3))
         S = np.zeros((3, 3))
         self._check(self.lib.lrx_evaluate(self.h, ctypes.byref(o), ctypes.byref(E), _ptr(F, _f64p), _ptr(S, _f64p)))
         return E.value, F, S
 
-    def evaluate_noalloc(self, theta=0.0, theta_cs=0.0, precision="fp64"):
+    def evaluate_noalloc(self, theta=0.0, theta_cs=0.0, precision="fp64", thresholds=None):
         """lrx_evaluate_noalloc: the evaluation with the library's fixed device
         scratch for its work buffers (no device allocation)."""
-        o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), 0, 0, 0)
+        o = _options(theta, theta_cs, precision, thresholds=thresholds)
         E = ctypes.c_double()
         F = np.zeros((self.natom, 3))
         S = np.zeros((3, 3))
@@ -213,9 +230,9 @@ class Context:
                                                   _ptr(S, _f64p)))
         return E.value, F, S
 
-    def submit(self, theta=0.0, theta_cs=0.0, precision="fp64"):
+    def submit(self, theta=0.0, theta_cs=0.0, precision="fp64", thresholds=None):
         """lrx_submit: queue an evaluation on the context's stream; returns its ticket."""
-        o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), 0, 0, 0)
+        o = _options(theta, theta_cs, precision, thresholds=thresholds)
         t = ctypes.c_int64()
         self._check(self.lib.lrx_submit(self.h, ctypes.byref(o), ctypes.byref(t)))
         return t.value
@@ -280,7 +297,7 @@ def context_for(structure, mats, device: int = 0, stream=None) -> Context:
     return ctx
 
 
-def evaluate_batch(contexts, theta=0.0, theta_cs=0.0, precision="fp64", eager=False, tune=True):
+def evaluate_batch(contexts, theta=0.0, theta_cs=0.0, precision="fp64", eager=False, tune=True, thresholds=None):
     """lrx_evaluate_batch over ``contexts`` (distinct, one device): returns
     lists of E, F [natom][3] and sigma [3][3], one entry per context."""
     if not contexts:
@@ -289,7 +306,7 @@ def evaluate_batch(contexts, theta=0.0, theta_cs=0.0, precision="fp64", eager=Fa
     n = len(contexts)
     handles = (ctypes.c_void_p * n)(*[c.h.value for c in contexts])
     flags = (BATCH_EAGER if eager else 0) | (0 if tune else BATCH_NO_TUNE)
-    o = Options(float(theta), float(theta_cs), PRECISIONS.get(precision, precision), 0, flags, 0)
+    o = _options(theta, theta_cs, precision, flags=flags, thresholds=thresholds)
     E = np.zeros(n)
     nat = [c.natom for c in contexts]
     F = np.zeros((sum(nat), 3))

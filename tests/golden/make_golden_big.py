@@ -15,6 +15,10 @@ Cases (the thresholds are the workloads' own unless stated):
                  exploitation, the Cauchy-Schwarz bound)
   abx3_320       320-atom ABX3 cell, theta 1e-4, theta_cs 1e-7
   abx3_1080      1080-atom strained, substituted ABX3 cell, theta 1e-5, theta_cs 1e-8
+  diamond64_pt   the 64-atom cell with one threshold per tensor (Table
+                 thr_default's five lists): C 1e-4, V 1e-2, D 1e-3, dC 1e-4,
+                 dV 1e-3, theta_cs 1e-7; the keep masks are then bit masks
+                 (1 value list, 2 derivative list)
 
 Usage: python tests/golden/make_golden_big.py [case ...]   (default: all)
 Threads: THREADS (default: all host cores).  The oracle parallelises over V
@@ -39,7 +43,10 @@ CASES = {
     "diamond64_s2": (2, 0.3),
     "abx3_320": (3, None),
     "abx3_1080": (4, None),
+    "diamond64_pt": (2, None),
 }
+# per-tensor thresholds (C, V, D, dC, dV) of the cases that use them
+PER_TENSOR = {"diamond64_pt": (1e-4, 1e-2, 1e-3, 1e-4, 1e-3)}
 
 
 def path_of(case):
@@ -70,9 +77,15 @@ def make(case, threads):
     mats = st.materialize("cpu")
     pr = oracle.Problem.from_structure(st, mats)
     t0 = time.time()
-    keep = pr.screen(st.theta, st.theta_cs)
-    s1 = pr.screen(st.theta, 0.0)
-    E, gC, gV = pr.contract(keep, nthreads=threads)
+    thr = PER_TENSOR.get(case)
+    if thr is None:
+        keep = pr.screen(st.theta, st.theta_cs)
+        s1 = pr.screen(st.theta, 0.0)
+        E, gC, gV = pr.contract(keep, nthreads=threads)
+    else:
+        keep = pr.screen5(thr, st.theta_cs)
+        s1 = pr.screen5(thr, 0.0)
+        E, gC, gV = pr.contract(keep, nthreads=threads, bits=True)
     F, sig = pr.forces_stress(gC, gV)
     dt = time.time() - t0
     np.savez_compressed(
@@ -80,14 +93,15 @@ def make(case, threads):
         case=case, workload=k, seed=st.seed, theta=st.theta, theta_cs=st.theta_cs,
         natom=st.natom, nC=pr.nC, nV=pr.nV,
         E=E, F=F, sigma=sig, gC=gC, gV=gV,
-        keepC=np.packbits(keep[0]), keepV=np.packbits(keep[1]), keepD=np.packbits(keep[2]),
-        kept_v_step1=int(s1[1].sum()),
+        keepC=keep[0] if thr else np.packbits(keep[0]), keepV=keep[1] if thr else np.packbits(keep[1]),
+        keepD=np.packbits(keep[2]), kept_v_step1=int((s1[1] != 0).sum()),
+        thresholds=np.array(thr if thr else [st.theta] * 5),
         fingerprint=fingerprint(mats),
         oracle_seconds=dt, oracle_threads=threads,
         written_by="tests/golden/make_golden_big.py (CPU oracle only)",
     )
-    print(f"{case}: E = {E:.15e}, kept C {int(keep[0].sum())}/{pr.nC}, kept V {int(keep[1].sum())}/{pr.nV} "
-          f"(step 1 alone {int(s1[1].sum())}), max|F| {np.abs(F).max():.3e}, oracle {dt:.1f} s on {threads} threads",
+    print(f"{case}: E = {E:.15e}, kept C {int((keep[0] != 0).sum())}/{pr.nC}, kept V {int((keep[1] != 0).sum())}/{pr.nV} "
+          f"(step 1 alone {int((s1[1] != 0).sum())}), max|F| {np.abs(F).max():.3e}, oracle {dt:.1f} s on {threads} threads",
           flush=True)
 
 
@@ -95,8 +109,9 @@ def load(case):
     """The stored result as a dict, masks unpacked to uint8 arrays."""
     z = np.load(path_of(case), allow_pickle=False)
     r = {k: z[k] for k in z.files}
-    r["keepC"] = np.unpackbits(r["keepC"])[: int(r["nC"])]
-    r["keepV"] = np.unpackbits(r["keepV"])[: int(r["nV"])]
+    if str(r["case"]) not in PER_TENSOR:   # bit masks are stored as they are
+        r["keepC"] = np.unpackbits(r["keepC"])[: int(r["nC"])]
+        r["keepV"] = np.unpackbits(r["keepV"])[: int(r["nV"])]
     n = int(r["natom"])
     r["keepD"] = np.unpackbits(r["keepD"])[: n * n]
     r["E"] = float(r["E"])
