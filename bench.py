@@ -206,6 +206,86 @@ def serving_benchmark(n, precision="bf16x3", budget_gib=160, max_batch=8, worker
             "max_bytes_held_gib": burst["max_bytes_held"] / 2**30}
 
 
+# Table thr_default: the largest per-tensor thresholds (C, V, D, dC, dV) the
+# paper accepts at a force tolerance of 1e-3 eV/Angstrom, and its theta_cs
+TABLE_THR_DEFAULT = (1e-4, 1e0, 1e-3, 1e-4, 1e-1)
+PAPER_THETA_CS = 1e-7
+HA_BOHR_TO_EV_ANG = 27.211386245988 / 0.529177210903
+
+
+def theta_sweep(workload, steps=3):
+    """Screening error against time on one workload, the analogue of Figs.
+    thr_tensor and thr_cs (Sec. Sparsity exploitation and the screening
+    tests of the results section): every row is one screening setting,
+    evaluated in FP64 on the graph path; errors are taken against the
+    unscreened evaluation of the same inputs.
+
+    Rows: (1) each tensor's own threshold swept with the other four at zero,
+    (2) Table thr_default's five thresholds together, (3) theta_cs swept with
+    no tensor screening and on top of Table thr_default, (4) the single
+    threshold of the workloads (one theta for all five tensors, theta_cs =
+    1e-3 theta).  Prints a markdown report."""
+    import numpy as np
+    import torch
+
+    from paper_2412_11081_amd import lrx, synth
+
+    st = synth.workload(workload).build()
+    mats = st.materialize("cuda")
+    ctx = lrx.context_for(st, mats)
+
+    def run(theta, theta_cs, thr=None):
+        for _ in range(2):         # plan built, then captured
+            ctx.evaluate(theta, theta_cs, thresholds=thr)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            E, F, S = ctx.evaluate(theta, theta_cs, thresholds=thr)
+            ts.append(time.perf_counter() - t0)
+        kC, kV, kD = ctx.keep_masks()
+        return dict(E=E, F=np.asarray(F), S=np.asarray(S), ms=1e3 * float(np.median(ts)),
+                    kC=int((kC != 0).sum()), kV=int((kV != 0).sum()), kD=int(kD.sum()))
+
+    ref = run(0.0, 0.0)
+    fmax = float(np.abs(ref["F"]).max())
+    rows = []
+
+    def row(group, label, theta, theta_cs, thr=None):
+        r = run(theta, theta_cs, thr)
+        dF = float(np.abs(r["F"] - ref["F"]).max())
+        rows.append((group, label, r["ms"], r["ms"] / ref["ms"], abs(r["E"] - ref["E"]) / st.natom, dF,
+                     dF * HA_BOHR_TO_EV_ANG, float(np.abs(r["S"] - ref["S"]).max()), r["kC"], r["kV"], r["kD"]))
+        print(f"# sweep {group} {label}: {r['ms']:.1f} ms, max|dF| {dF:.2e} Ha/Bohr", file=sys.stderr, flush=True)
+
+    names = ("C", "V", "D", "dC", "dV")
+    for i, nm in enumerate(names):
+        for t in (1e-7, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1, 1e0):
+            thr = [0.0] * 5
+            thr[i] = t
+            row(f"{nm} alone", f"{t:.0e}", 0.0, 0.0, thr)
+    row("Table thr_default", "theta_cs 0", 0.0, 0.0, TABLE_THR_DEFAULT)
+    for tcs in (1e-10, 1e-9, 1e-8, 1e-7, 1e-6, 1e-5, 1e-4, 1e-3):
+        row("theta_cs alone", f"{tcs:.0e}", 0.0, tcs, (0.0,) * 5)
+    for tcs in (1e-10, 1e-9, 1e-8, 1e-7, 1e-6, 1e-5, 1e-4, 1e-3):
+        row("theta_cs + thr_default", f"{tcs:.0e}", 0.0, tcs, TABLE_THR_DEFAULT)
+    for th in (1e-8, 1e-7, 1e-6, 1e-5, 1e-4, 1e-3):
+        row("single theta", f"{th:.0e} (cs {1e-3 * th:.0e})", th, 1e-3 * th)
+    ctx.close()
+    print(f"# Screening sweep: {WORKLOADS[workload]}")
+    print()
+    print(f"Unscreened FP64 evaluation: {ref['ms']:.2f} ms, kept C {ref['kC']}, V {ref['kV']}, D {ref['kD']}; "
+          f"max|F| {fmax:.3e} Ha/Bohr, E {ref['E']:.10e} Ha.  Times: median of {steps} graph-replayed "
+          f"evaluations (host wall clock, results on the host).  Errors against the unscreened result.")
+    print()
+    print("| group | threshold | ms | rel. time | abs dE/atom (Ha) | max abs dF (Ha/Bohr) | (eV/A) "
+          "| max abs dsigma (Ha/Bohr^3) | C kept | V kept | D kept |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    for g, lab, ms, rel, de, df, dfe, ds, kc, kv, kd in rows:
+        print(f"| {g} | {lab} | {ms:.2f} | {100 * rel:.1f}% | {de:.2e} | {df:.2e} | {dfe:.2e} | {ds:.2e} "
+              f"| {kc} | {kv} | {kd} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +300,8 @@ def main():
                     help="also run the serving stream with this many requests (p50/p99 latency)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scale for HBM byte counters)")
+    ap.add_argument("--theta-sweep", action="store_true",
+                    help="only run the screening sweep (error against time) on --workload; prints markdown")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
@@ -240,6 +322,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": 8 * n, "copy_calibration_bytes_written": 8 * n,
                           "copies": 3}))
+        return
+    if args.theta_sweep:
+        theta_sweep(args.workload)
         return
     t0 = time.time()
     st = synth.workload(args.workload).build()

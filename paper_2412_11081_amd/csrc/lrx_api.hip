@@ -755,6 +755,7 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
     d.unitV0 = c->upload(c->unitV0); d.unitV1 = c->upload(c->unitV1); d.unitS = c->upload(c->unitS);
     d.unitYonly = c->upload(c->unitYonly);
+    d.unitRole = c->dalloc<uint8_t>((int64_t)c->unitYonly.size());
     d.nsplit = c->upload(c->nsplit);
     d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);
     d.triHF = c->upload(triHF); d.triHA = c->upload(triHA);
@@ -782,16 +783,15 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     d.gC = c->dalloc<double>(3 * c->nC);
     d.gV = c->dalloc<double>(3 * c->nV);
     d.Ep = c->dalloc<double>(nVp);
-    d.Ecp = c->dalloc<double>(nCp);
     d.atCfRow = c->upload(atCfRow); d.atCf = c->upload(atCf);
     d.atCsRow = c->upload(atCsRow); d.atCs = c->upload(atCs);
     d.atVfRow = c->upload(atVfRow); d.atVf = c->upload(atVf);
     d.atVsRow = c->upload(atVsRow); d.atVs = c->upload(atVs);
-    d.out = c->dalloc<double>(1 + 3 * N + 9 + 1);
+    d.out = c->dalloc<double>(1 + 3 * N + 9);
     d.err = c->dalloc<int>(1);
     g_pinned.put(c->h_out, c->h_out_bytes);
     c->h_out = nullptr;
-    c->h_out_bytes = sizeof(double) * (1 + 3 * N + 9 + 1);
+    c->h_out_bytes = sizeof(double) * (1 + 3 * N + 9);
     c->h_out = (double*)g_pinned.get(c->h_out_bytes);
 
     // ---- value validation on the device ------------------------------------
@@ -938,19 +938,21 @@ int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
       if (kV[b]) { s->kept_v_blocks++; fl += 8 * sz; }
     }
     by += (double)c->ao[c->N] * c->ao[c->N] * 8;
-    for (int i = 0; i < d.nCp; ++i) s->alive_c_pairs += aC[i];
-    for (int i = 0; i < d.nVp; ++i) s->alive_v_pairs += aV[i];
+    for (int i = 0; i < d.nCp; ++i) s->alive_c_pairs += aC[i] != 0;
+    for (int i = 0; i < d.nVp; ++i) s->alive_v_pairs += aV[i] != 0;
     const Pairs& cp = c->cp;
     const Pairs& vp = c->vp;
     for (int i = 0; i < d.nCp; ++i) {
       if (!aC[i]) continue;
       const int A = cp.pA[i], Fa = cp.pB[i];
       for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
-        if (!aV[p]) continue;
         const int B = vp.pB[p];
+        if (!lrx::triple_live(aC[i], aV[p], B < A)) continue;
         s->alive_triples++;
-        // Y and (for B >= A; the other half is its transpose) Z, and the X-build
-        const double t = (B >= A ? 4.0 : 2.0) * nb[A] * nb[B] * na[A] * na[Fa] + 4.0 * nb[B] * na[A] * na[B] * na[Fa];
+        // Y and (when this unit forms it: B >= A and Cf(A,F) live; the other
+        // half is the transpose) Z, and the X-build
+        const double zy = lrx::unit_y_only(aC[i], B < A) ? 2.0 : 4.0;
+        const double t = zy * nb[A] * nb[B] * na[A] * na[Fa] + 4.0 * nb[B] * na[A] * na[B] * na[Fa];
         ft += t;
         s->flop_triple_group[(nb[A] + 15) / 16] += t;
       }
@@ -961,7 +963,7 @@ int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
       const int B = c->slotB[sl], X = c->slotX[sl];
       double depth = 0;
       for (int i = cp.row[B]; i < cp.row[B + 1]; ++i)
-        if (aC[i]) depth += na[cp.pB[i]];
+        if (aC[i] & 1) depth += na[cp.pB[i]];
       fl += 2.0 * nb[B] * na[B] * na[X] * depth;
     }
     s->flop_triple = ft;
@@ -1274,7 +1276,7 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
     }
     HIPCHK(hipGetLastError());
     const int N = c->N;
-    HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * N + 9), hipMemcpyDeviceToHost,
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (timing) {
@@ -1304,7 +1306,7 @@ int lrx_submit(lrx_ctx* c, const lrx_options* opts, int64_t* ticket) {
     HIPCHK(hipGetLastError());
     lrx_ctx::Ticket t;
     t.N = c->N;
-    t.bytes = sizeof(double) * (1 + 3 * c->N + 9 + 1);
+    t.bytes = sizeof(double) * (1 + 3 * c->N + 9);
     HIPCHK(hipEventCreateWithFlags(&t.done, hipEventDisableTiming));
     try {
       t.h = (double*)g_pinned.get(t.bytes);
@@ -1360,7 +1362,7 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
     HIPCHK(hipGetLastError());
     for (int i = 0; i < n; ++i) {
       lrx_ctx* c = ctxs[i];
-      HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * c->N + 9 + 1), hipMemcpyDeviceToHost,
+      HIPCHK(hipMemcpyAsync(c->h_out, c->dev.out, sizeof(double) * (1 + 3 * c->N + 9), hipMemcpyDeviceToHost,
                             s));
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -1436,7 +1438,7 @@ int lrx_evaluate_noalloc(lrx_ctx* c, const lrx_options* opts, double* E, double*
     lrx::launch_contract(d, tl, prec, c->stream, c->side.data(), c->fork.data(), nullptr, nullptr);
     HIPCHK(hipGetLastError());
     const int N = c->N;
-    HIPCHK(hipMemcpyAsync(c->h_out, d.out, sizeof(double) * (1 + 3 * N + 9 + 1), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_out, d.out, sizeof(double) * (1 + 3 * N + 9), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->timed = false;
     c->evaluated = true;

@@ -370,9 +370,13 @@ struct Chunk {
   int p, B, mB, nB, b0;   // p < 0: no chunk
 };
 
+// VMASK: the liveness bits of a V pair that give the unit work (3 when it
+// forms Z, which is read for any live pair; 1 when it forms Y alone, which
+// only V pairs with Vf != 0 change)
+template <int VMASK>
 __device__ inline Chunk chunk_at(const Dev& d, const UnitGeo& U, int p, int b0) {
   Chunk c;
-  for (; p < U.ve && !ldu(d.aliveV, p); ++p) {
+  for (; p < U.ve && !(ldu(d.aliveV, p) & VMASK); ++p) {
   }
   c.p = p < U.ve ? p : -1;
   c.b0 = b0;
@@ -385,6 +389,7 @@ __device__ inline Chunk chunk_at(const Dev& d, const UnitGeo& U, int p, int b0) 
   }
   return c;
 }
+template <int VMASK>
 __device__ inline Chunk chunk_next(const Dev& d, const UnitGeo& U, const Chunk& c) {
   if (c.p < 0) return c;
   if (c.b0 + 16 < c.mB) {
@@ -392,7 +397,7 @@ __device__ inline Chunk chunk_next(const Dev& d, const UnitGeo& U, const Chunk& 
     n.b0 += 16;
     return n;
   }
-  return chunk_at(d, U, c.p + 1, 0);
+  return chunk_at<VMASK>(d, U, c.p + 1, 0);
 }
 __device__ inline int64_t chunk_tri(const Dev& d, const UnitGeo& U, const Chunk& c) {
   return ldu(d.tBase, U.A) + (int64_t)U.fpos * U.nVpA + (c.p - U.vp0);
@@ -783,7 +788,8 @@ __device__ __forceinline__ void triple_role(const Dev& d, const UnitGeo& U, type
   const int nYJ = min(JW, (U.NTc - ww + NYW - 1) / NYW);
 
   // prologue: stage the first chunk
-  Chunk ch = chunk_at(d, U, U.vb, 0);
+  constexpr int VMASK = ROLE == kRoleY8 ? 1 : 3;
+  Chunk ch = chunk_at<VMASK>(d, U, U.vb, 0);
   StageGeo sg = stage_geo<T>(U, ch.nB);
   if (ch.p >= 0) {
     Stager<T> st;
@@ -793,7 +799,7 @@ __device__ __forceinline__ void triple_role(const Dev& d, const UnitGeo& U, type
   __builtin_amdgcn_s_waitcnt(0);
   lds_sync();
   while (ch.p >= 0) {
-    const Chunk nx = chunk_next(d, U, ch);
+    const Chunk nx = chunk_next<VMASK>(d, U, ch);
     const int64_t tri = chunk_tri(d, U, ch);
     // V fragments of this chunk (Y waves), read before the stage is reused
     T avn[(ZROLE || B3) ? 1 : 4][(ZROLE || B3) ? 1 : MT];
@@ -1050,7 +1056,13 @@ __device__ __forceinline__ void triple_unit(const Dev& d, int u, typename Triple
   // the stage starts zeroed: padding rows the X-build reads past nB are finite
   for (int e = tid; e < Cfg::kStage; e += kTNT) S[e] = T(0);
   __syncthreads();
-  if (ldu(d.unitYonly, u))
+  // Y alone when Z is not formed here (partners B < A) or Cf(A,F) folds to
+  // zero; then nothing when Y(A,F) is not read, else only V pairs with
+  // Vf != 0 (the role is read here, not before the geometry: that placement
+  // keeps the persistent FP64 kernels free of register spills)
+  const int role = ldu(d.unitRole, u);
+  if (role == 0) return;
+  if (role == 2)
     triple_role<MT, P, kRoleY8>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
   else if (w < 4)
     triple_role<MT, P, kRoleZ>(d, U, X, Zred, S, Buf<T>::D(d), Buf<T>::Vf(d), Buf<T>::H(d), w, lane, q, g);
@@ -1136,7 +1148,7 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
     const int vp0 = d.vpRow[A], nVpA = d.vpRow[A + 1] - vp0, bpos = p - vp0;
     const int c0 = d.cpRow[A], ncp = d.cpRow[A + 1] - c0;
     for (int i = threadIdx.x; i < ncp && i < kZMax; i += kNT) {
-      zk[i] = d.aliveC[c0 + i] ? d.nkc[c0 + i] : 0;
+      zk[i] = (d.aliveC[c0 + i] & 1) ? d.nkc[c0 + i] : 0;   // Cf(A,F) = 0 adds nothing
       zb[i] = d.zOff[d.tBase[A] + (int64_t)i * nVpA + bpos];
     }
     __syncthreads();
@@ -1203,7 +1215,7 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
 }
 
 // ---------------------------------------------------------------------------
-// C-block gradients: g_c = -2 <dC_c, Y(A,F)> (FP64); E from the Y side.
+// C-block gradients: g_c = -2 <dC_c, Y(A,F)> (FP64).
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(kNT) k_cgrad(Dev d) {
@@ -1216,20 +1228,10 @@ __global__ void __launch_bounds__(kNT) k_cgrad(Dev d) {
       const int64_t b = d.cpBlk[k];
       d.gC[3 * b] = d.gC[3 * b + 1] = d.gC[3 * b + 2] = 0.0;
     }
-    if (threadIdx.x == 0) d.Ecp[cp] = 0.0;
     return;
   }
   const T* Y = Buf<T>::Y(d) + d.yOff[cp];
   const int ns = d.nsplit[cp];
-  const double* cf = d.Cf + d.cfOff[cp];
-  double s[4] = {0, 0, 0, 0};
-  for (int e = threadIdx.x; e < n; e += kNT) {
-    double y = 0;
-    for (int k = 0; k < ns; ++k) y += (double)Y[(int64_t)k * n + e];
-    s[0] += cf[e] * y;
-  }
-  block_sum_n<1>(s, sh);
-  if (threadIdx.x == 0) d.Ecp[cp] = -s[0];
   for (int k = d.cpB0[cp]; k < d.cpB1[cp]; ++k) {
     const int64_t b = d.cpBlk[k];
     if (!(d.keepC[b] & 2)) {   // not in the derivative list
@@ -1272,10 +1274,9 @@ __global__ void k_forces(Dev d) {
 // Energy and virial: one workgroup, fixed-order reductions.
 constexpr int kFinalNT = 1024;
 __global__ void __launch_bounds__(kFinalNT) k_final(Dev d) {
-  __shared__ double sh[(kFinalNT / 64) * 11];
-  double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // E, W[9], E from the Y side
+  __shared__ double sh[(kFinalNT / 64) * 10];
+  double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // E, W[9]
   for (int p = threadIdx.x; p < d.nVp; p += kFinalNT) v[0] += d.Ep[p];
-  for (int c = threadIdx.x; c < d.nCp; c += kFinalNT) v[10] += d.Ecp[c];
   for (int pass = 0; pass < 2; ++pass) {
     const int64_t nb = pass ? d.nV : d.nC;
     const int* fi = pass ? d.Vfirst : d.Cfirst;
@@ -1291,11 +1292,10 @@ __global__ void __launch_bounds__(kFinalNT) k_final(Dev d) {
         for (int y = 0; y < 3; ++y) v[1 + 3 * x + y] += gr[3 * b + x] * r[y];
     }
   }
-  block_sum_n<11>(v, sh);
+  block_sum_n<10>(v, sh);
   if (threadIdx.x == 0) {
     d.out[0] = v[0];
     for (int i = 0; i < 9; ++i) d.out[1 + 3 * d.N + i] = -v[1 + i] / d.omega;
-    d.out[1 + 3 * d.N + 9] = v[10];
   }
 }
 

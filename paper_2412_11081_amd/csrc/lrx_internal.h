@@ -121,6 +121,7 @@ struct Dev {
   const int* unitCp; const int* unitK0; const int* unitK1; const int* unitKc;
   const int* unitV0; const int* unitV1; const int* unitS;   // V-pair range and split index of a unit
   const uint8_t* unitYonly; // 1: every V partner B of the unit has B < A (only Y is formed)
+  uint8_t* unitRole;        // per evaluation: 0 no work, 1 Z and Y, 2 Y alone (unit_y_only)
   const int* nsplit;       // [nCp] number of V-pair ranges (Y partials) of a C pair
   const int* unitOrder;    // units grouped by the alpha-tile count of their atom A
   int mtStart[kMaxAlphaTiles + 2];
@@ -143,12 +144,11 @@ struct Dev {
   double* gC;    // [nC][3]
   double* gV;    // [nV][3]
   double* Ep;    // [nVp]
-  double* Ecp;   // [nCp]
   const int* atCfRow; const int64_t* atCf;   // C blocks by first atom
   const int* atCsRow; const int64_t* atCs;   // ... by second atom
   const int* atVfRow; const int64_t* atVf;
   const int* atVsRow; const int64_t* atVs;
-  double* out;   // [1 + 3N + 9 + 1]: E, F, sigma, E from the Y side
+  double* out;   // [1 + 3N + 9]: E, F, sigma
   int* err;      // validation error code (0 = ok)
 };
 
@@ -164,6 +164,21 @@ struct Opts {
   int per_tensor = 0;
   double th[5] = {0, 0, 0, 0, 0};
 };
+
+// Work of the triple (A,F,B) given the liveness bits of C pair (A,F) and V
+// pair (A,B) (bit 1: a block in the value list, bit 2: one in the
+// derivative list; the joint screening sets both).  Z(A,B) takes
+// Cf(A,F) X^{AFB} and is formed for B >= A (the rest is its transpose); it
+// is read when (A,B) is live at all.  Y(A,F) takes Vf(A,B) X^{AFB} and is
+// read only when (A,F) has a block in the derivative list.  A unit whose C
+// pair has no value-list block, or whose partners all have B < A, forms Y
+// alone (y_only) and then only over V pairs with a value-list block.
+__host__ __device__ inline bool unit_y_only(int aliveC, bool b_below_a) { return b_below_a || !(aliveC & 1); }
+__host__ __device__ inline bool triple_live(int aliveC, int aliveV, bool b_below_a) {
+  if (!aliveC || !aliveV) return false;
+  if (unit_y_only(aliveC, b_below_a)) return (aliveC & 2) && (aliveV & 1);
+  return true;
+}
 
 // kernels (lrx_screen.hip)
 void launch_validate(const Dev& d, hipStream_t s);

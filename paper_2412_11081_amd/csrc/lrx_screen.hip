@@ -233,13 +233,11 @@ __global__ void k_screen_c(Dev d, Opts o) {
     else
       bits = (!(o.theta > 0) || nr[0] > o.theta || nr[1] > o.theta) ? 3 : 0;
     d.keepC[b] = (uint8_t)bits;
-    if (bits) {
-      c += fmax((bits & 1) ? sqrt(nr[2]) : 0.0, (bits & 2) ? sqrt(nr[3]) : 0.0);
-      alive = 1;
-    }
+    if (bits) c += fmax((bits & 1) ? sqrt(nr[2]) : 0.0, (bits & 2) ? sqrt(nr[3]) : 0.0);
+    alive |= (uint8_t)bits;
   }
   d.cval[cp] = c;
-  d.aliveC[cp] = alive;
+  d.aliveC[cp] = alive;   // bit 1: Cf(A,F) != 0 may hold; bit 2: Y(A,F) is read
 }
 
 __global__ void k_screen_d(Dev d, Opts o) {
@@ -301,9 +299,9 @@ __global__ void k_screen_v(Dev d, Opts o) {
                            (bits & 2) ? fmax(sqrt(n1[3]), sqrt(n2[3])) : 0.0);
     if (bits && o.theta_cs > 0 && !(nv * S > o.theta_cs)) bits = 0;
     d.keepV[b] = (uint8_t)bits;
-    alive |= bits != 0;
+    alive |= (uint8_t)bits;
   }
-  d.aliveV[p] = alive;
+  d.aliveV[p] = alive;    // bit 1: Vf(A,B) != 0 may hold; bit 2: some dV is kept
 }
 
 // ---------------------------------------------------------------------------
@@ -377,18 +375,31 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n) {
 
 __global__ void k_mark(Dev d) {
   const int cp = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cp >= d.nCp || !d.aliveC[cp]) return;
+  if (cp >= d.nCp) return;
+  const int ac = d.aliveC[cp];
+  if (!ac) return;
   const int A = d.cpA[cp], F = d.cpF[cp];
   for (int p = d.vpRow[A]; p < d.vpRow[A + 1]; ++p) {
-    if (!d.aliveV[p]) continue;
     const int B = d.vpB[p];
+    if (!triple_live(ac, d.aliveV[p], B < A)) continue;
     d.need[d.hSlotMap[(int64_t)B * d.N + F]] = 1;
     d.need[d.hSlotMap[(int64_t)B * d.N + A]] = 1;
   }
 }
 
+// What each triple-product unit forms in this evaluation (triple_live):
+// 0 nothing, 1 Z and Y, 2 Y alone.
+__global__ void k_unit_role(Dev d) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= d.nUnit) return;
+  const int ac = d.aliveC[d.unitCp[u]];
+  const bool yonly = unit_y_only(ac, d.unitYonly[u] != 0);
+  d.unitRole[u] = (!ac || (yonly && !(ac & 2))) ? 0 : (yonly ? 2 : 1);
+}
+
 // Compaction of the H-build tables of atom B (one workgroup per atom):
-// depth entries of live C pairs (B,G), in table order, padded with entries
+// depth entries of C pairs (B,G) with a block in the value list (the others
+// fold to Cf(B,G) = 0), in table order, padded with entries
 // of no atom to a multiple of 4 (at least 4, so a slot whose C pairs are all
 // screened is still written, as zeros); columns of the needed slots (B,X),
 // in table order.  Ordered prefix sums over the ballots of each 64-lane
@@ -418,7 +429,7 @@ __global__ void __launch_bounds__(kNT) k_hcompact(Dev d) {
     for (int k0 = 0; k0 < hn; k0 += kNT) {
       const int k = k0 + threadIdx.x;
       const int t = k < hn ? d.hdCp[h0 + k] : -1;
-      const bool live = t >= 0 && d.aliveC[t >> 6];
+      const bool live = t >= 0 && (d.aliveC[t >> 6] & 1);   // Cf(B,G) in the value list
       int tot;
       const int pos = h0 + n + block_exclusive_scan(live, sh, &tot);
       if (live) {
@@ -480,6 +491,7 @@ void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev) {
   hipLaunchKernelGGL(k_fill_u8, dim3(cdiv(d.nSlot, kNT)), dim3(kNT), 0, s, d.need,
                      (int64_t)d.nSlot);
   hipLaunchKernelGGL(k_mark, dim3(cdiv(d.nCp, kNT)), dim3(kNT), 0, s, d);
+  hipLaunchKernelGGL(k_unit_role, dim3(cdiv(d.nUnit, kNT)), dim3(kNT), 0, s, d);
   hipLaunchKernelGGL(k_hcompact, dim3((unsigned)d.N), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[3], s);
 }
