@@ -63,6 +63,8 @@ def _load():
         lib.orc_contract2.restype = ctypes.c_int
         lib.orc_screen5.argtypes = [ctypes.POINTER(OrcInput), _f64p, ctypes.c_double, _u8p, _u8p, _u8p, _f64p]
         lib.orc_screen5.restype = ctypes.c_int
+        lib.orc_hamiltonian.argtypes = [ctypes.POINTER(OrcInput), _u8p, _u8p, _u8p, ctypes.c_int, _f64p]
+        lib.orc_hamiltonian.restype = ctypes.c_int
         lib.orc_forces_stress.argtypes = [ctypes.POINTER(OrcInput), _f64p, _f64p, _f64p, _f64p]
         lib.orc_has_openmp.restype = ctypes.c_int
         _lib = lib
@@ -168,6 +170,23 @@ class Problem:
                           _p(E, _f64p), _p(gC, _f64p), _p(gV, _f64p), _p(sk, _f64p))
         self.skipped_bound = float(sk[0])
         return float(E[0]), gC, gV
+
+    def hamiltonian(self, keep, nthreads=1, bits=False):
+        """H^X = dE/dD (Eq. Exx2), dense [n_tot][n_tot], from the quartets'
+        energy items; keep as for contract()."""
+        lib = _load()
+        kC, kV, kD = keep[:3]
+        if not bits:
+            kC = np.where(np.asarray(kC) != 0, 3, 0).astype(np.uint8)
+            kV = np.where(np.asarray(kV) != 0, 3, 0).astype(np.uint8)
+        kC = np.ascontiguousarray(kC, np.uint8)
+        kV = np.ascontiguousarray(kV, np.uint8)
+        kD = np.ascontiguousarray(kD, np.uint8)
+        nt = int(self.nao.sum())
+        H = np.zeros((nt, nt))
+        lib.orc_hamiltonian(ctypes.byref(self.s), _p(kC, _u8p), _p(kV, _u8p), _p(kD, _u8p), int(nthreads),
+                            _p(H, _f64p))
+        return H
 
     def forces_stress(self, gC, gV):
         lib = _load()

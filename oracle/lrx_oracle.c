@@ -574,6 +574,114 @@ int orc_contract2(const orc_input* in, const uint8_t* keepC, const uint8_t* keep
   return 0;
 }
 
+/*
+ * The exact-exchange Hamiltonian of Eq. Exx2, H^X = dE/dD (the derivative of
+ * Eq. exx_expand with respect to every element of the density matrix, which
+ * equals -sum_{kl} (ik|jl) D_kl): the quartet loop above, the energy item of
+ * each quartet only (C1, V, C2 in their value lists), with its four D slots.
+ * With T[a][f][b][g] = sum_{al,be} C1[al][a][f] V[al][be] C2[be][b][g], a
+ * quartet adds
+ *   -sum_{fg} T D(F,G)[f][g]  to H(A,B)[a][b],   -sum_{ab} T D(A,B)[a][b]  to H(F,G)[f][g],
+ *   -sum_{fb} T D(F,B)[f][b]  to H(A,G)[a][g],   -sum_{ag} T D(A,G)[a][g]  to H(F,B)[f][b],
+ * each only where that D pair is kept (a screened pair is zero in E, so E
+ * does not depend on it).  H is dense [n_tot][n_tot]; the caller zeroes it.
+ * nthreads > 1: private copies over V blocks, summed in thread order.
+ */
+int orc_hamiltonian(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV, const uint8_t* keepD,
+                    int nthreads, double* H) {
+  const int N = in->natom;
+  int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+  const int64_t nt = ntot_of(in, ao);
+  int64_t* crow = (int64_t*)calloc(N + 1, sizeof(int64_t));
+  int64_t* clist = (int64_t*)malloc(sizeof(int64_t) * (in->nC + 1));
+  for (int64_t b = 0; b < in->nC; ++b) if (keepC[b] & 1) crow[in->C_first[b] + 1]++;
+  for (int i = 0; i < N; ++i) crow[i + 1] += crow[i];
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * N);
+    for (int i = 0; i < N; ++i) fill[i] = crow[i];
+    for (int64_t b = 0; b < in->nC; ++b) if (keepC[b] & 1) clist[fill[in->C_first[b]]++] = b;
+    free(fill);
+  }
+  int mmax = 0, nmax = 0;
+  for (int i = 0; i < N; ++i) { if (in->nabf[i] > mmax) mmax = in->nabf[i]; if (in->nao[i] > nmax) nmax = in->nao[i]; }
+  int nth = nthreads > 1 ? nthreads : 1;
+#ifndef _OPENMP
+  nth = 1;
+#endif
+  /* per thread: U[be][a][f], T[a][f][b][g] and a private H */
+  const size_t usz = (size_t)mmax * nmax * nmax, tsz = (size_t)nmax * nmax * nmax * nmax;
+  double** ws = (double**)malloc(sizeof(double*) * nth);
+  double** hp = (double**)malloc(sizeof(double*) * nth);
+  for (int t = 0; t < nth; ++t) {
+    ws[t] = (double*)malloc(sizeof(double) * (usz + tsz + 1));
+    hp[t] = (double*)calloc((size_t)nt * nt, sizeof(double));
+  }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+#endif
+  for (int64_t v = 0; v < in->nV; ++v) {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    if (!(keepV[v] & 1)) continue;
+    const int A = in->V_first[v], B = in->V_second[v];
+    const int mA = in->nabf[A], mB = in->nabf[B], nA = in->nao[A], nB = in->nao[B];
+    const double* V = in->V_val + in->V_off[v];
+    double* U = ws[t];
+    double* T = U + usz;
+    double* Hm = hp[t];
+    for (int64_t i1 = crow[A]; i1 < crow[A + 1]; ++i1) {
+      const int64_t c1 = clist[i1];
+      const int F = in->C_second[c1], nF = in->nao[F];
+      const double* C1 = in->C_val + in->C_off[c1];
+      /* U[be][a f] = sum_al V[al][be] C1[al][a f] */
+      const int k1 = nA * nF;
+      for (int be = 0; be < mB; ++be)
+        for (int k = 0; k < k1; ++k) {
+          double s = 0;
+          for (int al = 0; al < mA; ++al) s += V[(int64_t)al * mB + be] * C1[(int64_t)al * k1 + k];
+          U[(size_t)be * k1 + k] = s;
+        }
+      for (int64_t i2 = crow[B]; i2 < crow[B + 1]; ++i2) {
+        const int64_t c2 = clist[i2];
+        const int G = in->C_second[c2], nG = in->nao[G];
+        const double* C2 = in->C_val + in->C_off[c2];
+        const int k2 = nB * nG;
+        /* T[a f][b g] = sum_be U[be][a f] C2[be][b g] */
+        for (int k = 0; k < k1; ++k)
+          for (int l = 0; l < k2; ++l) {
+            double s = 0;
+            for (int be = 0; be < mB; ++be) s += U[(size_t)be * k1 + k] * C2[(int64_t)be * k2 + l];
+            T[(size_t)k * k2 + l] = s;
+          }
+        const int kAB = keepD[A * N + B], kFG = keepD[F * N + G], kAG = keepD[A * N + G], kFB = keepD[F * N + B];
+        const double* D = in->D;
+        for (int a = 0; a < nA; ++a)
+          for (int f = 0; f < nF; ++f)
+            for (int b = 0; b < nB; ++b)
+              for (int g = 0; g < nG; ++g) {
+                const double x = T[(size_t)(a * nF + f) * k2 + b * nG + g];
+                const int64_t ia = ao[A] + a, jf = ao[F] + f, kb = ao[B] + b, lg = ao[G] + g;
+                const double dAB = kAB ? D[ia * nt + kb] : 0.0, dFG = kFG ? D[jf * nt + lg] : 0.0;
+                const double dAG = kAG ? D[ia * nt + lg] : 0.0, dFB = kFB ? D[jf * nt + kb] : 0.0;
+                if (kAB) Hm[ia * nt + kb] -= x * dFG;
+                if (kFG) Hm[jf * nt + lg] -= x * dAB;
+                if (kAG) Hm[ia * nt + lg] -= x * dFB;
+                if (kFB) Hm[jf * nt + kb] -= x * dAG;
+              }
+      }
+    }
+  }
+  for (int t = 0; t < nth; ++t) {
+    for (int64_t i = 0; i < nt * nt; ++i) H[i] += hp[t][i];
+    free(ws[t]);
+    free(hp[t]);
+  }
+  free(ws); free(hp); free(ao); free(crow); free(clist);
+  return 0;
+}
+
 /* The joint lists of orc_screen (a kept block in both lists), no item test. */
 int orc_contract(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV,
                  const uint8_t* keepD, int64_t v_begin, int64_t v_end, int focus_kind,

@@ -55,3 +55,14 @@ def energy_assoc(st, mats, keepC=None, keepV=None, D=None):
     Q = np.einsum("ij,bjl,lk->bik", D, P, D, optimize=True)
     M = P.reshape(P.shape[0], -1) @ Q.reshape(Q.shape[0], -1).T
     return -0.5 * float(np.sum(Vd * M))
+
+
+def hamiltonian_literal(st, mats, D=None):
+    """H^X_ij = -sum_kl (ik|jl) D_kl (Eq. Exx2) from the same fitted
+    4-index integrals, without forming them (small cells)."""
+    P, Vd = dense_ri(st, mats)
+    D = st.D if D is None else D
+    # (PD)[b][j][k] = sum_l P[b][j][l] D[k][l]; W[a][j][k] = sum_b Vd[a][b] (PD)[b][j][k]
+    PD = np.einsum("bjl,kl->bjk", P, D, optimize=True)
+    W = np.einsum("ab,bjk->ajk", Vd, PD, optimize=True)
+    return -np.einsum("aik,ajk->ij", P, W, optimize=True)

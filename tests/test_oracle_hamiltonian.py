@@ -1,0 +1,94 @@
+"""Pins of the oracle's exact-exchange Hamiltonian H^X = dE/dD (Eq. Exx2),
+CPU only.
+
+* The 4-index definition H^X_ij = -sum_kl (ik|jl) D_kl with the fitted
+  integrals of Eq. Exx-LRI (tests/ref_bruteforce.py, code that shares nothing
+  with the quartet loop).
+* Euler's identity for a quadratic form: E = 1/2 <H^X, D>.
+* Central differences of the oracle's energy along a symmetric direction S:
+  E is quadratic in D, so (E(D + eS) - E(D - eS)) / 2e = <H^X, S> up to
+  rounding, for any e.
+* H^X is symmetric for a symmetric D.
+* Screening: H^X of the screened energy equals the unscreened H^X of the
+  inputs with the dropped blocks zeroed, on the kept D pairs, and zero on the
+  dropped ones (E does not depend on them).
+A dropped D slot, a transposed slot or a wrong sign fails the first three.
+"""
+import numpy as np
+import pytest
+
+from paper_2412_11081_amd import synth
+from tests import ref_bruteforce as bf
+
+
+def _case(natom=3, seed=41, n_ao=4, n_abf=6, box=7.0, rc=5.5, rv=9.0, nspecies=2):
+    st = synth.small_case(natom=natom, seed=seed, nspecies=nspecies, n_ao=n_ao, n_abf=n_abf, box=box, rc=rc,
+                          rv=rv).build()
+    return st, st.materialize("cpu")
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("seed,natom,n_ao,n_abf", [(41, 3, 4, 6), (42, 2, 5, 7), (43, 4, 3, 5)])
+def test_hamiltonian_equals_the_four_index_definition(oracle_lib, seed, natom, n_ao, n_abf):
+    st, mats = _case(natom, seed, n_ao, n_abf)
+    pr = oracle_lib.Problem.from_structure(st, mats)
+    H = pr.hamiltonian(pr.screen(0.0, 0.0))
+    Hb = bf.hamiltonian_literal(st, mats)
+    print(f"max|H| {np.abs(H).max():.3e}, rel diff {_rel(H, Hb):.2e}")
+    assert _rel(H, Hb) <= 1e-12
+
+
+def test_hamiltonian_euler_identity_and_symmetry(oracle_lib):
+    st, mats = _case(4, 44, 5, 8)
+    pr = oracle_lib.Problem.from_structure(st, mats)
+    keep = pr.screen(0.0, 0.0)
+    E, _, _ = pr.contract(keep)
+    H = pr.hamiltonian(keep)
+    assert abs(0.5 * float(np.sum(H * st.D)) - E) <= 1e-12 * abs(E)
+    assert _rel(H, H.T) <= 1e-13
+
+
+def test_hamiltonian_is_the_derivative_of_the_energy(oracle_lib):
+    st, mats = _case(3, 45, 4, 6)
+    pr = oracle_lib.Problem.from_structure(st, mats)
+    keep = pr.screen(0.0, 0.0)
+    H = pr.hamiltonian(keep)
+    rng = np.random.default_rng(7)
+    nt = st.D.shape[0]
+    for _ in range(3):
+        S = rng.standard_normal((nt, nt))
+        S = S + S.T
+        eps = 1e-2
+        Ep = oracle_lib.Problem(st.tau, st.lat, st.nao, st.nabf, mats["C"], mats["V"], st.D + eps * S).contract(keep)[0]
+        Em = oracle_lib.Problem(st.tau, st.lat, st.nao, st.nabf, mats["C"], mats["V"], st.D - eps * S).contract(keep)[0]
+        fd = (Ep - Em) / (2 * eps)
+        an = float(np.sum(H * S))
+        print(f"fd {fd:.15e} analytic {an:.15e}")
+        assert abs(fd - an) <= 1e-10 * max(abs(an), abs(Ep), abs(Em))
+
+
+def test_hamiltonian_of_the_screened_energy(oracle_lib):
+    from tests.test_oracle_screen_modes import _zeroed
+
+    st, mats = _case(4, 19, 3, 4)
+    pr = oracle_lib.Problem.from_structure(st, mats)
+    thr = (1e-3, 0.0, 0.3, 0.0, 5e-2)    # drops D pairs and C blocks from the value list
+    keep = pr.screen5(thr, 0.0)
+    kC, kV, kD = keep[:3]
+    assert not kD.all() and ((kC & 1) == 0).any()
+    H = pr.hamiltonian(keep, bits=True)
+    m2, D = _zeroed(st, mats, kC, kV, kD)
+    H0 = oracle_lib.Problem(st.tau, st.lat, st.nao, st.nabf, m2["C"], m2["V"], D).hamiltonian(
+        oracle_lib.Problem(st.tau, st.lat, st.nao, st.nabf, m2["C"], m2["V"], D).screen(0.0, 0.0))
+    ao = np.concatenate([[0], np.cumsum(st.nao)])
+    N = st.natom
+    mask = np.zeros_like(H, dtype=bool)
+    for X in range(N):
+        for Y in range(N):
+            if kD[X * N + Y]:
+                mask[ao[X]:ao[X + 1], ao[Y]:ao[Y + 1]] = True
+    assert np.all(H[~mask] == 0.0)
+    assert _rel(H[mask], H0[mask]) <= 1e-12
