@@ -135,6 +135,36 @@ def cpu_full_small():
     return {"value": 1.0 / dt, "unit": "evals/s", "cores": 1, "workload": WORKLOADS[1], "seconds": dt}
 
 
+def hamiltonian_benchmark(ctx, st, steps, E_forces):
+    """lrx_hamiltonian (Eq. Exx2) on the same context: H^X written into a
+    device tensor, its stages timed with HIP events, its algorithmic FLOPs
+    counted from the lists; E = <H^X, D> / 2 beside the force path's E."""
+    import numpy as np
+    import torch
+
+    nt = int(np.sum(st.nao))
+    out = torch.empty((nt, nt), dtype=torch.float64, device="cuda")
+    ctx.hamiltonian(st.theta, st.theta_cs, out=out)          # buffers allocated
+    torch.cuda.synchronize()
+    wall, stages = [], None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        E, _ = ctx.hamiltonian(st.theta, st.theta_cs, out=out, timing=True)
+        wall.append(time.perf_counter() - t0)
+        ms, flop = ctx.hamiltonian_info()
+        stages = ms if stages is None else {k: stages[k] + ms[k] for k in ms}
+    stages = {k: v / steps for k, v in stages.items()}
+    ms_call = 1e3 * float(np.median(wall))
+    slot_tf = flop["slot"] / (stages["slot"] * 1e-3) / 1e12
+    del out
+    return {"what": "lrx_hamiltonian: H^X = dE/dD [n_tot][n_tot] into a device tensor, same screening",
+            "n_tot": nt, "ms_per_call": ms_call, "calls_per_s": 1e3 / ms_call, "E": E,
+            "E_rel_diff_vs_force_path": abs(E - E_forces) / abs(E_forces), "stage_ms": stages,
+            "flop": flop, "tflops_alg": flop["total"] / (ms_call * 1e-3) / 1e12,
+            "slot_kernel": {"bound": "mfma", "achieved": slot_tf, "peak": 78.6, "unit": "TFLOP/s",
+                            "frac": slot_tf / 78.6}}
+
+
 def _build_request(i):
     from paper_2412_11081_amd import synth
 
@@ -443,6 +473,9 @@ def main():
                                       "achieved": stage_tflops, "frac": stage_tflops / peak,
                                       "group_ms": {str(k): v for k, v in sorted(group_avg.items())}}},
     }
+    E_forces = ctx.evaluate(st.theta, st.theta_cs)[0]
+    out["hamiltonian"] = hamiltonian_benchmark(ctx, st, max(3, min(args.steps, 5)), E_forces)
+    print(f"# hamiltonian: {out['hamiltonian']['ms_per_call']:.1f} ms per call", file=sys.stderr, flush=True)
     ctx.close()
     if not args.no_cpu_baseline:
         total_kept = stats["kept_v_blocks"]

@@ -276,6 +276,29 @@ int lrx_batch_tuning(const lrx_ctx* ctx, int32_t* mode, float* ms);
 int lrx_enumerate_pairs(int32_t device, int32_t natom, const double* tau, const double* lattice, double rcut,
                         int64_t capacity, int32_t* first, int32_t* second, int32_t* R, int64_t* count);
 
+/* The exact-exchange Hamiltonian (Eq. Exx2): H^X[i][j] = dE/dD[i][j] =
+ * -sum_kl (ik|jl) D_kl, the part of the energy's variation that comes from
+ * the density matrix, for the tensors of the context and the screening of
+ * opts (as lrx_evaluate; a screened D pair is zero in E, so H^X is zero
+ * there).  Hx: [n_tot][n_tot] row-major (n_tot = sum of nao), symmetric;
+ * a host buffer, or with hx_on_device != 0 a device buffer of the context's
+ * device (written on the context's stream; the call returns after it is
+ * written).  Hx may be NULL.  *E (optional) receives <H^X, D> / 2, the
+ * energy of the same screening (a quadratic form in D).  FP64 only
+ * (opts->precision must be LRX_FP64; LRX_EINVAL otherwise).  The first call
+ * allocates its work buffers: an adjoint of the H slots and three
+ * [n_tot][n_tot] matrices. */
+int lrx_hamiltonian(lrx_ctx* ctx, const lrx_options* opts, double* E, double* Hx, int32_t hx_on_device);
+
+/* After lrx_hamiltonian: ms[5] (when that call had opts->timing set; else
+ * LRX_ESTATE) the HIP-event times of its stages -- screening with folding,
+ * H build, adjoint per H slot, gradient through H, symmetrisation --; flop[4]
+ * (optional) the algorithmic FLOPs counted from its lists: total, the slot
+ * stage (per triple with value-list C and V pairs: 2 mA mB nA nF once for
+ * Vf^T Cf, 2 mB nA nF nB per D-block contraction), the gradient through H,
+ * the H build. */
+int lrx_hamiltonian_info(lrx_ctx* ctx, float* ms, double* flop);
+
 /* Size of the fixed device scratch of lrx_evaluate_noalloc (bytes per GPU). */
 #define LRX_SCRATCH_BYTES (128ull << 20)
 

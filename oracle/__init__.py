@@ -63,7 +63,8 @@ def _load():
         lib.orc_contract2.restype = ctypes.c_int
         lib.orc_screen5.argtypes = [ctypes.POINTER(OrcInput), _f64p, ctypes.c_double, _u8p, _u8p, _u8p, _f64p]
         lib.orc_screen5.restype = ctypes.c_int
-        lib.orc_hamiltonian.argtypes = [ctypes.POINTER(OrcInput), _u8p, _u8p, _u8p, ctypes.c_int, _f64p]
+        lib.orc_hamiltonian.argtypes = [ctypes.POINTER(OrcInput), _u8p, _u8p, _u8p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, _f64p]
         lib.orc_hamiltonian.restype = ctypes.c_int
         lib.orc_forces_stress.argtypes = [ctypes.POINTER(OrcInput), _f64p, _f64p, _f64p, _f64p]
         lib.orc_has_openmp.restype = ctypes.c_int
@@ -171,9 +172,11 @@ class Problem:
         self.skipped_bound = float(sk[0])
         return float(E[0]), gC, gV
 
-    def hamiltonian(self, keep, nthreads=1, bits=False):
+    def hamiltonian(self, keep, nthreads=1, bits=False, focus=None):
         """H^X = dE/dD (Eq. Exx2), dense [n_tot][n_tot], from the quartets'
-        energy items; keep as for contract()."""
+        energy items; keep as for contract().  focus = (X, Y): only the
+        quartets that reach the D block of atoms (X, Y), whose H block is
+        then complete (the rest of the matrix is not)."""
         lib = _load()
         kC, kV, kD = keep[:3]
         if not bits:
@@ -184,7 +187,8 @@ class Problem:
         kD = np.ascontiguousarray(kD, np.uint8)
         nt = int(self.nao.sum())
         H = np.zeros((nt, nt))
-        lib.orc_hamiltonian(ctypes.byref(self.s), _p(kC, _u8p), _p(kV, _u8p), _p(kD, _u8p), int(nthreads),
+        fx, fy = (-1, -1) if focus is None else (int(focus[0]), int(focus[1]))
+        lib.orc_hamiltonian(ctypes.byref(self.s), _p(kC, _u8p), _p(kV, _u8p), _p(kD, _u8p), fx, fy, int(nthreads),
                             _p(H, _f64p))
         return H
 

@@ -585,10 +585,12 @@ int orc_contract2(const orc_input* in, const uint8_t* keepC, const uint8_t* keep
  *   -sum_{fb} T D(F,B)[f][b]  to H(A,G)[a][g],   -sum_{ag} T D(A,G)[a][g]  to H(F,B)[f][b],
  * each only where that D pair is kept (a screened pair is zero in E, so E
  * does not depend on it).  H is dense [n_tot][n_tot]; the caller zeroes it.
+ * focus_x >= 0: only the quartets with a D slot on the atom pair
+ * (focus_x, focus_y), so that block of H is complete and the rest is not.
  * nthreads > 1: private copies over V blocks, summed in thread order.
  */
 int orc_hamiltonian(const orc_input* in, const uint8_t* keepC, const uint8_t* keepV, const uint8_t* keepD,
-                    int nthreads, double* H) {
+                    int focus_x, int focus_y, int nthreads, double* H) {
   const int N = in->natom;
   int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
   const int64_t nt = ntot_of(in, ao);
@@ -635,6 +637,8 @@ int orc_hamiltonian(const orc_input* in, const uint8_t* keepC, const uint8_t* ke
       const int64_t c1 = clist[i1];
       const int F = in->C_second[c1], nF = in->nao[F];
       const double* C1 = in->C_val + in->C_off[c1];
+      /* every D slot of a quartet has A or F as its first atom */
+      if (focus_x >= 0 && A != focus_x && F != focus_x) continue;
       /* U[be][a f] = sum_al V[al][be] C1[al][a f] */
       const int k1 = nA * nF;
       for (int be = 0; be < mB; ++be)
@@ -646,6 +650,9 @@ int orc_hamiltonian(const orc_input* in, const uint8_t* keepC, const uint8_t* ke
       for (int64_t i2 = crow[B]; i2 < crow[B + 1]; ++i2) {
         const int64_t c2 = clist[i2];
         const int G = in->C_second[c2], nG = in->nao[G];
+        if (focus_x >= 0 && !((A == focus_x && B == focus_y) || (F == focus_x && G == focus_y) ||
+                              (A == focus_x && G == focus_y) || (F == focus_x && B == focus_y)))
+          continue;
         const double* C2 = in->C_val + in->C_off[c2];
         const int k2 = nB * nG;
         /* T[a f][b g] = sum_be U[be][a f] C2[be][b g] */

@@ -230,6 +230,13 @@ struct lrx_ctx {
   // sizes of the FP32 buffers of the reduced-precision forms
   int64_t n_cf = 0, n_vf = 0, n_h = 0, n_z = 0, n_y = 0;
   bool have_f32 = false, have_f64 = false;
+  // the Hamiltonian's buffers (allocated by its first call)
+  bool have_hx = false;
+  lrx::HxBufs hx{};
+  double* hx_host_E = nullptr;            // pinned
+  std::array<float, 5> hx_ms{};
+  bool hx_timed = false;
+  bool hx_done = false;
 
   // device memory
   std::vector<void*> allocs;
@@ -298,6 +305,8 @@ struct lrx_ctx {
     dev_bytes = 0;
     have_tensors = false;
     have_f32 = have_f64 = false;
+    have_hx = false;
+    hx_done = false;
     evaluated = false;
   }
 };
@@ -1445,6 +1454,100 @@ int lrx_evaluate_noalloc(lrx_ctx* c, const lrx_options* opts, double* E, double*
     if (E) *E = c->h_out[0];
     if (F) std::memcpy(F, c->h_out + 1, sizeof(double) * 3 * N);
     if (sigma) std::memcpy(sigma, c->h_out + 1 + 3 * N, sizeof(double) * 9);
+  });
+}
+
+int lrx_hamiltonian(lrx_ctx* c, const lrx_options* opts, double* E, double* Hx, int32_t hx_on_device) {
+  return guarded(c, [&] {
+    prepare(c, opts);
+    require(opts->precision == LRX_FP64, "the Hamiltonian is computed in FP64 only");
+    Dev& d = c->dev;
+    const int64_t nt = c->ao[c->N];
+    if (!c->have_hx) {
+      int kmax = 1;
+      for (size_t i = 0; i < c->cp.pA.size(); ++i) kmax = std::max(kmax, c->nao[c->cp.pA[i]] * c->nao[c->cp.pB[i]]);
+      c->hx.kmax = kmax;
+      c->hx.nmax = *std::max_element(c->nao.begin(), c->nao.end());
+      c->hx.Hbar = c->dalloc<double>(c->n_h);
+      c->hx.G12 = c->dalloc<double>(nt * nt);
+      c->hx.G3 = c->dalloc<double>(nt * nt);
+      c->hx.Hx = c->dalloc<double>(nt * nt);
+      c->hx.Etile = c->dalloc<double>(lrx::hx_tiles(nt));
+      c->hx.E = c->dalloc<double>(1);
+      c->have_hx = true;
+    }
+    const lrx::Opts o = make_opts(opts);
+    const bool timing = opts->timing != 0;
+    lrx::HxBufs b = c->hx;
+    if (hx_on_device && Hx) b.Hx = Hx;   // written straight into the caller's device buffer
+    if (timing) HIPCHK(hipEventRecord(c->ev[0], c->stream));
+    lrx::launch_screen(d, o, c->stream, nullptr, true);
+    if (timing) HIPCHK(hipEventRecord(c->ev[1], c->stream));
+    lrx::launch_hbuild(d, lrx::kP64, c->stream);
+    if (timing) HIPCHK(hipEventRecord(c->ev[2], c->stream));
+    lrx::launch_hx(d, b, c->stream, timing ? c->ev.data() + 3 : nullptr);
+    HIPCHK(hipGetLastError());
+    double e = 0;
+    HIPCHK(hipMemcpyAsync(&e, b.E, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (Hx && !hx_on_device)
+      HIPCHK(hipMemcpyAsync(Hx, b.Hx, sizeof(double) * nt * nt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (timing)
+      for (int i = 0; i < 5; ++i) HIPCHK(hipEventElapsedTime(&c->hx_ms[i], c->ev[i], c->ev[i + 1]));
+    c->hx_timed = timing;
+    c->hx_done = true;
+    c->per_tensor = (opts->flags & LRX_SCREEN_PER_TENSOR) != 0;
+    if (E) *E = e;
+  });
+}
+
+int lrx_hamiltonian_info(lrx_ctx* c, float* ms, double* flop) {
+  return guarded(c, [&] {
+    require(c->hx_done, "no Hamiltonian evaluated yet");
+    if (ms) {
+      require(c->hx_timed, "the last Hamiltonian call was not timed");
+      for (int i = 0; i < 5; ++i) ms[i] = c->hx_ms[i];
+    }
+    if (!flop) return;
+    const Dev& d = c->dev;
+    const int N = c->N;
+    std::vector<uint8_t> aC(d.nCp), aV(d.nVp), need(d.nSlot), kD((size_t)N * N);
+    if (d.nCp) HIPCHK(hipMemcpyAsync(aC.data(), d.aliveC, d.nCp, hipMemcpyDeviceToHost, c->stream));
+    if (d.nVp) HIPCHK(hipMemcpyAsync(aV.data(), d.aliveV, d.nVp, hipMemcpyDeviceToHost, c->stream));
+    if (d.nSlot) HIPCHK(hipMemcpyAsync(need.data(), d.need, d.nSlot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(kD.data(), d.keepD, (size_t)N * N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const auto& na = c->nao;
+    const auto& nb = c->nabf;
+    const Pairs& cp = c->cp;
+    const Pairs& vp = c->vp;
+    // per triple with value-list C and V pairs: Q once, and its four
+    // contractions (Hbar twice where the D pair is kept, G1 and G2)
+    double fs = 0, fg = 0, fh = 0;
+    for (int i = 0; i < d.nCp; ++i) {
+      if (!(aC[i] & 1)) continue;
+      const int A = cp.pA[i], F = cp.pB[i];
+      for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
+        if (!(aV[p] & 1)) continue;
+        const int B = vp.pB[p];
+        const double k = (double)nb[B] * na[A] * na[F];
+        fs += 2.0 * nb[A] * k + 2.0 * k * na[B] * (2 + kD[(size_t)A * N + B] + kD[(size_t)F * N + B]);
+      }
+    }
+    // the H build and its adjoint G3 run over the same (slot, C partner) pairs
+    for (int sl = 0; sl < d.nSlot; ++sl) {
+      if (!need[sl]) continue;
+      const int B = c->slotB[sl], X = c->slotX[sl];
+      double depth = 0;
+      for (int i = cp.row[B]; i < cp.row[B + 1]; ++i)
+        if (aC[i] & 1) depth += na[cp.pB[i]];
+      fg += 2.0 * nb[B] * na[B] * na[X] * depth;
+    }
+    fh = fg;
+    flop[0] = fs + fg + fh;
+    flop[1] = fs;
+    flop[2] = fg;
+    flop[3] = fh;
   });
 }
 

@@ -182,7 +182,9 @@ __host__ __device__ inline bool triple_live(int aliveC, int aliveV, bool b_below
 
 // kernels (lrx_screen.hip)
 void launch_validate(const Dev& d, hipStream_t s);
-void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev);
+// for_hx: the H slots the Hamiltonian reads (every triple whose C pair and V
+// pair have value-list blocks) instead of those of the forces
+void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev, bool for_hx = false);
 // kernels (lrx_contract.hip)
 
 // Work of the triple-product kernels: per alpha-tile group MT, a list of
@@ -220,5 +222,21 @@ void launch_grads(const Dev& d, int prec, hipStream_t s, hipEvent_t* ev);
 void launch_contract(const Dev& d, const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side,
                      const hipEvent_t* fork, hipEvent_t* ev, hipEvent_t* gev = nullptr);
 void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipStream_t s);
+
+// kernels (lrx_fock.hip): the exact-exchange Hamiltonian H^X = dE/dD
+struct HxBufs {
+  double* Hbar;    // adjoint of H, laid out as the H slots (n_h)
+  double* G12;     // [ntot][ntot] gradient parts through D(A,B) and D(F,B)
+  double* G3;      // [ntot][ntot] gradient part through H
+  double* Hx;      // [ntot][ntot] output (device)
+  double* Etile;   // [hx_tiles(ntot)]
+  double* E;       // [1] <H^X, D> / 2
+  int kmax;        // largest n_A n_X over the C pairs (Q tile row length)
+  int nmax;        // largest NAO count of an atom
+};
+int64_t hx_tiles(int64_t ntot);
+// after launch_screen(..., for_hx = true) and the FP64 H build; ev
+// (optional) marks after the slot kernel, after G3 and at the end
+void launch_hx(const Dev& d, const HxBufs& b, hipStream_t s, hipEvent_t* ev);
 
 }  // namespace lrx

@@ -387,6 +387,20 @@ __global__ void k_mark(Dev d) {
   }
 }
 
+// H slots the Hamiltonian reads: H(B,F) and H(B,A) of every triple (A,F,B)
+// whose C pair and V pair have value-list blocks (its energy item).
+__global__ void k_mark_hx(Dev d) {
+  const int cp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cp >= d.nCp || !(d.aliveC[cp] & 1)) return;
+  const int A = d.cpA[cp], F = d.cpF[cp];
+  for (int p = d.vpRow[A]; p < d.vpRow[A + 1]; ++p) {
+    if (!(d.aliveV[p] & 1)) continue;
+    const int B = d.vpB[p];
+    d.need[d.hSlotMap[(int64_t)B * d.N + F]] = 1;
+    d.need[d.hSlotMap[(int64_t)B * d.N + A]] = 1;
+  }
+}
+
 // What each triple-product unit forms in this evaluation (triple_live):
 // 0 nothing, 1 Z and Y, 2 Y alone.
 __global__ void k_unit_role(Dev d) {
@@ -473,7 +487,7 @@ __global__ void __launch_bounds__(kNT) k_hcompact(Dev d) {
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)(a > 0 ? (a + b - 1) / b : 1); }
 
-void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev) {
+void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev, bool for_hx) {
   const int64_t NN = (int64_t)d.N * d.N;
   if (d.nC) hipLaunchKernelGGL(k_block_norms, dim3((unsigned)d.nC), dim3(kNT), 0, s, d.Cval, d.Cdval, d.Coff, d.Csz, d.nrmC);
   if (d.nV) hipLaunchKernelGGL(k_block_norms, dim3((unsigned)d.nV), dim3(kNT), 0, s, d.Vval, d.Vdval, d.Voff, d.Vsz, d.nrmV);
@@ -490,8 +504,12 @@ void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[2], s);
   hipLaunchKernelGGL(k_fill_u8, dim3(cdiv(d.nSlot, kNT)), dim3(kNT), 0, s, d.need,
                      (int64_t)d.nSlot);
-  hipLaunchKernelGGL(k_mark, dim3(cdiv(d.nCp, kNT)), dim3(kNT), 0, s, d);
-  hipLaunchKernelGGL(k_unit_role, dim3(cdiv(d.nUnit, kNT)), dim3(kNT), 0, s, d);
+  if (for_hx) {
+    hipLaunchKernelGGL(k_mark_hx, dim3(cdiv(d.nCp, kNT)), dim3(kNT), 0, s, d);
+  } else {
+    hipLaunchKernelGGL(k_mark, dim3(cdiv(d.nCp, kNT)), dim3(kNT), 0, s, d);
+    hipLaunchKernelGGL(k_unit_role, dim3(cdiv(d.nUnit, kNT)), dim3(kNT), 0, s, d);
+  }
   hipLaunchKernelGGL(k_hcompact, dim3((unsigned)d.N), dim3(kNT), 0, s, d);
   if (ev) (void)hipEventRecord(ev[3], s);
 }

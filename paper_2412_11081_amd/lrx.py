@@ -89,7 +89,8 @@ _lib = None
 EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
            "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim", "lrx_group_times",
-           "lrx_submit", "lrx_wait", "lrx_evaluate_noalloc", "lrx_enumerate_pairs"]
+           "lrx_submit", "lrx_wait", "lrx_evaluate_noalloc", "lrx_enumerate_pairs", "lrx_hamiltonian",
+           "lrx_hamiltonian_info"]
 
 
 def load(path: Optional[str] = None):
@@ -125,7 +126,9 @@ def load(path: Optional[str] = None):
     lib.lrx_evaluate_noalloc.argtypes = [vp, ctypes.POINTER(Options), _f64p, _f64p, _f64p]
     lib.lrx_enumerate_pairs.argtypes = [ctypes.c_int32, ctypes.c_int32, _f64p, _f64p, ctypes.c_double, ctypes.c_int64,
                                         _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_int64)]
-    for f in ("lrx_evaluate_noalloc", "lrx_enumerate_pairs", "lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
+    lib.lrx_hamiltonian.argtypes = [vp, ctypes.POINTER(Options), _f64p, vp, ctypes.c_int32]
+    lib.lrx_hamiltonian_info.argtypes = [vp, _f32p, _f64p]
+    for f in ("lrx_hamiltonian", "lrx_hamiltonian_info", "lrx_evaluate_noalloc", "lrx_enumerate_pairs", "lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
               "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning",
               "lrx_pool_trim", "lrx_group_times", "lrx_submit", "lrx_wait"):
         getattr(lib, f).restype = ctypes.c_int
@@ -229,6 +232,36 @@ class Context:
         self._check(self.lib.lrx_evaluate_noalloc(self.h, ctypes.byref(o), ctypes.byref(E), _ptr(F, _f64p),
                                                   _ptr(S, _f64p)))
         return E.value, F, S
+
+    def hamiltonian(self, theta=0.0, theta_cs=0.0, thresholds=None, out=None, timing=False):
+        """lrx_hamiltonian: (E, H^X).  out: a contiguous float64 torch tensor
+        [n_tot][n_tot] on the context's device to write H^X into (returned
+        as is); otherwise H^X comes back as a numpy array."""
+        o = _options(theta, theta_cs, "fp64", timing, thresholds=thresholds)
+        E = ctypes.c_double()
+        if out is not None:
+            if not (out.is_cuda and out.is_contiguous() and str(out.dtype) == "torch.float64"):
+                raise ValueError("out: a contiguous float64 device tensor")
+            import torch
+
+            torch.cuda.current_stream().synchronize()
+            self._check(self.lib.lrx_hamiltonian(self.h, ctypes.byref(o), ctypes.byref(E),
+                                                 ctypes.c_void_p(out.data_ptr()), 1))
+            return E.value, out
+        nt = int(np.sum(self._nao))
+        H = np.zeros((nt, nt))
+        self._check(self.lib.lrx_hamiltonian(self.h, ctypes.byref(o), ctypes.byref(E),
+                                             ctypes.c_void_p(H.ctypes.data), 0))
+        return E.value, H
+
+    def hamiltonian_info(self, timing=True):
+        """lrx_hamiltonian_info: ({stage: ms} or None, {flop kind: count})."""
+        ms = (ctypes.c_float * 5)()
+        fl = (ctypes.c_double * 4)()
+        self._check(self.lib.lrx_hamiltonian_info(self.h, ms if timing else None, fl))
+        names = ("screen", "hbuild", "slot", "g3", "final")
+        return ({n: float(ms[i]) for i, n in enumerate(names)} if timing else None,
+                {"total": fl[0], "slot": fl[1], "g3": fl[2], "hbuild": fl[3]})
 
     def submit(self, theta=0.0, theta_cs=0.0, precision="fp64", thresholds=None):
         """lrx_submit: queue an evaluation on the context's stream; returns its ticket."""

@@ -92,3 +92,18 @@ def test_hamiltonian_of_the_screened_energy(oracle_lib):
                 mask[ao[X]:ao[X + 1], ao[Y]:ao[Y + 1]] = True
     assert np.all(H[~mask] == 0.0)
     assert _rel(H[mask], H0[mask]) <= 1e-12
+
+
+def test_hamiltonian_focus_gives_the_block_exactly(oracle_lib):
+    """The focused loop (for sampled blocks of large cells) reproduces the
+    block of the full H bit for bit: it takes the same quartets of that
+    block in the same order."""
+    st, mats = _case(4, 46, 4, 6)
+    pr = oracle_lib.Problem.from_structure(st, mats)
+    keep = pr.screen(0.0, 0.0)
+    H = pr.hamiltonian(keep)
+    ao = np.concatenate([[0], np.cumsum(st.nao)])
+    for X, Y in ((0, 0), (1, 3), (3, 1), (2, 0)):
+        Hf = pr.hamiltonian(keep, focus=(X, Y))
+        blk = (slice(ao[X], ao[X + 1]), slice(ao[Y], ao[Y + 1]))
+        np.testing.assert_array_equal(Hf[blk], H[blk])
