@@ -24,13 +24,17 @@
 //   k_hx_slot   one workgroup per needed H slot (B,X): Hbar(B,X) and the
 //               D block (X,B) of G1 + G2.  Q tiles of 16 beta rows on the
 //               matrix cores (operands from global memory, result in LDS),
-//               the contractions with D and H on the vector units.
-//   k_hx_g3     one workgroup per D block (G,X): G3 over the C partners B.
+//               then the contractions with the staged D block and H slice,
+//               also on the matrix cores.
+//   k_hx_g3     one workgroup per D block (G,X): G3 over the C partners B,
+//               on the matrix cores.
 //   k_hx_final  32 x 32 tiles: (G + G^T) / 2 on kept D pairs, and the tile's
 //               share of <H^X, D> / 2; k_hx_sum adds the shares in order.
 // No atomics: every output element has one writer, so two calls agree bit
 // for bit.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "lrx_internal.h"
 
@@ -39,10 +43,7 @@ namespace lrx {
 namespace {
 
 constexpr int kHxNT = 256;
-constexpr int kGPer = kMaxNao * kMaxNao / kHxNT;         // D-block elements per thread
-// Hbar elements of a beta tile per thread, for NAO counts up to NMAX
-template <int NMAX>
-constexpr int hb_per() { return (16 * NMAX * NMAX + kHxNT - 1) / kHxNT; }
+static_assert(kMaxNao <= 32, "two 16-wide tiles per NAO index");
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -61,192 +62,265 @@ __device__ inline int find_partner(const int* __restrict__ list, int r0, int r1,
 //   Q[beta][k] = sum_alpha Vf[alpha][16 t + beta] Cf[alpha][k],
 // Vf rows ldv apart (B's ABFs padded to 16, zero padding), Cf rows K1 apart.
 // f64 16x16x4 MFMA: lane (q, g) gives A[m = q][k = g] = Vf[4 s + g][16 t + q]
-// and B[k = g][n = q] = Cf[4 s + g][16 j + q]; result i is row g + 4 i.
-__device__ void q_tile(const double* __restrict__ Vf, int ldv, const double* __restrict__ Cf, int mA, int K1, int t,
-                       double* Q, int w, int q, int g) {
+// and B[k = g][n = q] = Cf[4 s + g][16 j + q]; result i is row g + 4 i.  A
+// wave keeps three column tiles (j, j + 4, j + 8) in flight; they share the
+// Vf operand.
+__device__ inline void q_tile(const double* __restrict__ Vf, int ldv, const double* __restrict__ Cf, int mA, int K1,
+                              int t, double* Q, int w, int q, int g) {
   const int nj = (K1 + 15) >> 4, ns = (mA + 3) >> 2;
-  for (int j = w; j < nj; j += kHxNT / 64) {
-    const int c = 16 * j + q;
-    d4 acc = {0, 0, 0, 0};
+  for (int j0 = w; j0 < nj; j0 += 12) {
+    const int c0 = 16 * j0 + q, c1 = c0 + 64, c2 = c0 + 128;
+    d4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0}, a2 = {0, 0, 0, 0};
+#pragma unroll 4
     for (int s = 0; s < ns; ++s) {
       const int al = 4 * s + g;
-      const double a = al < mA ? Vf[(int64_t)al * ldv + 16 * t + q] : 0.0;
-      const double b = (al < mA && c < K1) ? Cf[(int64_t)al * K1 + c] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      const bool ok = al < mA;
+      const double* cr = Cf + (int64_t)al * K1;
+      const double a = ok ? Vf[(int64_t)al * ldv + 16 * t + q] : 0.0;
+      const double b0 = (ok && c0 < K1) ? cr[c0] : 0.0;
+      const double b1 = (ok && c1 < K1) ? cr[c1] : 0.0;
+      const double b2 = (ok && c2 < K1) ? cr[c2] : 0.0;
+      a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, a1, 0, 0, 0);
+      a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b2, a2, 0, 0, 0);
     }
-    if (c < K1) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) Q[(g + 4 * i) * K1 + c] = acc[i];
+    for (int i = 0; i < 4; ++i) {
+      const int r = (g + 4 * i) * K1;
+      if (c0 < K1) Q[r + c0] = a0[i];
+      if (c1 < K1) Q[r + c1] = a1[i];
+      if (c2 < K1) Q[r + c2] = a2[i];
     }
   }
 }
 
-template <int NMAX>
-__global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ Hbar, double* __restrict__ G12) {
-  constexpr int kHbPer = hb_per<NMAX>();
-  extern __shared__ double Q[];   // [16][K1], K1 <= the largest n_A n_X of the structure
+// One triple's contractions with its staged D block Ds [nk][nB] (row k of
+// the contracted AO index) and H slice Hb (HS: in LDS; else global memory),
+// [b][beta][k] with k < nk:
+//   Hbar tile of beta:  acc_h[b][x] += sum_k Ds[k][b] Q[beta][qi(x, k)]
+//   G tile:             acc_g[x][b] += sum_{beta, k} Q[beta][qi(x, k)] Hb[b][beta][k]
+// qi(x, k) = k nX + x for the first kind of triple (k = a), x nF + k for the
+// second (k = f); a wave takes beta = w + 4 j, j < 4.
+template <int NT>
+__device__ inline void contract_triple(const double* __restrict__ Q, int K1, const double* __restrict__ Ds,
+                                       const double* __restrict__ Hb, bool with_d, int nk, int nB, int nX,
+                                       int qs_x, int qs_k, d4 (&hacc)[4][NT][NT], d4 (&gacc)[NT][NT], int w,
+                                       int q, int g) {
+  const int nsk = (nk + 3) >> 2;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int be = w + 4 * j;
+    const double* Qb = Q + be * K1;
+    for (int s = 0; s < nsk; ++s) {
+      const int k = 4 * s + g;
+      const bool kok = k < nk;
+      double qv[NT], dv[NT], hv[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int x = 16 * u + q, b = 16 * u + q;
+        qv[u] = (kok && x < nX) ? Qb[x * qs_x + k * qs_k] : 0.0;
+        dv[u] = (kok && b < nB && with_d) ? Ds[k * nB + b] : 0.0;
+        hv[u] = (kok && b < nB) ? Hb[(b * 16 + be) * nk + k] : 0.0;
+      }
+#pragma unroll
+      for (int ib = 0; ib < NT; ++ib)
+#pragma unroll
+        for (int ix = 0; ix < NT; ++ix) {
+          // Hbar: A[m = b][k] = Ds[k][b], B[k][n = x] = Q[beta][x, k]
+          hacc[j][ib][ix] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[ib], qv[ix], hacc[j][ib][ix], 0, 0, 0);
+          // G: A[m = x][k] = Q[beta][x, k], B[k][n = b] = H[b][beta][k]
+          gacc[ix][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(qv[ix], hv[ib], gacc[ix][ib], 0, 0, 0);
+        }
+    }
+  }
+}
+
+// NT: 16-wide tiles for the b and x indices; the launch for NT takes the
+// slots with 16 (NT - 1) < max(nB, nX) <= 16 NT.  HS: the H slice is staged
+// in LDS (else read from global memory).  LDS: Q [16][K1] (or the four
+// waves' G partials at the end) in qsize doubles, Ds [nk][nB] in dsize, Hs
+// [nB][16][nk].
+template <int NT, bool HS>
+__global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ Hbar, double* __restrict__ G12,
+                                                   int qsize, int dsize) {
+  extern __shared__ double lds[];
+  double* Q = lds;
+  double* Ds = lds + qsize;
+  double* Hs = Ds + dsize;
   const int s = blockIdx.x;
   if (!d.need[s]) return;
   const int N = d.N;
   const int64_t nt = d.ntot;
   const int B = d.slotB[s], X = d.slotX[s];
   const int mB = d.nabf[B], nB = d.nao[B], nX = d.nao[X];
+  const int nbx = max(nB, nX);
+  if (nbx > 16 * NT || nbx <= 16 * (NT - 1)) return;   // the other launch's slot
   const int ldv = (mB + 15) & ~15, nT = ldv >> 4;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
-  const int nHb = 16 * nB * nX, nG = nX * nB;
-  double gacc[kGPer];
+  d4 gacc[NT][NT];
 #pragma unroll
-  for (int k = 0; k < kGPer; ++k) gacc[k] = 0.0;
-  // the V pair (X,B), whose C partners F give the second kind of term
+  for (int ix = 0; ix < NT; ++ix)
+#pragma unroll
+    for (int ib = 0; ib < NT; ++ib) gacc[ix][ib] = d4{0, 0, 0, 0};
+  // the V pair (X,B), whose C partners F give the second kind of triple
   const int vpX = find_partner(d.vpB, d.vpRow[X], d.vpRow[X + 1], B);
   const bool kindB = vpX >= 0 && (d.aliveV[vpX] & 1);
+  const int nA0 = d.cpRow[X + 1] - d.cpRow[X];
   for (int t = 0; t < nT; ++t) {
-    double hb[kHbPer];
+    d4 hacc[4][NT][NT];
 #pragma unroll
-    for (int k = 0; k < kHbPer; ++k) hb[k] = 0.0;
-    // first kind: triples (A, X, B), X a C partner of A
-    for (int i = d.cpRow[X]; i < d.cpRow[X + 1]; ++i) {
-      const int A = d.cpF[i];
-      const int cpA = find_partner(d.cpF, d.cpRow[A], d.cpRow[A + 1], X);
-      if (cpA < 0 || !(d.aliveC[cpA] & 1)) continue;
-      const int vpA = find_partner(d.vpB, d.vpRow[A], d.vpRow[A + 1], B);
-      if (vpA < 0 || !(d.aliveV[vpA] & 1)) continue;
-      const int nA = d.nao[A], K1 = nA * nX;
-      q_tile(d.Vf + d.vfOff[vpA], ldv, d.Cf + d.cfOff[cpA], d.nabf[A], K1, t, Q, w, q, g);
-      __syncthreads();
-      if (d.keepD[(int64_t)A * N + B]) {
-        // Hbar[b][beta][x] -= sum_a D(A,B)[a][b] Q[beta][a nX + x]
-        const double* Dab = d.D + d.ao[A] * nt + d.ao[B];
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int k = 0; k < kHbPer; ++k) {
-          const int e = tid + kHxNT * k;
-          if (e < nHb) {
-            const int x = e % nX, r = e / nX, be = r & 15, b = r >> 4;
-            double acc = 0.0;
-            for (int a = 0; a < nA; ++a) acc += Dab[(int64_t)a * nt + b] * Q[be * K1 + a * nX + x];
-            hb[k] -= acc;
-          }
-        }
-      }
-      // G2(X,B)[x][b] -= sum_{beta,a} Q[beta][a nX + x] H(B,A)[b][beta][a]
-      const int sBA = d.hSlotMap[(int64_t)B * N + A];
-      const double* Hba = d.H + d.hOff[sBA] + (int64_t)t * nB * 16 * nA;
+      for (int ib = 0; ib < NT; ++ib)
 #pragma unroll
-      for (int k = 0; k < kGPer; ++k) {
-        const int e = tid + kHxNT * k;
-        if (e < nG) {
-          const int x = e / nB, b = e % nB;
-          double acc = 0.0;
-          for (int be = 0; be < 16; ++be) {
-            const double* h = Hba + (b * 16 + be) * nA;
-            const double* qq = Q + be * K1 + x;
-            for (int a = 0; a < nA; ++a) acc += qq[a * nX] * h[a];
-          }
-          gacc[k] -= acc;
-        }
-      }
-      __syncthreads();
-    }
-    // second kind: triples (X, F, B) over the C partners F of X
-    if (kindB) {
-      for (int i = d.cpRow[X]; i < d.cpRow[X + 1]; ++i) {
+        for (int ix = 0; ix < NT; ++ix) hacc[j][ib][ix] = d4{0, 0, 0, 0};
+    // triples: first kind (A, X, B) for i < nA0, X a C partner of A; second
+    // kind (X, F, B) for i >= nA0 over the C partners F of X
+    for (int it = 0; it < nA0 + (kindB ? nA0 : 0); ++it) {
+      const bool first = it < nA0;
+      const int i = d.cpRow[X] + (first ? it : it - nA0);
+      int cp, vp, P, nk;
+      if (first) {
+        P = d.cpF[i];   // the atom A
+        cp = find_partner(d.cpF, d.cpRow[P], d.cpRow[P + 1], X);
+        if (cp < 0 || !(d.aliveC[cp] & 1)) continue;
+        vp = find_partner(d.vpB, d.vpRow[P], d.vpRow[P + 1], B);
+        if (vp < 0 || !(d.aliveV[vp] & 1)) continue;
+      } else {
         if (!(d.aliveC[i] & 1)) continue;
-        const int F = d.cpF[i], nF = d.nao[F], K1 = nX * nF;
-        q_tile(d.Vf + d.vfOff[vpX], ldv, d.Cf + d.cfOff[i], d.nabf[X], K1, t, Q, w, q, g);
-        __syncthreads();
-        if (d.keepD[(int64_t)F * N + B]) {
-          // Hbar[b][beta][x] -= sum_f Q[beta][x nF + f] D(F,B)[f][b]
-          const double* Dfb = d.D + d.ao[F] * nt + d.ao[B];
-#pragma unroll
-          for (int k = 0; k < kHbPer; ++k) {
-            const int e = tid + kHxNT * k;
-            if (e < nHb) {
-              const int x = e % nX, r = e / nX, be = r & 15, b = r >> 4;
-              double acc = 0.0;
-              const double* qq = Q + be * K1 + x * nF;
-              for (int f = 0; f < nF; ++f) acc += qq[f] * Dfb[(int64_t)f * nt + b];
-              hb[k] -= acc;
-            }
-          }
-        }
-        // G1(X,B)[x][b] -= sum_{beta,f} Q[beta][x nF + f] H(B,F)[b][beta][f]
-        const int sBF = d.hSlotMap[(int64_t)B * N + F];
-        const double* Hbf = d.H + d.hOff[sBF] + (int64_t)t * nB * 16 * nF;
-#pragma unroll
-        for (int k = 0; k < kGPer; ++k) {
-          const int e = tid + kHxNT * k;
-          if (e < nG) {
-            const int x = e / nB, b = e % nB;
-            double acc = 0.0;
-            for (int be = 0; be < 16; ++be) {
-              const double* h = Hbf + (b * 16 + be) * nF;
-              const double* qq = Q + be * K1 + x * nF;
-              for (int f = 0; f < nF; ++f) acc += qq[f] * h[f];
-            }
-            gacc[k] -= acc;
-          }
-        }
-        __syncthreads();
+        P = d.cpF[i];   // the atom F
+        cp = i;
+        vp = vpX;
       }
+      nk = d.nao[P];
+      const int K1 = nk * nX;
+      // D(A,B) or D(F,B) [nk][nB] and H(B,A) or H(B,F) [b][beta][k] of tile t
+      const bool with_d = d.keepD[(int64_t)P * N + B] != 0;
+      const double* Dsrc = d.D + d.ao[P] * nt + d.ao[B];
+      if (with_d)
+        for (int e = tid; e < nk * nB; e += kHxNT) Ds[e] = Dsrc[(int64_t)(e / nB) * nt + e % nB];
+      const double* Hsrc = d.H + d.hOff[d.hSlotMap[(int64_t)B * N + P]] + (int64_t)t * nB * 16 * nk;
+      if constexpr (HS)
+        for (int e = tid; e < nB * 16 * nk; e += kHxNT) Hs[e] = Hsrc[e];
+      q_tile(d.Vf + d.vfOff[vp], ldv, d.Cf + d.cfOff[cp], d.nabf[first ? P : X], K1, t, Q, w, q, g);
+      __syncthreads();
+      // Q index of (x, k): k nX + x (first kind), x nF + k (second)
+      contract_triple<NT>(Q, K1, Ds, HS ? Hs : Hsrc, with_d, nk, nB, nX, first ? 1 : nk, first ? nX : 1, hacc,
+                          gacc, w, q, g);
+      __syncthreads();
     }
     // the beta tile of Hbar(B,X), laid out as the H slot: [b][beta][x]
-    double* hout = Hbar + d.hOff[s] + (int64_t)t * nHb;
+    double* hout = Hbar + d.hOff[s] + (int64_t)t * 16 * nB * nX;
 #pragma unroll
-    for (int k = 0; k < kHbPer; ++k) {
-      const int e = tid + kHxNT * k;
-      if (e < nHb) hout[e] = hb[k];
+    for (int j = 0; j < 4; ++j) {
+      const int be = w + 4 * j;
+#pragma unroll
+      for (int ib = 0; ib < NT; ++ib)
+#pragma unroll
+        for (int ix = 0; ix < NT; ++ix)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int b = 16 * ib + g + 4 * r, x = 16 * ix + q;
+            if (b < nB && x < nX) hout[(b * 16 + be) * nX + x] = -hacc[j][ib][ix][r];
+          }
     }
   }
-  // the D block (X,B) of G1 + G2 (this workgroup is its only writer)
+  // the D block (X,B) of G1 + G2: the four waves' partials (each over its
+  // beta rows) added in wave order; this workgroup is the block's only writer
 #pragma unroll
-  for (int k = 0; k < kGPer; ++k) {
-    const int e = tid + kHxNT * k;
-    if (e < nG) {
-      const int x = e / nB, b = e % nB;
-      G12[(d.ao[X] + x) * nt + d.ao[B] + b] = gacc[k];
-    }
+  for (int ix = 0; ix < NT; ++ix)
+#pragma unroll
+    for (int ib = 0; ib < NT; ++ib)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Q[((w * NT + ix) * NT + ib) * 256 + r * 64 + lane] = gacc[ix][ib][r];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int ix = 0; ix < NT; ++ix)
+#pragma unroll
+      for (int ib = 0; ib < NT; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double v = 0.0;
+          for (int ww = 0; ww < 4; ++ww) v += Q[((ww * NT + ix) * NT + ib) * 256 + r * 64 + lane];
+          const int x = 16 * ix + g + 4 * r, b = 16 * ib + q;
+          if (x < nX && b < nB) G12[(d.ao[X] + x) * nt + d.ao[B] + b] = -v;
+        }
   }
 }
 
 // G3(G,X)[g][x] = sum_B sum_{beta,b} Cf(B,G)[beta][b][g] Hbar(B,X)[b][beta][x]
-// over the C pairs (B,G) with a value-list block and the needed slots (B,X).
+// over the C pairs (B,G) with a value-list block and the needed slots (B,X),
+// on the matrix cores: tiles (g, x) of 16 x 16, the contraction over
+// (beta, b) in k-steps of four b; wave w takes beta = w, w + 4, ...; the
+// four partial tiles are added in wave order.  NT as for k_hx_slot, on
+// max(nG, nX); every D block (G,X) is written by one workgroup (zeros when
+// nothing reaches it).
+template <int NT>
 __global__ void __launch_bounds__(kHxNT) k_hx_g3(Dev d, const double* __restrict__ Hbar, double* __restrict__ G3) {
+  __shared__ double red[4 * NT * NT * 256];
   const int N = d.N;
   const int G = blockIdx.x / N, X = blockIdx.x % N;
   const int64_t nt = d.ntot;
-  const int nG = d.nao[G], nX = d.nao[X], n = nG * nX;
-  const int tid = threadIdx.x;
-  double acc[kGPer];
+  const int nG = d.nao[G], nX = d.nao[X];
+  const int ngx = max(nG, nX);
+  if (ngx > 16 * NT || ngx <= 16 * (NT - 1)) return;   // the other launch's block
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  d4 acc[NT][NT];
 #pragma unroll
-  for (int k = 0; k < kGPer; ++k) acc[k] = 0.0;
+  for (int ig = 0; ig < NT; ++ig)
+#pragma unroll
+    for (int ix = 0; ix < NT; ++ix) acc[ig][ix] = d4{0, 0, 0, 0};
   for (int i = d.cpRow[G]; i < d.cpRow[G + 1]; ++i) {
     const int B = d.cpF[i];
     const int sl = d.hSlotMap[(int64_t)B * N + X];
     if (sl < 0 || !d.need[sl]) continue;
     const int cp = find_partner(d.cpF, d.cpRow[B], d.cpRow[B + 1], G);
     if (cp < 0 || !(d.aliveC[cp] & 1)) continue;
-    const int mB = d.nabf[B], nB = d.nao[B];
+    const int mB = d.nabf[B], nB = d.nao[B], nsb = (nB + 3) >> 2;
     const double* Cf = d.Cf + d.cfOff[cp];   // [beta][b][g]
     const double* Hb = Hbar + d.hOff[sl];    // [beta / 16][b][beta % 16][x]
+    for (int be = w; be < mB; be += 4) {
+      const double* cr = Cf + (int64_t)be * nB * nG;
+      const double* hr = Hb + ((int64_t)(be >> 4) * nB * 16 + (be & 15)) * nX;
+#pragma unroll 2
+      for (int sb = 0; sb < nsb; ++sb) {
+        const int b = 4 * sb + g;
+        const bool ok = b < nB;
+        double av[NT], hv[NT];
 #pragma unroll
-    for (int k = 0; k < kGPer; ++k) {
-      const int e = tid + kHxNT * k;
-      if (e < n) {
-        const int gg = e / nX, x = e % nX;
-        double s = 0.0;
-        for (int be = 0; be < mB; ++be) {
-          const double* c = Cf + (int64_t)be * nB * nG + gg;
-          const double* h = Hb + ((int64_t)(be >> 4) * nB * 16 + (be & 15)) * nX + x;
-          for (int b = 0; b < nB; ++b) s += c[b * nG] * h[b * 16 * nX];
+        for (int u = 0; u < NT; ++u) {
+          const int c = 16 * u + q;
+          av[u] = (ok && c < nG) ? cr[b * nG + c] : 0.0;          // A[m = g][k = b]
+          hv[u] = (ok && c < nX) ? hr[b * 16 * nX + c] : 0.0;     // B[k = b][n = x]
         }
-        acc[k] += s;
+#pragma unroll
+        for (int ig = 0; ig < NT; ++ig)
+#pragma unroll
+          for (int ix = 0; ix < NT; ++ix)
+            acc[ig][ix] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ig], hv[ix], acc[ig][ix], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < kGPer; ++k) {
-    const int e = tid + kHxNT * k;
-    if (e < n) G3[(d.ao[G] + e / nX) * nt + d.ao[X] + e % nX] = acc[k];
+  for (int ig = 0; ig < NT; ++ig)
+#pragma unroll
+    for (int ix = 0; ix < NT; ++ix)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[((w * NT + ig) * NT + ix) * 256 + r * 64 + lane] = acc[ig][ix][r];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int ig = 0; ig < NT; ++ig)
+#pragma unroll
+      for (int ix = 0; ix < NT; ++ix)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double v = 0.0;
+          for (int ww = 0; ww < 4; ++ww) v += red[((ww * NT + ig) * NT + ix) * 256 + r * 64 + lane];
+          const int gg = 16 * ig + g + 4 * r, x = 16 * ix + q;
+          if (gg < nG && x < nX) G3[(d.ao[G] + gg) * nt + d.ao[X] + x] = v;
+        }
   }
 }
 
@@ -333,22 +407,34 @@ void launch_hx(const Dev& d, const HxBufs& b, hipStream_t s, hipEvent_t* ev) {
   const int64_t nt = d.ntot;
   hipLaunchKernelGGL(k_fill_f64, dim3(2048), dim3(256), 0, s, b.G12, nt * nt);
   if (d.nSlot > 0) {
-    // the Q tile in LDS: 16 rows of at most kMaxNao^2 doubles (128 KiB)
-    const size_t lds = sizeof(double) * 16 * b.kmax;
-    auto go = [&](auto kern) {
-      if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipLaunchKernelGGL(kern, dim3((unsigned)d.nSlot), dim3(kHxNT), lds, s, d, b.Hbar, b.G12);
+    const int nmax = b.nmax;
+    // per launch NT: Q tile rows (or the G partials of four waves), the D
+    // block and the H slice, sized for b, x < 16 NT and k <= nmax; the H
+    // slice is staged when two workgroups still fit a CU's LDS
+    auto run = [&](auto kern_h, auto kern_g, int NT) {
+      const int bx = std::min(16 * NT, nmax);
+      const int qsize = std::max(16 * nmax * bx, 4 * NT * NT * 256);
+      const int dsize = nmax * bx;
+      const size_t base = sizeof(double) * ((size_t)qsize + dsize);
+      const size_t with_h = base + sizeof(double) * 16 * (size_t)bx * nmax;
+      const bool hs = with_h <= 80 * 1024;
+      const size_t lds = hs ? with_h : base;
+      const void* k = hs ? (const void*)kern_h : (const void*)kern_g;
+      if (lds > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (hs)
+        hipLaunchKernelGGL(kern_h, dim3((unsigned)d.nSlot), dim3(kHxNT), lds, s, d, b.Hbar, b.G12, qsize, dsize);
+      else
+        hipLaunchKernelGGL(kern_g, dim3((unsigned)d.nSlot), dim3(kHxNT), lds, s, d, b.Hbar, b.G12, qsize, dsize);
     };
-    if (b.nmax <= 16)
-      go(k_hx_slot<16>);
-    else if (b.nmax <= 24)
-      go(k_hx_slot<24>);
-    else
-      go(k_hx_slot<kMaxNao>);
+    run(k_hx_slot<1, true>, k_hx_slot<1, false>, 1);
+    if (nmax > 16) run(k_hx_slot<2, true>, k_hx_slot<2, false>, 2);
   }
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_hx_g3, dim3((unsigned)((int64_t)d.N * d.N)), dim3(kHxNT), 0, s, d, (const double*)b.Hbar,
+  hipLaunchKernelGGL(k_hx_g3<1>, dim3((unsigned)((int64_t)d.N * d.N)), dim3(kHxNT), 0, s, d, (const double*)b.Hbar,
                      b.G3);
+  if (b.nmax > 16)
+    hipLaunchKernelGGL(k_hx_g3<2>, dim3((unsigned)((int64_t)d.N * d.N)), dim3(kHxNT), 0, s, d,
+                       (const double*)b.Hbar, b.G3);
   if (ev) (void)hipEventRecord(ev[1], s);
   const int64_t nf = hx_tiles(nt);
   hipLaunchKernelGGL(k_hx_final, dim3((unsigned)nf), dim3(kHxNT), 0, s, d, (const double*)b.G12,
