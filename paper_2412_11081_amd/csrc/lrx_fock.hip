@@ -64,25 +64,37 @@ __device__ inline int find_partner(const int* __restrict__ list, int r0, int r1,
 // f64 16x16x4 MFMA: lane (q, g) gives A[m = q][k = g] = Vf[4 s + g][16 t + q]
 // and B[k = g][n = q] = Cf[4 s + g][16 j + q]; result i is row g + 4 i.  A
 // wave keeps three column tiles (j, j + 4, j + 8) in flight; they share the
-// Vf operand.
+// Vf operand.  Loads are unconditional from clamped addresses (no branches
+// in the loop): only the A operand of a k past mA is set to zero; columns
+// past K1 are computed from clamped data and not stored.
 __device__ inline void q_tile(const double* __restrict__ Vf, int ldv, const double* __restrict__ Cf, int mA, int K1,
                               int t, double* Q, int w, int q, int g) {
   const int nj = (K1 + 15) >> 4, ns = (mA + 3) >> 2;
+  const double* vq = Vf + 16 * t + q;
   for (int j0 = w; j0 < nj; j0 += 12) {
     const int c0 = 16 * j0 + q, c1 = c0 + 64, c2 = c0 + 128;
+    const int d0 = min(c0, K1 - 1), d1 = min(c1, K1 - 1), d2 = min(c2, K1 - 1);
     d4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0}, a2 = {0, 0, 0, 0};
-#pragma unroll 4
-    for (int s = 0; s < ns; ++s) {
-      const int al = 4 * s + g;
-      const bool ok = al < mA;
-      const double* cr = Cf + (int64_t)al * K1;
-      const double a = ok ? Vf[(int64_t)al * ldv + 16 * t + q] : 0.0;
-      const double b0 = (ok && c0 < K1) ? cr[c0] : 0.0;
-      const double b1 = (ok && c1 < K1) ? cr[c1] : 0.0;
-      const double b2 = (ok && c2 < K1) ? cr[c2] : 0.0;
-      a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, a0, 0, 0, 0);
-      a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, a1, 0, 0, 0);
-      a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b2, a2, 0, 0, 0);
+    // four k-steps per pass, their 16 loads issued before the products (a
+    // step past ns has al >= mA: zero A operand)
+    for (int s0 = 0; s0 < ns; s0 += 4) {
+      double a[4], b0[4], b1[4], b2[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int al = 4 * (s0 + u) + g, ac = min(al, mA - 1);
+        const double* cr = Cf + (int64_t)ac * K1;
+        const double av = vq[(int64_t)ac * ldv];
+        a[u] = al < mA ? av : 0.0;
+        b0[u] = cr[d0];
+        b1[u] = cr[d1];
+        b2[u] = cr[d2];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b0[u], a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b1[u], a1, 0, 0, 0);
+        a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b2[u], a2, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -100,27 +112,39 @@ __device__ inline void q_tile(const double* __restrict__ Vf, int ldv, const doub
 //   Hbar tile of beta:  acc_h[b][x] += sum_k Ds[k][b] Q[beta][qi(x, k)]
 //   G tile:             acc_g[x][b] += sum_{beta, k} Q[beta][qi(x, k)] Hb[b][beta][k]
 // qi(x, k) = k nX + x for the first kind of triple (k = a), x nF + k for the
-// second (k = f); a wave takes beta = w + 4 j, j < 4.
+// second (k = f); a wave takes beta = w + 4 j, j < 4.  As in q_tile, loads
+// come from clamped addresses; the Ds and Hb operands of a k past nk (and
+// Ds when the D pair is screened) are zero, rows and columns past nB, nX
+// are not stored.
 template <int NT>
 __device__ inline void contract_triple(const double* __restrict__ Q, int K1, const double* __restrict__ Ds,
                                        const double* __restrict__ Hb, bool with_d, int nk, int nB, int nX,
                                        int qs_x, int qs_k, d4 (&hacc)[4][NT][NT], d4 (&gacc)[NT][NT], int w,
                                        int q, int g) {
   const int nsk = (nk + 3) >> 2;
+  int xo[NT], bo[NT], hb_[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    xo[u] = min(16 * u + q, nX - 1) * qs_x;
+    bo[u] = min(16 * u + q, nB - 1);
+    hb_[u] = bo[u] * 16 * nk;
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int be = w + 4 * j;
     const double* Qb = Q + be * K1;
+    const double* Hbe = Hb + be * nk;
     for (int s = 0; s < nsk; ++s) {
-      const int k = 4 * s + g;
-      const bool kok = k < nk;
+      const int k = 4 * s + g, kc = min(k, nk - 1);
+      const bool kd = k < nk && with_d, kh = k < nk;
       double qv[NT], dv[NT], hv[NT];
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
-        const int x = 16 * u + q, b = 16 * u + q;
-        qv[u] = (kok && x < nX) ? Qb[x * qs_x + k * qs_k] : 0.0;
-        dv[u] = (kok && b < nB && with_d) ? Ds[k * nB + b] : 0.0;
-        hv[u] = (kok && b < nB) ? Hb[(b * 16 + be) * nk + k] : 0.0;
+        qv[u] = Qb[xo[u] + kc * qs_k];
+        const double dd = Ds[kc * nB + bo[u]];
+        const double hh = Hbe[hb_[u] + kc];
+        dv[u] = kd ? dd : 0.0;
+        hv[u] = kh ? hh : 0.0;
       }
 #pragma unroll
       for (int ib = 0; ib < NT; ++ib)
