@@ -264,6 +264,67 @@ class Structure:
 
 
 # ----------------------------------------------------------------------------
+# three-centre integrals (P|phi phi) for the preparation of C
+# ----------------------------------------------------------------------------
+def three_center(st: Structure, device: str = "cpu", seed_shift: int = 104723):
+    """Synthetic (P|phi_A phi_F) for every C key (A,F,R): the ABFs of A then
+    those of F against the AO pair (A a, F f), [mA + mF][nA][nF], or
+    [mA][nA][nA] for the on-site key (A,A,0), with d/dr as [3][block] (r the
+    key's displacement).  Base tensors per species pair times the C envelope;
+    the rows on F of (A,F,R) are the rows on F of (F,A,-R) with the AO pair
+    swapped, as for real integrals, and on-site blocks are symmetric in the
+    AO pair.  Returns a dict like the C and V blocks of materialize()."""
+    import torch
+
+    rng = np.random.default_rng(st.seed + seed_shift)
+    dims = st.species_dims
+    used = sorted(set(int(x) for x in st.species))
+    u = {}
+    for s_ in used:
+        n, m = dims[s_]
+        t = rng.normal(0.0, 0.1, size=(m, n, n))
+        u[("on", s_)] = 0.5 * (t + t.transpose(0, 2, 1))
+    for s_ in used:
+        for s2 in used:
+            n, m = dims[s_]
+            u[(s_, s2)] = rng.normal(0.0, 0.1, size=(m, n, dims[s2][0]))
+    first, second, R = st.keysC
+    first, second, R = np.asarray(first), np.asarray(second), np.asarray(R)
+    d = displacement(st.tau, st.lat, first, second, R)
+    r = np.sqrt(np.einsum("ij,ij->i", d, d))
+    f, fp = env_c(r, st.rc)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        unit = np.where(r[:, None] > 0, d / np.where(r > 0, r, 1.0)[:, None], 0.0)
+    sp = np.asarray(st.species)
+    nb = first.shape[0]
+    rows = np.zeros(nb, np.int64)
+    sizes = np.zeros(nb, np.int64)
+    onsite = (first == second) & np.all(R == 0, axis=1)
+    for b in range(nb):
+        A, F = int(first[b]), int(second[b])
+        rows[b] = st.nabf[A] if onsite[b] else st.nabf[A] + st.nabf[F]
+        sizes[b] = rows[b] * st.nao[A] * st.nao[F]
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    total = int(sizes.sum())
+    val = np.empty(total)
+    dval = np.empty(3 * total)
+    for b in range(nb):
+        A, F = int(first[b]), int(second[b])
+        sA, sF = int(sp[A]), int(sp[F])
+        if onsite[b]:
+            base = u[("on", sA)]
+        else:
+            base = np.concatenate([u[(sA, sF)], u[(sF, sA)].transpose(0, 2, 1)], axis=0)
+        flat = base.reshape(-1)
+        o, n = int(off[b]), int(sizes[b])
+        val[o:o + n] = f[b] * flat
+        for x in range(3):
+            dval[3 * o + x * n:3 * o + (x + 1) * n] = (fp[b] * unit[b, x]) * flat
+    return dict(first=first, second=second, R=R, off=off, rows=rows, onsite=onsite,
+                val=torch.from_numpy(val).to(device), dval=torch.from_numpy(dval).to(device))
+
+
+# ----------------------------------------------------------------------------
 # density matrices
 # ----------------------------------------------------------------------------
 def make_density(n: int, kind: str, rng: np.random.Generator) -> np.ndarray:
