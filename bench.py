@@ -165,6 +165,31 @@ def hamiltonian_benchmark(ctx, st, steps, E_forces):
                             "frac": slot_tf / 78.6}}
 
 
+def prepare_benchmark(st, mats, reps=3):
+    """lrx_prepare_c (Eq. C_VA and the gradient of C) for every C key of the
+    workload from device-resident V and three-centre integrals: wall time of
+    the call (its workspace allocation and key lookup included), algorithmic
+    FLOPs, and the FP64 vector rate they imply."""
+    import numpy as np
+    import torch
+
+    from paper_2412_11081_amd import lrx, synth
+
+    T = synth.three_center(st, "cuda")
+    torch.cuda.synchronize()
+    wall = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        C, flop = lrx.prepare_c(st.nao, st.nabf, mats["V"], T)
+        wall.append(time.perf_counter() - t0)
+    ms = 1e3 * float(np.median(wall))
+    tf = flop / (ms * 1e-3) / 1e12
+    del T, C
+    return {"what": "lrx_prepare_c: C and dC of every C key from V and (P|phi phi) on the device",
+            "keys": int(len(st.keysC[0])), "ms_per_call": ms, "flop": flop, "tflops_alg": tf,
+            "roofline": {"bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6}}
+
+
 def _build_request(i):
     from paper_2412_11081_amd import synth
 
@@ -477,6 +502,8 @@ def main():
     out["hamiltonian"] = hamiltonian_benchmark(ctx, st, max(3, min(args.steps, 5)), E_forces)
     print(f"# hamiltonian: {out['hamiltonian']['ms_per_call']:.1f} ms per call", file=sys.stderr, flush=True)
     ctx.close()
+    out["prepare_c"] = prepare_benchmark(st, mats)
+    print(f"# prepare_c: {out['prepare_c']['ms_per_call']:.1f} ms per call", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         total_kept = stats["kept_v_blocks"]
         spent, nsample, picked, threads = cpu_baseline(st, mats)

@@ -299,6 +299,32 @@ int lrx_hamiltonian(lrx_ctx* ctx, const lrx_options* opts, double* E, double* Hx
  * the H build. */
 int lrx_hamiltonian_info(lrx_ctx* ctx, float* ms, double* flop);
 
+/* Preparation of C and dC (Eq. C_VA; the gradient after Eq. V_inverse).
+ * For every key (A,F,R) of T -- the C keys, A carrying the ABF index of the
+ * result -- the LRI coefficients of the AO pair (A a, F f) on the ABFs of A
+ * and F solve
+ *   M [C^A; C^F] = T,  M = [[V(A,A,0), V(A,F,R)], [V(A,F,R)^T, V(F,F,0)]],
+ * and the key's C block is C^A; the on-site key (A,A,0) uses the ABFs of A
+ * alone, M = V(A,A,0).  Derivatives with respect to the key's displacement:
+ *   M dC = -[[0, dV(A,F,R)], [dV(A,F,R)^T, 0]] [C^A; C^F] + dT,
+ * and dC = 0 for the on-site key (its blocks do not move with the atom).
+ * T: one block per key, the three-centre integrals (P|phi_A phi_F) with the
+ * ABFs of A then those of F, [mA + mF][nA][nF] (on-site [mA][nA][nA]), and
+ * d/dr as [3][block] at 3 off, as lrx_blocks.  V: the Coulomb blocks (as for
+ * lrx_set_tensors), holding V(A,A,0), V(F,F,0) and V(A,F,R) for every key.
+ * Output: Cval [sum over keys of mA nA nF], the keys' blocks in key order,
+ * each [mA][nA][nF] (C^{A alpha}_{A a, F f}); Cdval [3][block] per block at
+ * 3 x its offset -- the layout lrx_set_tensors takes.  on_device != 0: the
+ * values of T and V and both outputs are device pointers of `device` (the
+ * keys stay on the host); else host arrays.  *flop (optional): algorithmic
+ * FLOPs (n^3 / 3 for the factorisation, 2 n^2 per right-hand side column,
+ * 12 mA mF nA nF for the products with dV).  Returns LRX_EINVAL for bad
+ * arguments, a missing V block or an M that is not positive definite.  Uses
+ * device memory of its own (a workspace of up to 512 x n_max (n_max + 4
+ * nA nF max) doubles) for the duration of the call. */
+int lrx_prepare_c(int32_t device, int32_t natom, const int32_t* nao, const int32_t* nabf, const lrx_blocks* V,
+                  const lrx_blocks* T, int32_t on_device, double* Cval, double* Cdval, double* flop);
+
 /* Size of the fixed device scratch of lrx_evaluate_noalloc (bytes per GPU). */
 #define LRX_SCRATCH_BYTES (128ull << 20)
 

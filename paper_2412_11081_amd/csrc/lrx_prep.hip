@@ -1,0 +1,281 @@
+// Preparation of the C tensor and its derivative from V and the three-centre
+// integrals (Eq. C_VA; the gradient after Eq. V_inverse).  For a C key
+// (A,F,R) the LRI coefficients of the AO pair (A a, F f) on the ABFs of both
+// atoms solve
+//
+//   M [C^A; C^F] = [(P_A|phi_A phi_F); (P_F|phi_A phi_F)],
+//   M = [[V(A,A,0), V(A,F,R)], [V(A,F,R)^T, V(F,F,0)]]   (symmetric positive definite),
+//
+// and the key's C block is C^A (the first mA rows).  The on-site key (A,A,0)
+// uses the ABFs of A alone.  With dV the derivative of V(A,F,R) and dP that
+// of the integrals (both with respect to the key's displacement r),
+//
+//   M dC = -[[0, dV], [dV^T, 0]] [C^A; C^F] + dP,
+//
+// from the derivative of M^-1 (Eq. V_inverse); on-site blocks do not move
+// with their atom, so their dC is zero.
+//
+// One workgroup per key (a grid of workgroups takes the keys in turn): M is
+// assembled in the workgroup's slice of a device workspace and factorised in
+// place, M = L L^T (left-looking, one thread per row of the current column);
+// the right-hand sides -- the integrals, then the three derivative columns --
+// are solved with one thread per column (forward and back substitution; the
+// column's elements are read by consecutive threads at once, L by all
+// threads at once).  FP64 throughout; no atomics but the error flag.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lrx.h"
+
+namespace {
+
+constexpr int kPT = 256;
+
+struct PrepItem {
+  int A, F, onsite;
+  int64_t t;      // element offset of the integrals (derivatives at 3 t)
+  int64_t vAA, vFF, vAF;   // element offsets of V(A,A,0), V(F,F,0), V(A,F,R)
+  int64_t c;      // element offset of the output C block (derivatives at 3 c)
+};
+
+// L L^T = M for the n x n matrix at M (row-major, in place, lower triangle);
+// returns false when a pivot is not positive
+__device__ bool cholesky(double* M, int n) {
+  const int tid = threadIdx.x;
+  bool ok = true;
+  for (int j = 0; j < n; ++j) {
+    const double* rj = M + (int64_t)j * n;
+    for (int i = j + tid; i < n; i += kPT) {
+      double* ri = M + (int64_t)i * n;
+      double s0 = ri[j], s1 = 0, s2 = 0, s3 = 0;
+      int k = 0;
+      for (; k + 4 <= j; k += 4) {
+        s0 -= ri[k] * rj[k];
+        s1 -= ri[k + 1] * rj[k + 1];
+        s2 -= ri[k + 2] * rj[k + 2];
+        s3 -= ri[k + 3] * rj[k + 3];
+      }
+      for (; k < j; ++k) s0 -= ri[k] * rj[k];
+      ri[j] = (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
+    const double djj = rj[j];
+    ok = ok && djj > 0.0;
+    const double d = djj > 0.0 ? sqrt(djj) : 1.0;
+    __syncthreads();
+    for (int i = j + 1 + tid; i < n; i += kPT) M[(int64_t)i * n + j] /= d;
+    if (tid == 0) M[(int64_t)j * n + j] = d;
+    __syncthreads();
+  }
+  return ok;
+}
+
+// solve L L^T x = b in place for the columns [c0, c1) of X (row stride ld)
+__device__ void solve_cols(const double* L, int n, double* X, int ld, int c0, int c1) {
+  for (int c = c0 + threadIdx.x; c < c1; c += kPT) {
+    double* x = X + c;
+    for (int i = 0; i < n; ++i) {
+      const double* li = L + (int64_t)i * n;
+      double s0 = x[(int64_t)i * ld], s1 = 0, s2 = 0, s3 = 0;
+      int k = 0;
+      for (; k + 4 <= i; k += 4) {
+        s0 -= li[k] * x[(int64_t)k * ld];
+        s1 -= li[k + 1] * x[(int64_t)(k + 1) * ld];
+        s2 -= li[k + 2] * x[(int64_t)(k + 2) * ld];
+        s3 -= li[k + 3] * x[(int64_t)(k + 3) * ld];
+      }
+      for (; k < i; ++k) s0 -= li[k] * x[(int64_t)k * ld];
+      x[(int64_t)i * ld] = ((s0 + s1) + (s2 + s3)) / li[i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s0 = x[(int64_t)i * ld], s1 = 0, s2 = 0, s3 = 0;
+      int k = i + 1;
+      for (; k + 4 <= n; k += 4) {
+        s0 -= L[(int64_t)k * n + i] * x[(int64_t)k * ld];
+        s1 -= L[(int64_t)(k + 1) * n + i] * x[(int64_t)(k + 1) * ld];
+        s2 -= L[(int64_t)(k + 2) * n + i] * x[(int64_t)(k + 2) * ld];
+        s3 -= L[(int64_t)(k + 3) * n + i] * x[(int64_t)(k + 3) * ld];
+      }
+      for (; k < n; ++k) s0 -= L[(int64_t)k * n + i] * x[(int64_t)k * ld];
+      x[(int64_t)i * ld] = ((s0 + s1) + (s2 + s3)) / L[(int64_t)i * n + i];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kPT) k_prep(const PrepItem* __restrict__ items, int nitem, const int* __restrict__ nao,
+                                              const int* __restrict__ nabf, const double* __restrict__ Tval,
+                                              const double* __restrict__ Tdval, const double* __restrict__ Vval,
+                                              const double* __restrict__ Vdval, double* __restrict__ Cval,
+                                              double* __restrict__ Cdval, double* __restrict__ ws, int64_t wsStride,
+                                              int nmax, int* __restrict__ err) {
+  double* M = ws + blockIdx.x * wsStride;
+  double* X = M + (int64_t)nmax * nmax;
+  const int tid = threadIdx.x;
+  for (int p = blockIdx.x; p < nitem; p += gridDim.x) {
+    const PrepItem it = items[p];
+    const int mA = nabf[it.A], mF = nabf[it.F], nA = nao[it.A], nF = nao[it.F];
+    const int n = it.onsite ? mA : mA + mF, K1 = nA * nF, ld = it.onsite ? K1 : 4 * K1;
+    const double* VAA = Vval + it.vAA;
+    const double* VFF = Vval + it.vFF;
+    const double* VAF = Vval + it.vAF;
+    for (int64_t e = tid; e < (int64_t)n * n; e += kPT) {
+      const int i = (int)(e / n), j = (int)(e % n);
+      double v;
+      if (i < mA)
+        v = j < mA ? VAA[i * mA + j] : VAF[i * mF + (j - mA)];
+      else
+        v = j < mA ? VAF[j * mF + (i - mA)] : VFF[(i - mA) * mF + (j - mA)];
+      M[e] = v;
+    }
+    for (int64_t e = tid; e < (int64_t)n * K1; e += kPT) X[(e / K1) * ld + e % K1] = Tval[it.t + e];
+    __syncthreads();
+    if (!cholesky(M, n) && tid == 0) atomicMax(err, 1);
+    solve_cols(M, n, X, ld, 0, K1);
+    __syncthreads();
+    if (!it.onsite) {
+      // W_x = dP_x - [[0, dV_x], [dV_x^T, 0]] C in columns K1 + x K1 + c
+      const double* dV = Vdval + 3 * it.vAF;
+      const double* dP = Tdval + 3 * it.t;
+      for (int64_t e = tid; e < (int64_t)n * 3 * K1; e += kPT) {
+        const int i = (int)(e / (3 * K1)), rem = (int)(e % (3 * K1)), x = rem / K1, c = rem % K1;
+        const double* dVx = dV + (int64_t)x * mA * mF;
+        double s = dP[(int64_t)x * n * K1 + (int64_t)i * K1 + c];
+        if (i < mA) {
+          for (int j = 0; j < mF; ++j) s -= dVx[i * mF + j] * X[(int64_t)(mA + j) * ld + c];
+        } else {
+          const int ii = i - mA;
+          for (int j = 0; j < mA; ++j) s -= dVx[j * mF + ii] * X[(int64_t)j * ld + c];
+        }
+        X[(int64_t)i * ld + K1 + rem] = s;
+      }
+      __syncthreads();
+      solve_cols(M, n, X, ld, K1, 4 * K1);
+      __syncthreads();
+    }
+    // the key's block: the rows of A
+    for (int64_t e = tid; e < (int64_t)mA * K1; e += kPT) Cval[it.c + e] = X[(e / K1) * ld + e % K1];
+    for (int64_t e = tid; e < (int64_t)3 * mA * K1; e += kPT) {
+      const int x = (int)(e / ((int64_t)mA * K1));
+      const int64_t r = e % ((int64_t)mA * K1);
+      Cdval[3 * it.c + e] = it.onsite ? 0.0 : X[(r / K1) * ld + K1 + (int64_t)x * K1 + r % K1];
+    }
+    __syncthreads();
+  }
+}
+
+struct DevMem {
+  void* p = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" int lrx_prepare_c(int32_t device, int32_t natom, const int32_t* nao, const int32_t* nabf,
+                             const lrx_blocks* V, const lrx_blocks* T, int32_t on_device, double* Cval,
+                             double* Cdval, double* flop) {
+  if (natom <= 0 || !nao || !nabf || !V || !T || !Cval || !Cdval) return LRX_EINVAL;
+  if (T->nblk < 0 || V->nblk <= 0 || !T->first || !T->second || !T->R || !T->off || !V->first || !V->second ||
+      !V->R || !V->off || !T->val || !T->dval || !V->val || !V->dval)
+    return LRX_EINVAL;
+  for (int a = 0; a < natom; ++a)
+    if (nao[a] <= 0 || nabf[a] <= 0 || nao[a] > 32 || nabf[a] > 128) return LRX_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LRX_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return LRX_EHIP;
+  // V keys -> block
+  std::map<std::tuple<int, int, int, int, int>, int64_t> vk;
+  for (int64_t i = 0; i < V->nblk; ++i) {
+    const int f = V->first[i], s = V->second[i];
+    if (f < 0 || f >= natom || s < 0 || s >= natom) return LRX_EINVAL;
+    vk[{f, s, V->R[3 * i], V->R[3 * i + 1], V->R[3 * i + 2]}] = i;
+  }
+  auto vsize = [&](int64_t i) { return (int64_t)nabf[V->first[i]] * nabf[V->second[i]]; };
+  for (int64_t i = 0; i < V->nblk; ++i)
+    if (V->off[i] < 0 || V->off[i] + vsize(i) > V->nval) return LRX_EINVAL;
+  std::vector<PrepItem> items((size_t)T->nblk);
+  int64_t ctot = 0;
+  int nmax = 1, ldmax = 1;
+  double fl = 0;
+  for (int64_t b = 0; b < T->nblk; ++b) {
+    PrepItem& it = items[(size_t)b];
+    it.A = T->first[b];
+    it.F = T->second[b];
+    if (it.A < 0 || it.A >= natom || it.F < 0 || it.F >= natom) return LRX_EINVAL;
+    const int r0 = T->R[3 * b], r1 = T->R[3 * b + 1], r2 = T->R[3 * b + 2];
+    it.onsite = it.A == it.F && r0 == 0 && r1 == 0 && r2 == 0;
+    const int mA = nabf[it.A], mF = nabf[it.F], K1 = nao[it.A] * nao[it.F];
+    const int n = it.onsite ? mA : mA + mF;
+    if (T->off[b] < 0 || T->off[b] + (int64_t)n * K1 > T->nval) return LRX_EINVAL;
+    it.t = T->off[b];
+    auto find = [&](int f, int s, int a, int c, int d, int64_t* off) {
+      auto q = vk.find({f, s, a, c, d});
+      if (q == vk.end()) return false;
+      *off = V->off[q->second];
+      return true;
+    };
+    if (!find(it.A, it.A, 0, 0, 0, &it.vAA)) return LRX_EINVAL;
+    it.vFF = it.vAF = it.vAA;
+    if (!it.onsite && (!find(it.F, it.F, 0, 0, 0, &it.vFF) || !find(it.A, it.F, r0, r1, r2, &it.vAF)))
+      return LRX_EINVAL;
+    it.c = ctot;
+    ctot += (int64_t)mA * K1;
+    nmax = std::max(nmax, n);
+    ldmax = std::max(ldmax, it.onsite ? K1 : 4 * K1);
+    // Cholesky, the solves, and the products with dV
+    fl += (double)n * n * n / 3.0 + 2.0 * n * n * (it.onsite ? K1 : 4 * K1) +
+          (it.onsite ? 0.0 : 12.0 * mA * mF * K1);
+  }
+  if (flop) *flop = fl;
+  if (T->nblk == 0) return LRX_OK;
+  const int grid = (int)std::min<int64_t>(T->nblk, 512);
+  const int64_t wsStride = (int64_t)nmax * nmax + (int64_t)nmax * ldmax;
+  DevMem dItems, dNao, dNabf, dWs, dErr, dTv, dTd, dVv, dVd, dCv, dCd;
+  auto alloc = [](DevMem& m, size_t bytes) { return hipMalloc(&m.p, std::max<size_t>(bytes, 8)) == hipSuccess; };
+  if (!alloc(dItems, sizeof(PrepItem) * items.size()) || !alloc(dNao, sizeof(int) * natom) ||
+      !alloc(dNabf, sizeof(int) * natom) || !alloc(dWs, sizeof(double) * wsStride * grid) ||
+      !alloc(dErr, sizeof(int)))
+    return LRX_ENOMEM;
+  const double *tv = T->val, *td = T->dval, *vv = V->val, *vd = V->dval;
+  double *cv = Cval, *cd = Cdval;
+  if (!on_device) {
+    if (!alloc(dTv, sizeof(double) * T->nval) || !alloc(dTd, sizeof(double) * 3 * T->nval) ||
+        !alloc(dVv, sizeof(double) * V->nval) || !alloc(dVd, sizeof(double) * 3 * V->nval) ||
+        !alloc(dCv, sizeof(double) * ctot) || !alloc(dCd, sizeof(double) * 3 * ctot))
+      return LRX_ENOMEM;
+    if (hipMemcpy(dTv.p, T->val, sizeof(double) * T->nval, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dTd.p, T->dval, sizeof(double) * 3 * T->nval, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dVv.p, V->val, sizeof(double) * V->nval, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dVd.p, V->dval, sizeof(double) * 3 * V->nval, hipMemcpyHostToDevice) != hipSuccess)
+      return LRX_EHIP;
+    tv = (const double*)dTv.p;
+    td = (const double*)dTd.p;
+    vv = (const double*)dVv.p;
+    vd = (const double*)dVd.p;
+    cv = (double*)dCv.p;
+    cd = (double*)dCd.p;
+  }
+  if (hipMemcpy(dItems.p, items.data(), sizeof(PrepItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dNao.p, nao, sizeof(int) * natom, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dNabf.p, nabf, sizeof(int) * natom, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(dErr.p, 0, sizeof(int)) != hipSuccess)
+    return LRX_EHIP;
+  hipLaunchKernelGGL(k_prep, dim3(grid), dim3(kPT), 0, nullptr, (const PrepItem*)dItems.p, (int)T->nblk,
+                     (const int*)dNao.p, (const int*)dNabf.p, tv, td, vv, vd, cv, cd, (double*)dWs.p, wsStride, nmax,
+                     (int*)dErr.p);
+  if (hipGetLastError() != hipSuccess) return LRX_EHIP;
+  int herr = 0;
+  if (hipMemcpy(&herr, dErr.p, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return LRX_EHIP;
+  if (!on_device && (hipMemcpy(Cval, cv, sizeof(double) * ctot, hipMemcpyDeviceToHost) != hipSuccess ||
+                     hipMemcpy(Cdval, cd, sizeof(double) * 3 * ctot, hipMemcpyDeviceToHost) != hipSuccess))
+    return LRX_EHIP;
+  if (herr) return LRX_EINVAL;   // a Coulomb matrix M that is not positive definite
+  return LRX_OK;
+}

@@ -90,7 +90,7 @@ EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
            "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim", "lrx_group_times",
            "lrx_submit", "lrx_wait", "lrx_evaluate_noalloc", "lrx_enumerate_pairs", "lrx_hamiltonian",
-           "lrx_hamiltonian_info"]
+           "lrx_hamiltonian_info", "lrx_prepare_c"]
 
 
 def load(path: Optional[str] = None):
@@ -128,7 +128,9 @@ def load(path: Optional[str] = None):
                                         _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_int64)]
     lib.lrx_hamiltonian.argtypes = [vp, ctypes.POINTER(Options), _f64p, vp, ctypes.c_int32]
     lib.lrx_hamiltonian_info.argtypes = [vp, _f32p, _f64p]
-    for f in ("lrx_hamiltonian", "lrx_hamiltonian_info", "lrx_evaluate_noalloc", "lrx_enumerate_pairs", "lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
+    lib.lrx_prepare_c.argtypes = [ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, ctypes.POINTER(Blocks),
+                                  ctypes.POINTER(Blocks), ctypes.c_int32, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    for f in ("lrx_prepare_c", "lrx_hamiltonian", "lrx_hamiltonian_info", "lrx_evaluate_noalloc", "lrx_enumerate_pairs", "lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate", "lrx_block_gradients",
               "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_evaluate_batch", "lrx_batch_tuning",
               "lrx_pool_trim", "lrx_group_times", "lrx_submit", "lrx_wait"):
         getattr(lib, f).restype = ctypes.c_int
@@ -361,6 +363,42 @@ def batch_tuning(context):
     ms = (ctypes.c_float * (2 * (MAX_ALPHA_TILES + 1)))()
     context.lib.lrx_batch_tuning(context.h, mode, ms)
     return {mt: (int(mode[mt]), float(ms[2 * mt]), float(ms[2 * mt + 1])) for mt in range(1, MAX_ALPHA_TILES + 1)}
+
+
+def prepare_c(nao, nabf, V, T, device: int = 0):
+    """lrx_prepare_c (Eq. C_VA and the gradient of C): the C blocks of the keys
+    of T from V and the three-centre integrals T, in key order.  Returns
+    (blocks, flop): blocks as for lrx_set_tensors (keys of T, offsets, val,
+    dval) on the device when T's values are device tensors, else numpy."""
+    lib = load()
+    keep = []
+    bv, v_dev = Context._blocks(None, V, keep)
+    bt, t_dev = Context._blocks(None, T, keep)
+    if v_dev != t_dev:
+        raise ValueError("V and T must both be on the device or both on the host")
+    nao_, nabf_ = _np(nao, np.int32), _np(nabf, np.int32)
+    first, second = _np(T["first"], np.int32), _np(T["second"], np.int32)
+    sizes = nabf_[first].astype(np.int64) * nao_[first] * nao_[second]
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    total = int(sizes.sum())
+    if t_dev:
+        import torch
+
+        dev = T["val"].device
+        torch.cuda.current_stream().synchronize()
+        cv = torch.empty(max(total, 1), dtype=torch.float64, device=dev)
+        cd = torch.empty(max(3 * total, 1), dtype=torch.float64, device=dev)
+        pv, pd = ctypes.c_void_p(cv.data_ptr()), ctypes.c_void_p(cd.data_ptr())
+    else:
+        cv, cd = np.empty(max(total, 1)), np.empty(max(3 * total, 1))
+        pv, pd = ctypes.c_void_p(cv.ctypes.data), ctypes.c_void_p(cd.ctypes.data)
+    fl = ctypes.c_double()
+    rc = lib.lrx_prepare_c(int(device), int(nao_.shape[0]), _ptr(nao_, _i32p), _ptr(nabf_, _i32p), ctypes.byref(bv),
+                           ctypes.byref(bt), int(t_dev), pv, pd, ctypes.byref(fl))
+    if rc != 0:
+        raise LrxError(rc, "lrx_prepare_c failed (bad arguments, a missing V block, or a Coulomb matrix of a "
+                           "pair that is not positive definite)")
+    return dict(first=T["first"], second=T["second"], R=T["R"], off=off, val=cv[:total], dval=cd[:3 * total]), fl.value
 
 
 def enumerate_pairs(tau, lat, rcut, device: int = 0, capacity: int = 0):
