@@ -187,7 +187,7 @@ def prepare_benchmark(st, mats, reps=3):
     del T, C
     return {"what": "lrx_prepare_c: C and dC of every C key from V and (P|phi phi) on the device",
             "keys": int(len(st.keysC[0])), "ms_per_call": ms, "flop": flop, "tflops_alg": tf,
-            "roofline": {"bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6}}
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6}}
 
 
 def _build_request(i):

@@ -18,10 +18,11 @@
 // One workgroup per key (a grid of workgroups takes the keys in turn): M is
 // assembled in the workgroup's slice of a device workspace and factorised in
 // place, M = L L^T (left-looking, one thread per row of the current column);
-// the right-hand sides -- the integrals, then the three derivative columns --
-// are solved with one thread per column (forward and back substitution; the
-// column's elements are read by consecutive threads at once, L by all
-// threads at once).  FP64 throughout; no atomics but the error flag.
+// L^-1 follows by forward substitution (one thread per column) and
+// M^-1 = L^-T L^-1 on the matrix cores.  The products with the right-hand
+// sides -- C = M^-1 (P|phi phi), the derivative columns -dV C + dP, and
+// dC = M^-1 W -- are GEMMs on the matrix cores.  FP64 throughout; no atomics
+// but the error flag.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -76,38 +77,68 @@ __device__ bool cholesky(double* M, int n) {
   return ok;
 }
 
-// solve L L^T x = b in place for the columns [c0, c1) of X (row stride ld)
-__device__ void solve_cols(const double* L, int n, double* X, int ld, int c0, int c1) {
-  for (int c = c0 + threadIdx.x; c < c1; c += kPT) {
-    double* x = X + c;
-    for (int i = 0; i < n; ++i) {
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Y = L^-1 (lower triangular, n x n, row-major at Y) by forward substitution,
+// one thread per column
+__device__ void invert_lower(const double* L, int n, double* Y) {
+  for (int c = threadIdx.x; c < n; c += kPT) {
+    for (int i = 0; i < c; ++i) Y[(int64_t)i * n + c] = 0.0;
+    Y[(int64_t)c * n + c] = 1.0 / L[(int64_t)c * n + c];
+    for (int i = c + 1; i < n; ++i) {
       const double* li = L + (int64_t)i * n;
-      double s0 = x[(int64_t)i * ld], s1 = 0, s2 = 0, s3 = 0;
-      int k = 0;
-      for (; k + 4 <= i; k += 4) {
-        s0 -= li[k] * x[(int64_t)k * ld];
-        s1 -= li[k + 1] * x[(int64_t)(k + 1) * ld];
-        s2 -= li[k + 2] * x[(int64_t)(k + 2) * ld];
-        s3 -= li[k + 3] * x[(int64_t)(k + 3) * ld];
+      double s0 = 0, s1 = 0;
+      int k = c;
+      for (; k + 2 <= i; k += 2) {
+        s0 -= li[k] * Y[(int64_t)k * n + c];
+        s1 -= li[k + 1] * Y[(int64_t)(k + 1) * n + c];
       }
-      for (; k < i; ++k) s0 -= li[k] * x[(int64_t)k * ld];
-      x[(int64_t)i * ld] = ((s0 + s1) + (s2 + s3)) / li[i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double s0 = x[(int64_t)i * ld], s1 = 0, s2 = 0, s3 = 0;
-      int k = i + 1;
-      for (; k + 4 <= n; k += 4) {
-        s0 -= L[(int64_t)k * n + i] * x[(int64_t)k * ld];
-        s1 -= L[(int64_t)(k + 1) * n + i] * x[(int64_t)(k + 1) * ld];
-        s2 -= L[(int64_t)(k + 2) * n + i] * x[(int64_t)(k + 2) * ld];
-        s3 -= L[(int64_t)(k + 3) * n + i] * x[(int64_t)(k + 3) * ld];
-      }
-      for (; k < n; ++k) s0 -= L[(int64_t)k * n + i] * x[(int64_t)k * ld];
-      x[(int64_t)i * ld] = ((s0 + s1) + (s2 + s3)) / L[(int64_t)i * n + i];
+      for (; k < i; ++k) s0 -= li[k] * Y[(int64_t)k * n + c];
+      Y[(int64_t)i * n + c] = (s0 + s1) / li[i];
     }
   }
 }
 
+// C[i][j] = alpha sum_k A(i,k) B(k,j) (+ Cadd[i][j]) for i < M, j < N on the
+// matrix cores; A(i,k) = A[i sai + k sak], B(k,j) = B[k sbk + j sbj].  The
+// workgroup's four waves take 16 x 16 tiles in turn; f64 16x16x4 MFMA with
+// lane (q, g): A[m = q][k = g], B[k = g][n = q], result r is row g + 4 r.
+// Operands are read from clamped addresses (no branches); the A operand of a
+// k past K is zero; rows and columns past M, N are not stored.  The loads of
+// four k-steps are issued before their products.
+__device__ void wg_gemm(int M, int N, int K, const double* __restrict__ A, int64_t sai, int64_t sak,
+                        const double* __restrict__ B, int64_t sbk, int64_t sbj, double alpha, const double* Cadd,
+                        int64_t ldadd, double* C, int64_t ldc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane & 15, g = lane >> 4;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, ns = (K + 3) >> 2;
+  for (int tile = w; tile < tm * tn; tile += kPT / 64) {
+    const int i0 = 16 * (tile / tn), j0 = 16 * (tile % tn);
+    const double* ap = A + (int64_t)min(i0 + q, M - 1) * sai;
+    const double* bp = B + (int64_t)min(j0 + q, N - 1) * sbj;
+    d4 acc = {0, 0, 0, 0};
+    for (int s0 = 0; s0 < ns; s0 += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 4 * (s0 + u) + g, kc = min(k, K - 1);
+        const double av = ap[(int64_t)kc * sak];
+        a[u] = k < K ? av : 0.0;
+        b[u] = bp[(int64_t)kc * sbk];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + g + 4 * r, j = j0 + q;
+      if (i < M && j < N) C[(int64_t)i * ldc + j] = alpha * acc[r] + (Cadd ? Cadd[(int64_t)i * ldadd + j] : 0.0);
+    }
+  }
+}
+
+// Workspace of a workgroup: L (the factor, in place of M), Linv, Minv (each
+// nmax x nmax), then X [n][ld]: C in columns [0, K1), the derivative
+// right-hand sides W_x in columns K1 + x K1 + [0, K1).
 __global__ void __launch_bounds__(kPT) k_prep(const PrepItem* __restrict__ items, int nitem, const int* __restrict__ nao,
                                               const int* __restrict__ nabf, const double* __restrict__ Tval,
                                               const double* __restrict__ Tdval, const double* __restrict__ Vval,
@@ -115,7 +146,9 @@ __global__ void __launch_bounds__(kPT) k_prep(const PrepItem* __restrict__ items
                                               double* __restrict__ Cdval, double* __restrict__ ws, int64_t wsStride,
                                               int nmax, int* __restrict__ err) {
   double* M = ws + blockIdx.x * wsStride;
-  double* X = M + (int64_t)nmax * nmax;
+  double* Li = M + (int64_t)nmax * nmax;
+  double* Mi = Li + (int64_t)nmax * nmax;
+  double* X = Mi + (int64_t)nmax * nmax;
   const int tid = threadIdx.x;
   for (int p = blockIdx.x; p < nitem; p += gridDim.x) {
     const PrepItem it = items[p];
@@ -133,38 +166,39 @@ __global__ void __launch_bounds__(kPT) k_prep(const PrepItem* __restrict__ items
         v = j < mA ? VAF[j * mF + (i - mA)] : VFF[(i - mA) * mF + (j - mA)];
       M[e] = v;
     }
-    for (int64_t e = tid; e < (int64_t)n * K1; e += kPT) X[(e / K1) * ld + e % K1] = Tval[it.t + e];
     __syncthreads();
     if (!cholesky(M, n) && tid == 0) atomicMax(err, 1);
-    solve_cols(M, n, X, ld, 0, K1);
+    invert_lower(M, n, Li);
+    __syncthreads();
+    // M^-1 = L^-T L^-1: Mi(i,j) = sum_k Li[k][i] Li[k][j]
+    wg_gemm(n, n, n, Li, 1, n, Li, n, 1, 1.0, nullptr, 0, Mi, n);
+    __syncthreads();
+    // C = M^-1 (P|phi phi)  [n][K1]
+    const double* T = Tval + it.t;
+    wg_gemm(n, K1, n, Mi, n, 1, T, K1, 1, 1.0, nullptr, 0, X, ld);
     __syncthreads();
     if (!it.onsite) {
-      // W_x = dP_x - [[0, dV_x], [dV_x^T, 0]] C in columns K1 + x K1 + c
+      // W_x = dP_x - [[0, dV_x], [dV_x^T, 0]] C:
+      //   rows of A: dP_x[top] - dV_x C[rows of F];  rows of F: dP_x[bottom] - dV_x^T C[rows of A]
       const double* dV = Vdval + 3 * it.vAF;
       const double* dP = Tdval + 3 * it.t;
-      for (int64_t e = tid; e < (int64_t)n * 3 * K1; e += kPT) {
-        const int i = (int)(e / (3 * K1)), rem = (int)(e % (3 * K1)), x = rem / K1, c = rem % K1;
+      for (int x = 0; x < 3; ++x) {
         const double* dVx = dV + (int64_t)x * mA * mF;
-        double s = dP[(int64_t)x * n * K1 + (int64_t)i * K1 + c];
-        if (i < mA) {
-          for (int j = 0; j < mF; ++j) s -= dVx[i * mF + j] * X[(int64_t)(mA + j) * ld + c];
-        } else {
-          const int ii = i - mA;
-          for (int j = 0; j < mA; ++j) s -= dVx[j * mF + ii] * X[(int64_t)j * ld + c];
-        }
-        X[(int64_t)i * ld + K1 + rem] = s;
+        const double* dPx = dP + (int64_t)x * n * K1;
+        double* Wx = X + K1 + (int64_t)x * K1;
+        wg_gemm(mA, K1, mF, dVx, mF, 1, X + (int64_t)mA * ld, ld, 1, -1.0, dPx, K1, Wx, ld);
+        wg_gemm(mF, K1, mA, dVx, 1, mF, X, ld, 1, -1.0, dPx + (int64_t)mA * K1, K1, Wx + (int64_t)mA * ld, ld);
       }
       __syncthreads();
-      solve_cols(M, n, X, ld, K1, 4 * K1);
-      __syncthreads();
+      // dC of the key (rows of A): M^-1[rows of A] W_x, straight to the output
+      for (int x = 0; x < 3; ++x)
+        wg_gemm(mA, K1, n, Mi, n, 1, X + K1 + (int64_t)x * K1, ld, 1, 1.0, nullptr, 0,
+                Cdval + 3 * it.c + (int64_t)x * mA * K1, K1);
     }
     // the key's block: the rows of A
     for (int64_t e = tid; e < (int64_t)mA * K1; e += kPT) Cval[it.c + e] = X[(e / K1) * ld + e % K1];
-    for (int64_t e = tid; e < (int64_t)3 * mA * K1; e += kPT) {
-      const int x = (int)(e / ((int64_t)mA * K1));
-      const int64_t r = e % ((int64_t)mA * K1);
-      Cdval[3 * it.c + e] = it.onsite ? 0.0 : X[(r / K1) * ld + K1 + (int64_t)x * K1 + r % K1];
-    }
+    if (it.onsite)
+      for (int64_t e = tid; e < (int64_t)3 * mA * K1; e += kPT) Cdval[3 * it.c + e] = 0.0;
     __syncthreads();
   }
 }
@@ -236,7 +270,7 @@ extern "C" int lrx_prepare_c(int32_t device, int32_t natom, const int32_t* nao, 
   if (flop) *flop = fl;
   if (T->nblk == 0) return LRX_OK;
   const int grid = (int)std::min<int64_t>(T->nblk, 512);
-  const int64_t wsStride = (int64_t)nmax * nmax + (int64_t)nmax * ldmax;
+  const int64_t wsStride = 3 * (int64_t)nmax * nmax + (int64_t)nmax * ldmax;
   DevMem dItems, dNao, dNabf, dWs, dErr, dTv, dTd, dVv, dVd, dCv, dCd;
   auto alloc = [](DevMem& m, size_t bytes) { return hipMalloc(&m.p, std::max<size_t>(bytes, 8)) == hipSuccess; };
   if (!alloc(dItems, sizeof(PrepItem) * items.size()) || !alloc(dNao, sizeof(int) * natom) ||
