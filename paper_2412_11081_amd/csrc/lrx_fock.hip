@@ -168,6 +168,10 @@ template <int NT, bool HS>
 __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ Hbar, double* __restrict__ G12,
                                                    int qsize, int dsize) {
   extern __shared__ double lds[];
+  // the slot's triples: C pair, V pair and third atom (A for the first kind,
+  // F for the second); a C pair's atom has at most 64 C partners
+  __shared__ int tcp[2 * 64], tvp[2 * 64], tat[2 * 64];
+  __shared__ int ntri;
   double* Q = lds;
   double* Ds = lds + qsize;
   double* Hs = Ds + dsize;
@@ -186,10 +190,45 @@ __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ H
   for (int ix = 0; ix < NT; ++ix)
 #pragma unroll
     for (int ib = 0; ib < NT; ++ib) gacc[ix][ib] = d4{0, 0, 0, 0};
-  // the V pair (X,B), whose C partners F give the second kind of triple
-  const int vpX = find_partner(d.vpB, d.vpRow[X], d.vpRow[X + 1], B);
-  const bool kindB = vpX >= 0 && (d.aliveV[vpX] & 1);
-  const int nA0 = d.cpRow[X + 1] - d.cpRow[X];
+  // the slot's triples, found once (one thread per candidate partner) and
+  // listed in a fixed order: first kind (A, X, B) for the C partners A of X
+  // with (A,X) and (A,B) in the value lists, then second kind (X, F, B)
+  // for the value-list C pairs (X,F) when (X,B) is in the value list
+  {
+    const int vpX = find_partner(d.vpB, d.vpRow[X], d.vpRow[X + 1], B);
+    const bool kindB = vpX >= 0 && (d.aliveV[vpX] & 1);
+    const int nA0 = d.cpRow[X + 1] - d.cpRow[X];
+    for (int it = tid; it < 2 * nA0; it += kHxNT) {
+      const bool first = it < nA0;
+      const int i = d.cpRow[X] + (first ? it : it - nA0);
+      int cp = -1, vp = -1, P = d.cpF[i];
+      if (first) {
+        cp = find_partner(d.cpF, d.cpRow[P], d.cpRow[P + 1], X);
+        vp = find_partner(d.vpB, d.vpRow[P], d.vpRow[P + 1], B);
+        if (cp < 0 || !(d.aliveC[cp] & 1) || vp < 0 || !(d.aliveV[vp] & 1)) cp = -1;
+      } else if (kindB && (d.aliveC[i] & 1)) {
+        cp = i;
+        vp = vpX;
+      }
+      tcp[it] = cp;
+      tvp[it] = vp;
+      tat[it] = P;
+    }
+    __syncthreads();
+    if (tid == 0) {   // compaction in list order
+      int n = 0;
+      for (int it = 0; it < 2 * nA0; ++it)
+        if (tcp[it] >= 0) {
+          tcp[n] = tcp[it];
+          tvp[n] = tvp[it];
+          tat[n] = it < nA0 ? tat[it] : -1 - tat[it];   // second kind: -1 - F
+          ++n;
+        }
+      ntri = n;
+    }
+    __syncthreads();
+  }
+  const int nTri = ntri;
   for (int t = 0; t < nT; ++t) {
     d4 hacc[4][NT][NT];
 #pragma unroll
@@ -198,25 +237,11 @@ __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ H
       for (int ib = 0; ib < NT; ++ib)
 #pragma unroll
         for (int ix = 0; ix < NT; ++ix) hacc[j][ib][ix] = d4{0, 0, 0, 0};
-    // triples: first kind (A, X, B) for i < nA0, X a C partner of A; second
-    // kind (X, F, B) for i >= nA0 over the C partners F of X
-    for (int it = 0; it < nA0 + (kindB ? nA0 : 0); ++it) {
-      const bool first = it < nA0;
-      const int i = d.cpRow[X] + (first ? it : it - nA0);
-      int cp, vp, P, nk;
-      if (first) {
-        P = d.cpF[i];   // the atom A
-        cp = find_partner(d.cpF, d.cpRow[P], d.cpRow[P + 1], X);
-        if (cp < 0 || !(d.aliveC[cp] & 1)) continue;
-        vp = find_partner(d.vpB, d.vpRow[P], d.vpRow[P + 1], B);
-        if (vp < 0 || !(d.aliveV[vp] & 1)) continue;
-      } else {
-        if (!(d.aliveC[i] & 1)) continue;
-        P = d.cpF[i];   // the atom F
-        cp = i;
-        vp = vpX;
-      }
-      nk = d.nao[P];
+    for (int it = 0; it < nTri; ++it) {
+      const int cp = tcp[it], vp = tvp[it], code = tat[it];
+      const bool first = code >= 0;
+      const int P = first ? code : -1 - code;   // the atom A (first kind) or F (second)
+      const int nk = d.nao[P];
       const int K1 = nk * nX;
       // D(A,B) or D(F,B) [nk][nB] and H(B,A) or H(B,F) [b][beta][k] of tile t
       const bool with_d = d.keepD[(int64_t)P * N + B] != 0;
