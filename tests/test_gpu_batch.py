@@ -117,3 +117,23 @@ def test_plan_follows_new_tensors():
     assert E1[1] == Es and abs(E1[1] - 2 * E0[1]) <= 1e-3 * abs(E0[1])
     for c in ctxs:
         c.close()
+
+
+def test_batch_per_tensor_thresholds_equal_single():
+    """Per-tensor screening (Table thr_default's five lists) through the
+    batched, captured and replayed path: bit-identical to single evaluations
+    with the same thresholds, on cells where some block sits on one list
+    only."""
+    H.require_gpu()
+    structs = [synth.serving_request(i).build() for i in REQUESTS[:3]]
+    ctxs, mats = _contexts(structs)
+    thr = (1e-4, 1e-2, 1e-3, 1e-4, 1e-3)
+    E, F, S = lrx.evaluate_batch(ctxs, thresholds=thr)
+    E2, F2, S2 = lrx.evaluate_batch(ctxs, thresholds=thr)     # graph replay
+    for i, c in enumerate(ctxs):
+        r = c.evaluate(thresholds=thr)
+        assert _same((E[i], F[i], S[i]), r) and _same((E2[i], F2[i], S2[i]), r), f"structure {i}"
+        kC, kV, _ = c.keep_masks()
+        assert ((kV == 1) | (kV == 2)).any() or ((kC == 1) | (kC == 2)).any(), "the lists do not split"
+    for c in ctxs:
+        c.close()

@@ -71,3 +71,19 @@ def test_noalloc_refuses_structures_beyond_the_scratch():
     print("refused:", e.value, flush=True)
     assert e.value.code == LRX_EBUDGET and "scratch" in str(e.value)
     ctx.close()
+
+
+def test_noalloc_per_tensor_thresholds():
+    """Per-tensor lists (the unit roles and liveness bits live in the
+    context, the work buffers in the scratch): the same result as
+    lrx_evaluate with the same thresholds."""
+    H.require_gpu()
+    st = synth.small_case(natom=4, nspecies=2, n_ao=13, n_abf=33, box=7.5, rc=5.0, rv=8.0, seed=61).build()
+    mats = st.materialize("cuda")
+    ctx = H.gpu_context(st, mats)
+    thr = (3e-3, 2e-2, 1e-1, 5e-3, 3e-2)
+    ref = ctx.evaluate(thresholds=thr)
+    kC, kV, _ = ctx.keep_masks()
+    print(f"C bits {np.bincount(kC, minlength=4)}, V bits {np.bincount(kV, minlength=4)}", flush=True)
+    _compare("per-tensor", ctx.evaluate_noalloc(thresholds=thr), ref, st.natom)
+    ctx.close()
