@@ -68,6 +68,11 @@ def _load():
         lib.orc_hamiltonian.restype = ctypes.c_int
         lib.orc_forces_stress.argtypes = [ctypes.POINTER(OrcInput), _f64p, _f64p, _f64p, _f64p]
         lib.orc_has_openmp.restype = ctypes.c_int
+        lib.orc_screen_d_kp.argtypes = [ctypes.POINTER(OrcInput), _i32p, _f64p, _f64p, ctypes.c_double, _u8p]
+        lib.orc_screen_d_kp.restype = None
+        lib.orc_contract_kp.argtypes = [ctypes.POINTER(OrcInput), _i32p, _f64p, _f64p, _u8p, _u8p, _u8p,
+                                        ctypes.c_int, _f64p, _f64p, _f64p]
+        lib.orc_contract_kp.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -217,6 +222,56 @@ class Problem:
         F, sig = self.forces_stress(gC, gV)
         return dict(E=E, F=F, sigma=sig, gC=gC, gV=gV, keepC=keep[0], keepV=keep[1], keepD=keep[2],
                     skipped_bound=self.skipped_bound)
+
+
+class KProblem(Problem):
+    """A unit cell with k-point sampling on an nk[0] x nk[1] x nk[2] mesh:
+    the density matrix per cell offset of the Born-von Karman supercell,
+    Dk[r][n_tot][n_tot] complex (or real), r = r0 + nk0 (r1 + nk1 r2)
+    (lrx_oracle.c, orc_contract_kp)."""
+
+    def __init__(self, tau, lat, nao, nabf, C, V, nk, Dk):
+        Dk = Dk.detach().cpu().numpy() if hasattr(Dk, "detach") else np.asarray(Dk)
+        self.nk = np.ascontiguousarray(nk, np.int32)
+        nr = int(np.prod(self.nk))
+        nt = int(np.asarray(nao).sum())
+        assert Dk.shape == (nr, nt, nt), Dk.shape
+        self.Dre = np.ascontiguousarray(Dk.real, np.float64)
+        self.Dim = np.ascontiguousarray(Dk.imag, np.float64) if np.iscomplexobj(Dk) else None
+        super().__init__(tau, lat, nao, nabf, C, V, self.Dre[0])
+
+    def screen_d(self, theta_D):
+        lib = _load()
+        nr = int(np.prod(self.nk))
+        kD = np.zeros(nr * self.natom * self.natom, np.uint8)
+        lib.orc_screen_d_kp(ctypes.byref(self.s), _p(self.nk, _i32p), _p(self.Dre, _f64p),
+                            None if self.Dim is None else _p(self.Dim, _f64p), float(theta_D), _p(kD, _u8p))
+        return kD
+
+    def evaluate(self, theta=0.0, thr=None, nthreads=1):
+        """E, F, sigma per unit cell: joint screening with theta (C, V, D),
+        or per-tensor thresholds thr = (C, V, D, dC, dV); no step 2.
+        keepD is [n_cells][natom][natom]."""
+        if thr is None:
+            kC, kV, _, _ = self.screen(theta, 0.0)
+            kC = np.where(kC != 0, 3, 0).astype(np.uint8)
+            kV = np.where(kV != 0, 3, 0).astype(np.uint8)
+            kD = self.screen_d(theta)
+        else:
+            kC, kV, _, _ = self.screen5(thr, 0.0)
+            kD = self.screen_d(thr[2])
+        kC = np.ascontiguousarray(kC, np.uint8)
+        kV = np.ascontiguousarray(kV, np.uint8)
+        lib = _load()
+        E = np.zeros(1)
+        gC = np.zeros((self.nC, 3))
+        gV = np.zeros((self.nV, 3))
+        lib.orc_contract_kp(ctypes.byref(self.s), _p(self.nk, _i32p), _p(self.Dre, _f64p),
+                            None if self.Dim is None else _p(self.Dim, _f64p), _p(kC, _u8p), _p(kV, _u8p),
+                            _p(kD, _u8p), int(nthreads), _p(E, _f64p), _p(gC, _f64p), _p(gV, _f64p))
+        F, sig = self.forces_stress(gC, gV)
+        return dict(E=float(E[0]), F=F, sigma=sig, gC=gC, gV=gV, keepC=kC, keepV=kV,
+                    keepD=kD.reshape(-1, self.natom, self.natom))
 
 
 def evaluate_structure(st, theta=None, theta_cs=None, nthreads=1, mats=None):

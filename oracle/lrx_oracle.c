@@ -745,3 +745,145 @@ int orc_has_openmp(void) {
   return 0;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/*
+ * k-point sampling (Methods, Eq. Eexx with the k-sum definition of D, and
+ * Eq. exx_expand).  The k mesh of nk[0] x nk[1] x nk[2] points makes the
+ * Born-von Karman (BvK) supercell of as many unit cells, and the density
+ * matrix of two orbitals depends on the offset of their cells modulo that
+ * supercell:
+ *   D_{(I,R_I) i, (J,R_J) j} = Dk[r][ao(I) + i][ao(J) + j],
+ *   r = r_0 + nk_0 (r_1 + nk_1 r_2),  r_x = (R_J - R_I)_x mod nk_x,
+ * complex (Dre, Dim; Dim = NULL for a real D(R)) and Hermitian.  The energy
+ * per unit cell is the quartet sum of orc_contract2 with the atom of the V
+ * block in the home cell and the weight
+ *   Re[ D_AB D*_FG + D_AG D*_FB ],
+ *   D_AB at offset R_B, D_FG at R_B + R_G - R_F, D_AG at R_B + R_G, D_FB at R_B - R_F
+ * (C1 = C(A,F,R_F), V = V(A,B,R_B), C2 = C(B,G,R_G): F sits at R_F, B at
+ * R_B, G at R_B + R_G).  There is no folding: every image keeps its own
+ * offset.  Since Re[z w*] = Re z Re w + Im z Im w, a quartet is the real
+ * quartet of the real parts plus the real quartet of the imaginary parts,
+ * with the same blocks and lists.  With nk = (1,1,1) and Dim = NULL this is
+ * exactly orc_contract2 without the item test.
+ */
+static int kp_offset(const int32_t* nk, int x, int y, int z) {
+  int r[3] = {x, y, z};
+  for (int k = 0; k < 3; ++k) r[k] = ((r[k] % nk[k]) + nk[k]) % nk[k];
+  return r[0] + nk[0] * (r[1] + nk[1] * r[2]);
+}
+
+/* D pairs per offset: keepD[(r * N + X) * N + Y] = 1 iff the largest modulus
+ * of an element of D(r)_XY exceeds theta_D (theta_D <= 0 keeps every pair).
+ * The mirror block D(-r)_YX holds the conjugate transpose, so the decision is
+ * the same for both. */
+void orc_screen_d_kp(const orc_input* in, const int32_t* nk, const double* Dre, const double* Dim,
+                     double theta_D, uint8_t* keepD) {
+  const int N = in->natom;
+  int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+  const int64_t nt = ntot_of(in, ao);
+  const int nr = nk[0] * nk[1] * nk[2];
+  for (int r = 0; r < nr; ++r)
+    for (int X = 0; X < N; ++X)
+      for (int Y = 0; Y < N; ++Y) {
+        double mx = 0;
+        for (int i = 0; i < in->nao[X]; ++i)
+          for (int j = 0; j < in->nao[Y]; ++j) {
+            const int64_t e = (int64_t)r * nt * nt + (ao[X] + i) * nt + ao[Y] + j;
+            const double re = Dre[e], im = Dim ? Dim[e] : 0.0;
+            const double m = sqrt(re * re + im * im);
+            if (m > mx) mx = m;
+          }
+        keepD[((int64_t)r * N + X) * N + Y] = (uint8_t)(!(theta_D > 0) || mx > theta_D);
+      }
+  free(ao);
+}
+
+int orc_contract_kp(const orc_input* in, const int32_t* nk, const double* Dre, const double* Dim,
+                    const uint8_t* keepC, const uint8_t* keepV, const uint8_t* keepD, int nthreads, double* E,
+                    double* gC, double* gV) {
+  const int N = in->natom;
+  int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+  const int64_t nt = ntot_of(in, ao);
+  const int64_t nn = nt * nt;
+  int64_t* crow = (int64_t*)calloc(N + 1, sizeof(int64_t));
+  int64_t* clist = (int64_t*)malloc(sizeof(int64_t) * (in->nC + 1));
+  for (int64_t b = 0; b < in->nC; ++b) if (keepC[b] & 3) crow[in->C_first[b] + 1]++;
+  for (int i = 0; i < N; ++i) crow[i + 1] += crow[i];
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * N);
+    for (int i = 0; i < N; ++i) fill[i] = crow[i];
+    for (int64_t b = 0; b < in->nC; ++b) if (keepC[b] & 3) clist[fill[in->C_first[b]]++] = b;
+    free(fill);
+  }
+  int mmax = 0, nmax = 0;
+  for (int i = 0; i < N; ++i) { if (in->nabf[i] > mmax) mmax = in->nabf[i]; if (in->nao[i] > nmax) nmax = in->nao[i]; }
+  const size_t wsz = (size_t)2 * mmax * nmax * nmax + 4 * nmax * nmax + 16;
+  int nth = nthreads > 1 ? nthreads : 1;
+#ifndef _OPENMP
+  nth = 1;
+#endif
+  double* accE = (double*)calloc(nth, sizeof(double));
+  double* accC = (double*)calloc((size_t)nth * in->nC * 3, sizeof(double));
+  double* accV = (double*)calloc((size_t)nth * in->nV * 3, sizeof(double));
+  double** wsv = (double**)malloc(sizeof(double*) * nth);
+  for (int t = 0; t < nth; ++t) wsv[t] = (double*)malloc(sizeof(double) * wsz);
+
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+#endif
+  for (int64_t v = 0; v < in->nV; ++v) {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    if (!(keepV[v] & 3)) continue;
+    const int A = in->V_first[v], B = in->V_second[v];
+    const int mA = in->nabf[A], mB = in->nabf[B], nA = in->nao[A], nB = in->nao[B];
+    const int32_t* RB = in->V_R + 3 * v;
+    const double* V = in->V_val + in->V_off[v];
+    const double* dV = in->V_dval + 3 * in->V_off[v];
+    for (int64_t i1 = crow[A]; i1 < crow[A + 1]; ++i1) {
+      const int64_t c1 = clist[i1];
+      const int F = in->C_second[c1], nF = in->nao[F];
+      const int32_t* RF = in->C_R + 3 * c1;
+      for (int64_t i2 = crow[B]; i2 < crow[B + 1]; ++i2) {
+        const int64_t c2 = clist[i2];
+        const int G = in->C_second[c2], nG = in->nao[G];
+        const int32_t* RG = in->C_R + 3 * c2;
+        const int rAB = kp_offset(nk, RB[0], RB[1], RB[2]);
+        const int rFG = kp_offset(nk, RB[0] + RG[0] - RF[0], RB[1] + RG[1] - RF[1], RB[2] + RG[2] - RF[2]);
+        const int rAG = kp_offset(nk, RB[0] + RG[0], RB[1] + RG[1], RB[2] + RG[2]);
+        const int rFB = kp_offset(nk, RB[0] - RF[0], RB[1] - RF[1], RB[2] - RF[2]);
+        const int kAB = keepD[((int64_t)rAB * N + A) * N + B], kFG = keepD[((int64_t)rFG * N + F) * N + G];
+        const int kAG = keepD[((int64_t)rAG * N + A) * N + G], kFB = keepD[((int64_t)rFB * N + F) * N + B];
+        const int e1 = keepC[c1] & 1, d1 = keepC[c1] & 2, ev = keepV[v] & 1, dv = keepV[v] & 2;
+        const int e2 = keepC[c2] & 1, d2 = keepC[c2] & 2;
+        const int want = (e1 && ev && e2 ? 1 : 0) | (d1 && ev && e2 ? 2 : 0) | (e1 && dv && e2 ? 4 : 0) |
+                         (e1 && ev && d2 ? 8 : 0);
+        if (!want) continue;
+        for (int part = 0; part < (Dim ? 2 : 1); ++part) {
+          const double* Dp = part ? Dim : Dre;
+          dblk DAB = {kAB ? Dp + rAB * nn + ao[A] * nt + ao[B] : NULL, nt};
+          dblk DFG = {kFG ? Dp + rFG * nn + ao[F] * nt + ao[G] : NULL, nt};
+          dblk DAG = {kAG ? Dp + rAG * nn + ao[A] * nt + ao[G] : NULL, nt};
+          dblk DFB = {kFB ? Dp + rFB * nn + ao[F] * nt + ao[B] : NULL, nt};
+          quartet(mA, mB, nA, nF, nB, nG,
+                  in->C_val + in->C_off[c1], in->C_dval + 3 * in->C_off[c1], V, dV,
+                  in->C_val + in->C_off[c2], in->C_dval + 3 * in->C_off[c2],
+                  DAB, DFG, DAG, DFB, wsv[t], want, &accE[t],
+                  accC + ((size_t)t * in->nC + c1) * 3, accV + ((size_t)t * in->nV + v) * 3,
+                  accC + ((size_t)t * in->nC + c2) * 3);
+        }
+      }
+    }
+  }
+  for (int t = 0; t < nth; ++t) {
+    *E += accE[t];
+    for (int64_t i = 0; i < 3 * in->nC; ++i) gC[i] += accC[(size_t)t * in->nC * 3 + i];
+    for (int64_t i = 0; i < 3 * in->nV; ++i) gV[i] += accV[(size_t)t * in->nV * 3 + i];
+    free(wsv[t]);
+  }
+  free(wsv); free(accE); free(accC); free(accV); free(ao); free(crow); free(clist);
+  return 0;
+}

@@ -374,6 +374,47 @@ def gersh_density(n: int, seed: int, device: str = "cpu"):
     return S.contiguous()
 
 
+def kpoint_density(n: int, nk, seed: int, trs: bool = False) -> np.ndarray:
+    """Density matrix per Born-von Karman cell offset, drawn through the k-sum
+    definition of D (Methods): on the Gamma-centred mesh k_m = m / nk, a
+    Hermitian D(k_m) with eigenvalues in (0, 2) (I + S/rho, S = (G + G^H)/sqrt 2
+    from complex Gaussian G, rho = 1.001 * max_i sum_j |S_ij|, so Gershgorin
+    bounds the spectrum), then
+        D(r)[i][j] = (1/N_k) sum_m exp(-2 pi i k_m . r) D(k_m)[i][j],
+    returned as a complex array [N_k][n][n] with r = r0 + nk0 (r1 + nk1 r2).
+    D(-r) = D(r)^H for every draw.  trs=True draws D(k_-m) = conj(D(k_m))
+    (time-reversal symmetry; real D(k) where k_m = k_-m), which makes every
+    D(r) real; otherwise the D(k_m) are independent and D(r) is complex."""
+    nk = tuple(int(x) for x in nk)
+    rng = np.random.default_rng(seed)
+    Dk = np.zeros(nk + (n, n), np.complex128)
+    done = np.zeros(nk, bool)
+    for m in np.ndindex(*nk):
+        if done[m]:
+            continue
+        mm = tuple((-mi) % ni for mi, ni in zip(m, nk))
+        self_conj = mm == m
+        if trs and self_conj:
+            g = rng.normal(size=(n, n))
+        else:
+            g = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        S = (g + g.conj().T) / math.sqrt(2.0)
+        S /= 1.001 * float(np.abs(S).sum(axis=1).max())
+        S[np.diag_indices(n)] += 1.0
+        Dk[m] = S
+        done[m] = True
+        if trs and not self_conj:
+            Dk[mm] = S.conj()
+            done[mm] = True
+    # sum_m exp(-2 pi i m.r / nk) over the three mesh axes is numpy's forward FFT
+    Dr = np.fft.fftn(Dk, axes=(0, 1, 2)) / float(np.prod(nk))
+    # [r0][r1][r2] -> flat index r0 + nk0 (r1 + nk1 r2)
+    Dr = np.ascontiguousarray(Dr.transpose(2, 1, 0, 3, 4)).reshape(-1, n, n)
+    if trs:
+        assert np.abs(Dr.imag).max() <= 1e-12 * max(1.0, np.abs(Dr.real).max())
+    return Dr
+
+
 # ----------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------
