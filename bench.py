@@ -190,6 +190,52 @@ def prepare_benchmark(st, mats, reps=3):
             "roofline": {"bound": "mfma", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6}}
 
 
+KPOINT_MESH = (2, 2, 2)
+
+
+def kpoint_benchmark(steps=5):
+    """k-point sampling (lrx_set_kpoint_tensors): the 64-atom cell (its own
+    blocks and theta) on a 2 x 2 x 2 mesh with a complex density matrix per
+    Born-von Karman offset (synth.kpoint_density, seed = cell seed + 6007),
+    so two real passes per evaluation.  Wall time of lrx_evaluate (it returns
+    with the result on the host), the set-up time of the tensors, and the
+    FP64 rate of the algorithmic FLOPs of both passes."""
+    import numpy as np
+    import torch
+
+    from paper_2412_11081_amd import lrx, synth
+
+    st = synth.workload(2).build()
+    mats = st.materialize("cuda")
+    Dk = torch.from_numpy(synth.kpoint_density(st.n_tot, KPOINT_MESH, st.seed + 6007)).to("cuda")
+    torch.cuda.synchronize()
+    ctx = lrx.Context()
+    ctx.set_structure(st.tau, st.lat, st.nao, st.nabf)
+    t0 = time.perf_counter()
+    ctx.set_kpoint_tensors(KPOINT_MESH, mats["C"], mats["V"], Dk)
+    set_ms = 1e3 * (time.perf_counter() - t0)
+    for _ in range(2):
+        E, F, S = ctx.evaluate(st.theta, 0.0)
+    wall = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        E, F, S = ctx.evaluate(st.theta, 0.0)
+        wall.append(time.perf_counter() - t0)
+    ms = 1e3 * float(np.median(wall))
+    stats = ctx.stats()
+    passes = 2
+    flop = passes * stats["flop_alg"]
+    ctx.close()
+    ncell = int(np.prod(KPOINT_MESH))
+    tf = flop / (ms * 1e-3) / 1e12
+    return {"what": "lrx_evaluate with k-point sampling: E, F, sigma per unit cell, complex D(R), "
+                    "64-atom cell, 2x2x2 mesh, theta 1e-4",
+            "natom": st.natom, "supercell_atoms": st.natom * ncell, "evals_per_s": 1e3 / ms, "ms_per_eval": ms,
+            "set_tensors_ms": set_ms, "E": E, "passes": passes, "flop": flop, "tflops_alg": tf,
+            "frac_fp64_peak": tf / 78.6, "kept_v_blocks": stats["kept_v_blocks"],
+            "alive_v_pairs": stats["alive_v_pairs"], "alive_triples": stats["alive_triples"]}
+
+
 def _build_request(i):
     from paper_2412_11081_amd import synth
 
@@ -379,6 +425,8 @@ def main():
                     help="also run the serving stream with this many requests (p50/p99 latency)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scale for HBM byte counters)")
+    ap.add_argument("--kpoint-only", action="store_true",
+                    help="only the k-point section (64-atom cell, 2x2x2 mesh); prints its JSON")
     ap.add_argument("--theta-sweep", action="store_true",
                     help="only run the screening sweep (error against time) on --workload; prints markdown")
     args = ap.parse_args()
@@ -403,6 +451,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": 8 * n, "copy_calibration_bytes_written": 8 * n,
                           "copies": 3}))
+        return
+    if args.kpoint_only:
+        print(json.dumps(kpoint_benchmark(args.steps)))
         return
     if args.theta_sweep:
         theta_sweep(args.workload)
@@ -504,6 +555,8 @@ def main():
     ctx.close()
     out["prepare_c"] = prepare_benchmark(st, mats)
     print(f"# prepare_c: {out['prepare_c']['ms_per_call']:.1f} ms per call", file=sys.stderr, flush=True)
+    out["kpoint"] = kpoint_benchmark(max(3, min(args.steps, 5)))
+    print(f"# kpoint: {out['kpoint']['ms_per_eval']:.1f} ms per evaluation", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         total_kept = stats["kept_v_blocks"]
         spent, nsample, picked, threads = cpu_baseline(st, mats)

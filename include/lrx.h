@@ -147,6 +147,37 @@ int lrx_set_structure(lrx_ctx* ctx, int32_t natom, const double* tau, const doub
 int lrx_set_tensors(lrx_ctx* ctx, const lrx_blocks* C, const lrx_blocks* V, const double* D,
                     int32_t data_on_device);
 
+/* k-point sampling (Methods: Eq. Eexx with the k-sum definition of the
+ * density matrix, and Eq. exx_expand).  A Gamma-centred mesh of
+ * nk[0] x nk[1] x nk[2] points (each 1..64) makes the Born-von Karman (BvK)
+ * supercell of as many unit cells, and the density matrix of two orbitals
+ * depends on the offset of their cells modulo it:
+ *   D_{(I,R_I) i, (J,R_J) j} = Dk[r][ao(I) + i][ao(J) + j],
+ *   r = r0 + nk0 (r1 + nk1 r2),  r_x = (R_J - R_I)_x mod nk_x,
+ * with Dk = Dre + i Dim, each [nk0 nk1 nk2][n_tot][n_tot] of the unit cell
+ * set by lrx_set_structure; Dim = NULL for a real D(R) (time-reversal
+ * symmetry).  Dk must be Hermitian: Dk[-r] = Dk[r]^H (checked).  C and V
+ * are the unit cell's blocks exactly as for lrx_set_tensors (first atom in
+ * the home cell, any lattice index R).  lrx_evaluate then returns, per unit
+ * cell,
+ *   E = - sum C(A,F,R_F) V(A,B,R_B) C(B,G,R_G) Re[D_AB D*_FG + D_AG D*_FB]
+ * (D_AB at offset R_B, D_FG at R_B + R_G - R_F, D_AG at R_B + R_G, D_FB at
+ * R_B - R_F; no Gamma folding: images fold only modulo the BvK cell), the
+ * forces F [natom][3] on the unit cell's atoms (every periodic image moved
+ * together, D(R) held fixed) and sigma [3][3] per unit-cell volume.
+ * Screening as for lrx_evaluate, with the D pairs decided per cell offset on
+ * the modulus |D|; step 2 (theta_cs > 0) is refused.  lrx_keep_masks then
+ * reports keepD over the supercell's atoms [natom * cells]^2 (atom (t, i)
+ * at t * natom + i).  lrx_evaluate_batch, lrx_evaluate_noalloc, lrx_submit
+ * and lrx_hamiltonian refuse such a context.  Memory: the dense supercell
+ * density matrix (cells^2 n_tot^2 doubles; twice for a complex D) besides
+ * the buffers of lrx_set_tensors on the supercell's pairs.  data_on_device
+ * as for lrx_set_tensors (the Dk arrays, like val/dval, are then device
+ * pointers; they are copied into the supercell matrix and not kept).
+ * A later lrx_set_tensors returns the context to the Gamma point. */
+int lrx_set_kpoint_tensors(lrx_ctx* ctx, const int32_t nk[3], const lrx_blocks* C, const lrx_blocks* V,
+                           const double* Dre, const double* Dim, int32_t data_on_device);
+
 /* Evaluate E (Ha), F [natom][3] (Ha/Bohr) and sigma [3][3] (Ha/Bohr^3) into
  * host buffers; outputs are written only on success.  Blocks the caller's
  * thread until the result is on the host.  Every step (screening, list

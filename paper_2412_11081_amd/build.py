@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["lrx_api.hip", "lrx_mem.hip", "lrx_screen.hip", "lrx_contract.hip", "lrx_pairs.hip", "lrx_fock.hip", "lrx_prep.hip"]
+SOURCES = ["lrx_api.hip", "lrx_mem.hip", "lrx_screen.hip", "lrx_contract.hip", "lrx_pairs.hip", "lrx_fock.hip", "lrx_prep.hip", "lrx_kpoint.hip"]
 LIB = os.path.join(HERE, "liblrx.so")
 
 

@@ -262,6 +262,17 @@ struct lrx_ctx {
   bool timed = false;
   bool evaluated = false;
   bool per_tensor = false;   // screening mode of the last evaluation
+  // k-point sampling (lrx_set_kpoint_tensors): the context then describes the
+  // Born-von Karman supercell (N = N0 * cells atoms, atom (t, i) at t * N0 + i,
+  // the home cell first) and keeps the unit cell here
+  bool bvk = false;
+  int nk[3] = {1, 1, 1};
+  int N0 = 0;
+  std::vector<double> tau0, lat0;
+  std::vector<int> nao0, nabf0;
+  std::vector<int64_t> ao0;
+  double* DscIm = nullptr;   // imaginary part of the supercell D (nullptr: a real D)
+  double* keep2 = nullptr;   // gC, gV and out of the first real pass
   // evaluations queued by lrx_submit: results land in their own pinned buffer
   struct Ticket {
     hipEvent_t done = nullptr;
@@ -308,6 +319,8 @@ struct lrx_ctx {
     have_hx = false;
     hx_done = false;
     evaluated = false;
+    DscIm = nullptr;
+    keep2 = nullptr;
   }
 };
 
@@ -346,6 +359,498 @@ void check_blocks(const lrx_ctx* c, const lrx_blocks* B, bool isC, const char* n
     const int64_t sz = isC ? (int64_t)c->nabf[f] * c->nao[f] * c->nao[s] : (int64_t)c->nabf[f] * c->nabf[s];
     require(B->off[b] >= 0 && B->off[b] + sz <= B->nval, std::string(name) + ": block exceeds nval");
   }
+}
+
+// The supercell of k-point sampling as the host list build sees it: atom
+// (t, i) at index t * N0 + i, cell t = t0 + nk0 (t1 + nk1 t2).
+struct KMap {
+  int N0 = 0;
+  int nk[3] = {1, 1, 1};
+  const int32_t* VR0 = nullptr;   // the caller's lattice indices of the V blocks (mirror check)
+  const double* Dim = nullptr;    // imaginary part of the supercell D on the device, or nullptr
+  int home(int a) const { return a % N0; }
+  int cell(int a) const { return a / N0; }
+  // atom a moved back by the cell of atom b (cell(a) - cell(b) modulo nk)
+  int back(int a, int b) const {
+    const int ta = cell(a), tb = cell(b);
+    const int a0 = ta % nk[0], a1 = (ta / nk[0]) % nk[1], a2 = ta / (nk[0] * nk[1]);
+    const int b0 = tb % nk[0], b1 = (tb / nk[0]) % nk[1], b2 = tb / (nk[0] * nk[1]);
+    const int t = (a0 - b0 + nk[0]) % nk[0] + nk[0] * ((a1 - b1 + nk[1]) % nk[1] + nk[1] * ((a2 - b2 + nk[2]) % nk[2]));
+    return t * N0 + home(a);
+  }
+};
+
+// The static work structure of one set of tensors (keys checked by the
+// caller): pairs, H slots, work units, offsets; device buffers; value checks.
+// km == nullptr: the Gamma point.  Otherwise the context describes the BvK
+// supercell, every block's first atom lies in the home cell, and D is the
+// dense supercell matrix (real part; km->Dim the imaginary part).
+void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const double* D, bool d_on_device,
+                   bool on_device, const KMap* km) {
+  const int N = c->N;
+  const int64_t ntot = c->ao[N];
+  // rows of D are addressed with 24-bit byte strides inside the kernels
+  require(ntot * (int64_t)sizeof(double) < (int64_t)1 << 24, "D: more than 2097151 NAOs in the cell");
+  const int Nh = km ? km->N0 : N;   // atoms of the home cell (the atoms of every C and V block's first index)
+  c->nC = C->nblk;
+  c->nV = V->nblk;
+  c->Cf.assign(C->first, C->first + c->nC);
+  c->Cs.assign(C->second, C->second + c->nC);
+  c->CR.assign(C->R, C->R + 3 * c->nC);
+  c->Vf.assign(V->first, V->first + c->nV);
+  c->Vs.assign(V->second, V->second + c->nV);
+  c->VR.assign(V->R, V->R + 3 * c->nV);
+
+  // ---- pairs ---------------------------------------------------------
+  c->cp = group_pairs(N, c->nC, C->first, C->second, C->R);
+  c->vp = group_pairs(N, c->nV, V->first, V->second, V->R);
+  const Pairs& cp = c->cp;
+  const Pairs& vp = c->vp;
+  const int nCp = (int)cp.pA.size(), nVp = (int)vp.pA.size();
+  {  // every atom has its on-site C block
+    std::vector<char> on(N, 0);
+    for (int64_t b = 0; b < c->nC; ++b)
+      if (C->first[b] == C->second[b] && !C->R[3 * b] && !C->R[3 * b + 1] && !C->R[3 * b + 2]) on[C->first[b]] = 1;
+    for (int i = 0; i < Nh; ++i) require(on[i], "C: atom " + std::to_string(i) + " has no on-site block (A,A,0)");
+  }
+  // mirror of every V block: (B, A, -R) for (A, B, R).  The blocks of a pair
+  // are sorted by R, so the mirrors of pair (A,B)'s blocks are pair (B,A)'s
+  // blocks in reverse order; every pairing is checked.  On a k-point
+  // supercell the mirror is moved back into the home cell: pair (A, (t, B))
+  // has the mirror (B, (-t, A)), whose lattice indices are again sorted in
+  // reverse order (the caller's R is checked).
+  const int32_t* VR0 = km ? km->VR0 : V->R;
+  std::vector<int64_t> vmir(c->nV);
+  std::vector<int> vpmir(nVp);
+  for (int p = 0; p < nVp; ++p) {
+    const int A = vp.pA[p], B = vp.pB[p];
+    const int mf = km ? km->home(B) : B, ms = km ? km->back(A, B) : A;
+    const auto beg = vp.pB.begin() + vp.row[mf], end = vp.pB.begin() + vp.row[mf + 1];
+    const auto it = std::lower_bound(beg, end, ms);
+    require(it != end && *it == ms, "V: block without its mirror (second, first, -R)");
+    const int pm = (int)(it - vp.pB.begin());
+    const int n = vp.b1[p] - vp.b0[p];
+    require(vp.b1[pm] - vp.b0[pm] == n, "V: block without its mirror (second, first, -R)");
+    vpmir[p] = pm;
+    for (int j = 0; j < n; ++j) {
+      const int64_t b = vp.order[vp.b0[p] + j], bm = vp.order[vp.b1[pm] - 1 - j];
+      require(V->first[bm] == mf && V->second[bm] == ms && VR0[3 * bm] == -VR0[3 * b] &&
+                  VR0[3 * bm + 1] == -VR0[3 * b + 1] && VR0[3 * bm + 2] == -VR0[3 * b + 2],
+              "V: block without its mirror (second, first, -R)");
+      vmir[b] = bm;
+    }
+  }
+  // ---- per-pair sizes and offsets --------------------------------------
+  std::vector<int64_t> cfOff(nCp + 1, 0), vfOff(nVp + 1, 0);
+  for (int i = 0; i < nCp; ++i)
+    cfOff[i + 1] = cfOff[i] + (int64_t)c->nabf[cp.pA[i]] * c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
+  int max_mm = 1;
+  for (int i = 0; i < nVp; ++i) {
+    const int mm = c->nabf[vp.pA[i]] * c->nabf[vp.pB[i]];
+    vfOff[i + 1] = vfOff[i] + (int64_t)c->nabf[vp.pA[i]] * ((c->nabf[vp.pB[i]] + 15) & ~15);   // rows padded
+    max_mm = std::max(max_mm, mm);
+  }
+  c->max_mm = max_mm;
+  // ---- H slots: (B,F) and (B,A) for every candidate triple (A,F,B) -----
+  // On a k-point supercell H(B,X) depends only on the cells' offset: the
+  // slot of (B, X) is that of (B in the home cell, X moved back by B's
+  // cell), so slots are formed for home-cell atoms B only and slotmap sends
+  // every (B, X) to its home slot.
+  std::vector<int> slotmap((size_t)N * N, -1);
+  {
+    auto home_pair = [&](int B, int X) -> size_t {
+      return km ? (size_t)km->home(B) * N + km->back(X, B) : (size_t)B * N + X;
+    };
+    std::vector<char> needm((size_t)Nh * N, 0);
+    for (int i = 0; i < nCp; ++i) {
+      const int A = cp.pA[i], F = cp.pB[i];
+      for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
+        const int B = vp.pB[p];
+        needm[home_pair(B, F)] = 1;
+        needm[home_pair(B, A)] = 1;
+      }
+    }
+    c->slotB.clear();
+    c->slotX.clear();
+    std::vector<int> home_slot((size_t)Nh * N, -1);
+    for (int B = 0; B < Nh; ++B)
+      for (int X = 0; X < N; ++X)
+        if (needm[(size_t)B * N + X]) {
+          home_slot[(size_t)B * N + X] = (int)c->slotB.size();
+          c->slotB.push_back(B);
+          c->slotX.push_back(X);
+        }
+    for (int B = 0; B < N; ++B)
+      for (int X = 0; X < N; ++X) slotmap[(size_t)B * N + X] = home_slot[home_pair(B, X)];
+  }
+  const int nSlot = (int)c->slotB.size();
+  std::vector<int64_t> hOff(nSlot + 1, 0);
+  for (int s = 0; s < nSlot; ++s) {
+    const int B = c->slotB[s], X = c->slotX[s];
+    hOff[s + 1] = hOff[s] + (int64_t)((c->nabf[B] + 15) / 16 * 16) * c->nao[B] * c->nao[X];
+  }
+  std::vector<int> slotRow(N + 1, 0), hbB, hbR0, hbC0, hColRow(N + 1, 0), hColSlot, hColX, hColD, hColAtom;
+  for (int s = 0; s < nSlot; ++s) slotRow[c->slotB[s] + 1]++;
+  for (int B = 0; B < N; ++B) slotRow[B + 1] += slotRow[B];
+  c->max_depth = 4;
+  for (int B = 0; B < N; ++B) {  // depth of every H build fits the kernel's table
+    int k = 0;
+    for (int i = cp.row[B]; i < cp.row[B + 1]; ++i) k += c->nao[cp.pB[i]];
+    require(k + 3 <= lrx::kHMaxDepth,
+            "atom " + std::to_string(B) + ": its C partners have more than 508 NAOs in total");
+    c->max_depth = std::max(c->max_depth, (k + 3) & ~3);
+  }
+  {
+    int64_t ncol = 0;
+    for (int s = 0; s < nSlot; ++s) ncol += c->nao[c->slotX[s]];
+    hColSlot.reserve(ncol);
+    hColX.reserve(ncol);
+    hColD.reserve(ncol);
+    hColAtom.reserve(ncol);
+  }
+  for (int B = 0; B < N; ++B) {
+    for (int s = slotRow[B]; s < slotRow[B + 1]; ++s)
+      for (int x = 0; x < c->nao[c->slotX[s]]; ++x) {
+        hColSlot.push_back(s);
+        hColX.push_back(x);
+        hColD.push_back((int)(c->ao[c->slotX[s]] + x));
+        hColAtom.push_back(c->slotX[s]);
+      }
+    hColRow[B + 1] = (int)hColSlot.size();
+    const int rows = c->nabf[B] * c->nao[B], cols = hColRow[B + 1] - hColRow[B];
+    for (int r0 = 0; r0 < rows; r0 += lrx::kHRows)
+      for (int c0 = 0; c0 < cols; c0 += lrx::kHItemCols) {
+        hbB.push_back(B);
+        hbR0.push_back(r0);
+        hbC0.push_back(c0);
+      }
+  }
+  // ---- work units and triple offsets -----------------------------------
+  c->unitCp.clear(); c->unitK0.clear(); c->unitK1.clear(); c->unitKc.clear();
+  c->unitV0.clear(); c->unitV1.clear(); c->unitS.clear();
+  c->nkc.assign(nCp, 1);
+  // B-split: the V partners of a C pair are divided into nsplit ranges (Y
+  // partials summed later) so every alpha-tile group has enough units to
+  // fill the device.
+  c->nsplit.assign(nCp, 1);
+  {
+    std::vector<int64_t> per_mt(lrx::kMaxAlphaTiles + 2, 0);
+    for (int i = 0; i < nCp; ++i) {
+      const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
+      const int mt = (c->nabf[cp.pA[i]] + 15) / 16;
+      const int cols = lrx::unit_cols(mt);
+      per_mt[mt] += (K1 + cols - 1) / cols;
+    }
+    for (int i = 0; i < nCp; ++i) {
+      const int mt = (c->nabf[cp.pA[i]] + 15) / 16;
+      const int nv = vp.row[cp.pA[i] + 1] - vp.row[cp.pA[i]];
+      const int64_t want = (3 * 256 + per_mt[mt] - 1) / std::max<int64_t>(1, per_mt[mt]);
+      c->nsplit[i] = (int)std::max<int64_t>(1, std::min<int64_t>({want, (int64_t)nv, 16}));
+    }
+  }
+  // The V partners of A (sorted by B) fall in two ranges: B < A, where only
+  // Y is formed (Z(A,B) is the transpose of Z(B,A), formed by the units of
+  // atom B), and B >= A, where Z and Y are both formed.  Each range is
+  // divided into its share of the C pair's nsplit V ranges.
+  c->unitYonly.clear();
+  for (int i = 0; i < nCp; ++i) {
+    const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
+    const int cols = lrx::unit_cols((c->nabf[cp.pA[i]] + 15) / 16);
+    const int nk = (K1 + cols - 1) / cols;
+    int chunk = (K1 + nk - 1) / nk;
+    chunk = std::min(cols, (chunk + 15) / 16 * 16);
+    int cnt = 0;
+    const int A = cp.pA[i];
+    const int r0 = vp.row[A], r1 = vp.row[A + 1], nv = r1 - r0, ns = c->nsplit[i];
+    const int mid = (int)(std::lower_bound(vp.pB.begin() + r0, vp.pB.begin() + r1, A) - vp.pB.begin());
+    const int ny = mid - r0, nz = r1 - mid;
+    const int nsY = ny > 0 ? std::max(1, (int)(((int64_t)ns * ny + nv / 2) / std::max(1, nv))) : 0;
+    const int nsZ = nz > 0 ? std::max(1, ns - nsY) : 0;
+    for (int k0 = 0; k0 < K1; k0 += chunk, ++cnt)
+      for (int sp = 0; sp < nsY + nsZ; ++sp) {
+        const bool yo = sp < nsY;
+        const int b0 = yo ? r0 : mid, len = yo ? ny : nz, m = yo ? nsY : nsZ, k = yo ? sp : sp - nsY;
+        c->unitCp.push_back(i);
+        c->unitK0.push_back(k0);
+        c->unitK1.push_back(std::min(K1, k0 + chunk));
+        c->unitKc.push_back(cnt);
+        c->unitV0.push_back(b0 + (int)((int64_t)len * k / m));
+        c->unitV1.push_back(b0 + (int)((int64_t)len * (k + 1) / m));
+        c->unitS.push_back(sp);
+        c->unitYonly.push_back(yo ? 1 : 0);
+      }
+    c->nkc[i] = cnt;
+    c->nsplit[i] = nsY + nsZ;
+  }
+  for (int A = 0; A < N; ++A) {
+    int z = 0;
+    for (int i = cp.row[A]; i < cp.row[A + 1]; ++i) z += c->nkc[i];
+    require(z <= 64, "atom " + std::to_string(A) + ": more than 64 C-pair column chunks");
+  }
+  c->tBase.assign(N + 1, 0);
+  for (int A = 0; A < N; ++A)
+    c->tBase[A + 1] = c->tBase[A] + (int64_t)(cp.row[A + 1] - cp.row[A]) * (vp.row[A + 1] - vp.row[A]);
+  const int64_t ntri = c->tBase[N];
+  std::vector<int64_t> zOff(ntri + 1, 0);
+  for (int A = 0; A < N; ++A) {
+    const int nvA = vp.row[A + 1] - vp.row[A];
+    for (int i = cp.row[A]; i < cp.row[A + 1]; ++i)
+      for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
+        const int64_t t = c->tBase[A] + (int64_t)(i - cp.row[A]) * nvA + (p - vp.row[A]);
+        // Z partials only where Z(A,B) is formed (B >= A)
+        zOff[t + 1] = vp.pB[p] >= A ? (int64_t)c->nkc[i] * c->nabf[A] * c->nabf[vp.pB[p]] : 0;
+      }
+  }
+  for (int64_t t = 0; t < ntri; ++t) zOff[t + 1] += zOff[t];
+  std::vector<int64_t> triHF(std::max<int64_t>(1, ntri)), triHA(std::max<int64_t>(1, ntri));
+  for (int A = 0; A < N; ++A) {
+    const int nvA = vp.row[A + 1] - vp.row[A];
+    for (int i = cp.row[A]; i < cp.row[A + 1]; ++i)
+      for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
+        const int64_t t = c->tBase[A] + (int64_t)(i - cp.row[A]) * nvA + (p - vp.row[A]);
+        const int B = vp.pB[p];
+        triHF[t] = hOff[slotmap[(size_t)B * N + cp.pB[i]]];
+        triHA[t] = hOff[slotmap[(size_t)B * N + A]];
+      }
+  }
+  // static depth tables of the H build: every g of every C pair (B, G)
+  std::vector<int> hdRow(N + 1, 0), hdRowD, hdG, hdCp, hdStride;
+  std::vector<int64_t> hdCf;
+  for (int B = 0; B < N; ++B) {
+    int k = 0;
+    for (int i = cp.row[B]; i < cp.row[B + 1]; ++i)
+      for (int gg = 0; gg < c->nao[cp.pB[i]]; ++gg, ++k) {
+        hdRowD.push_back((int)(c->ao[cp.pB[i]] + gg));
+        hdG.push_back(cp.pB[i]);
+        hdCp.push_back((i << 6) | gg);
+        hdCf.push_back(cfOff[i] + gg);
+        hdStride.push_back(c->nao[cp.pB[i]]);
+      }
+    // padding to a multiple of 4 entries, at least 4 (atoms outside the
+    // home cell of a k-point supercell have no C pairs)
+    for (; (k & 3) || k == 0; ++k) {
+      hdRowD.push_back(0);
+      hdG.push_back(-1);
+      hdCp.push_back(-1);
+      hdCf.push_back(0);
+      hdStride.push_back(0);
+    }
+    hdRow[B + 1] = (int)hdRowD.size();
+  }
+  // ---- per-atom block lists for the force reduction ---------------------
+  std::vector<int> atCfRow, atCsRow, atVfRow, atVsRow;
+  std::vector<int64_t> atCf, atCs, atVf, atVs;
+  // (on a k-point supercell the second atom counts for its home-cell atom:
+  // the forces per unit cell)
+  std::vector<int32_t> homeCs, homeVs;
+  const int32_t* Cs_at = C->second;
+  const int32_t* Vs_at = V->second;
+  if (km) {
+    homeCs.resize(c->nC);
+    homeVs.resize(c->nV);
+    for (int64_t b = 0; b < c->nC; ++b) homeCs[b] = km->home(C->second[b]);
+    for (int64_t b = 0; b < c->nV; ++b) homeVs[b] = km->home(V->second[b]);
+    Cs_at = homeCs.data();
+    Vs_at = homeVs.data();
+  }
+  by_atom(N, c->nC, C->first, atCfRow, atCf);
+  by_atom(N, c->nC, Cs_at, atCsRow, atCs);
+  by_atom(N, c->nV, V->first, atVfRow, atVf);
+  by_atom(N, c->nV, Vs_at, atVsRow, atVs);
+  std::vector<int> Csz(c->nC), Vsz(c->nV);
+  for (int64_t b = 0; b < c->nC; ++b) Csz[b] = c->nabf[C->first[b]] * c->nao[C->first[b]] * c->nao[C->second[b]];
+  for (int64_t b = 0; b < c->nV; ++b) Vsz[b] = c->nabf[V->first[b]] * c->nabf[V->second[b]];
+
+  // ---- device buffers ----------------------------------------------------
+  Dev& d = c->dev;
+  d = Dev{};
+  d.N = N;
+  d.ntot = ntot;
+  d.omega = c->omega;
+  d.tau = c->upload(c->tau);
+  d.lat = c->upload(c->lat);
+  d.nao = c->upload(c->nao);
+  d.nabf = c->upload(c->nabf);
+  d.ao = c->upload(c->ao);
+  d.nC = c->nC;
+  d.nV = c->nV;
+  d.Cfirst = c->upload(c->Cf);
+  d.Csecond = c->upload(c->Cs);
+  d.CR = c->upload(c->CR);
+  d.Coff = c->upload(std::vector<int64_t>(C->off, C->off + c->nC));
+  d.Csz = c->upload(Csz);
+  d.Vfirst = c->upload(c->Vf);
+  d.Vsecond = c->upload(c->Vs);
+  d.VR = c->upload(c->VR);
+  d.Voff = c->upload(std::vector<int64_t>(V->off, V->off + c->nV));
+  d.Vsz = c->upload(Vsz);
+  d.Vmir = c->upload(vmir);
+  if (on_device) {
+    d.Cval = C->val; d.Cdval = C->dval; d.Vval = V->val; d.Vdval = V->dval;
+  } else {
+    double* p;
+    p = c->dalloc<double>(C->nval); HIPCHK(hipMemcpyAsync(p, C->val, C->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Cval = p;
+    p = c->dalloc<double>(3 * C->nval); HIPCHK(hipMemcpyAsync(p, C->dval, 3 * C->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Cdval = p;
+    p = c->dalloc<double>(V->nval); HIPCHK(hipMemcpyAsync(p, V->val, V->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Vval = p;
+    p = c->dalloc<double>(3 * V->nval); HIPCHK(hipMemcpyAsync(p, V->dval, 3 * V->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Vdval = p;
+  }
+  if (d_on_device) {
+    d.D = D;
+  } else {
+    double* p = c->dalloc<double>(ntot * ntot);
+    HIPCHK(hipMemcpyAsync(p, D, ntot * ntot * 8, hipMemcpyHostToDevice, c->stream));
+    d.D = p;
+  }
+  d.DnRe = d.D;
+  d.DnIm = km ? km->Dim : nullptr;
+  d.nCp = nCp;
+  d.nVp = nVp;
+  std::vector<int64_t> cpBlk(cp.order), vpBlk(vp.order);
+  d.cpA = c->upload(cp.pA); d.cpF = c->upload(cp.pB); d.cpB0 = c->upload(cp.b0); d.cpB1 = c->upload(cp.b1);
+  d.cpBlk = c->upload(cpBlk); d.cpRow = c->upload(cp.row);
+  d.vpA = c->upload(vp.pA); d.vpB = c->upload(vp.pB); d.vpB0 = c->upload(vp.b0); d.vpB1 = c->upload(vp.b1);
+  d.vpBlk = c->upload(vpBlk); d.vpRow = c->upload(vp.row); d.vpMir = c->upload(vpmir);
+  d.cfOff = c->upload(cfOff); d.vfOff = c->upload(vfOff);
+  d.Cf = c->dalloc<double>(cfOff[nCp]);
+  d.Vf = c->dalloc<double>(vfOff[nVp]);
+  d.nrmC = c->dalloc<double>(4 * c->nC);
+  d.nrmV = c->dalloc<double>(4 * c->nV);
+  d.dmax = c->dalloc<double>((int64_t)N * N);
+  d.dss = c->dalloc<double>((int64_t)N * N);
+  d.keepC = c->dalloc<uint8_t>(c->nC);
+  d.keepV = c->dalloc<uint8_t>(c->nV);
+  d.keepD = c->dalloc<uint8_t>((int64_t)N * N);
+  d.cval = c->dalloc<double>(nCp);
+  d.dnrm = c->dalloc<double>((int64_t)N * N);
+  d.Svp = c->dalloc<double>(nVp);
+  d.aliveC = c->dalloc<uint8_t>(nCp);
+  d.aliveV = c->dalloc<uint8_t>(nVp);
+  d.nSlot = nSlot;
+  d.slotB = c->upload(c->slotB); d.slotX = c->upload(c->slotX); d.hOff = c->upload(hOff);
+  d.hSlotMap = c->upload(slotmap);
+  d.need = c->dalloc<uint8_t>(nSlot);
+  d.H = nullptr;   // work buffers of a precision are allocated on its first evaluation
+  c->n_cf = cfOff[nCp];
+  c->n_vf = vfOff[nVp];
+  c->n_h = hOff[nSlot];
+
+  d.nUnit = (int)c->unitCp.size();
+  std::vector<int> unitOrder(d.nUnit);
+  {
+    std::iota(unitOrder.begin(), unitOrder.end(), 0);
+    auto mt = [&](int u) { return (c->nabf[cp.pA[c->unitCp[u]]] + 15) / 16; };
+    std::stable_sort(unitOrder.begin(), unitOrder.end(), [&](int a, int b) { return mt(a) < mt(b); });
+    for (int m = 0; m <= lrx::kMaxAlphaTiles + 1; ++m) d.mtStart[m] = 0;
+    for (int u = 0; u < d.nUnit; ++u) d.mtStart[mt(u) + 1]++;
+    for (int m = 0; m <= lrx::kMaxAlphaTiles; ++m) d.mtStart[m + 1] += d.mtStart[m];
+  }
+  d.unitOrder = c->upload(unitOrder);
+  c->unitOrderHost = unitOrder;
+  for (int m = 0; m <= lrx::kMaxAlphaTiles + 1; ++m) c->mtStartHost[m] = d.mtStart[m];
+  {
+    std::vector<int2> items(d.nUnit);
+    for (int k = 0; k < d.nUnit; ++k) items[k] = make_int2(0, unitOrder[k]);
+    int2* it = c->upload(items);
+    c->tl = lrx::TripleLaunch{};
+    for (int mt = 1; mt <= lrx::kMaxAlphaTiles; ++mt) {
+      c->tl.items[mt] = it + d.mtStart[mt];
+      c->tl.n[mt] = d.mtStart[mt + 1] - d.mtStart[mt];
+    }
+    c->tl.counters = c->dalloc<int>(8 * (lrx::kMaxAlphaTiles + 1));
+  }
+  d.slotRow = c->upload(slotRow);
+  d.nHB = (int)hbB.size();
+  d.hbB = c->upload(hbB);
+  d.hbR0 = c->upload(hbR0);
+  d.hbC0 = c->upload(hbC0);
+  d.hColRow = c->upload(hColRow);
+  d.hColSlot = c->upload(hColSlot);
+  d.hColX = c->upload(hColX);
+  d.hColD = c->upload(hColD);
+  d.hColAtom = c->upload(hColAtom);
+  d.unitCp = c->upload(c->unitCp); d.unitK0 = c->upload(c->unitK0); d.unitK1 = c->upload(c->unitK1);
+  d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
+  d.unitV0 = c->upload(c->unitV0); d.unitV1 = c->upload(c->unitV1); d.unitS = c->upload(c->unitS);
+  d.unitYonly = c->upload(c->unitYonly);
+  d.unitRole = c->dalloc<uint8_t>((int64_t)c->unitYonly.size());
+  d.nsplit = c->upload(c->nsplit);
+  d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);
+  d.triHF = c->upload(triHF); d.triHA = c->upload(triHA);
+  d.hdRow = c->upload(hdRow); d.hdRowD = c->upload(hdRowD); d.hdG = c->upload(hdG); d.hdCp = c->upload(hdCp);
+  d.hdCf = c->upload(hdCf); d.hdStride = c->upload(hdStride);
+  d.hcK = c->dalloc<int>(N);
+  d.hcNcol = c->dalloc<int>(N);
+  d.hcRowD = c->dalloc<int>((int64_t)hdRowD.size());
+  d.hcG = c->dalloc<int>((int64_t)hdRowD.size());
+  d.hcCp = c->dalloc<int>((int64_t)hdRowD.size());
+  d.hcCf = c->dalloc<int64_t>((int64_t)hdRowD.size());
+  d.hcStride = c->dalloc<int>((int64_t)hdRowD.size());
+  d.hcColSlot = c->dalloc<int>((int64_t)hColSlot.size());
+  d.hcColD = c->dalloc<int>((int64_t)hColSlot.size());
+  d.hcColAtom = c->dalloc<int>((int64_t)hColSlot.size());
+  d.Zbuf = nullptr;
+  c->n_z = zOff[ntri];
+  std::vector<int64_t> yOff(nCp + 1, 0);
+  for (int i = 0; i < nCp; ++i) yOff[i + 1] = yOff[i] + (cfOff[i + 1] - cfOff[i]) * c->nsplit[i];
+  d.yOff = c->upload(yOff);
+  d.Ybuf = nullptr;
+  c->n_y = yOff[nCp];
+  c->have_f32 = c->have_f64 = false;
+  d.Cf32 = nullptr; d.Vf32 = nullptr; d.D32 = nullptr; d.H32 = nullptr; d.Zbuf32 = nullptr; d.Ybuf32 = nullptr;
+  d.gC = c->dalloc<double>(3 * c->nC);
+  d.gV = c->dalloc<double>(3 * c->nV);
+  d.Ep = c->dalloc<double>(nVp);
+  d.atCfRow = c->upload(atCfRow); d.atCf = c->upload(atCf);
+  d.atCsRow = c->upload(atCsRow); d.atCs = c->upload(atCs);
+  d.atVfRow = c->upload(atVfRow); d.atVf = c->upload(atVf);
+  d.atVsRow = c->upload(atVsRow); d.atVs = c->upload(atVs);
+  d.out = c->dalloc<double>(1 + 3 * N + 9);
+  d.err = c->dalloc<int>(1);
+  g_pinned.put(c->h_out, c->h_out_bytes);
+  c->h_out = nullptr;
+  c->h_out_bytes = sizeof(double) * (1 + 3 * N + 9);
+  c->h_out = (double*)g_pinned.get(c->h_out_bytes);
+
+  // ---- value validation on the device ------------------------------------
+  HIPCHK(hipMemsetAsync(d.err, 0, sizeof(int), c->stream));
+  lrx::launch_validate_finite(d.Cval, C->nval, d.err, 1, c->stream);
+  lrx::launch_validate_finite(d.Cdval, 3 * C->nval, d.err, 1, c->stream);
+  // V and dV: finiteness is checked by the mirror pass of launch_validate
+  lrx::launch_validate(d, c->stream);
+  lrx::launch_validate_dsym(d.D, ntot, 0, d.err, c->stream);
+  if (d.DnIm) {   // Hermitian: the imaginary part antisymmetric
+    lrx::launch_validate_dsym(d.DnIm, ntot, 1, d.err, c->stream);
+    lrx::launch_validate_finite(d.DnIm, ntot * ntot, d.err, 4, c->stream);
+  }
+  HIPCHK(hipGetLastError());
+  int herr = 0;
+  HIPCHK(hipMemcpyAsync(&herr, d.err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (herr) {
+    std::string m = "invalid tensor values:";
+    if (herr & 1) m += " non-finite C/dC;";
+    if (herr & 2) m += " non-finite V/dV;";
+    if (herr & 4) m += " non-finite D;";
+    if (herr & 8) m += " V(B,A,-R) != V(A,B,R)^T;";
+    if (herr & 16) m += " dV(B,A,-R) != -dV(A,B,R)^T;";
+    if (herr & 32) m += " on-site C block not symmetric in (a,f);";
+    if (herr & 64) m += km ? " D(-R) != D(R)^H;" : " D not symmetric;";
+    c->free_tensors();
+    throw Fail{LRX_EINVAL, m};
+  }
+  c->have_tensors = true;
+  c->gen = g_gen++;
+}
+
+// Back from a k-point supercell to the unit cell the caller set.
+void restore_unit_cell(lrx_ctx* c) {
+  c->N = c->N0;
+  c->tau = c->tau0;
+  c->lat = c->lat0;
+  c->nao = c->nao0;
+  c->nabf = c->nabf0;
+  c->ao = c->ao0;
+  c->bvk = false;
 }
 
 }  // namespace
@@ -390,6 +895,7 @@ int lrx_set_structure(lrx_ctx* c, int32_t natom, const double* tau, const double
     drop_plans_of(c);
     c->free_tensors();
     c->have_structure = false;
+    c->bvk = false;
     c->N = natom;
     c->tau.assign(tau, tau + 3 * natom);
     c->lat.assign(lattice, lattice + 9);
@@ -415,418 +921,103 @@ int lrx_set_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const 
     require(c->have_structure, "lrx_set_tensors before lrx_set_structure");
     drop_plans_of(c);
     c->free_tensors();
+    if (c->bvk) restore_unit_cell(c);
     check_blocks(c, C, true, "C");
     check_blocks(c, V, false, "V");
     require(D != nullptr, "D: NULL");
-    const int N = c->N;
-    const int64_t ntot = c->ao[N];
-    // rows of D are addressed with 24-bit byte strides inside the kernels
-    require(ntot * (int64_t)sizeof(double) < (int64_t)1 << 24, "D: more than 2097151 NAOs in the cell");
-    c->nC = C->nblk;
-    c->nV = V->nblk;
-    c->Cf.assign(C->first, C->first + c->nC);
-    c->Cs.assign(C->second, C->second + c->nC);
-    c->CR.assign(C->R, C->R + 3 * c->nC);
-    c->Vf.assign(V->first, V->first + c->nV);
-    c->Vs.assign(V->second, V->second + c->nV);
-    c->VR.assign(V->R, V->R + 3 * c->nV);
+    build_tensors(c, C, V, D, on_device != 0, on_device != 0, nullptr);
+  });
+}
 
-    // ---- pairs ---------------------------------------------------------
-    c->cp = group_pairs(N, c->nC, C->first, C->second, C->R);
-    c->vp = group_pairs(N, c->nV, V->first, V->second, V->R);
-    const Pairs& cp = c->cp;
-    const Pairs& vp = c->vp;
-    const int nCp = (int)cp.pA.size(), nVp = (int)vp.pA.size();
-    {  // every atom has its on-site C block
-      std::vector<char> on(N, 0);
-      for (int64_t b = 0; b < c->nC; ++b)
-        if (C->first[b] == C->second[b] && !C->R[3 * b] && !C->R[3 * b + 1] && !C->R[3 * b + 2]) on[C->first[b]] = 1;
-      for (int i = 0; i < N; ++i) require(on[i], "C: atom " + std::to_string(i) + " has no on-site block (A,A,0)");
-    }
-    // mirror of every V block: (B, A, -R) for (A, B, R).  The blocks of a pair
-    // are sorted by R, so the mirrors of pair (A,B)'s blocks are pair (B,A)'s
-    // blocks in reverse order; every pairing is checked.
-    std::vector<int64_t> vmir(c->nV);
-    std::vector<int> vpmir(nVp);
-    for (int p = 0; p < nVp; ++p) {
-      const int A = vp.pA[p], B = vp.pB[p];
-      const auto beg = vp.pB.begin() + vp.row[B], end = vp.pB.begin() + vp.row[B + 1];
-      const auto it = std::lower_bound(beg, end, A);
-      require(it != end && *it == A, "V: block without its mirror (second, first, -R)");
-      const int pm = (int)(it - vp.pB.begin());
-      const int n = vp.b1[p] - vp.b0[p];
-      require(vp.b1[pm] - vp.b0[pm] == n, "V: block without its mirror (second, first, -R)");
-      vpmir[p] = pm;
-      for (int j = 0; j < n; ++j) {
-        const int64_t b = vp.order[vp.b0[p] + j], bm = vp.order[vp.b1[pm] - 1 - j];
-        require(V->first[bm] == B && V->second[bm] == A && V->R[3 * bm] == -V->R[3 * b] &&
-                    V->R[3 * bm + 1] == -V->R[3 * b + 1] && V->R[3 * bm + 2] == -V->R[3 * b + 2],
-                "V: block without its mirror (second, first, -R)");
-        vmir[b] = bm;
+int lrx_set_kpoint_tensors(lrx_ctx* c, const int32_t* nk, const lrx_blocks* C, const lrx_blocks* V,
+                           const double* Dre, const double* Dim, int32_t on_device) {
+  return guarded(c, [&] {
+    require(c->have_structure, "lrx_set_kpoint_tensors before lrx_set_structure");
+    require(nk != nullptr && Dre != nullptr, "lrx_set_kpoint_tensors: NULL argument");
+    drop_plans_of(c);
+    c->free_tensors();
+    if (c->bvk) restore_unit_cell(c);
+    for (int x = 0; x < 3; ++x) require(nk[x] >= 1 && nk[x] <= 64, "nk out of range 1..64");
+    const int ncell = nk[0] * nk[1] * nk[2];
+    const int N0 = c->N;
+    require((int64_t)N0 * ncell <= 16384, "k-point supercell of more than 16384 atoms");
+    check_blocks(c, C, true, "C");   // the caller's keys, on the unit cell
+    check_blocks(c, V, false, "V");
+    const int64_t nt0 = c->ao[N0];
+    // keys on the supercell: (A, F, R) -> (A, (R mod nk, F), (R - R mod nk) / nk)
+    KMap km;
+    km.N0 = N0;
+    for (int x = 0; x < 3; ++x) km.nk[x] = nk[x];
+    km.VR0 = V->R;
+    std::vector<int32_t> cS, cR, vS, vR;
+    auto convert = [&](const lrx_blocks* B, std::vector<int32_t>& S, std::vector<int32_t>& R) {
+      S.resize(B->nblk);
+      R.resize(3 * B->nblk);
+      for (int64_t b = 0; b < B->nblk; ++b) {
+        int r[3];
+        for (int x = 0; x < 3; ++x) {
+          const int v = B->R[3 * b + x];
+          r[x] = ((v % nk[x]) + nk[x]) % nk[x];
+          R[3 * b + x] = (v - r[x]) / nk[x];
+        }
+        S[b] = (r[0] + nk[0] * (r[1] + nk[1] * r[2])) * N0 + B->second[b];
+      }
+    };
+    convert(C, cS, cR);
+    convert(V, vS, vR);
+    lrx_blocks C2 = *C, V2 = *V;
+    C2.second = cS.data();
+    C2.R = cR.data();
+    V2.second = vS.data();
+    V2.R = vR.data();
+    // the unit cell is kept; the context describes the supercell (the volume
+    // stays the unit cell's: the stress per unit cell)
+    c->N0 = N0;
+    c->tau0 = c->tau;
+    c->lat0 = c->lat;
+    c->nao0 = c->nao;
+    c->nabf0 = c->nabf;
+    c->ao0 = c->ao;
+    for (int x = 0; x < 3; ++x) c->nk[x] = nk[x];
+    const int Ns = N0 * ncell;
+    c->N = Ns;
+    c->tau.assign(3 * (size_t)Ns, 0.0);
+    c->nao.assign(Ns, 0);
+    c->nabf.assign(Ns, 0);
+    for (int t = 0; t < ncell; ++t) {
+      const int t0 = t % nk[0], t1 = (t / nk[0]) % nk[1], t2 = t / (nk[0] * nk[1]);
+      for (int i = 0; i < N0; ++i) {
+        for (int x = 0; x < 3; ++x)
+          c->tau[3 * ((size_t)t * N0 + i) + x] =
+              c->tau0[3 * i + x] + t0 * c->lat0[x] + t1 * c->lat0[3 + x] + t2 * c->lat0[6 + x];
+        c->nao[t * N0 + i] = c->nao0[i];
+        c->nabf[t * N0 + i] = c->nabf0[i];
       }
     }
-    // ---- per-pair sizes and offsets --------------------------------------
-    std::vector<int64_t> cfOff(nCp + 1, 0), vfOff(nVp + 1, 0);
-    for (int i = 0; i < nCp; ++i)
-      cfOff[i + 1] = cfOff[i] + (int64_t)c->nabf[cp.pA[i]] * c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
-    int max_mm = 1;
-    for (int i = 0; i < nVp; ++i) {
-      const int mm = c->nabf[vp.pA[i]] * c->nabf[vp.pB[i]];
-      vfOff[i + 1] = vfOff[i] + (int64_t)c->nabf[vp.pA[i]] * ((c->nabf[vp.pB[i]] + 15) & ~15);   // rows padded
-      max_mm = std::max(max_mm, mm);
-    }
-    c->max_mm = max_mm;
-    // ---- H slots: (B,F) and (B,A) for every candidate triple (A,F,B) -----
-    std::vector<int> slotmap((size_t)N * N, -1);
-    {
-      std::vector<char> needm((size_t)N * N, 0);
-      for (int i = 0; i < nCp; ++i) {
-        const int A = cp.pA[i], F = cp.pB[i];
-        for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
-          const int B = vp.pB[p];
-          needm[(size_t)B * N + F] = 1;
-          needm[(size_t)B * N + A] = 1;
-        }
+    for (int r = 0; r < 3; ++r)
+      for (int x = 0; x < 3; ++x) c->lat[3 * r + x] = nk[r] * c->lat0[3 * r + x];
+    c->ao.assign(Ns + 1, 0);
+    for (int i = 0; i < Ns; ++i) c->ao[i + 1] = c->ao[i] + c->nao[i];
+    c->bvk = true;
+    const int64_t ns = c->ao[Ns];
+    require(ns * (int64_t)sizeof(double) < (int64_t)1 << 24, "D: more than 2097151 NAOs in the supercell");
+    // the supercell density matrix, block circulant, on the device
+    auto expand = [&](const double* Dk) {
+      const double* src = Dk;
+      if (!on_device) {
+        double* p = c->dalloc<double>(ncell * nt0 * nt0);
+        HIPCHK(hipMemcpyAsync(p, Dk, sizeof(double) * ncell * nt0 * nt0, hipMemcpyHostToDevice, c->stream));
+        src = p;
       }
-      c->slotB.clear();
-      c->slotX.clear();
-      for (int B = 0; B < N; ++B)
-        for (int X = 0; X < N; ++X)
-          if (needm[(size_t)B * N + X]) {
-            slotmap[(size_t)B * N + X] = (int)c->slotB.size();
-            c->slotB.push_back(B);
-            c->slotX.push_back(X);
-          }
-    }
-    const int nSlot = (int)c->slotB.size();
-    std::vector<int64_t> hOff(nSlot + 1, 0);
-    for (int s = 0; s < nSlot; ++s) {
-      const int B = c->slotB[s], X = c->slotX[s];
-      hOff[s + 1] = hOff[s] + (int64_t)((c->nabf[B] + 15) / 16 * 16) * c->nao[B] * c->nao[X];
-    }
-    std::vector<int> slotRow(N + 1, 0), hbB, hbR0, hbC0, hColRow(N + 1, 0), hColSlot, hColX, hColD, hColAtom;
-    for (int s = 0; s < nSlot; ++s) slotRow[c->slotB[s] + 1]++;
-    for (int B = 0; B < N; ++B) slotRow[B + 1] += slotRow[B];
-    c->max_depth = 4;
-    for (int B = 0; B < N; ++B) {  // depth of every H build fits the kernel's table
-      int k = 0;
-      for (int i = cp.row[B]; i < cp.row[B + 1]; ++i) k += c->nao[cp.pB[i]];
-      require(k + 3 <= lrx::kHMaxDepth,
-              "atom " + std::to_string(B) + ": its C partners have more than 508 NAOs in total");
-      c->max_depth = std::max(c->max_depth, (k + 3) & ~3);
-    }
-    {
-      int64_t ncol = 0;
-      for (int s = 0; s < nSlot; ++s) ncol += c->nao[c->slotX[s]];
-      hColSlot.reserve(ncol);
-      hColX.reserve(ncol);
-      hColD.reserve(ncol);
-      hColAtom.reserve(ncol);
-    }
-    for (int B = 0; B < N; ++B) {
-      for (int s = slotRow[B]; s < slotRow[B + 1]; ++s)
-        for (int x = 0; x < c->nao[c->slotX[s]]; ++x) {
-          hColSlot.push_back(s);
-          hColX.push_back(x);
-          hColD.push_back((int)(c->ao[c->slotX[s]] + x));
-          hColAtom.push_back(c->slotX[s]);
-        }
-      hColRow[B + 1] = (int)hColSlot.size();
-      const int rows = c->nabf[B] * c->nao[B], cols = hColRow[B + 1] - hColRow[B];
-      for (int r0 = 0; r0 < rows; r0 += lrx::kHRows)
-        for (int c0 = 0; c0 < cols; c0 += lrx::kHItemCols) {
-          hbB.push_back(B);
-          hbR0.push_back(r0);
-          hbC0.push_back(c0);
-        }
-    }
-    // ---- work units and triple offsets -----------------------------------
-    c->unitCp.clear(); c->unitK0.clear(); c->unitK1.clear(); c->unitKc.clear();
-    c->unitV0.clear(); c->unitV1.clear(); c->unitS.clear();
-    c->nkc.assign(nCp, 1);
-    // B-split: the V partners of a C pair are divided into nsplit ranges (Y
-    // partials summed later) so every alpha-tile group has enough units to
-    // fill the device.
-    c->nsplit.assign(nCp, 1);
-    {
-      std::vector<int64_t> per_mt(lrx::kMaxAlphaTiles + 2, 0);
-      for (int i = 0; i < nCp; ++i) {
-        const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
-        const int mt = (c->nabf[cp.pA[i]] + 15) / 16;
-        const int cols = lrx::unit_cols(mt);
-        per_mt[mt] += (K1 + cols - 1) / cols;
-      }
-      for (int i = 0; i < nCp; ++i) {
-        const int mt = (c->nabf[cp.pA[i]] + 15) / 16;
-        const int nv = vp.row[cp.pA[i] + 1] - vp.row[cp.pA[i]];
-        const int64_t want = (3 * 256 + per_mt[mt] - 1) / std::max<int64_t>(1, per_mt[mt]);
-        c->nsplit[i] = (int)std::max<int64_t>(1, std::min<int64_t>({want, (int64_t)nv, 16}));
-      }
-    }
-    // The V partners of A (sorted by B) fall in two ranges: B < A, where only
-    // Y is formed (Z(A,B) is the transpose of Z(B,A), formed by the units of
-    // atom B), and B >= A, where Z and Y are both formed.  Each range is
-    // divided into its share of the C pair's nsplit V ranges.
-    c->unitYonly.clear();
-    for (int i = 0; i < nCp; ++i) {
-      const int K1 = c->nao[cp.pA[i]] * c->nao[cp.pB[i]];
-      const int cols = lrx::unit_cols((c->nabf[cp.pA[i]] + 15) / 16);
-      const int nk = (K1 + cols - 1) / cols;
-      int chunk = (K1 + nk - 1) / nk;
-      chunk = std::min(cols, (chunk + 15) / 16 * 16);
-      int cnt = 0;
-      const int A = cp.pA[i];
-      const int r0 = vp.row[A], r1 = vp.row[A + 1], nv = r1 - r0, ns = c->nsplit[i];
-      const int mid = (int)(std::lower_bound(vp.pB.begin() + r0, vp.pB.begin() + r1, A) - vp.pB.begin());
-      const int ny = mid - r0, nz = r1 - mid;
-      const int nsY = ny > 0 ? std::max(1, (int)(((int64_t)ns * ny + nv / 2) / std::max(1, nv))) : 0;
-      const int nsZ = nz > 0 ? std::max(1, ns - nsY) : 0;
-      for (int k0 = 0; k0 < K1; k0 += chunk, ++cnt)
-        for (int sp = 0; sp < nsY + nsZ; ++sp) {
-          const bool yo = sp < nsY;
-          const int b0 = yo ? r0 : mid, len = yo ? ny : nz, m = yo ? nsY : nsZ, k = yo ? sp : sp - nsY;
-          c->unitCp.push_back(i);
-          c->unitK0.push_back(k0);
-          c->unitK1.push_back(std::min(K1, k0 + chunk));
-          c->unitKc.push_back(cnt);
-          c->unitV0.push_back(b0 + (int)((int64_t)len * k / m));
-          c->unitV1.push_back(b0 + (int)((int64_t)len * (k + 1) / m));
-          c->unitS.push_back(sp);
-          c->unitYonly.push_back(yo ? 1 : 0);
-        }
-      c->nkc[i] = cnt;
-      c->nsplit[i] = nsY + nsZ;
-    }
-    for (int A = 0; A < N; ++A) {
-      int z = 0;
-      for (int i = cp.row[A]; i < cp.row[A + 1]; ++i) z += c->nkc[i];
-      require(z <= 64, "atom " + std::to_string(A) + ": more than 64 C-pair column chunks");
-    }
-    c->tBase.assign(N + 1, 0);
-    for (int A = 0; A < N; ++A)
-      c->tBase[A + 1] = c->tBase[A] + (int64_t)(cp.row[A + 1] - cp.row[A]) * (vp.row[A + 1] - vp.row[A]);
-    const int64_t ntri = c->tBase[N];
-    std::vector<int64_t> zOff(ntri + 1, 0);
-    for (int A = 0; A < N; ++A) {
-      const int nvA = vp.row[A + 1] - vp.row[A];
-      for (int i = cp.row[A]; i < cp.row[A + 1]; ++i)
-        for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
-          const int64_t t = c->tBase[A] + (int64_t)(i - cp.row[A]) * nvA + (p - vp.row[A]);
-          // Z partials only where Z(A,B) is formed (B >= A)
-          zOff[t + 1] = vp.pB[p] >= A ? (int64_t)c->nkc[i] * c->nabf[A] * c->nabf[vp.pB[p]] : 0;
-        }
-    }
-    for (int64_t t = 0; t < ntri; ++t) zOff[t + 1] += zOff[t];
-    std::vector<int64_t> triHF(std::max<int64_t>(1, ntri)), triHA(std::max<int64_t>(1, ntri));
-    for (int A = 0; A < N; ++A) {
-      const int nvA = vp.row[A + 1] - vp.row[A];
-      for (int i = cp.row[A]; i < cp.row[A + 1]; ++i)
-        for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
-          const int64_t t = c->tBase[A] + (int64_t)(i - cp.row[A]) * nvA + (p - vp.row[A]);
-          const int B = vp.pB[p];
-          triHF[t] = hOff[slotmap[(size_t)B * N + cp.pB[i]]];
-          triHA[t] = hOff[slotmap[(size_t)B * N + A]];
-        }
-    }
-    // static depth tables of the H build: every g of every C pair (B, G)
-    std::vector<int> hdRow(N + 1, 0), hdRowD, hdG, hdCp, hdStride;
-    std::vector<int64_t> hdCf;
-    for (int B = 0; B < N; ++B) {
-      int k = 0;
-      for (int i = cp.row[B]; i < cp.row[B + 1]; ++i)
-        for (int gg = 0; gg < c->nao[cp.pB[i]]; ++gg, ++k) {
-          hdRowD.push_back((int)(c->ao[cp.pB[i]] + gg));
-          hdG.push_back(cp.pB[i]);
-          hdCp.push_back((i << 6) | gg);
-          hdCf.push_back(cfOff[i] + gg);
-          hdStride.push_back(c->nao[cp.pB[i]]);
-        }
-      for (; k & 3; ++k) {
-        hdRowD.push_back(0);
-        hdG.push_back(-1);
-        hdCp.push_back(-1);
-        hdCf.push_back(0);
-        hdStride.push_back(0);
-      }
-      hdRow[B + 1] = (int)hdRowD.size();
-    }
-    // ---- per-atom block lists for the force reduction ---------------------
-    std::vector<int> atCfRow, atCsRow, atVfRow, atVsRow;
-    std::vector<int64_t> atCf, atCs, atVf, atVs;
-    by_atom(N, c->nC, C->first, atCfRow, atCf);
-    by_atom(N, c->nC, C->second, atCsRow, atCs);
-    by_atom(N, c->nV, V->first, atVfRow, atVf);
-    by_atom(N, c->nV, V->second, atVsRow, atVs);
-    std::vector<int> Csz(c->nC), Vsz(c->nV);
-    for (int64_t b = 0; b < c->nC; ++b) Csz[b] = c->nabf[C->first[b]] * c->nao[C->first[b]] * c->nao[C->second[b]];
-    for (int64_t b = 0; b < c->nV; ++b) Vsz[b] = c->nabf[V->first[b]] * c->nabf[V->second[b]];
-
-    // ---- device buffers ----------------------------------------------------
-    Dev& d = c->dev;
-    d = Dev{};
-    d.N = N;
-    d.ntot = ntot;
-    d.omega = c->omega;
-    d.tau = c->upload(c->tau);
-    d.lat = c->upload(c->lat);
-    d.nao = c->upload(c->nao);
-    d.nabf = c->upload(c->nabf);
-    d.ao = c->upload(c->ao);
-    d.nC = c->nC;
-    d.nV = c->nV;
-    d.Cfirst = c->upload(c->Cf);
-    d.Csecond = c->upload(c->Cs);
-    d.CR = c->upload(c->CR);
-    d.Coff = c->upload(std::vector<int64_t>(C->off, C->off + c->nC));
-    d.Csz = c->upload(Csz);
-    d.Vfirst = c->upload(c->Vf);
-    d.Vsecond = c->upload(c->Vs);
-    d.VR = c->upload(c->VR);
-    d.Voff = c->upload(std::vector<int64_t>(V->off, V->off + c->nV));
-    d.Vsz = c->upload(Vsz);
-    d.Vmir = c->upload(vmir);
-    if (on_device) {
-      d.Cval = C->val; d.Cdval = C->dval; d.Vval = V->val; d.Vdval = V->dval; d.D = D;
-    } else {
-      double* p;
-      p = c->dalloc<double>(C->nval); HIPCHK(hipMemcpyAsync(p, C->val, C->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Cval = p;
-      p = c->dalloc<double>(3 * C->nval); HIPCHK(hipMemcpyAsync(p, C->dval, 3 * C->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Cdval = p;
-      p = c->dalloc<double>(V->nval); HIPCHK(hipMemcpyAsync(p, V->val, V->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Vval = p;
-      p = c->dalloc<double>(3 * V->nval); HIPCHK(hipMemcpyAsync(p, V->dval, 3 * V->nval * 8, hipMemcpyHostToDevice, c->stream)); d.Vdval = p;
-      p = c->dalloc<double>(ntot * ntot); HIPCHK(hipMemcpyAsync(p, D, ntot * ntot * 8, hipMemcpyHostToDevice, c->stream)); d.D = p;
-    }
-    d.nCp = nCp;
-    d.nVp = nVp;
-    std::vector<int64_t> cpBlk(cp.order), vpBlk(vp.order);
-    d.cpA = c->upload(cp.pA); d.cpF = c->upload(cp.pB); d.cpB0 = c->upload(cp.b0); d.cpB1 = c->upload(cp.b1);
-    d.cpBlk = c->upload(cpBlk); d.cpRow = c->upload(cp.row);
-    d.vpA = c->upload(vp.pA); d.vpB = c->upload(vp.pB); d.vpB0 = c->upload(vp.b0); d.vpB1 = c->upload(vp.b1);
-    d.vpBlk = c->upload(vpBlk); d.vpRow = c->upload(vp.row); d.vpMir = c->upload(vpmir);
-    d.cfOff = c->upload(cfOff); d.vfOff = c->upload(vfOff);
-    d.Cf = c->dalloc<double>(cfOff[nCp]);
-    d.Vf = c->dalloc<double>(vfOff[nVp]);
-    d.nrmC = c->dalloc<double>(4 * c->nC);
-    d.nrmV = c->dalloc<double>(4 * c->nV);
-    d.dmax = c->dalloc<double>((int64_t)N * N);
-    d.dss = c->dalloc<double>((int64_t)N * N);
-    d.keepC = c->dalloc<uint8_t>(c->nC);
-    d.keepV = c->dalloc<uint8_t>(c->nV);
-    d.keepD = c->dalloc<uint8_t>((int64_t)N * N);
-    d.cval = c->dalloc<double>(nCp);
-    d.dnrm = c->dalloc<double>((int64_t)N * N);
-    d.Svp = c->dalloc<double>(nVp);
-    d.aliveC = c->dalloc<uint8_t>(nCp);
-    d.aliveV = c->dalloc<uint8_t>(nVp);
-    d.nSlot = nSlot;
-    d.slotB = c->upload(c->slotB); d.slotX = c->upload(c->slotX); d.hOff = c->upload(hOff);
-    d.hSlotMap = c->upload(slotmap);
-    d.need = c->dalloc<uint8_t>(nSlot);
-    d.H = nullptr;   // work buffers of a precision are allocated on its first evaluation
-    c->n_cf = cfOff[nCp];
-    c->n_vf = vfOff[nVp];
-    c->n_h = hOff[nSlot];
-
-    d.nUnit = (int)c->unitCp.size();
-    std::vector<int> unitOrder(d.nUnit);
-    {
-      std::iota(unitOrder.begin(), unitOrder.end(), 0);
-      auto mt = [&](int u) { return (c->nabf[cp.pA[c->unitCp[u]]] + 15) / 16; };
-      std::stable_sort(unitOrder.begin(), unitOrder.end(), [&](int a, int b) { return mt(a) < mt(b); });
-      for (int m = 0; m <= lrx::kMaxAlphaTiles + 1; ++m) d.mtStart[m] = 0;
-      for (int u = 0; u < d.nUnit; ++u) d.mtStart[mt(u) + 1]++;
-      for (int m = 0; m <= lrx::kMaxAlphaTiles; ++m) d.mtStart[m + 1] += d.mtStart[m];
-    }
-    d.unitOrder = c->upload(unitOrder);
-    c->unitOrderHost = unitOrder;
-    for (int m = 0; m <= lrx::kMaxAlphaTiles + 1; ++m) c->mtStartHost[m] = d.mtStart[m];
-    {
-      std::vector<int2> items(d.nUnit);
-      for (int k = 0; k < d.nUnit; ++k) items[k] = make_int2(0, unitOrder[k]);
-      int2* it = c->upload(items);
-      c->tl = lrx::TripleLaunch{};
-      for (int mt = 1; mt <= lrx::kMaxAlphaTiles; ++mt) {
-        c->tl.items[mt] = it + d.mtStart[mt];
-        c->tl.n[mt] = d.mtStart[mt + 1] - d.mtStart[mt];
-      }
-      c->tl.counters = c->dalloc<int>(8 * (lrx::kMaxAlphaTiles + 1));
-    }
-    d.slotRow = c->upload(slotRow);
-    d.nHB = (int)hbB.size();
-    d.hbB = c->upload(hbB);
-    d.hbR0 = c->upload(hbR0);
-    d.hbC0 = c->upload(hbC0);
-    d.hColRow = c->upload(hColRow);
-    d.hColSlot = c->upload(hColSlot);
-    d.hColX = c->upload(hColX);
-    d.hColD = c->upload(hColD);
-    d.hColAtom = c->upload(hColAtom);
-    d.unitCp = c->upload(c->unitCp); d.unitK0 = c->upload(c->unitK0); d.unitK1 = c->upload(c->unitK1);
-    d.unitKc = c->upload(c->unitKc); d.nkc = c->upload(c->nkc);
-    d.unitV0 = c->upload(c->unitV0); d.unitV1 = c->upload(c->unitV1); d.unitS = c->upload(c->unitS);
-    d.unitYonly = c->upload(c->unitYonly);
-    d.unitRole = c->dalloc<uint8_t>((int64_t)c->unitYonly.size());
-    d.nsplit = c->upload(c->nsplit);
-    d.tBase = c->upload(c->tBase); d.zOff = c->upload(zOff);
-    d.triHF = c->upload(triHF); d.triHA = c->upload(triHA);
-    d.hdRow = c->upload(hdRow); d.hdRowD = c->upload(hdRowD); d.hdG = c->upload(hdG); d.hdCp = c->upload(hdCp);
-    d.hdCf = c->upload(hdCf); d.hdStride = c->upload(hdStride);
-    d.hcK = c->dalloc<int>(N);
-    d.hcNcol = c->dalloc<int>(N);
-    d.hcRowD = c->dalloc<int>((int64_t)hdRowD.size());
-    d.hcG = c->dalloc<int>((int64_t)hdRowD.size());
-    d.hcCp = c->dalloc<int>((int64_t)hdRowD.size());
-    d.hcCf = c->dalloc<int64_t>((int64_t)hdRowD.size());
-    d.hcStride = c->dalloc<int>((int64_t)hdRowD.size());
-    d.hcColSlot = c->dalloc<int>((int64_t)hColSlot.size());
-    d.hcColD = c->dalloc<int>((int64_t)hColSlot.size());
-    d.hcColAtom = c->dalloc<int>((int64_t)hColSlot.size());
-    d.Zbuf = nullptr;
-    c->n_z = zOff[ntri];
-    std::vector<int64_t> yOff(nCp + 1, 0);
-    for (int i = 0; i < nCp; ++i) yOff[i + 1] = yOff[i] + (cfOff[i + 1] - cfOff[i]) * c->nsplit[i];
-    d.yOff = c->upload(yOff);
-    d.Ybuf = nullptr;
-    c->n_y = yOff[nCp];
-    c->have_f32 = c->have_f64 = false;
-    d.Cf32 = nullptr; d.Vf32 = nullptr; d.D32 = nullptr; d.H32 = nullptr; d.Zbuf32 = nullptr; d.Ybuf32 = nullptr;
-    d.gC = c->dalloc<double>(3 * c->nC);
-    d.gV = c->dalloc<double>(3 * c->nV);
-    d.Ep = c->dalloc<double>(nVp);
-    d.atCfRow = c->upload(atCfRow); d.atCf = c->upload(atCf);
-    d.atCsRow = c->upload(atCsRow); d.atCs = c->upload(atCs);
-    d.atVfRow = c->upload(atVfRow); d.atVf = c->upload(atVf);
-    d.atVsRow = c->upload(atVsRow); d.atVs = c->upload(atVs);
-    d.out = c->dalloc<double>(1 + 3 * N + 9);
-    d.err = c->dalloc<int>(1);
-    g_pinned.put(c->h_out, c->h_out_bytes);
-    c->h_out = nullptr;
-    c->h_out_bytes = sizeof(double) * (1 + 3 * N + 9);
-    c->h_out = (double*)g_pinned.get(c->h_out_bytes);
-
-    // ---- value validation on the device ------------------------------------
-    HIPCHK(hipMemsetAsync(d.err, 0, sizeof(int), c->stream));
-    lrx::launch_validate_finite(d.Cval, C->nval, d.err, 1, c->stream);
-    lrx::launch_validate_finite(d.Cdval, 3 * C->nval, d.err, 1, c->stream);
-    // V and dV: finiteness is checked by the mirror pass of launch_validate
-    lrx::launch_validate(d, c->stream);
-    HIPCHK(hipGetLastError());
-    int herr = 0;
-    HIPCHK(hipMemcpyAsync(&herr, d.err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (herr) {
-      std::string m = "invalid tensor values:";
-      if (herr & 1) m += " non-finite C/dC;";
-      if (herr & 2) m += " non-finite V/dV;";
-      if (herr & 4) m += " non-finite D;";
-      if (herr & 8) m += " V(B,A,-R) != V(A,B,R)^T;";
-      if (herr & 16) m += " dV(B,A,-R) != -dV(A,B,R)^T;";
-      if (herr & 32) m += " on-site C block not symmetric in (a,f);";
-      if (herr & 64) m += " D not symmetric;";
-      c->free_tensors();
-      throw Fail{LRX_EINVAL, m};
-    }
-    c->have_tensors = true;
-    c->gen = g_gen++;
+      double* out = c->dalloc<double>(ns * ns);
+      lrx::launch_bvk_expand(src, nk, nt0, out, c->stream);
+      return out;
+    };
+    double* DscRe = expand(Dre);
+    double* DscIm = Dim ? expand(Dim) : nullptr;
+    km.Dim = DscIm;
+    build_tensors(c, &C2, &V2, DscRe, true, on_device != 0, &km);
+    c->DscIm = DscIm;
   });
 }
 
@@ -875,6 +1066,54 @@ void prepare(lrx_ctx* c, const lrx_options* opts) {
     c->have_f32 = true;
     c->gen = g_gen++;
   }
+}
+
+// One evaluation with k-point sampling: the screening and contraction kernels
+// on the supercell (home-cell rows), once with the real part of D and, for a
+// complex D, once more with its imaginary part.  The kernels weigh a quartet
+// with M_AB M_GF + M_FB M_GA (H(B,X) reads the rows G of M).  For a
+// Hermitian D, Re[D_AB D*_FG + D_AG D*_FB] is that weight of the symmetric
+// real part minus that weight of the antisymmetric imaginary part, so E, F,
+// sigma and the block gradients are the first pass minus the second.  Both
+// passes keep the same blocks: C and V are real, and the D screen measures
+// the modulus.
+void bvk_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, double* sigma) {
+  prepare(c, opts);
+  require(!(opts->theta_cs > 0), "k-point sampling: step 2 (theta_cs > 0) is not available");
+  const lrx::Opts o = make_opts(opts);
+  const int64_t nout = 1 + 3 * (int64_t)c->N + 9;
+  for (int mt = 0; mt <= lrx::kMaxAlphaTiles; ++mt) c->tl.mode[mt] = 1;
+  Dev d = c->dev;
+  const int passes = c->DscIm ? 2 : 1;
+  if (passes == 2 && !c->keep2) c->keep2 = c->dalloc<double>(3 * c->nC + 3 * c->nV + nout);
+  for (int pass = 0; pass < passes; ++pass) {
+    if (pass == 1) {
+      if (c->nC)
+        HIPCHK(hipMemcpyAsync(c->keep2, d.gC, sizeof(double) * 3 * c->nC, hipMemcpyDeviceToDevice, c->stream));
+      if (c->nV)
+        HIPCHK(hipMemcpyAsync(c->keep2 + 3 * c->nC, d.gV, sizeof(double) * 3 * c->nV, hipMemcpyDeviceToDevice,
+                              c->stream));
+      HIPCHK(hipMemcpyAsync(c->keep2 + 3 * c->nC + 3 * c->nV, d.out, sizeof(double) * nout,
+                            hipMemcpyDeviceToDevice, c->stream));
+      d.D = c->DscIm;
+    }
+    lrx::launch_screen(d, o, c->stream, nullptr);
+    c->tl.devs.s[0] = d;
+    lrx::launch_contract(d, c->tl, opts->precision, c->stream, c->side.data(), c->fork.data(), nullptr, nullptr);
+  }
+  if (passes == 2) {
+    lrx::launch_sub_from(c->keep2, d.gC, 3 * c->nC, c->stream);
+    lrx::launch_sub_from(c->keep2 + 3 * c->nC, d.gV, 3 * c->nV, c->stream);
+    lrx::launch_sub_from(c->keep2 + 3 * c->nC + 3 * c->nV, d.out, nout, c->stream);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_out, d.out, sizeof(double) * nout, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->timed = false;
+  c->evaluated = true;
+  if (E) *E = c->h_out[0];
+  if (F) std::memcpy(F, c->h_out + 1, sizeof(double) * 3 * c->N0);
+  if (sigma) std::memcpy(sigma, c->h_out + 1 + 3 * c->N, sizeof(double) * 9);
 }
 
 }  // namespace
@@ -1265,6 +1504,10 @@ extern "C" {
 
 int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, double* sigma) {
   return guarded(c, [&] {
+    if (c->bvk) {
+      bvk_evaluate(c, opts, E, F, sigma);
+      return;
+    }
     prepare(c, opts);
     lrx_ctx* one[1] = {c};
     // launch shapes from the autotuner; the captured graph unless stage
@@ -1306,6 +1549,7 @@ int lrx_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, doub
 int lrx_submit(lrx_ctx* c, const lrx_options* opts, int64_t* ticket) {
   return guarded(c, [&] {
     require(ticket != nullptr, "ticket: NULL");
+    require(!c->bvk, "lrx_submit: k-point contexts are evaluated with lrx_evaluate");
     require(opts != nullptr, "opts: NULL");
     require(opts->timing == 0, "lrx_submit: stage times need lrx_evaluate");
     prepare(c, opts);
@@ -1360,6 +1604,7 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
   return guarded(c0, [&] {
     for (int i = 0; i < n; ++i) {
       require(ctxs[i]->device == c0->device, "batch: contexts on different devices");
+      require(!ctxs[i]->bvk, "batch: k-point contexts are evaluated with lrx_evaluate");
       for (int j = 0; j < i; ++j) require(ctxs[i] != ctxs[j], "batch: a context appears twice");
       prepare(ctxs[i], opts);
     }
@@ -1391,6 +1636,7 @@ int lrx_evaluate_batch(lrx_ctx* const* ctxs, int32_t n, const lrx_options* opts,
 int lrx_evaluate_noalloc(lrx_ctx* c, const lrx_options* opts, double* E, double* F, double* sigma) {
   return guarded(c, [&] {
     require(opts != nullptr, "opts: NULL");
+    require(!c->bvk, "lrx_evaluate_noalloc: k-point contexts are evaluated with lrx_evaluate");
     require(c->have_tensors, "evaluation before lrx_set_tensors");
     const int prec = opts->precision;
     require(prec == LRX_FP64 || prec == LRX_FP32 || prec == LRX_BF16X3, "unknown precision");
@@ -1459,6 +1705,7 @@ int lrx_evaluate_noalloc(lrx_ctx* c, const lrx_options* opts, double* E, double*
 
 int lrx_hamiltonian(lrx_ctx* c, const lrx_options* opts, double* E, double* Hx, int32_t hx_on_device) {
   return guarded(c, [&] {
+    require(!c->bvk, "lrx_hamiltonian: not available with k-point sampling");
     prepare(c, opts);
     require(opts->precision == LRX_FP64, "the Hamiltonian is computed in FP64 only");
     Dev& d = c->dev;

@@ -1132,16 +1132,23 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
   const int p = blockIdx.x;
   const int A = d.vpA[p], B = d.vpB[p];
   if (A > B) return;   // written by the mirror pair (B,A)
-  const bool mirror = A < B;
   const int pm = d.vpMir[p];
+  // the mirror's gradients and energy term are written here when the mirror
+  // pair returns above (always at the Gamma point); on a k-point supercell
+  // the mirror of a pair that crosses cells is another home-cell pair with
+  // A < B, which writes its own
+  const bool mirror = A < B && d.vpA[pm] > d.vpB[pm];
   const int mA = d.nabf[A], mB = d.nabf[B], n = mA * mB;
   if (!d.aliveV[p]) {
     for (int k = d.vpB0[p] + threadIdx.x; k < d.vpB1[p]; k += kNT) {
       const int64_t b = d.vpBlk[k], bm = d.Vmir[b];
       d.gV[3 * b] = d.gV[3 * b + 1] = d.gV[3 * b + 2] = 0.0;
-      d.gV[3 * bm] = d.gV[3 * bm + 1] = d.gV[3 * bm + 2] = 0.0;
+      if (mirror) d.gV[3 * bm] = d.gV[3 * bm + 1] = d.gV[3 * bm + 2] = 0.0;
     }
-    if (threadIdx.x == 0) d.Ep[p] = d.Ep[pm] = 0.0;
+    if (threadIdx.x == 0) {
+      d.Ep[p] = 0.0;
+      if (mirror) d.Ep[pm] = 0.0;
+    }
     return;
   }
   {

@@ -76,6 +76,11 @@ struct Dev {
   const double* Vval; const double* Vdval;
   const int64_t* Vmir;    // mirror block (second, first, -R)
   const double* D;        // [ntot][ntot]
+  // the matrices the D screen measures: DnRe (= D at the Gamma point) and,
+  // for a complex density matrix, its imaginary part DnIm (else nullptr); the
+  // screen then takes the modulus, so both real passes of a complex D keep
+  // the same pairs
+  const double* DnRe; const double* DnIm;
 
   // pairs
   int nCp, nVp;
@@ -181,7 +186,19 @@ __host__ __device__ inline bool triple_live(int aliveC, int aliveV, bool b_below
 }
 
 // kernels (lrx_screen.hip)
+// Value checks of the inputs (mirror blocks, on-site symmetry, finiteness of
+// V and D); the symmetry of D is checked by launch_validate_dsym.
 void launch_validate(const Dev& d, hipStream_t s);
+// D[i][j] == D[j][i] (anti = 0) or == -D[j][i] (anti = 1) within rounding,
+// for a dense [nt][nt] matrix; a failure sets kErrDSym in *err.
+void launch_validate_dsym(const double* D, int64_t nt, int anti, int* err, hipStream_t s);
+// k-point sampling (lrx_kpoint.hip).  The Born-von Karman supercell of
+// nk0 x nk1 x nk2 cells, atom (t, i) at index t * N0 + i: the dense supercell
+// matrix Dsc[(t, i)][(u, j)] = Dk[u - t][i][j] (offsets modulo nk, flat index
+// r0 + nk0 (r1 + nk1 r2)) from Dk[n_cells][nt][nt].
+void launch_bvk_expand(const double* Dk, const int* nk, int64_t nt, double* Dsc, hipStream_t s);
+// x[i] = keep[i] - x[i] for i < n (the second real pass of a complex D).
+void launch_sub_from(const double* keep, double* x, int64_t n, hipStream_t s);
 // for_hx: the H slots the Hamiltonian reads (every triple whose C pair and V
 // pair have value-list blocks) instead of those of the forces
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev, bool for_hx = false);

@@ -121,14 +121,14 @@ __global__ void k_val_onsite(Dev d) {
   }
 }
 
-// D = D^T, checked on the 32 x 32 tiles (tr, tc) with tr <= tc: tile (tc, tr)
-// is read along its rows into LDS and compared transposed.  Workgroup w
-// takes tiles w, w + gridDim.x, ... of the T x T tiles and skips those
-// below the diagonal (the skip is uniform over the workgroup).
-__global__ void __launch_bounds__(kNT) k_val_dsym(Dev d) {
+// D = D^T (anti: D = -D^T), checked on the 32 x 32 tiles (tr, tc) with
+// tr <= tc: tile (tc, tr) is read along its rows into LDS and compared
+// transposed.  Workgroup w takes tiles w, w + gridDim.x, ... of the T x T
+// tiles and skips those below the diagonal (the skip is uniform over the
+// workgroup).
+__global__ void __launch_bounds__(kNT) k_val_dsym(const double* D, int64_t nt, double sgn, int* err) {
   constexpr int kT = 32;
   __shared__ double tile[kT][kT + 1];
-  const int64_t nt = d.ntot;
   const int64_t T = (nt + kT - 1) / kT;
   int bad = 0;
   for (int64_t w = blockIdx.x; w < T * T; w += gridDim.x) {
@@ -137,24 +137,27 @@ __global__ void __launch_bounds__(kNT) k_val_dsym(Dev d) {
     const int64_t r0 = tr * kT, c0 = tc * kT;
     for (int e = threadIdx.x; e < kT * kT; e += kNT) {
       const int i = e / kT, j = e % kT;
-      if (c0 + i < nt && r0 + j < nt) tile[i][j] = d.D[(c0 + i) * nt + r0 + j];
+      if (c0 + i < nt && r0 + j < nt) tile[i][j] = D[(c0 + i) * nt + r0 + j];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kT * kT; e += kNT) {
       const int i = e / kT, j = e % kT;
       const int64_t r = r0 + i, c = c0 + j;
-      if (c > r && c < nt && !close_rel(d.D[r * nt + c], tile[j][i])) bad = 1;
+      if (c > r && c < nt && !close_rel(D[r * nt + c], sgn * tile[j][i])) bad = 1;
     }
     __syncthreads();
   }
-  if (bad) atomicOr(d.err, kErrDSym);
+  if (bad) atomicOr(err, kErrDSym);
+}
+
+void launch_validate_dsym(const double* D, int64_t nt, int anti, int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_val_dsym, dim3(2048), dim3(kNT), 0, s, D, nt, anti ? -1.0 : 1.0, err);
 }
 
 void launch_validate(const Dev& d, hipStream_t s) {
   const int g = 2048;
   if (d.nV) hipLaunchKernelGGL(k_val_vmirror, dim3((unsigned)d.nV), dim3(kNT), 0, s, d);
   if (d.nC) hipLaunchKernelGGL(k_val_onsite, dim3((unsigned)d.nC), dim3(kNT), 0, s, d);
-  hipLaunchKernelGGL(k_val_dsym, dim3(g), dim3(kNT), 0, s, d);
   hipLaunchKernelGGL(k_val_finite, dim3(g), dim3(kNT), 0, s, d.D, d.ntot * d.ntot, d.err, (int)kErrNonfiniteD);
 }
 
@@ -204,13 +207,16 @@ __global__ void k_d_norms(Dev d) {
   const int X = (int)(t / d.N), Y = (int)(t % d.N);
   if (Y < X) return;
   const int nX = d.nao[X], nY = d.nao[Y];
-  const double* p = d.D + d.ao[X] * d.ntot + d.ao[Y];
+  const int64_t o = d.ao[X] * d.ntot + d.ao[Y];
+  const double* p = d.DnRe + o;
+  const double* q = d.DnIm ? d.DnIm + o : nullptr;   // a complex D: the modulus
   double mx = 0, ss = 0;
   for (int i = 0; i < nX; ++i)
     for (int j = 0; j < nY; ++j) {
-      const double v = p[i * d.ntot + j];
-      mx = fmax(mx, fabs(v));
-      ss += v * v;
+      const double v = p[i * d.ntot + j], w = q ? q[i * d.ntot + j] : 0.0;
+      const double v2 = v * v + w * w;
+      mx = fmax(mx, q ? sqrt(v2) : fabs(v));
+      ss += v2;
     }
   d.dmax[t] = mx;
   d.dss[t] = ss;
@@ -275,7 +281,8 @@ __global__ void k_screen_s(Dev d) {
     }
   }
   d.Svp[p] = s;
-  d.Svp[d.vpMir[p]] = s;
+  const int pm = d.vpMir[p];
+  if (d.vpA[pm] > d.vpB[pm]) d.Svp[pm] = s;   // a mirror that crosses cells of a k-point supercell writes its own
 }
 
 // V blocks: step 1 with the mirror, then step 2; pair liveness.

@@ -90,7 +90,7 @@ EXPORTS = ["lrx_create", "lrx_set_structure", "lrx_set_tensors", "lrx_evaluate",
            "lrx_keep_masks", "lrx_get_stats", "lrx_stage_times", "lrx_stage_name", "lrx_evaluate_batch",
            "lrx_batch_tuning", "lrx_last_error", "lrx_destroy", "lrx_pool_trim", "lrx_group_times",
            "lrx_submit", "lrx_wait", "lrx_evaluate_noalloc", "lrx_enumerate_pairs", "lrx_hamiltonian",
-           "lrx_hamiltonian_info", "lrx_prepare_c"]
+           "lrx_hamiltonian_info", "lrx_prepare_c", "lrx_set_kpoint_tensors"]
 
 
 def load(path: Optional[str] = None):
@@ -106,6 +106,8 @@ def load(path: Optional[str] = None):
     lib.lrx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp]
     lib.lrx_set_structure.argtypes = [vp, ctypes.c_int32, _f64p, _f64p, _i32p, _i32p]
     lib.lrx_set_tensors.argtypes = [vp, ctypes.POINTER(Blocks), ctypes.POINTER(Blocks), vp, ctypes.c_int32]
+    lib.lrx_set_kpoint_tensors.argtypes = [vp, _i32p, ctypes.POINTER(Blocks), ctypes.POINTER(Blocks), vp, vp,
+                                           ctypes.c_int32]
     lib.lrx_evaluate.argtypes = [vp, ctypes.POINTER(Options), _f64p, _f64p, _f64p]
     lib.lrx_block_gradients.argtypes = [vp, _f64p, _f64p]
     lib.lrx_keep_masks.argtypes = [vp, _u8p, _u8p, _u8p]
@@ -160,6 +162,7 @@ class Context:
         self._keep = []
         self.natom = 0
         self.nC = self.nV = 0
+        self.ncell = 1   # cells of the k-point supercell (1: the Gamma point)
 
     def _check(self, rc, init=False):
         if rc != 0:
@@ -170,6 +173,7 @@ class Context:
         self._tau, self._lat = _np(tau, np.float64), _np(lat, np.float64)
         self._nao, self._nabf = _np(nao, np.int32), _np(nabf, np.int32)
         self.natom = int(self._nao.shape[0])
+        self.ncell = 1
         self._check(self.lib.lrx_set_structure(self.h, self.natom, _ptr(self._tau, _f64p), _ptr(self._lat, _f64p),
                                                _ptr(self._nao, _i32p), _ptr(self._nabf, _i32p)))
 
@@ -214,6 +218,43 @@ class Context:
         self._check(self.lib.lrx_set_tensors(self.h, ctypes.byref(bc), ctypes.byref(bv), ctypes.c_void_p(dptr), int(dc)))
         self._keep = keep
         self.nC, self.nV = int(bc.nblk), int(bv.nblk)
+        self.ncell = 1
+
+    def set_kpoint_tensors(self, nk, C: Dict, V: Dict, Dk):
+        """lrx_set_kpoint_tensors: Dk [n_cells][n_tot][n_tot], complex or real
+        (numpy, or a torch tensor on the context's device), per offset
+        r = r0 + nk0 (r1 + nk1 r2) of the Born-von Karman supercell."""
+        keep = []
+        bc, dc = self._blocks(C, keep)
+        bv, dv = self._blocks(V, keep)
+        nkv = np.ascontiguousarray(nk, np.int32)
+        assert nkv.shape == (3,)
+        keep.append(nkv)
+        if hasattr(Dk, "data_ptr"):
+            import torch
+
+            dd = Dk.is_cuda
+            re = Dk.real.contiguous() if Dk.is_complex() else Dk.to(torch.float64).contiguous()
+            im = Dk.imag.contiguous() if Dk.is_complex() else None
+            keep += [re] + ([im] if im is not None else [])
+            pre, pim = re.data_ptr(), (im.data_ptr() if im is not None else None)
+        else:
+            Dn = np.asarray(Dk)
+            re = np.ascontiguousarray(Dn.real, np.float64)
+            im = np.ascontiguousarray(Dn.imag, np.float64) if np.iscomplexobj(Dn) else None
+            keep += [re] + ([im] if im is not None else [])
+            pre, pim, dd = re.ctypes.data, (im.ctypes.data if im is not None else None), False
+        if not (dc == dv == dd):
+            raise ValueError("C, V and D must all be on the device or all on the host")
+        if dc:
+            import torch
+
+            torch.cuda.current_stream().synchronize()
+        self._check(self.lib.lrx_set_kpoint_tensors(self.h, _ptr(nkv, _i32p), ctypes.byref(bc), ctypes.byref(bv),
+                                                    ctypes.c_void_p(pre), ctypes.c_void_p(pim), int(dc)))
+        self._keep = keep
+        self.nC, self.nV = int(bc.nblk), int(bv.nblk)
+        self.ncell = int(np.prod(nkv))
 
     def evaluate(self, theta=0.0, theta_cs=0.0, precision="fp64", timing=False, thresholds=None):
         """lrx_evaluate; thresholds = (C, V, D, dC, dV) for per-tensor screening."""
@@ -287,7 +328,8 @@ class Context:
 
     def keep_masks(self):
         kC, kV = np.zeros(self.nC, np.uint8), np.zeros(self.nV, np.uint8)
-        kD = np.zeros(self.natom * self.natom, np.uint8)
+        ns = self.natom * self.ncell   # supercell atoms with k-point sampling
+        kD = np.zeros(ns * ns, np.uint8)
         self._check(self.lib.lrx_keep_masks(self.h, _ptr(kC, _u8p), _ptr(kV, _u8p), _ptr(kD, _u8p)))
         return kC, kV, kD
 
