@@ -225,6 +225,7 @@ struct lrx_ctx {
   Pairs cp, vp;
   std::vector<int> slotB, slotX, unitCp, unitK0, unitK1, unitKc, unitV0, unitV1, unitS, nkc, nsplit;
   std::vector<uint8_t> unitYonly;
+  std::vector<uint8_t> vpZown;   // per V pair: 1 if this pair forms Z (of a pair and its mirror, exactly one)
   std::vector<int64_t> tBase;
   int max_mm = 1, max_depth = 4;
   // sizes of the FP32 buffers of the reduced-precision forms
@@ -440,6 +441,47 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
       vmir[b] = bm;
     }
   }
+  // Z(B,A) = Z(A,B)^T: of a pair and its mirror the one with the lower index
+  // forms Z and writes both pairs' energy terms and V gradients (at the Gamma
+  // point: the pair with B >= A).  The V pairs of every atom are then put in
+  // the order (forms Z, partner), so the pairs that form Z are one range and a
+  // work unit forms Z for all of its V pairs or for none.  At the Gamma point
+  // that order is the sorted order.
+  {
+    std::vector<uint8_t> zown(nVp);
+    for (int p = 0; p < nVp; ++p) zown[p] = p <= vpmir[p];
+    std::vector<int> perm(nVp);   // new position -> pair in sorted order
+    bool moved = false;
+    for (int A = 0; A < N; ++A) {
+      int k = vp.row[A];
+      for (int z = 0; z < 2; ++z)
+        for (int p = vp.row[A]; p < vp.row[A + 1]; ++p)
+          if (zown[p] == z) {
+            moved = moved || p != k;
+            perm[k++] = p;
+          }
+    }
+    if (moved) {
+      std::vector<int> inv(nVp), mir(nVp);
+      for (int q = 0; q < nVp; ++q) inv[perm[q]] = q;
+      Pairs w = vp;
+      std::vector<uint8_t> z2(nVp);
+      for (int q = 0; q < nVp; ++q) {
+        const int o = perm[q];
+        w.pA[q] = vp.pA[o];
+        w.pB[q] = vp.pB[o];
+        w.b0[q] = vp.b0[o];
+        w.b1[q] = vp.b1[o];
+        mir[q] = inv[vpmir[o]];
+        z2[q] = zown[o];
+      }
+      c->vp = std::move(w);
+      vpmir = std::move(mir);
+      zown = std::move(z2);
+    }
+    c->vpZown = std::move(zown);
+  }
+  const std::vector<uint8_t>& zown = c->vpZown;
   // ---- per-pair sizes and offsets --------------------------------------
   std::vector<int64_t> cfOff(nCp + 1, 0), vfOff(nVp + 1, 0);
   for (int i = 0; i < nCp; ++i)
@@ -548,9 +590,10 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
       c->nsplit[i] = (int)std::max<int64_t>(1, std::min<int64_t>({want, (int64_t)nv, 16}));
     }
   }
-  // The V partners of A (sorted by B) fall in two ranges: B < A, where only
-  // Y is formed (Z(A,B) is the transpose of Z(B,A), formed by the units of
-  // atom B), and B >= A, where Z and Y are both formed.  Each range is
+  // The V partners of A fall in two ranges: the pairs whose mirror forms Z,
+  // where only Y is formed (Z(A,B) is the transpose of the mirror's Z,
+  // formed by the units of the mirror's atom; at the Gamma point B < A), and
+  // the pairs that form Z, where Z and Y are both formed.  Each range is
   // divided into its share of the C pair's nsplit V ranges.
   c->unitYonly.clear();
   for (int i = 0; i < nCp; ++i) {
@@ -562,7 +605,8 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
     int cnt = 0;
     const int A = cp.pA[i];
     const int r0 = vp.row[A], r1 = vp.row[A + 1], nv = r1 - r0, ns = c->nsplit[i];
-    const int mid = (int)(std::lower_bound(vp.pB.begin() + r0, vp.pB.begin() + r1, A) - vp.pB.begin());
+    int mid = r0;
+    while (mid < r1 && !zown[mid]) ++mid;
     const int ny = mid - r0, nz = r1 - mid;
     const int nsY = ny > 0 ? std::max(1, (int)(((int64_t)ns * ny + nv / 2) / std::max(1, nv))) : 0;
     const int nsZ = nz > 0 ? std::max(1, ns - nsY) : 0;
@@ -597,8 +641,8 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
     for (int i = cp.row[A]; i < cp.row[A + 1]; ++i)
       for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
         const int64_t t = c->tBase[A] + (int64_t)(i - cp.row[A]) * nvA + (p - vp.row[A]);
-        // Z partials only where Z(A,B) is formed (B >= A)
-        zOff[t + 1] = vp.pB[p] >= A ? (int64_t)c->nkc[i] * c->nabf[A] * c->nabf[vp.pB[p]] : 0;
+        // Z partials only where Z(A,B) is formed
+        zOff[t + 1] = zown[p] ? (int64_t)c->nkc[i] * c->nabf[A] * c->nabf[vp.pB[p]] : 0;
       }
   }
   for (int64_t t = 0; t < ntri; ++t) zOff[t + 1] += zOff[t];
@@ -710,6 +754,7 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
   d.cpBlk = c->upload(cpBlk); d.cpRow = c->upload(cp.row);
   d.vpA = c->upload(vp.pA); d.vpB = c->upload(vp.pB); d.vpB0 = c->upload(vp.b0); d.vpB1 = c->upload(vp.b1);
   d.vpBlk = c->upload(vpBlk); d.vpRow = c->upload(vp.row); d.vpMir = c->upload(vpmir);
+  d.vpZ = c->upload(zown);
   d.cfOff = c->upload(cfOff); d.vfOff = c->upload(vfOff);
   d.Cf = c->dalloc<double>(cfOff[nCp]);
   d.Vf = c->dalloc<double>(vfOff[nVp]);
@@ -1097,7 +1142,13 @@ void bvk_evaluate(lrx_ctx* c, const lrx_options* opts, double* E, double* F, dou
                             hipMemcpyDeviceToDevice, c->stream));
       d.D = c->DscIm;
     }
-    lrx::launch_screen(d, o, c->stream, nullptr);
+    // the second pass keeps every decision, list and folded block of the
+    // first (they do not depend on D's values beyond the modulus the D
+    // screen measured); only D's FP32 copy changes
+    if (pass == 0)
+      lrx::launch_screen(d, o, c->stream, nullptr);
+    else
+      lrx::launch_d_to_f32(d, opts->precision, c->stream);
     c->tl.devs.s[0] = d;
     lrx::launch_contract(d, c->tl, opts->precision, c->stream, c->side.data(), c->fork.data(), nullptr, nullptr);
   }
@@ -1195,11 +1246,11 @@ int lrx_get_stats(lrx_ctx* c, lrx_stats* s) {
       const int A = cp.pA[i], Fa = cp.pB[i];
       for (int p = vp.row[A]; p < vp.row[A + 1]; ++p) {
         const int B = vp.pB[p];
-        if (!lrx::triple_live(aC[i], aV[p], B < A)) continue;
+        if (!lrx::triple_live(aC[i], aV[p], !c->vpZown[p])) continue;
         s->alive_triples++;
-        // Y and (when this unit forms it: B >= A and Cf(A,F) live; the other
-        // half is the transpose) Z, and the X-build
-        const double zy = lrx::unit_y_only(aC[i], B < A) ? 2.0 : 4.0;
+        // Y and (when this unit forms it: the pair forms Z and Cf(A,F) is
+        // live; the mirror's Z is the transpose) Z, and the X-build
+        const double zy = lrx::unit_y_only(aC[i], !c->vpZown[p]) ? 2.0 : 4.0;
         const double t = zy * nb[A] * nb[B] * na[A] * na[Fa] + 4.0 * nb[B] * na[A] * na[B] * na[Fa];
         ft += t;
         s->flop_triple_group[(nb[A] + 15) / 16] += t;

@@ -721,10 +721,11 @@ __device__ __forceinline__ void xbuild(const UnitGeo& U, int nB, const T* HF, in
   xterm<T, DIRECT, NU, XW, true>(U, nB, HA, hsA, Dfb, X2, ((w - U.N1) % XW + XW) % XW, U.N2, q, g);
 }
 
-// Roles of a wave in a unit: a Z wave (units whose V partners B have B >= A:
-// Z and Y are both formed), a Y wave beside four Z waves, or one of eight Y
-// waves (units whose partners all have B < A: Z(A,B) is the transpose of
-// Z(B,A), which the units of atom B form, so only Y is formed).
+// Roles of a wave in a unit: a Z wave (units whose V pairs form Z, B >= A at
+// the Gamma point: Z and Y are both formed), a Y wave beside four Z waves, or
+// one of eight Y waves (units whose V pairs do not form Z: Z(A,B) is the
+// transpose of the mirror pair's Z, which the units of the mirror's atom
+// form, so only Y is formed).
 enum Role : int { kRoleZ = 0, kRoleY = 1, kRoleY8 = 2 };
 
 template <int MT, int P, int ROLE>
@@ -1056,7 +1057,7 @@ __device__ __forceinline__ void triple_unit(const Dev& d, int u, typename Triple
   // the stage starts zeroed: padding rows the X-build reads past nB are finite
   for (int e = tid; e < Cfg::kStage; e += kTNT) S[e] = T(0);
   __syncthreads();
-  // Y alone when Z is not formed here (partners B < A) or Cf(A,F) folds to
+  // Y alone when Z is not formed here (the mirror pairs form it) or Cf(A,F) folds to
   // zero; then nothing when Y(A,F) is not read, else only V pairs with
   // Vf != 0 (the role is read here, not before the geometry: that placement
   // keeps the persistent FP64 kernels free of register spills)
@@ -1113,10 +1114,10 @@ __global__ void __launch_bounds__(kTNT, 1)
 // ---------------------------------------------------------------------------
 // Z(A,B) = sum over live (A,F) and column chunks of the Z partials; then, in
 // one pass over the pair's blocks, E = -<Vf, Z> and g_v = -<dV_v, Z> (FP64).
-// Only pairs with A <= B: the mirror pair (B,A) has Z(B,A) = Z(A,B)^T and
-// Vf(B,A) = Vf(A,B)^T, so its energy term is the same, and each mirror block
-// (B,A,-R) has dV = -dV(A,B,R)^T, so its gradient is -g_v (input checks hold
-// these symmetries to 1e-12 relative).
+// Only pairs that form Z (A <= B at the Gamma point): the mirror pair (B,A)
+// has Z(B,A) = Z(A,B)^T and Vf(B,A) = Vf(A,B)^T, so its energy term is the
+// same, and each mirror block (B,A,-R) has dV = -dV(A,B,R)^T, so its
+// gradient is -g_v (input checks hold these symmetries to 1e-12 relative).
 // ---------------------------------------------------------------------------
 constexpr int kZB = 4;      // V image blocks contracted per pass over Z
 constexpr int kZMax = 64;   // Z partials (live C pairs x column chunks) of one V pair
@@ -1130,14 +1131,10 @@ __global__ void __launch_bounds__(kNT) k_zgrad(Dev d) {
   __shared__ int nz;
   const T* Zb = Buf<T>::Z(d);
   const int p = blockIdx.x;
+  if (!d.vpZ[p]) return;   // written by the mirror pair, which forms Z
   const int A = d.vpA[p], B = d.vpB[p];
-  if (A > B) return;   // written by the mirror pair (B,A)
   const int pm = d.vpMir[p];
-  // the mirror's gradients and energy term are written here when the mirror
-  // pair returns above (always at the Gamma point); on a k-point supercell
-  // the mirror of a pair that crosses cells is another home-cell pair with
-  // A < B, which writes its own
-  const bool mirror = A < B && d.vpA[pm] > d.vpB[pm];
+  const bool mirror = pm != p;   // the mirror's energy term and V gradients are written here too
   const int mA = d.nabf[A], mB = d.nabf[B], n = mA * mB;
   if (!d.aliveV[p]) {
     for (int k = d.vpB0[p] + threadIdx.x; k < d.vpB1[p]; k += kNT) {

@@ -14,7 +14,9 @@
 //   H        H(B,X)[b][beta][x] = sum_G Cf(B,G)[beta][b][g] D(G,X)[g][x] for
 //            every (B,X) a triple (A,F,B) needs (X = A or X = F); beta runs
 //            over the ABFs of B rounded up to 16 (padding rows stay zero);
-//   Zbuf     per triple (A,F,B) with A <= B and column chunk: the F-partial of
+//   Zbuf     per triple (A,F,B) whose V pair forms Z (vpZ: of a pair and its
+//            mirror the one with the lower index; A <= B at the Gamma point)
+//            and column chunk: the F-partial of
 //            Z(A,B)[alpha][beta] = sum_{F,a,f} Cf(A,F)[alpha][a][f] X^{AFB}[beta][a][f]
 //            (Z(B,A) = Z(A,B)^T: D is symmetric and the screening keeps
 //            mirror pairs together, so pairs with A > B take the transpose),
@@ -87,6 +89,7 @@ struct Dev {
   const int* cpA; const int* cpF; const int* cpB0; const int* cpB1; const int64_t* cpBlk; const int* cpRow;
   const int* vpA; const int* vpB; const int* vpB0; const int* vpB1; const int64_t* vpBlk; const int* vpRow;
   const int* vpMir;
+  const uint8_t* vpZ;      // 1: the pair forms Z(A,B) (of a pair and its mirror exactly one; B >= A at the Gamma point)
   const int64_t* cfOff; const int64_t* vfOff;
   double* Cf;             // folded C pair blocks [mA][nA][nF] at cfOff
   double* Vf;             // folded V pair blocks [mA][mB padded to 16] at vfOff (zero padding)
@@ -125,7 +128,7 @@ struct Dev {
   int nUnit;
   const int* unitCp; const int* unitK0; const int* unitK1; const int* unitKc;
   const int* unitV0; const int* unitV1; const int* unitS;   // V-pair range and split index of a unit
-  const uint8_t* unitYonly; // 1: every V partner B of the unit has B < A (only Y is formed)
+  const uint8_t* unitYonly; // 1: no V pair of the unit forms Z (only Y is formed; B < A at the Gamma point)
   uint8_t* unitRole;        // per evaluation: 0 no work, 1 Z and Y, 2 Y alone (unit_y_only)
   const int* nsplit;       // [nCp] number of V-pair ranges (Y partials) of a C pair
   const int* unitOrder;    // units grouped by the alpha-tile count of their atom A
@@ -173,15 +176,16 @@ struct Opts {
 // Work of the triple (A,F,B) given the liveness bits of C pair (A,F) and V
 // pair (A,B) (bit 1: a block in the value list, bit 2: one in the
 // derivative list; the joint screening sets both).  Z(A,B) takes
-// Cf(A,F) X^{AFB} and is formed for B >= A (the rest is its transpose); it
-// is read when (A,B) is live at all.  Y(A,F) takes Vf(A,B) X^{AFB} and is
-// read only when (A,F) has a block in the derivative list.  A unit whose C
-// pair has no value-list block, or whose partners all have B < A, forms Y
-// alone (y_only) and then only over V pairs with a value-list block.
-__host__ __device__ inline bool unit_y_only(int aliveC, bool b_below_a) { return b_below_a || !(aliveC & 1); }
-__host__ __device__ inline bool triple_live(int aliveC, int aliveV, bool b_below_a) {
+// Cf(A,F) X^{AFB} and is formed by the V pairs that own it (vpZ; the
+// mirror's Z is its transpose); it is read when (A,B) is live at all.
+// Y(A,F) takes Vf(A,B) X^{AFB} and is read only when (A,F) has a block in
+// the derivative list.  A unit whose C pair has no value-list block, or
+// whose V pairs do not form Z (z_elsewhere), forms Y alone (y_only) and
+// then only over V pairs with a value-list block.
+__host__ __device__ inline bool unit_y_only(int aliveC, bool z_elsewhere) { return z_elsewhere || !(aliveC & 1); }
+__host__ __device__ inline bool triple_live(int aliveC, int aliveV, bool z_elsewhere) {
   if (!aliveC || !aliveV) return false;
-  if (unit_y_only(aliveC, b_below_a)) return (aliveC & 2) && (aliveV & 1);
+  if (unit_y_only(aliveC, z_elsewhere)) return (aliveC & 2) && (aliveV & 1);
   return true;
 }
 
@@ -202,6 +206,9 @@ void launch_sub_from(const double* keep, double* x, int64_t n, hipStream_t s);
 // for_hx: the H slots the Hamiltonian reads (every triple whose C pair and V
 // pair have value-list blocks) instead of those of the forces
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev, bool for_hx = false);
+// Only the FP32 copy of D that the reduced-precision kernels read (nothing at
+// FP64): for a second pass with another D and the same screening decisions.
+void launch_d_to_f32(const Dev& d, int prec, hipStream_t s);
 // kernels (lrx_contract.hip)
 
 // Work of the triple-product kernels: per alpha-tile group MT, a list of

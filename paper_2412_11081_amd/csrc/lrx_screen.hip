@@ -258,13 +258,13 @@ __global__ void k_screen_d(Dev d, Opts o) {
 }
 
 // ---------------------------------------------------------------------------
-// step 2: S(A,B) per V pair (evaluated for A <= B and mirrored)
+// step 2: S(A,B) per V pair (evaluated by the pair that forms Z, and mirrored)
 // ---------------------------------------------------------------------------
 __global__ void k_screen_s(Dev d) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.nVp) return;
+  if (!d.vpZ[p]) return;   // S(A,B) = S(B,A): written by the pair that forms Z
   const int A = d.vpA[p], B = d.vpB[p];
-  if (A > B) return;
   const int N = d.N;
   const double dAB = d.dnrm[(int64_t)A * N + B];
   double s = 0;
@@ -281,8 +281,7 @@ __global__ void k_screen_s(Dev d) {
     }
   }
   d.Svp[p] = s;
-  const int pm = d.vpMir[p];
-  if (d.vpA[pm] > d.vpB[pm]) d.Svp[pm] = s;   // a mirror that crosses cells of a k-point supercell writes its own
+  d.Svp[d.vpMir[p]] = s;
 }
 
 // V blocks: step 1 with the mirror, then step 2; pair liveness.
@@ -388,7 +387,7 @@ __global__ void k_mark(Dev d) {
   const int A = d.cpA[cp], F = d.cpF[cp];
   for (int p = d.vpRow[A]; p < d.vpRow[A + 1]; ++p) {
     const int B = d.vpB[p];
-    if (!triple_live(ac, d.aliveV[p], B < A)) continue;
+    if (!triple_live(ac, d.aliveV[p], !d.vpZ[p])) continue;
     d.need[d.hSlotMap[(int64_t)B * d.N + F]] = 1;
     d.need[d.hSlotMap[(int64_t)B * d.N + A]] = 1;
   }
@@ -493,6 +492,10 @@ __global__ void __launch_bounds__(kNT) k_hcompact(Dev d) {
 }
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)(a > 0 ? (a + b - 1) / b : 1); }
+
+void launch_d_to_f32(const Dev& d, int prec, hipStream_t s) {
+  if (prec != kP64) hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kNT), 0, s, d.D, d.D32, d.ntot * d.ntot);
+}
 
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev, bool for_hx) {
   const int64_t NN = (int64_t)d.N * d.N;

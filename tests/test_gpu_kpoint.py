@@ -152,6 +152,26 @@ def test_per_tensor_thresholds(oracle_lib):
     _compare(_gpu(st, mats, nk, Dk, thresholds=thr), r, st, nk, bits=True)
 
 
+@pytest.mark.parametrize("prec,rel_e,rel_f", [("fp32", 1e-7, 1e-5), ("bf16x3", 1e-6, 1e-4)])
+def test_reduced_precision_forms(oracle_lib, prec, rel_e, rel_f):
+    """The FP32 and BF16x3 forms on the supercell (both passes of a complex D)
+    against the FP64 oracle, with the bounds of the Gamma-point forms: |dE| <=
+    rel_e |E|, and max|d| <= rel_f times the largest magnitude for F, sigma
+    and the block gradients."""
+    H.require_gpu()
+    st, nk = _cell(CELLS[3])
+    mats = st.materialize("cuda")
+    Dk = _dk(st, nk, False)
+    r = oracle_lib.KProblem(st.tau, st.lat, st.nao, st.nabf, mats["C"], mats["V"], nk, Dk).evaluate(
+        0.0, nthreads=H.nthreads())
+    g = _gpu(st, mats, nk, Dk, precision=prec)
+    for name, rel in (("E", rel_e), ("F", rel_f), ("sigma", rel_f), ("gC", rel_f), ("gV", rel_f)):
+        got, ref = np.asarray(g[name], np.float64), np.asarray(r[name], np.float64)
+        err, scale = float(np.max(np.abs(got - ref))), float(np.max(np.abs(ref)))
+        print(f"  {prec} {name}: max abs error {err:.3e} (scale {scale:.3e})", flush=True)
+        assert err <= rel * scale + 1e-12, name
+
+
 def test_host_inputs_and_repeat_bitwise():
     H.require_gpu()
     st, nk = _cell(CELLS[3])
