@@ -169,6 +169,39 @@ void launch_validate_finite(const double* p, int64_t n, int* err, int code, hipS
 // ---------------------------------------------------------------------------
 // step 1: block norms (one workgroup per block)
 // ---------------------------------------------------------------------------
+// max |x| and sum x^2 of this thread's elements i = tid, tid + kNT, ... of
+// p[0, n): eight loads in flight per thread, eight partial sums added in a
+// fixed order
+__device__ inline void block_max_sq(const double* __restrict__ p, int n, double& mx, double& ss) {
+  constexpr int U = 8;
+  double m[U], s[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) m[u] = s[u] = 0.0;
+  int i = threadIdx.x;
+  for (; i + (U - 1) * kNT < n; i += U * kNT) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = p[i + u * kNT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      m[u] = fmax(m[u], fabs(x[u]));
+      s[u] += x[u] * x[u];
+    }
+  }
+  for (; i < n; i += kNT) {
+    const double x = p[i];
+    m[0] = fmax(m[0], fabs(x));
+    s[0] += x * x;
+  }
+#pragma unroll
+  for (int u = 1; u < U; ++u) {
+    m[0] = fmax(m[0], m[u]);
+    s[0] += s[u];
+  }
+  mx = m[0];
+  ss = s[0];
+}
+
 __global__ void __launch_bounds__(kNT) k_block_norms(const double* val, const double* dval, const int64_t* off,
                                                      const int* sz, double* out) {
   __shared__ double sh[kNT / 64 + 1];
@@ -178,16 +211,8 @@ __global__ void __launch_bounds__(kNT) k_block_norms(const double* val, const do
   double mv = 0, sv = 0, md = 0, sd = 0;
   const double* v = val + o;
   const double* dv = dval + 3 * o;
-  for (int i = threadIdx.x; i < n; i += kNT) {
-    const double x = v[i];
-    mv = fmax(mv, fabs(x));
-    sv += x * x;
-  }
-  for (int i = threadIdx.x; i < 3 * n; i += kNT) {
-    const double x = dv[i];
-    md = fmax(md, fabs(x));
-    sd += x * x;
-  }
+  block_max_sq(v, n, mv, sv);
+  block_max_sq(dv, 3 * n, md, sd);
   mv = block_max(mv, sh);
   md = block_max(md, sh);
   sv = block_sum(sv, sh);
