@@ -239,6 +239,15 @@ class Structure:
         import torch
 
         out = {}
+        on_gpu = torch.device(device).type == "cuda"
+
+        def up(a):
+            # small host arrays go to the device through pinned memory,
+            # asynchronously on the current stream: a copy from pageable memory
+            # would block the calling thread behind other work on the device
+            t = torch.from_numpy(np.ascontiguousarray(a))
+            return t.pin_memory().to(device, non_blocking=True) if on_gpu else t.to(device)
+
         for kind in ("C", "V"):
             off, glist, total = self._layout(kind)
             f, fpx, disp = self.radial(kind)
@@ -246,9 +255,9 @@ class Structure:
             dval = torch.empty(3 * total, dtype=torch.float64, device=device)
             for key, idx, start, size in glist:
                 base = self.base_c[key] if kind == "C" else self.base_v[key]
-                b = torch.from_numpy(np.ascontiguousarray(base).reshape(-1)).to(device)
-                fi = torch.from_numpy(f[idx]).to(device)
-                fpi = torch.from_numpy(np.ascontiguousarray(fpx[idx])).to(device)
+                b = up(np.ascontiguousarray(base).reshape(-1))
+                fi = up(f[idx])
+                fpi = up(fpx[idx])
                 nb = idx.size
                 # written in place: no temporaries the size of the blocks
                 torch.mul(fi[:, None], b[None, :], out=val[start:start + nb * size].view(nb, size))
@@ -259,7 +268,7 @@ class Structure:
         if self.d_kind == "gersh" and self.D is None:
             out["D"] = gersh_density(self.n_tot, self.seed + 104729, device)
         else:
-            out["D"] = torch.from_numpy(self.D).to(device)
+            out["D"] = up(self.D)
         return out
 
 
@@ -368,7 +377,7 @@ def gersh_density(n: int, seed: int, device: str = "cpu"):
     G = torch.randn(n, n, generator=g, device=device, dtype=torch.float64)
     S = (G + G.T) * (1.0 / math.sqrt(2.0))
     del G
-    rho = 1.001 * float(S.abs().sum(dim=1).max())
+    rho = 1.001 * S.abs().sum(dim=1).max()   # stays on the device: no wait for the stream
     S /= rho
     S.diagonal().add_(1.0)
     return S.contiguous()
