@@ -1,7 +1,10 @@
 /*
  * lrx.h -- C-ABI of the MI355X (gfx950) library for the localized-RI (LRI)
  * exact-exchange energy E_X, the analytic forces F^{X1} and the stress
- * sigma^{X1} of a periodic cell at the Gamma point.
+ * sigma^{X1} of a periodic cell at the Gamma point (lrx_set_tensors) or with
+ * k-point sampling (lrx_set_kpoint_tensors), the exact-exchange Hamiltonian
+ * H^X (lrx_hamiltonian) and the preparation of the LRI coefficients C
+ * (lrx_prepare_c).
  *
  * What is computed (Lin, Ji, He, Ren, "Efficient hybrid-functional-based
  * force and stress calculations for periodic systems with thousands of
