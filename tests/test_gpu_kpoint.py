@@ -13,8 +13,8 @@ its own cell offset with no folding:
     theta; per-tensor thresholds with the D pairs decided per offset on |D|);
   * the keep masks, keepD mapped from supercell atom pairs to (offset, X, Y);
   * host and device inputs bit for bit; nk = (1,1,1) bit for bit equal to the
-    Gamma-point entry point; the 64-atom cell on a 2 x 2 x 2 mesh against the
-    stored oracle result;
+    Gamma-point entry point; the 64-atom cell on a 2 x 2 x 2 mesh and the
+    8-atom cell on a 3 x 3 x 1 mesh against stored oracle results;
   * refused inputs: a D that is not Hermitian, theta_cs > 0, and the entry
     points that do not take k-point contexts.
 """
@@ -207,26 +207,28 @@ def test_gamma_mesh_equals_gamma_entry_point():
     torch.cuda.synchronize()
 
 
-def test_diamond64_k222_against_stored_oracle():
-    """The 64-atom cell on a 2 x 2 x 2 mesh with a complex D (theta 1e-4):
-    E, F, sigma and every block gradient against the stored oracle result
-    (tests/golden/make_golden_kpoint.py)."""
+@pytest.mark.parametrize("case", ["diamond64_k222", "sc8_k331"])
+def test_workload_against_stored_oracle(case):
+    """Workload cells with a complex D: the 64-atom cell on a 2 x 2 x 2 mesh
+    (theta 1e-4) and the 8-atom cell on a 3 x 3 x 1 mesh (theta 0, offsets
+    that differ from their negatives): E, F, sigma and every block gradient
+    against the stored oracle results (tests/golden/make_golden_kpoint.py)."""
     import torch
 
     from tests.golden import make_golden_kpoint as G
 
     H.require_gpu()
-    ref = G.load()
-    st, mats, Dk = G.inputs("cuda")
+    ref = G.load(case)
+    st, mats, nk, Dk = G.inputs(case, "cuda")
     assert np.allclose(G.fingerprint(mats, Dk), ref["fingerprint"], rtol=1e-10, atol=0)
     ctx = lrx.Context()
     ctx.set_structure(st.tau, st.lat, st.nao, st.nabf)
-    ctx.set_kpoint_tensors(G.NK, mats["C"], mats["V"], torch.from_numpy(Dk).to("cuda"))
+    ctx.set_kpoint_tensors(nk, mats["C"], mats["V"], torch.from_numpy(Dk).to("cuda"))
     E, F, S = ctx.evaluate(float(ref["theta"]), 0.0)
     gC, gV = ctx.block_gradients()
     kC, kV, _ = ctx.keep_masks()
     ctx.close()
-    print(f"E {E:.15e} oracle {float(ref['E']):.15e}; max|F| {np.abs(ref['F']).max():.3e}", flush=True)
+    print(f"{case}: E {E:.15e} oracle {float(ref['E']):.15e}; max|F| {np.abs(ref['F']).max():.3e}", flush=True)
     np.testing.assert_array_equal(kC != 0, ref["keepC"] != 0)
     np.testing.assert_array_equal(kV != 0, ref["keepV"] != 0)
     H.assert_close_fp64("E", E, float(ref["E"]), H.TOL_E_PER_ATOM * st.natom)
