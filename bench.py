@@ -431,7 +431,7 @@ def main():
                     help="only run the screening sweep (error against time) on --workload; prints markdown")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU; the library has no multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
