@@ -172,12 +172,15 @@ int lrx_set_tensors(lrx_ctx* ctx, const lrx_blocks* C, const lrx_blocks* V, cons
  * the modulus |D|; step 2 (theta_cs > 0) is refused.  lrx_keep_masks then
  * reports keepD over the supercell's atoms [natom * cells]^2 (atom (t, i)
  * at t * natom + i).  lrx_evaluate_batch, lrx_evaluate_noalloc, lrx_submit
- * and lrx_hamiltonian refuse such a context.  Memory: the dense supercell
- * density matrix (cells^2 n_tot^2 doubles; twice for a complex D) besides
- * the buffers of lrx_set_tensors on the supercell's pairs.  data_on_device
- * as for lrx_set_tensors (the Dk arrays, like val/dval, are then device
- * pointers; they are copied into the supercell matrix and not kept).
- * A later lrx_set_tensors returns the context to the Gamma point. */
+ * and lrx_hamiltonian refuse such a context.  D(R) is read where it is (the
+ * block of two supercell atoms is the block of their cells' offset), so the
+ * memory is that of lrx_set_tensors on the supercell's pairs plus D(R)
+ * itself.  data_on_device as for lrx_set_tensors: the Dk arrays, like
+ * val/dval, are then device pointers, borrowed and not copied, and must stay
+ * valid and unchanged until the next set-up or lrx_destroy; host arrays are
+ * copied.  Limits: fewer than 1024 k points, at most 16384 atoms in the
+ * supercell, fewer than 2^21 NAOs in the unit cell.  A later lrx_set_tensors
+ * returns the context to the Gamma point. */
 int lrx_set_kpoint_tensors(lrx_ctx* ctx, const int32_t nk[3], const lrx_blocks* C, const lrx_blocks* V,
                            const double* Dre, const double* Dim, int32_t data_on_device);
 

@@ -272,7 +272,7 @@ struct lrx_ctx {
   std::vector<double> tau0, lat0;
   std::vector<int> nao0, nabf0;
   std::vector<int64_t> ao0;
-  double* DscIm = nullptr;   // imaginary part of the supercell D (nullptr: a real D)
+  const double* DscIm = nullptr;   // imaginary part of D(R) on the device (nullptr: a real D)
   double* keep2 = nullptr;   // gC, gV and out of the first real pass
   // evaluations queued by lrx_submit: results land in their own pinned buffer
   struct Ticket {
@@ -371,14 +371,14 @@ struct KMap {
   const double* Dim = nullptr;    // imaginary part of the supercell D on the device, or nullptr
   int home(int a) const { return a % N0; }
   int cell(int a) const { return a / N0; }
-  // atom a moved back by the cell of atom b (cell(a) - cell(b) modulo nk)
-  int back(int a, int b) const {
-    const int ta = cell(a), tb = cell(b);
-    const int a0 = ta % nk[0], a1 = (ta / nk[0]) % nk[1], a2 = ta / (nk[0] * nk[1]);
-    const int b0 = tb % nk[0], b1 = (tb / nk[0]) % nk[1], b2 = tb / (nk[0] * nk[1]);
-    const int t = (a0 - b0 + nk[0]) % nk[0] + nk[0] * ((a1 - b1 + nk[1]) % nk[1] + nk[1] * ((a2 - b2 + nk[2]) % nk[2]));
-    return t * N0 + home(a);
+  // the cell offset u - t of cells u and t (modulo nk)
+  int diff(int u, int t) const {
+    const int u0 = u % nk[0], u1 = (u / nk[0]) % nk[1], u2 = u / (nk[0] * nk[1]);
+    const int t0 = t % nk[0], t1 = (t / nk[0]) % nk[1], t2 = t / (nk[0] * nk[1]);
+    return (u0 - t0 + nk[0]) % nk[0] + nk[0] * ((u1 - t1 + nk[1]) % nk[1] + nk[1] * ((u2 - t2 + nk[2]) % nk[2]));
   }
+  // atom a moved back by the cell of atom b (cell(a) - cell(b) modulo nk)
+  int back(int a, int b) const { return diff(cell(a), cell(b)) * N0 + home(a); }
 };
 
 // The static work structure of one set of tensors (keys checked by the
@@ -393,6 +393,13 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
   // rows of D are addressed with 24-bit byte strides inside the kernels
   require(ntot * (int64_t)sizeof(double) < (int64_t)1 << 24, "D: more than 2097151 NAOs in the cell");
   const int Nh = km ? km->N0 : N;   // atoms of the home cell (the atoms of every C and V block's first index)
+  // D row/column index of AO x of atom X in the H-build tables: at the Gamma
+  // point the index in the dense D; with k-point sampling the atom's cell
+  // (bits 21 and up) and the AO index within the unit cell (d_block reads
+  // the block of the cells' offset)
+  auto dindex = [&](int X, int x) -> int {
+    return km ? (km->cell(X) << 21) | (int)(c->ao0[km->home(X)] + x) : (int)(c->ao[X] + x);
+  };
   c->nC = C->nblk;
   c->nV = V->nblk;
   c->Cf.assign(C->first, C->first + c->nC);
@@ -555,7 +562,7 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
       for (int x = 0; x < c->nao[c->slotX[s]]; ++x) {
         hColSlot.push_back(s);
         hColX.push_back(x);
-        hColD.push_back((int)(c->ao[c->slotX[s]] + x));
+        hColD.push_back(dindex(c->slotX[s], x));
         hColAtom.push_back(c->slotX[s]);
       }
     hColRow[B + 1] = (int)hColSlot.size();
@@ -664,7 +671,7 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
     int k = 0;
     for (int i = cp.row[B]; i < cp.row[B + 1]; ++i)
       for (int gg = 0; gg < c->nao[cp.pB[i]]; ++gg, ++k) {
-        hdRowD.push_back((int)(c->ao[cp.pB[i]] + gg));
+        hdRowD.push_back(dindex(cp.pB[i], gg));
         hdG.push_back(cp.pB[i]);
         hdCp.push_back((i << 6) | gg);
         hdCf.push_back(cfOff[i] + gg);
@@ -747,6 +754,32 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
   }
   d.DnRe = d.D;
   d.DnIm = km ? km->Dim : nullptr;
+  {
+    std::vector<int> acell(N, 0), dsub(1, 0);
+    std::vector<int64_t> aloc(c->ao.begin(), c->ao.begin() + N);
+    d.ncell = 1;
+    d.dld = ntot;
+    d.dcellsz = 0;
+    d.dsize = ntot * ntot;
+    if (km) {
+      const int nc = km->nk[0] * km->nk[1] * km->nk[2];
+      const int64_t nt0 = c->ao0[km->N0];
+      for (int a = 0; a < N; ++a) {
+        acell[a] = km->cell(a);
+        aloc[a] = c->ao0[km->home(a)];
+      }
+      dsub.assign((size_t)nc * nc, 0);
+      for (int t = 0; t < nc; ++t)
+        for (int u = 0; u < nc; ++u) dsub[(size_t)t * nc + u] = km->diff(u, t);
+      d.ncell = nc;
+      d.dld = nt0;
+      d.dcellsz = nt0 * nt0;
+      d.dsize = nc * nt0 * nt0;
+    }
+    d.acell = c->upload(acell);
+    d.aloc = c->upload(aloc);
+    d.dsub = c->upload(dsub);
+  }
   d.nCp = nCp;
   d.nVp = nVp;
   std::vector<int64_t> cpBlk(cp.order), vpBlk(vp.order);
@@ -862,10 +895,11 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
   lrx::launch_validate_finite(d.Cdval, 3 * C->nval, d.err, 1, c->stream);
   // V and dV: finiteness is checked by the mirror pass of launch_validate
   lrx::launch_validate(d, c->stream);
-  lrx::launch_validate_dsym(d.D, ntot, 0, d.err, c->stream);
-  if (d.DnIm) {   // Hermitian: the imaginary part antisymmetric
-    lrx::launch_validate_dsym(d.DnIm, ntot, 1, d.err, c->stream);
-    lrx::launch_validate_finite(d.DnIm, ntot * ntot, d.err, 4, c->stream);
+  if (!km) {
+    lrx::launch_validate_dsym(d.D, ntot, 0, d.err, c->stream);
+  } else {   // D(-R) = D(R)^H
+    lrx::launch_validate_herm(d.D, d.DnIm, km->nk, d.dld, d.err, c->stream);
+    if (d.DnIm) lrx::launch_validate_finite(d.DnIm, d.dsize, d.err, 4, c->stream);
   }
   HIPCHK(hipGetLastError());
   int herr = 0;
@@ -986,6 +1020,8 @@ int lrx_set_kpoint_tensors(lrx_ctx* c, const int32_t* nk, const lrx_blocks* C, c
     const int ncell = nk[0] * nk[1] * nk[2];
     const int N0 = c->N;
     require((int64_t)N0 * ncell <= 16384, "k-point supercell of more than 16384 atoms");
+    require(ncell < 1024, "k mesh of 1024 points or more");
+    require(c->ao[N0] < (1 << 21), "more than 2097151 NAOs in the unit cell");
     check_blocks(c, C, true, "C");   // the caller's keys, on the unit cell
     check_blocks(c, V, false, "V");
     const int64_t nt0 = c->ao[N0];
@@ -1044,25 +1080,19 @@ int lrx_set_kpoint_tensors(lrx_ctx* c, const int32_t* nk, const lrx_blocks* C, c
     c->ao.assign(Ns + 1, 0);
     for (int i = 0; i < Ns; ++i) c->ao[i + 1] = c->ao[i] + c->nao[i];
     c->bvk = true;
-    const int64_t ns = c->ao[Ns];
-    require(ns * (int64_t)sizeof(double) < (int64_t)1 << 24, "D: more than 2097151 NAOs in the supercell");
-    // the supercell density matrix, block circulant, on the device
-    auto expand = [&](const double* Dk) {
-      const double* src = Dk;
-      if (!on_device) {
-        double* p = c->dalloc<double>(ncell * nt0 * nt0);
-        HIPCHK(hipMemcpyAsync(p, Dk, sizeof(double) * ncell * nt0 * nt0, hipMemcpyHostToDevice, c->stream));
-        src = p;
-      }
-      double* out = c->dalloc<double>(ns * ns);
-      lrx::launch_bvk_expand(src, nk, nt0, out, c->stream);
-      return out;
+    // D(R) on the device, read where it is (the block of two supercell atoms is
+    // that of their cells' offset): device arrays are borrowed, host arrays copied
+    auto to_device = [&](const double* Dk) -> const double* {
+      if (on_device) return Dk;
+      double* p = c->dalloc<double>((int64_t)ncell * nt0 * nt0);
+      HIPCHK(hipMemcpyAsync(p, Dk, sizeof(double) * ncell * nt0 * nt0, hipMemcpyHostToDevice, c->stream));
+      return p;
     };
-    double* DscRe = expand(Dre);
-    double* DscIm = Dim ? expand(Dim) : nullptr;
-    km.Dim = DscIm;
-    build_tensors(c, &C2, &V2, DscRe, true, on_device != 0, &km);
-    c->DscIm = DscIm;
+    const double* DkRe = to_device(Dre);
+    const double* DkIm = Dim ? to_device(Dim) : nullptr;
+    km.Dim = DkIm;
+    build_tensors(c, &C2, &V2, DkRe, true, on_device != 0, &km);
+    c->DscIm = DkIm;
   });
 }
 
@@ -1103,7 +1133,7 @@ void prepare(lrx_ctx* c, const lrx_options* opts) {
     const int64_t nt = c->ao[c->N];
     d.Cf32 = c->dalloc<float>(c->n_cf);
     d.Vf32 = c->dalloc<float>(c->n_vf);
-    d.D32 = c->dalloc<float>(nt * nt);
+    d.D32 = c->dalloc<float>(d.dsize);
     d.H32 = c->dalloc<float>(c->n_h);
     HIPCHK(hipMemsetAsync(d.H32, 0, sizeof(float) * std::max<int64_t>(1, c->n_h), c->stream));
     d.Zbuf32 = c->dalloc<float>(c->n_z);

@@ -131,6 +131,15 @@ __device__ __forceinline__ T ldu(const T* p, int64_t i) {
   return ((const __attribute__((address_space(4))) T*)p)[i];
 }
 
+// First element of the D block (X,Y) (d_block) through scalar loads; the
+// cell term only with k-point sampling (a uniform branch), so that at the
+// Gamma point the address costs two independent loads.
+__device__ __forceinline__ int64_t d_blk(const Dev& d, int X, int Y) {
+  int64_t o = ldu(d.aloc, X) * d.dld + ldu(d.aloc, Y);
+  if (d.ncell > 1) o += (int64_t)ldu(d.dsub, ldu(d.acell, X) * d.ncell + ldu(d.acell, Y)) * d.dcellsz;
+  return o;
+}
+
 // ---------------------------------------------------------------------------
 // H(B,X)[b][beta][x] = sum_{G alive} sum_g Cf(B,G)[beta][b][g] D(G,X)[g][x],
 // stored in blocks of 16 beta: [beta / 16][b][beta mod 16][x], so the slice
@@ -142,13 +151,17 @@ __device__ __forceinline__ T ldu(const T* p, int64_t i) {
 // in registers and walks the item's 64-column blocks (4 tiles of 16 per
 // wave) and depth passes of at most kHPass; the D tile of the next step is
 // loaded into registers while the current one is contracted from LDS
-// (double buffer, one barrier per step).
+// (double buffer, one barrier per step).  BVK (k-point sampling): a D row or
+// column index of the tables packs the atom's cell (bits 21 and up) and the
+// AO index within the unit cell, and the element of D(G,X) is read from the
+// cell offset's block of D(R) (d_block).
 // ---------------------------------------------------------------------------
 constexpr int kHT = 512;
 constexpr int kHCB = 64;                         // columns of one block: 4 tiles of 16
 constexpr int kHPre = kHPass * kHCB / kHT;       // D elements each thread stages per step
 static_assert(kHRows == 16 * (kHT / 64), "one 16-row tile per wave");
-template <class T>
+constexpr int kCellShift = 21;                   // packed D index: cell << 21 | AO index in the cell
+template <class T, bool BVK>
 __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIMD: two workgroups per CU
   using M = M4<T>;
   __shared__ int krow[kHMaxDepth];   // D row (ao[G] + g) of depth index k
@@ -225,7 +238,8 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
   T pv[kHPre];
   auto fetch = [&](int blk, int p) __attribute__((always_inline)) {
     const int kb = p * kHPass, cl = blk * kHCB + (tid & (kHCB - 1));
-    const T* Dc = Dm + cD[cl];
+    constexpr int kLoc = (1 << kCellShift) - 1;
+    const T* Dc = Dm + (BVK ? (cD[cl] & kLoc) : cD[cl]);
     const bool cok = cSl[cl] >= 0;
     const int cx = cxi[cl], ca = cAt[cl];
 #pragma unroll
@@ -233,7 +247,14 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
       const int k = kb + (tid >> 6) + (kHT >> 6) * i;
       const int kk = k < K ? k : kb;
       const int G = k < K ? kG[kk] : -1;
-      const T v = Dc[(int64_t)krow[kk] * d.ntot];
+      T v;
+      if constexpr (BVK) {
+        const int kr = krow[kk];
+        v = Dc[(int64_t)d.dsub[(kr >> kCellShift) * d.ncell + (cD[cl] >> kCellShift)] * d.dcellsz +
+               (int64_t)(kr & kLoc) * d.dld];
+      } else {
+        v = Dc[(int64_t)krow[kk] * d.ntot];
+      }
       const bool keep = G >= 0 && cok &&
                         (local ? keepL[kgi[kk] * 64 + cx] != 0 : d.keepD[(int64_t)G * N + ca] != 0);
       pv[i] = keep ? v : T(0);
@@ -277,7 +298,10 @@ __global__ void __launch_bounds__(kHT, 4) k_hbuild(Dev d) {   // 4 waves per SIM
         const int cl = blk * kHCB + 16 * j + q;
         const int sl = cSl[cl];
         if (sl >= 0) {
-          const int X = cAt[cl], nX = d.nao[X], x = cD[cl] - (int)d.ao[X];
+          // the AO index within atom X: its D column less the atom's first
+          // column (BVK: both within the unit cell)
+          const int X = cAt[cl], nX = d.nao[X];
+          const int x = BVK ? (cD[cl] & ((1 << kCellShift) - 1)) - (int)d.aloc[X] : cD[cl] - (int)d.ao[X];
           T* Hout = H + d.hOff[sl] + x;
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -482,9 +506,9 @@ struct Stager {
     nB = c.nB;
     kAB = with_d && ldu(d.keepD, (int64_t)U.A * d.N + c.B) != 0;
     kFB = with_d && ldu(d.keepD, (int64_t)U.F * d.N + c.B) != 0;
-    dRow = (unsigned)(d.ntot * sizeof(T));
-    dA = (const char*)(Dm + ldu(d.ao, U.A) * d.ntot + ldu(d.ao, c.B));
-    dF = (const char*)(Dm + ldu(d.ao, U.F) * d.ntot + ldu(d.ao, c.B));
+    dRow = (unsigned)(d.dld * sizeof(T));
+    dA = (const char*)(Dm + d_blk(d, U.A, c.B));
+    dF = (const char*)(Dm + d_blk(d, U.F, c.B));
     ldD = sg.ldD;
     if (with_d) dB.init(ldD);   // a division: only for chunks that stage D
     PA = W * U.nA * ldD;
@@ -1350,10 +1374,18 @@ void launch_triple_group(const TripleLaunch& tl, int mt, int prec, hipStream_t s
 
 void launch_hbuild(const Dev& d, int prec, hipStream_t s) {
   if (!d.nHB) return;
-  if (prec == kP64)
-    hipLaunchKernelGGL(k_hbuild<double>, dim3(d.nHB), dim3(kHT), 0, s, d);
-  else
-    hipLaunchKernelGGL(k_hbuild<float>, dim3(d.nHB), dim3(kHT), 0, s, d);
+  const bool bvk = d.ncell > 1;
+  if (prec == kP64) {
+    if (bvk)
+      hipLaunchKernelGGL((k_hbuild<double, true>), dim3(d.nHB), dim3(kHT), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_hbuild<double, false>), dim3(d.nHB), dim3(kHT), 0, s, d);
+  } else {
+    if (bvk)
+      hipLaunchKernelGGL((k_hbuild<float, true>), dim3(d.nHB), dim3(kHT), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_hbuild<float, false>), dim3(d.nHB), dim3(kHT), 0, s, d);
+  }
 }
 
 void launch_triples(const TripleLaunch& tl, int prec, hipStream_t s, const hipStream_t* side, const hipEvent_t* fork,

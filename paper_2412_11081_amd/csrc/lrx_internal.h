@@ -2,7 +2,9 @@
 //
 // Data layout on the device (all row-major, FP64 unless noted):
 //   inputs   C/V block values and derivatives exactly as the caller gave them
-//            (borrowed or copied), D dense [n_tot][n_tot];
+//            (borrowed or copied), D dense [n_tot][n_tot] (with k-point
+//            sampling: D(R) per Born-von Karman cell offset, read through
+//            d_block);
 //   pairs    the image blocks grouped by (first, second) atom pair: a "C pair"
 //            (A,F) and a "V pair" (A,B), each with the sorted list of its
 //            image blocks (R lexicographic);
@@ -77,12 +79,23 @@ struct Dev {
   const int* Vfirst; const int* Vsecond; const int* VR; const int64_t* Voff; const int* Vsz;
   const double* Vval; const double* Vdval;
   const int64_t* Vmir;    // mirror block (second, first, -R)
-  const double* D;        // [ntot][ntot]
+  const double* D;        // [ntot][ntot] at the Gamma point; D(R) [ncell][nt0][nt0] with k-points (d_block)
   // the matrices the D screen measures: DnRe (= D at the Gamma point) and,
   // for a complex density matrix, its imaginary part DnIm (else nullptr); the
   // screen then takes the modulus, so both real passes of a complex D keep
   // the same pairs
   const double* DnRe; const double* DnIm;
+  // Addressing of D blocks.  Block (X,Y) starts at element
+  //   dsub[acell[X] * ncell + acell[Y]] * dcellsz + aloc[X] * dld + aloc[Y]
+  // with rows dld elements apart (d_block).  At the Gamma point: one cell,
+  // aloc = ao, dld = ntot, so block (X,Y) is at ao[X] ntot + ao[Y].  With
+  // k-point sampling the atoms are those of the Born-von Karman supercell,
+  // acell the cell of an atom, aloc its AO offset within the unit cell, and
+  // D is the caller's D(R) [ncell][nt0][nt0] (dld = nt0, dcellsz = nt0^2),
+  // dsub[t][u] the offset u - t of two cells.  dsize = elements of D.
+  const int* acell; const int64_t* aloc; const int* dsub;
+  int ncell;
+  int64_t dld, dcellsz, dsize;
 
   // pairs
   int nCp, nVp;
@@ -196,11 +209,21 @@ void launch_validate(const Dev& d, hipStream_t s);
 // D[i][j] == D[j][i] (anti = 0) or == -D[j][i] (anti = 1) within rounding,
 // for a dense [nt][nt] matrix; a failure sets kErrDSym in *err.
 void launch_validate_dsym(const double* D, int64_t nt, int anti, int* err, hipStream_t s);
-// k-point sampling (lrx_kpoint.hip).  The Born-von Karman supercell of
-// nk0 x nk1 x nk2 cells, atom (t, i) at index t * N0 + i: the dense supercell
-// matrix Dsc[(t, i)][(u, j)] = Dk[u - t][i][j] (offsets modulo nk, flat index
-// r0 + nk0 (r1 + nk1 r2)) from Dk[n_cells][nt][nt].
-void launch_bvk_expand(const double* Dk, const int* nk, int64_t nt, double* Dsc, hipStream_t s);
+// Value-check error bits (Dev::err), reported by the set-up.
+enum : int {
+  kErrNonfiniteC = 1, kErrNonfiniteV = 2, kErrNonfiniteD = 4, kErrVMirror = 8, kErrDVMirror = 16,
+  kErrOnsiteC = 32, kErrDSym = 64
+};
+
+// First element of the D block (X,Y); rows d.dld elements apart.
+__device__ inline int64_t d_block(const Dev& d, int X, int Y) {
+  return (int64_t)d.dsub[d.acell[X] * d.ncell + d.acell[Y]] * d.dcellsz + d.aloc[X] * d.dld + d.aloc[Y];
+}
+// k-point sampling (lrx_kpoint.hip).  D(R) per Born-von Karman cell offset,
+// Dk[r][nt][nt] real part and (optionally) imaginary part: D(-r) = D(r)^H
+// within rounding, else kErrDSym in *err; non-finite values set
+// kErrNonfiniteD.  nk: the mesh; r = r0 + nk0 (r1 + nk1 r2).
+void launch_validate_herm(const double* Dre, const double* Dim, const int* nk, int64_t nt, int* err, hipStream_t s);
 // x[i] = keep[i] - x[i] for i < n (the second real pass of a complex D).
 void launch_sub_from(const double* keep, double* x, int64_t n, hipStream_t s);
 // for_hx: the H slots the Hamiltonian reads (every triple whose C pair and V

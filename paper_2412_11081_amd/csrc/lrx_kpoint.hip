@@ -1,14 +1,12 @@
-// k-point sampling: the density matrix of the Born-von Karman supercell.
+// k-point sampling: checks of the density matrix per Born-von Karman offset,
+// and the combination of the two real passes of a complex density matrix.
 //
 // With a k mesh of nk0 x nk1 x nk2 points the density matrix of two orbitals
 // depends only on the offset of their cells modulo the BvK supercell of as
 // many cells (Methods: the k-sum definition of D, Eq. Eexx).  The caller
-// gives it per offset, Dk[r][nt][nt] with r = r0 + nk0 (r1 + nk1 r2); the
-// contraction kernels read the supercell matrix
-//   Dsc[(t, i)][(u, j)] = Dk[u - t][i][j]   (atom (t, i) = cell t, orbital i)
-// as a dense row-major [nk nt][nk nt] block-circulant matrix, written here
-// once per set of tensors.  One workgroup per supercell row; the row's nk
-// blocks are contiguous rows of Dk, copied with coalesced loads and stores.
+// gives it per offset, Dk[r][nt][nt] with r = r0 + nk0 (r1 + nk1 r2), and the
+// kernels read it there directly (d_block): the block of two supercell atoms
+// is that of their cells' offset.
 #include <algorithm>
 
 #include "lrx_internal.h"
@@ -19,23 +17,26 @@ namespace {
 
 constexpr int kNT = 256;
 
-__global__ void __launch_bounds__(kNT) k_bvk_expand(const double* __restrict__ Dk, int nk0, int nk1, int nk2,
-                                                    int64_t nt, double* __restrict__ Dsc) {
-  const int ncell = nk0 * nk1 * nk2;
-  const int64_t ns = (int64_t)ncell * nt;
-  for (int64_t row = blockIdx.x; row < ns; row += gridDim.x) {
-    const int t = (int)(row / nt);
-    const int64_t i = row - (int64_t)t * nt;
-    const int t0 = t % nk0, t1 = (t / nk0) % nk1, t2 = t / (nk0 * nk1);
-    double* out = Dsc + row * ns;
-    for (int u = 0; u < ncell; ++u) {
-      const int u0 = u % nk0, u1 = (u / nk0) % nk1, u2 = u / (nk0 * nk1);
-      const int r = (u0 - t0 + nk0) % nk0 + nk0 * ((u1 - t1 + nk1) % nk1 + nk1 * ((u2 - t2 + nk2) % nk2));
-      const double* src = Dk + ((int64_t)r * nt + i) * nt;
-      double* dst = out + (int64_t)u * nt;
-      for (int64_t j = threadIdx.x; j < nt; j += kNT) dst[j] = src[j];
-    }
+__device__ inline bool close_rel(double x, double y) { return fabs(x - y) <= 1e-12 * (fabs(x) + fabs(y)); }
+
+// D(-r) = D(r)^H: Re Dk[-r][j][i] = Re Dk[r][i][j] and Im Dk[-r][j][i] =
+// -Im Dk[r][i][j], each pair checked once (from the element that comes first
+// in memory; an element that is its own partner is not checked).
+__global__ void k_val_herm(const double* __restrict__ Dre, const double* __restrict__ Dim, int nk0, int nk1, int nk2,
+                           int64_t nt, int* err) {
+  const int64_t nn = nt * nt, n = (int64_t)nk0 * nk1 * nk2 * nn;
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / nn);
+    const int64_t ij = e - (int64_t)r * nn, i = ij / nt, j = ij - i * nt;
+    const int r0 = r % nk0, r1 = (r / nk0) % nk1, r2 = r / (nk0 * nk1);
+    const int m = (nk0 - r0) % nk0 + nk0 * ((nk1 - r1) % nk1 + nk1 * ((nk2 - r2) % nk2));
+    const int64_t f = (int64_t)m * nn + j * nt + i;   // the partner element
+    if (f <= e) continue;
+    if (!close_rel(Dre[e], Dre[f])) bad = 1;
+    if (Dim && !close_rel(Dim[e], -Dim[f])) bad = 1;
   }
+  if (bad) atomicOr(err, kErrDSym);
 }
 
 __global__ void k_sub_from(const double* __restrict__ keep, double* __restrict__ x, int64_t n) {
@@ -45,10 +46,8 @@ __global__ void k_sub_from(const double* __restrict__ keep, double* __restrict__
 
 }  // namespace
 
-void launch_bvk_expand(const double* Dk, const int* nk, int64_t nt, double* Dsc, hipStream_t s) {
-  const int64_t rows = (int64_t)nk[0] * nk[1] * nk[2] * nt;
-  const unsigned g = (unsigned)std::min<int64_t>(rows, 65536);
-  hipLaunchKernelGGL(k_bvk_expand, dim3(g), dim3(kNT), 0, s, Dk, nk[0], nk[1], nk[2], nt, Dsc);
+void launch_validate_herm(const double* Dre, const double* Dim, const int* nk, int64_t nt, int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_val_herm, dim3(2048), dim3(kNT), 0, s, Dre, Dim, nk[0], nk[1], nk[2], nt, err);
 }
 
 void launch_sub_from(const double* keep, double* x, int64_t n, hipStream_t s) {

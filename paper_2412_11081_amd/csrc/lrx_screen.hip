@@ -54,10 +54,6 @@ __device__ inline double block_max(double v, double* sh) {
 // ---------------------------------------------------------------------------
 // validation (run once per lrx_set_tensors)
 // ---------------------------------------------------------------------------
-enum : int {
-  kErrNonfiniteC = 1, kErrNonfiniteV = 2, kErrNonfiniteD = 4, kErrVMirror = 8, kErrDVMirror = 16,
-  kErrOnsiteC = 32, kErrDSym = 64
-};
 
 __device__ inline bool close_rel(double x, double y) {
   return fabs(x - y) <= 1e-12 * (fabs(x) + fabs(y));
@@ -158,7 +154,7 @@ void launch_validate(const Dev& d, hipStream_t s) {
   const int g = 2048;
   if (d.nV) hipLaunchKernelGGL(k_val_vmirror, dim3((unsigned)d.nV), dim3(kNT), 0, s, d);
   if (d.nC) hipLaunchKernelGGL(k_val_onsite, dim3((unsigned)d.nC), dim3(kNT), 0, s, d);
-  hipLaunchKernelGGL(k_val_finite, dim3(g), dim3(kNT), 0, s, d.D, d.ntot * d.ntot, d.err, (int)kErrNonfiniteD);
+  hipLaunchKernelGGL(k_val_finite, dim3(g), dim3(kNT), 0, s, d.D, d.dsize, d.err, (int)kErrNonfiniteD);
 }
 
 // Finite checks of the block values (sizes known on the host).
@@ -232,13 +228,13 @@ __global__ void k_d_norms(Dev d) {
   const int X = (int)(t / d.N), Y = (int)(t % d.N);
   if (Y < X) return;
   const int nX = d.nao[X], nY = d.nao[Y];
-  const int64_t o = d.ao[X] * d.ntot + d.ao[Y];
+  const int64_t o = d_block(d, X, Y);
   const double* p = d.DnRe + o;
   const double* q = d.DnIm ? d.DnIm + o : nullptr;   // a complex D: the modulus
   double mx = 0, ss = 0;
   for (int i = 0; i < nX; ++i)
     for (int j = 0; j < nY; ++j) {
-      const double v = p[i * d.ntot + j], w = q ? q[i * d.ntot + j] : 0.0;
+      const double v = p[i * d.dld + j], w = q ? q[i * d.dld + j] : 0.0;
       const double v2 = v * v + w * w;
       mx = fmax(mx, q ? sqrt(v2) : fabs(v));
       ss += v2;
@@ -519,7 +515,7 @@ __global__ void __launch_bounds__(kNT) k_hcompact(Dev d) {
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)(a > 0 ? (a + b - 1) / b : 1); }
 
 void launch_d_to_f32(const Dev& d, int prec, hipStream_t s) {
-  if (prec != kP64) hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kNT), 0, s, d.D, d.D32, d.ntot * d.ntot);
+  if (prec != kP64) hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kNT), 0, s, d.D, d.D32, d.dsize);
 }
 
 void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev, bool for_hx) {
@@ -535,7 +531,7 @@ void launch_screen(const Dev& d, const Opts& o, hipStream_t s, hipEvent_t* ev, b
   if (ev) (void)hipEventRecord(ev[1], s);
   if (d.nCp) hipLaunchKernelGGL(k_fold_c, dim3(d.nCp), dim3(kNT), 0, s, d, o.prec);
   if (d.nVp) hipLaunchKernelGGL(k_fold_v, dim3(d.nVp), dim3(kNT), 0, s, d, o.prec);
-  if (o.prec != kP64) hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kNT), 0, s, d.D, d.D32, d.ntot * d.ntot);
+  if (o.prec != kP64) hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(kNT), 0, s, d.D, d.D32, d.dsize);
   if (ev) (void)hipEventRecord(ev[2], s);
   hipLaunchKernelGGL(k_fill_u8, dim3(cdiv(d.nSlot, kNT)), dim3(kNT), 0, s, d.need,
                      (int64_t)d.nSlot);
