@@ -193,26 +193,28 @@ def prepare_benchmark(st, mats, reps=3):
 KPOINT_MESH = (2, 2, 2)
 
 
-def kpoint_benchmark(steps=5):
-    """k-point sampling (lrx_set_kpoint_tensors): the 64-atom cell (its own
-    blocks and theta) on a 2 x 2 x 2 mesh with a complex density matrix per
-    Born-von Karman offset (synth.kpoint_density, seed = cell seed + 6007),
-    so two real passes per evaluation.  Wall time of lrx_evaluate (it returns
-    with the result on the host), the set-up time of the tensors, and the
-    FP64 rate of the algorithmic FLOPs of both passes."""
+def kpoint_benchmark(steps=5, workload=2, mesh=KPOINT_MESH):
+    """k-point sampling (lrx_set_kpoint_tensors): a workload cell (its own
+    blocks and theta; by default the 64-atom cell on a 2 x 2 x 2 mesh) with a
+    complex density matrix per Born-von Karman offset (synth.kpoint_density,
+    seed = cell seed + 6007), so two real passes per evaluation.  Wall time
+    of lrx_evaluate (it returns with the result on the host), the set-up time
+    of the tensors, and the FP64 rate of the algorithmic FLOPs of both
+    passes."""
     import numpy as np
     import torch
 
     from paper_2412_11081_amd import lrx, synth
 
-    st = synth.workload(2).build()
+    nk = tuple(mesh)
+    st = synth.workload(workload).build()
     mats = st.materialize("cuda")
-    Dk = torch.from_numpy(synth.kpoint_density(st.n_tot, KPOINT_MESH, st.seed + 6007)).to("cuda")
+    Dk = torch.from_numpy(synth.kpoint_density(st.n_tot, nk, st.seed + 6007)).to("cuda")
     torch.cuda.synchronize()
     ctx = lrx.Context()
     ctx.set_structure(st.tau, st.lat, st.nao, st.nabf)
     t0 = time.perf_counter()
-    ctx.set_kpoint_tensors(KPOINT_MESH, mats["C"], mats["V"], Dk)
+    ctx.set_kpoint_tensors(nk, mats["C"], mats["V"], Dk)
     set_ms = 1e3 * (time.perf_counter() - t0)
     for _ in range(2):
         E, F, S = ctx.evaluate(st.theta, 0.0)
@@ -226,10 +228,11 @@ def kpoint_benchmark(steps=5):
     passes = 2
     flop = passes * stats["flop_alg"]
     ctx.close()
-    ncell = int(np.prod(KPOINT_MESH))
+    ncell = int(np.prod(nk))
     tf = flop / (ms * 1e-3) / 1e12
-    return {"what": "lrx_evaluate with k-point sampling: E, F, sigma per unit cell, complex D(R), "
-                    "64-atom cell, 2x2x2 mesh, theta 1e-4",
+    return {"what": f"lrx_evaluate with k-point sampling: E, F, sigma per unit cell, complex D(R), "
+                    f"{WORKLOADS[workload].split(':')[0]} ({st.natom} atoms), "
+                    f"{'x'.join(map(str, nk))} mesh, theta {st.theta:g}",
             "natom": st.natom, "supercell_atoms": st.natom * ncell, "evals_per_s": 1e3 / ms, "ms_per_eval": ms,
             "set_tensors_ms": set_ms, "E": E, "passes": passes, "flop": flop, "tflops_alg": tf,
             "frac_fp64_peak": tf / 78.6, "kept_v_blocks": stats["kept_v_blocks"],
@@ -557,6 +560,9 @@ def main():
     print(f"# prepare_c: {out['prepare_c']['ms_per_call']:.1f} ms per call", file=sys.stderr, flush=True)
     out["kpoint"] = kpoint_benchmark(max(3, min(args.steps, 5)))
     print(f"# kpoint: {out['kpoint']['ms_per_eval']:.1f} ms per evaluation", file=sys.stderr, flush=True)
+    out["kpoint_320"] = kpoint_benchmark(3, workload=3, mesh=(2, 2, 1))
+    print(f"# kpoint 320 atoms: {out['kpoint_320']['ms_per_eval']:.1f} ms per evaluation", file=sys.stderr,
+          flush=True)
     if not args.no_cpu_baseline:
         total_kept = stats["kept_v_blocks"]
         spent, nsample, picked, threads = cpu_baseline(st, mats)
