@@ -62,17 +62,18 @@ __device__ inline int find_partner(const int* __restrict__ list, int r0, int r1,
 //   Q[beta][k] = sum_alpha Vf[alpha][16 t + beta] Cf[alpha][k],
 // Vf rows ldv apart (B's ABFs padded to 16, zero padding), Cf rows K1 apart.
 // f64 16x16x4 MFMA: lane (q, g) gives A[m = q][k = g] = Vf[4 s + g][16 t + q]
-// and B[k = g][n = q] = Cf[4 s + g][16 j + q]; result i is row g + 4 i.  A
-// wave keeps three column tiles (j, j + 4, j + 8) in flight; they share the
-// Vf operand.  Loads are unconditional from clamped addresses (no branches
+// and B[k = g][n = q] = Cf[4 s + g][16 j + q]; result i is row g + 4 i.  Of
+// NW waves, a wave keeps three column tiles (j, j + NW, j + 2 NW) in flight;
+// they share the Vf operand.  Loads are unconditional from clamped addresses (no branches
 // in the loop): only the A operand of a k past mA is set to zero; columns
 // past K1 are computed from clamped data and not stored.
+template <int NW>
 __device__ inline void q_tile(const double* __restrict__ Vf, int ldv, const double* __restrict__ Cf, int mA, int K1,
                               int t, double* Q, int w, int q, int g) {
   const int nj = (K1 + 15) >> 4, ns = (mA + 3) >> 2;
   const double* vq = Vf + 16 * t + q;
-  for (int j0 = w; j0 < nj; j0 += 12) {
-    const int c0 = 16 * j0 + q, c1 = c0 + 64, c2 = c0 + 128;
+  for (int j0 = w; j0 < nj; j0 += 3 * NW) {
+    const int c0 = 16 * j0 + q, c1 = c0 + 16 * NW, c2 = c0 + 32 * NW;
     const int d0 = min(c0, K1 - 1), d1 = min(c1, K1 - 1), d2 = min(c2, K1 - 1);
     d4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0}, a2 = {0, 0, 0, 0};
     // four k-steps per pass, their 16 loads issued before the products (a
@@ -112,44 +113,46 @@ __device__ inline void q_tile(const double* __restrict__ Vf, int ldv, const doub
 //   Hbar tile of beta:  acc_h[b][x] += sum_k Ds[k][b] Q[beta][qi(x, k)]
 //   G tile:             acc_g[x][b] += sum_{beta, k} Q[beta][qi(x, k)] Hb[b][beta][k]
 // qi(x, k) = k nX + x for the first kind of triple (k = a), x nF + k for the
-// second (k = f); a wave takes beta = w + 4 j, j < 4.  As in q_tile, loads
-// come from clamped addresses; the Ds and Hb operands of a k past nk (and
-// Ds when the D pair is screened) are zero, rows and columns past nB, nX
-// are not stored.
-template <int NT>
+// second (k = f); NTB and NTX 16-wide tiles cover b and x; of NW waves, a
+// wave takes beta = w + NW j, j < 16 / NW.  As in q_tile, loads come from
+// clamped addresses; the Ds and Hb operands of a k past nk (and Ds when the
+// D pair is screened) are zero, rows and columns past nB, nX are not stored.
+template <int NTB, int NTX, int NW>
 __device__ inline void contract_triple(const double* __restrict__ Q, int K1, const double* __restrict__ Ds,
                                        const double* __restrict__ Hb, bool with_d, int nk, int nB, int nX,
-                                       int qs_x, int qs_k, d4 (&hacc)[4][NT][NT], d4 (&gacc)[NT][NT], int w,
-                                       int q, int g) {
+                                       int qs_x, int qs_k, d4 (&hacc)[16 / NW][NTB][NTX], d4 (&gacc)[NTX][NTB],
+                                       int w, int q, int g) {
   const int nsk = (nk + 3) >> 2;
-  int xo[NT], bo[NT], hb_[NT];
+  int xo[NTX], bo[NTB], hb_[NTB];
 #pragma unroll
-  for (int u = 0; u < NT; ++u) {
-    xo[u] = min(16 * u + q, nX - 1) * qs_x;
+  for (int u = 0; u < NTX; ++u) xo[u] = min(16 * u + q, nX - 1) * qs_x;
+#pragma unroll
+  for (int u = 0; u < NTB; ++u) {
     bo[u] = min(16 * u + q, nB - 1);
     hb_[u] = bo[u] * 16 * nk;
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int be = w + 4 * j;
+  for (int j = 0; j < 16 / NW; ++j) {
+    const int be = w + NW * j;
     const double* Qb = Q + be * K1;
     const double* Hbe = Hb + be * nk;
     for (int s = 0; s < nsk; ++s) {
       const int k = 4 * s + g, kc = min(k, nk - 1);
       const bool kd = k < nk && with_d, kh = k < nk;
-      double qv[NT], dv[NT], hv[NT];
+      double qv[NTX], dv[NTB], hv[NTB];
 #pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        qv[u] = Qb[xo[u] + kc * qs_k];
+      for (int u = 0; u < NTX; ++u) qv[u] = Qb[xo[u] + kc * qs_k];
+#pragma unroll
+      for (int u = 0; u < NTB; ++u) {
         const double dd = Ds[kc * nB + bo[u]];
         const double hh = Hbe[hb_[u] + kc];
         dv[u] = kd ? dd : 0.0;
         hv[u] = kh ? hh : 0.0;
       }
 #pragma unroll
-      for (int ib = 0; ib < NT; ++ib)
+      for (int ib = 0; ib < NTB; ++ib)
 #pragma unroll
-        for (int ix = 0; ix < NT; ++ix) {
+        for (int ix = 0; ix < NTX; ++ix) {
           // Hbar: A[m = b][k] = Ds[k][b], B[k][n = x] = Q[beta][x, k]
           hacc[j][ib][ix] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[ib], qv[ix], hacc[j][ib][ix], 0, 0, 0);
           // G: A[m = x][k] = Q[beta][x, k], B[k][n = b] = H[b][beta][k]
@@ -159,14 +162,20 @@ __device__ inline void contract_triple(const double* __restrict__ Q, int K1, con
   }
 }
 
-// NT: 16-wide tiles for the b and x indices; the launch for NT takes the
-// slots with 16 (NT - 1) < max(nB, nX) <= 16 NT.  HS: the H slice is staged
-// in LDS (else read from global memory).  LDS: Q [16][K1] (or the four
-// waves' G partials at the end) in qsize doubles, Ds [nk][nB] in dsize, Hs
-// [nB][16][nk].
-template <int NT, bool HS>
-__global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ Hbar, double* __restrict__ G12,
-                                                   int qsize, int dsize) {
+// Waves per SIMD that the register allocation of k_hx_slot<NTB, NTX, ., NW>
+// is held to (its Hbar accumulators take 64 NTB NTX / NW doubles per lane):
+// three for one tile per index, two for the other launches.
+constexpr int slot_waves_per_simd(int NTB, int NTX) { return NTB * NTX == 1 ? 3 : 2; }
+
+// NTB, NTX: 16-wide tiles for the b and x indices; the launch takes the slots
+// with ceil(nB / 16) = NTB and ceil(nX / 16) = NTX.  HS: the H slice is
+// staged in LDS (else read from global memory).  NW: waves per workgroup (4
+// or 8).  LDS: Q [16][K1] (or the NW waves' G partials at the end) in qsize
+// doubles, Ds [nk][nB] in dsize, Hs [nB][16][nk].
+template <int NTB, int NTX, bool HS, int NW>
+__global__ void __launch_bounds__(64 * NW, slot_waves_per_simd(NTB, NTX))
+    k_hx_slot(Dev d, double* __restrict__ Hbar, double* __restrict__ G12, int qsize, int dsize) {
+  constexpr int kNT = 64 * NW, kJ = 16 / NW;
   extern __shared__ double lds[];
   // the slot's triples: C pair, V pair and third atom (A for the first kind,
   // F for the second); a C pair's atom has at most 64 C partners
@@ -181,15 +190,14 @@ __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ H
   const int64_t nt = d.ntot;
   const int B = d.slotB[s], X = d.slotX[s];
   const int mB = d.nabf[B], nB = d.nao[B], nX = d.nao[X];
-  const int nbx = max(nB, nX);
-  if (nbx > 16 * NT || nbx <= 16 * (NT - 1)) return;   // the other launch's slot
+  if ((nB + 15) / 16 != NTB || (nX + 15) / 16 != NTX) return;   // another launch's slot
   const int ldv = (mB + 15) & ~15, nT = ldv >> 4;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
-  d4 gacc[NT][NT];
+  d4 gacc[NTX][NTB];
 #pragma unroll
-  for (int ix = 0; ix < NT; ++ix)
+  for (int ix = 0; ix < NTX; ++ix)
 #pragma unroll
-    for (int ib = 0; ib < NT; ++ib) gacc[ix][ib] = d4{0, 0, 0, 0};
+    for (int ib = 0; ib < NTB; ++ib) gacc[ix][ib] = d4{0, 0, 0, 0};
   // the slot's triples, found once (one thread per candidate partner) and
   // listed in a fixed order: first kind (A, X, B) for the C partners A of X
   // with (A,X) and (A,B) in the value lists, then second kind (X, F, B)
@@ -198,7 +206,7 @@ __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ H
     const int vpX = find_partner(d.vpB, d.vpRow[X], d.vpRow[X + 1], B);
     const bool kindB = vpX >= 0 && (d.aliveV[vpX] & 1);
     const int nA0 = d.cpRow[X + 1] - d.cpRow[X];
-    for (int it = tid; it < 2 * nA0; it += kHxNT) {
+    for (int it = tid; it < 2 * nA0; it += kNT) {
       const bool first = it < nA0;
       const int i = d.cpRow[X] + (first ? it : it - nA0);
       int cp = -1, vp = -1, P = d.cpF[i];
@@ -230,13 +238,13 @@ __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ H
   }
   const int nTri = ntri;
   for (int t = 0; t < nT; ++t) {
-    d4 hacc[4][NT][NT];
+    d4 hacc[kJ][NTB][NTX];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < kJ; ++j)
 #pragma unroll
-      for (int ib = 0; ib < NT; ++ib)
+      for (int ib = 0; ib < NTB; ++ib)
 #pragma unroll
-        for (int ix = 0; ix < NT; ++ix) hacc[j][ib][ix] = d4{0, 0, 0, 0};
+        for (int ix = 0; ix < NTX; ++ix) hacc[j][ib][ix] = d4{0, 0, 0, 0};
     for (int it = 0; it < nTri; ++it) {
       const int cp = tcp[it], vp = tvp[it], code = tat[it];
       const bool first = code >= 0;
@@ -247,26 +255,26 @@ __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ H
       const bool with_d = d.keepD[(int64_t)P * N + B] != 0;
       const double* Dsrc = d.D + d.ao[P] * nt + d.ao[B];
       if (with_d)
-        for (int e = tid; e < nk * nB; e += kHxNT) Ds[e] = Dsrc[(int64_t)(e / nB) * nt + e % nB];
+        for (int e = tid; e < nk * nB; e += kNT) Ds[e] = Dsrc[(int64_t)(e / nB) * nt + e % nB];
       const double* Hsrc = d.H + d.hOff[d.hSlotMap[(int64_t)B * N + P]] + (int64_t)t * nB * 16 * nk;
       if constexpr (HS)
-        for (int e = tid; e < nB * 16 * nk; e += kHxNT) Hs[e] = Hsrc[e];
-      q_tile(d.Vf + d.vfOff[vp], ldv, d.Cf + d.cfOff[cp], d.nabf[first ? P : X], K1, t, Q, w, q, g);
+        for (int e = tid; e < nB * 16 * nk; e += kNT) Hs[e] = Hsrc[e];
+      q_tile<NW>(d.Vf + d.vfOff[vp], ldv, d.Cf + d.cfOff[cp], d.nabf[first ? P : X], K1, t, Q, w, q, g);
       __syncthreads();
       // Q index of (x, k): k nX + x (first kind), x nF + k (second)
-      contract_triple<NT>(Q, K1, Ds, HS ? Hs : Hsrc, with_d, nk, nB, nX, first ? 1 : nk, first ? nX : 1, hacc,
+      contract_triple<NTB, NTX, NW>(Q, K1, Ds, HS ? Hs : Hsrc, with_d, nk, nB, nX, first ? 1 : nk, first ? nX : 1, hacc,
                           gacc, w, q, g);
       __syncthreads();
     }
     // the beta tile of Hbar(B,X), laid out as the H slot: [b][beta][x]
     double* hout = Hbar + d.hOff[s] + (int64_t)t * 16 * nB * nX;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int be = w + 4 * j;
+    for (int j = 0; j < kJ; ++j) {
+      const int be = w + NW * j;
 #pragma unroll
-      for (int ib = 0; ib < NT; ++ib)
+      for (int ib = 0; ib < NTB; ++ib)
 #pragma unroll
-        for (int ix = 0; ix < NT; ++ix)
+        for (int ix = 0; ix < NTX; ++ix)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int b = 16 * ib + g + 4 * r, x = 16 * ix + q;
@@ -274,24 +282,24 @@ __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ H
           }
     }
   }
-  // the D block (X,B) of G1 + G2: the four waves' partials (each over its
-  // beta rows) added in wave order; this workgroup is the block's only writer
+  // the D block (X,B) of G1 + G2: the NW waves' partials (each over its beta
+  // rows) added in wave order; this workgroup is the block's only writer
 #pragma unroll
-  for (int ix = 0; ix < NT; ++ix)
+  for (int ix = 0; ix < NTX; ++ix)
 #pragma unroll
-    for (int ib = 0; ib < NT; ++ib)
+    for (int ib = 0; ib < NTB; ++ib)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Q[((w * NT + ix) * NT + ib) * 256 + r * 64 + lane] = gacc[ix][ib][r];
+      for (int r = 0; r < 4; ++r) Q[((w * NTX + ix) * NTB + ib) * 256 + r * 64 + lane] = gacc[ix][ib][r];
   __syncthreads();
   if (w == 0) {
 #pragma unroll
-    for (int ix = 0; ix < NT; ++ix)
+    for (int ix = 0; ix < NTX; ++ix)
 #pragma unroll
-      for (int ib = 0; ib < NT; ++ib)
+      for (int ib = 0; ib < NTB; ++ib)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           double v = 0.0;
-          for (int ww = 0; ww < 4; ++ww) v += Q[((ww * NT + ix) * NT + ib) * 256 + r * 64 + lane];
+          for (int ww = 0; ww < NW; ++ww) v += Q[((ww * NTX + ix) * NTB + ib) * 256 + r * 64 + lane];
           const int x = 16 * ix + g + 4 * r, b = 16 * ib + q;
           if (x < nX && b < nB) G12[(d.ao[X] + x) * nt + d.ao[B] + b] = -v;
         }
@@ -302,8 +310,9 @@ __global__ void __launch_bounds__(kHxNT) k_hx_slot(Dev d, double* __restrict__ H
 // over the C pairs (B,G) with a value-list block and the needed slots (B,X),
 // on the matrix cores: tiles (g, x) of 16 x 16, the contraction over
 // (beta, b) in k-steps of four b; wave w takes beta = w, w + 4, ...; the
-// four partial tiles are added in wave order.  NT as for k_hx_slot, on
-// max(nG, nX); every D block (G,X) is written by one workgroup (zeros when
+// four partial tiles are added in wave order.  NT: 16-wide tiles for g and
+// x; the launch for NT takes the blocks with 16 (NT - 1) < max(nG, nX) <=
+// 16 NT.  Every D block (G,X) is written by one workgroup (zeros when
 // nothing reaches it).
 template <int NT>
 __global__ void __launch_bounds__(kHxNT) k_hx_g3(Dev d, const double* __restrict__ Hbar, double* __restrict__ G3) {
@@ -457,26 +466,34 @@ void launch_hx(const Dev& d, const HxBufs& b, hipStream_t s, hipEvent_t* ev) {
   hipLaunchKernelGGL(k_fill_f64, dim3(2048), dim3(256), 0, s, b.G12, nt * nt);
   if (d.nSlot > 0) {
     const int nmax = b.nmax;
-    // per launch NT: Q tile rows (or the G partials of four waves), the D
-    // block and the H slice, sized for b, x < 16 NT and k <= nmax; the H
-    // slice is staged when two workgroups still fit a CU's LDS
-    auto run = [&](auto kern_h, auto kern_g, int NT) {
-      const int bx = std::min(16 * NT, nmax);
-      const int qsize = std::max(16 * nmax * bx, 4 * NT * NT * 256);
-      const int dsize = nmax * bx;
+    // per launch (NTB, NTX): Q tile rows (or the G partials of the NW
+    // waves), the D block and the H slice, sized for b < 16 NTB, x < 16 NTX
+    // and k <= nmax; the H slice is staged when the workgroups that the
+    // registers let a CU hold still fit its 160 KiB of LDS, and at most
+    // 80 KiB per workgroup (a larger stage, at one workgroup per CU, was
+    // slower than reading the slice from global memory)
+    auto run = [&](auto kern_h, auto kern_g, int NTB, int NTX, int NW) {
+      const int bb = std::min(16 * NTB, nmax), bx = std::min(16 * NTX, nmax);
+      const int qsize = std::max(16 * nmax * bx, NW * NTB * NTX * 256);
+      const int dsize = nmax * bb;
       const size_t base = sizeof(double) * ((size_t)qsize + dsize);
-      const size_t with_h = base + sizeof(double) * 16 * (size_t)bx * nmax;
-      const bool hs = with_h <= 80 * 1024;
+      const size_t with_h = base + sizeof(double) * 16 * (size_t)bb * nmax;
+      const size_t per_cu = std::max(1, 4 * slot_waves_per_simd(NTB, NTX) / NW);
+      const bool hs = with_h <= std::min((size_t)81920, (size_t)163840 / per_cu);
       const size_t lds = hs ? with_h : base;
       const void* k = hs ? (const void*)kern_h : (const void*)kern_g;
       if (lds > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (hs)
-        hipLaunchKernelGGL(kern_h, dim3((unsigned)d.nSlot), dim3(kHxNT), lds, s, d, b.Hbar, b.G12, qsize, dsize);
+        hipLaunchKernelGGL(kern_h, dim3((unsigned)d.nSlot), dim3(64 * NW), lds, s, d, b.Hbar, b.G12, qsize, dsize);
       else
-        hipLaunchKernelGGL(kern_g, dim3((unsigned)d.nSlot), dim3(kHxNT), lds, s, d, b.Hbar, b.G12, qsize, dsize);
+        hipLaunchKernelGGL(kern_g, dim3((unsigned)d.nSlot), dim3(64 * NW), lds, s, d, b.Hbar, b.G12, qsize, dsize);
     };
-    run(k_hx_slot<1, true>, k_hx_slot<1, false>, 1);
-    if (nmax > 16) run(k_hx_slot<2, true>, k_hx_slot<2, false>, 2);
+    run(k_hx_slot<1, 1, true, 4>, k_hx_slot<1, 1, false, 4>, 1, 1, 4);
+    if (nmax > 16) {
+      run(k_hx_slot<1, 2, true, 4>, k_hx_slot<1, 2, false, 4>, 1, 2, 4);
+      run(k_hx_slot<2, 1, true, 4>, k_hx_slot<2, 1, false, 4>, 2, 1, 4);
+      run(k_hx_slot<2, 2, true, 8>, k_hx_slot<2, 2, false, 8>, 2, 2, 8);
+    }
   }
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_hx_g3<1>, dim3((unsigned)((int64_t)d.N * d.N)), dim3(kHxNT), 0, s, d, (const double*)b.Hbar,
