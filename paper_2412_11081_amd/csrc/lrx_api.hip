@@ -806,6 +806,12 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
   d.nSlot = nSlot;
   d.slotB = c->upload(c->slotB); d.slotX = c->upload(c->slotX); d.hOff = c->upload(hOff);
   d.hSlotMap = c->upload(slotmap);
+  {
+    std::vector<int> byX(nSlot);
+    for (int s = 0; s < nSlot; ++s) byX[s] = s;
+    std::stable_sort(byX.begin(), byX.end(), [&](int a, int b) { return c->slotX[a] < c->slotX[b]; });
+    d.slotByX = c->upload(byX);
+  }
   d.need = c->dalloc<uint8_t>(nSlot);
   d.H = nullptr;   // work buffers of a precision are allocated on its first evaluation
   c->n_cf = cfOff[nCp];

@@ -184,7 +184,13 @@ __global__ void __launch_bounds__(64 * NW, slot_waves_per_simd(NTB, NTX))
   double* Q = lds;
   double* Ds = lds + qsize;
   double* Hs = Ds + dsize;
-  const int s = blockIdx.x;
+  // Workgroups go round-robin to the 8 XCDs, each with its own L2.  XCD i
+  // takes the i-th eighth of the slots in (X, B) order: the slots of one X
+  // read the same C^Gamma blocks (Cf(A,X) and Cf(X,F)), which then stay in
+  // one L2 while its workgroups walk them.  The grid is a multiple of 8.
+  const int o = (int)(blockIdx.x & 7) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+  if (o >= d.nSlot) return;
+  const int s = d.slotByX[o];
   if (!d.need[s]) return;
   const int N = d.N;
   const int64_t nt = d.ntot;
@@ -472,6 +478,7 @@ void launch_hx(const Dev& d, const HxBufs& b, hipStream_t s, hipEvent_t* ev) {
     // registers let a CU hold still fit its 160 KiB of LDS, and at most
     // 80 KiB per workgroup (a larger stage, at one workgroup per CU, was
     // slower than reading the slice from global memory)
+    const unsigned grid = 8u * (unsigned)((d.nSlot + 7) / 8);   // see k_hx_slot's slot order
     auto run = [&](auto kern_h, auto kern_g, int NTB, int NTX, int NW) {
       const int bb = std::min(16 * NTB, nmax), bx = std::min(16 * NTX, nmax);
       const int qsize = std::max(16 * nmax * bx, NW * NTB * NTX * 256);
@@ -484,9 +491,9 @@ void launch_hx(const Dev& d, const HxBufs& b, hipStream_t s, hipEvent_t* ev) {
       const void* k = hs ? (const void*)kern_h : (const void*)kern_g;
       if (lds > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (hs)
-        hipLaunchKernelGGL(kern_h, dim3((unsigned)d.nSlot), dim3(64 * NW), lds, s, d, b.Hbar, b.G12, qsize, dsize);
+        hipLaunchKernelGGL(kern_h, dim3(grid), dim3(64 * NW), lds, s, d, b.Hbar, b.G12, qsize, dsize);
       else
-        hipLaunchKernelGGL(kern_g, dim3((unsigned)d.nSlot), dim3(64 * NW), lds, s, d, b.Hbar, b.G12, qsize, dsize);
+        hipLaunchKernelGGL(kern_g, dim3(grid), dim3(64 * NW), lds, s, d, b.Hbar, b.G12, qsize, dsize);
     };
     run(k_hx_slot<1, 1, true, 4>, k_hx_slot<1, 1, false, 4>, 1, 1, 4);
     if (nmax > 16) {

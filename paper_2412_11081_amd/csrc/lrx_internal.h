@@ -124,6 +124,7 @@ struct Dev {
   int nSlot;
   const int* slotB; const int* slotX; const int64_t* hOff; const int* hSlotMap; // [N][N] -> slot or -1
   const int* slotRow;      // [N+1] slots of atom B are slotRow[B] .. slotRow[B+1]-1 (sorted by X)
+  const int* slotByX;      // [nSlot] the slots in (X, B) order
   int nHB; const int* hbB; const int* hbR0; const int* hbC0;   // H-build work items: (B, first row, first column)
   const int* hColRow;      // [N+1] columns of atom B: the (slot, x) of every H slot of B, concatenated
   const int* hColSlot; const int* hColX; const int* hColD; const int* hColAtom;
