@@ -144,6 +144,11 @@ int lrx_set_structure(lrx_ctx* ctx, int32_t natom, const double* tau, const doub
  * Keys are always host arrays and are copied.  Validates keys on the host
  * and values on the device (finite, mirror and swap symmetries, D
  * symmetric); returns LRX_EINVAL with a message on the first violation.
+ * Per-atom limits (also LRX_EINVAL): the NAOs of an atom's C partners (the
+ * atoms it shares a C block with, over all images) sum to at most 508, and
+ * its C pairs take at most 64 column chunks of the triple products (a pair
+ * of nA nF AO pairs takes ceil(nA nF / w) of them, w = 176 when the atom
+ * has at most 80 ABFs, else 128), so an atom has at most 64 C partners.
  * Allocates the lists, folded blocks, norms, masks and gradients for the
  * worst case (nothing screened); the work buffers of a precision (see
  * lrx_stats.work_bytes) are allocated by its first evaluation. */

@@ -1793,6 +1793,11 @@ int lrx_evaluate_noalloc(lrx_ctx* c, const lrx_options* opts, double* E, double*
 int lrx_hamiltonian(lrx_ctx* c, const lrx_options* opts, double* E, double* Hx, int32_t hx_on_device) {
   return guarded(c, [&] {
     require(!c->bvk, "lrx_hamiltonian: not available with k-point sampling");
+    require(c->have_tensors, "evaluation before lrx_set_tensors");
+    for (int A = 0; A < c->N; ++A)
+      require(c->cp.row[A + 1] - c->cp.row[A] <= lrx::kHxMaxCPartners,
+              "lrx_hamiltonian: atom " + std::to_string(A) + " has more than " +
+                  std::to_string(lrx::kHxMaxCPartners) + " C partners");
     prepare(c, opts);
     require(opts->precision == LRX_FP64, "the Hamiltonian is computed in FP64 only");
     Dev& d = c->dev;

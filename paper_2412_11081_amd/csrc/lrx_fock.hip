@@ -178,8 +178,9 @@ __global__ void __launch_bounds__(64 * NW, slot_waves_per_simd(NTB, NTX))
   constexpr int kNT = 64 * NW, kJ = 16 / NW;
   extern __shared__ double lds[];
   // the slot's triples: C pair, V pair and third atom (A for the first kind,
-  // F for the second); a C pair's atom has at most 64 C partners
-  __shared__ int tcp[2 * 64], tvp[2 * 64], tat[2 * 64];
+  // F for the second); an atom has at most kHxMaxCPartners C partners
+  // (checked on the host)
+  __shared__ int tcp[2 * kHxMaxCPartners], tvp[2 * kHxMaxCPartners], tat[2 * kHxMaxCPartners];
   __shared__ int ntri;
   double* Q = lds;
   double* Ds = lds + qsize;

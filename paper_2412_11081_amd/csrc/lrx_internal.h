@@ -48,6 +48,7 @@ constexpr int kHRows = 128;        // rows (beta,b) of H one H-build workgroup o
 constexpr int kHItemCols = 256;    // columns (X,x) of H one H-build workgroup owns
 constexpr int kHMaxDepth = 512;    // max sum of NAOs over the C partners of one atom
 constexpr int kHPass = 64;         // depth of one H-build pass
+constexpr int kHxMaxCPartners = 64;   // C partners of one atom (at most one column chunk each, 64 chunks)
 
 enum Prec : int { kP64 = 0, kP32 = 1, kPB3 = 2 };
 

@@ -3,7 +3,8 @@ everything screened away, D blocks screened under live triples, a cell of
 one atom (only its own images), the largest block sizes the kernels take
 (32 NAOs and 128 ABFs per atom: eight alpha tiles, H slices too large for
 the LDS stage), and inputs the library must reject with an error instead of
-computing."""
+computing (non-finite values, broken symmetries, block sizes and C partner
+counts beyond the kernels)."""
 import numpy as np
 import pytest
 
@@ -201,3 +202,16 @@ def test_block_sizes_beyond_the_kernels_are_rejected():
     with pytest.raises(lrx.LrxError):
         ctx.set_structure(tau, np.eye(3) * 5.0, np.array([10], np.int32), np.array([129], np.int32))
     ctx.close()
+
+
+def test_too_many_c_partners_are_rejected():
+    """Every C pair takes at least one of the 64 column chunks an atom may
+    have, so an atom with more than 64 C partners is refused (the per-slot
+    lists of the Hamiltonian rely on that bound)."""
+    H.require_gpu()
+    # 130 one-NAO atoms in a cell of side 8.5 +- 0.3 Bohr: every pair has an
+    # image closer than 8.8 sqrt(3) / 2 < 8 Bohr, so every atom has 130 C
+    # partners (130 NAOs, within the depth limit of 508)
+    st = synth.small_case(natom=130, n_ao=1, n_abf=1, box=8.5, rc=8.0, rv=8.0, seed=41).build()
+    m = st.materialize("cuda")
+    _expect_rejected(st, m["C"], m["V"], m["D"], ["64 C-pair column chunks"])
