@@ -136,28 +136,33 @@ __device__ inline void contract_triple(const double* __restrict__ Q, int K1, con
     const int be = w + NW * j;
     const double* Qb = Q + be * K1;
     const double* Hbe = Hb + be * nk;
-    for (int s = 0; s < nsk; ++s) {
-      const int k = 4 * s + g, kc = min(k, nk - 1);
-      const bool kd = k < nk && with_d, kh = k < nk;
-      double qv[NTX], dv[NTB], hv[NTB];
+    for (int s0 = 0; s0 < nsk; s0 += 2) {
+      double qv[2][NTX], dv[2][NTB], hv[2][NTB];
 #pragma unroll
-      for (int u = 0; u < NTX; ++u) qv[u] = Qb[xo[u] + kc * qs_k];
+      for (int e = 0; e < 2; ++e) {
+        const int k = 4 * (s0 + e) + g, kc = min(k, nk - 1);
+        const bool kd = k < nk && with_d, kh = k < nk;
 #pragma unroll
-      for (int u = 0; u < NTB; ++u) {
-        const double dd = Ds[kc * nB + bo[u]];
-        const double hh = Hbe[hb_[u] + kc];
-        dv[u] = kd ? dd : 0.0;
-        hv[u] = kh ? hh : 0.0;
+        for (int u = 0; u < NTX; ++u) qv[e][u] = Qb[xo[u] + kc * qs_k];
+#pragma unroll
+        for (int u = 0; u < NTB; ++u) {
+          const double dd = Ds[kc * nB + bo[u]];
+          const double hh = Hbe[hb_[u] + kc];
+          dv[e][u] = kd ? dd : 0.0;
+          hv[e][u] = kh ? hh : 0.0;
+        }
       }
 #pragma unroll
-      for (int ib = 0; ib < NTB; ++ib)
+      for (int e = 0; e < 2; ++e)
 #pragma unroll
-        for (int ix = 0; ix < NTX; ++ix) {
-          // Hbar: A[m = b][k] = Ds[k][b], B[k][n = x] = Q[beta][x, k]
-          hacc[j][ib][ix] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[ib], qv[ix], hacc[j][ib][ix], 0, 0, 0);
-          // G: A[m = x][k] = Q[beta][x, k], B[k][n = b] = H[b][beta][k]
-          gacc[ix][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(qv[ix], hv[ib], gacc[ix][ib], 0, 0, 0);
-        }
+        for (int ib = 0; ib < NTB; ++ib)
+#pragma unroll
+          for (int ix = 0; ix < NTX; ++ix) {
+            // Hbar: A[m = b][k] = Ds[k][b], B[k][n = x] = Q[beta][x, k]
+            hacc[j][ib][ix] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[e][ib], qv[e][ix], hacc[j][ib][ix], 0, 0, 0);
+            // G: A[m = x][k] = Q[beta][x, k], B[k][n = b] = H[b][beta][k]
+            gacc[ix][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(qv[e][ix], hv[e][ib], gacc[ix][ib], 0, 0, 0);
+          }
     }
   }
 }
@@ -316,8 +321,10 @@ __global__ void __launch_bounds__(64 * NW, slot_waves_per_simd(NTB, NTX))
 // G3(G,X)[g][x] = sum_B sum_{beta,b} Cf(B,G)[beta][b][g] Hbar(B,X)[b][beta][x]
 // over the C pairs (B,G) with a value-list block and the needed slots (B,X),
 // on the matrix cores: tiles (g, x) of 16 x 16, the contraction over
-// (beta, b) in k-steps of four b; wave w takes beta = w, w + 4, ...; the
-// four partial tiles are added in wave order.  NT: 16-wide tiles for g and
+// (beta, b) in k-steps of four b, the loads of four k-steps issued before
+// their products from clamped addresses (zero operands past nB); wave w
+// takes beta = w, w + 4, ...; the four partial tiles are added in wave
+// order.  NT: 16-wide tiles for g and
 // x; the launch for NT takes the blocks with 16 (NT - 1) < max(nG, nX) <=
 // 16 NT.  Every D block (G,X) is written by one workgroup (zeros when
 // nothing reaches it).
@@ -348,22 +355,27 @@ __global__ void __launch_bounds__(kHxNT) k_hx_g3(Dev d, const double* __restrict
     for (int be = w; be < mB; be += 4) {
       const double* cr = Cf + (int64_t)be * nB * nG;
       const double* hr = Hb + ((int64_t)(be >> 4) * nB * 16 + (be & 15)) * nX;
-#pragma unroll 2
-      for (int sb = 0; sb < nsb; ++sb) {
-        const int b = 4 * sb + g;
-        const bool ok = b < nB;
-        double av[NT], hv[NT];
+      for (int s0 = 0; s0 < nsb; s0 += 4) {
+        double av[4][NT], hv[4][NT];
 #pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          const int c = 16 * u + q;
-          av[u] = (ok && c < nG) ? cr[b * nG + c] : 0.0;          // A[m = g][k = b]
-          hv[u] = (ok && c < nX) ? hr[b * 16 * nX + c] : 0.0;     // B[k = b][n = x]
+        for (int j = 0; j < 4; ++j) {
+          const int b = 4 * (s0 + j) + g, bc = min(b, nB - 1);
+          const bool ok = b < nB;
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            const int c = 16 * u + q;
+            const double a1 = cr[bc * nG + min(c, nG - 1)], h1 = hr[bc * 16 * nX + min(c, nX - 1)];
+            av[j][u] = (ok && c < nG) ? a1 : 0.0;
+            hv[j][u] = (ok && c < nX) ? h1 : 0.0;
+          }
         }
 #pragma unroll
-        for (int ig = 0; ig < NT; ++ig)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-          for (int ix = 0; ix < NT; ++ix)
-            acc[ig][ix] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ig], hv[ix], acc[ig][ix], 0, 0, 0);
+          for (int ig = 0; ig < NT; ++ig)
+#pragma unroll
+            for (int ix = 0; ix < NT; ++ix)
+              acc[ig][ix] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j][ig], hv[j][ix], acc[ig][ix], 0, 0, 0);
       }
     }
   }
