@@ -63,47 +63,60 @@ __device__ inline int find_partner(const int* __restrict__ list, int r0, int r1,
 // Vf rows ldv apart (B's ABFs padded to 16, zero padding), Cf rows K1 apart.
 // f64 16x16x4 MFMA: lane (q, g) gives A[m = q][k = g] = Vf[4 s + g][16 t + q]
 // and B[k = g][n = q] = Cf[4 s + g][16 j + q]; result i is row g + 4 i.  Of
-// NW waves, a wave keeps three column tiles (j, j + NW, j + 2 NW) in flight;
-// they share the Vf operand.  Loads are unconditional from clamped addresses (no branches
-// in the loop): only the A operand of a k past mA is set to zero; columns
-// past K1 are computed from clamped data and not stored.
+// NW waves, a wave keeps up to three column tiles (j, j + NW, j + 2 NW) in
+// flight, as many as remain below nj; they share the Vf operand.  Loads are
+// unconditional from clamped addresses (no branches in the loop): only the
+// A operand of a k past mA is set to zero; columns past K1 within a tile are
+// computed from clamped data and not stored.
+template <int NTL>
+__device__ inline void q_pass(const double* __restrict__ vq, int ldv, const double* __restrict__ Cf, int mA, int K1,
+                              int ns, const int (&c)[3], double* Q, int g) {
+  int d[NTL];
+#pragma unroll
+  for (int i = 0; i < NTL; ++i) d[i] = min(c[i], K1 - 1);
+  d4 acc[NTL];
+#pragma unroll
+  for (int i = 0; i < NTL; ++i) acc[i] = d4{0, 0, 0, 0};
+  // four k-steps per pass, their loads issued before the products (a step
+  // past ns has al >= mA: zero A operand)
+  for (int s0 = 0; s0 < ns; s0 += 4) {
+    double a[4], b[4][NTL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int al = 4 * (s0 + u) + g, ac = min(al, mA - 1);
+      const double* cr = Cf + (int64_t)ac * K1;
+      const double av = vq[(int64_t)ac * ldv];
+      a[u] = al < mA ? av : 0.0;
+#pragma unroll
+      for (int i = 0; i < NTL; ++i) b[u][i] = cr[d[i]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < NTL; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][i], acc[i], 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = (g + 4 * r) * K1;
+#pragma unroll
+    for (int i = 0; i < NTL; ++i)
+      if (c[i] < K1) Q[row + c[i]] = acc[i][r];
+  }
+}
+
 template <int NW>
 __device__ inline void q_tile(const double* __restrict__ Vf, int ldv, const double* __restrict__ Cf, int mA, int K1,
                               int t, double* Q, int w, int q, int g) {
   const int nj = (K1 + 15) >> 4, ns = (mA + 3) >> 2;
   const double* vq = Vf + 16 * t + q;
   for (int j0 = w; j0 < nj; j0 += 3 * NW) {
-    const int c0 = 16 * j0 + q, c1 = c0 + 16 * NW, c2 = c0 + 32 * NW;
-    const int d0 = min(c0, K1 - 1), d1 = min(c1, K1 - 1), d2 = min(c2, K1 - 1);
-    d4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0}, a2 = {0, 0, 0, 0};
-    // four k-steps per pass, their 16 loads issued before the products (a
-    // step past ns has al >= mA: zero A operand)
-    for (int s0 = 0; s0 < ns; s0 += 4) {
-      double a[4], b0[4], b1[4], b2[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int al = 4 * (s0 + u) + g, ac = min(al, mA - 1);
-        const double* cr = Cf + (int64_t)ac * K1;
-        const double av = vq[(int64_t)ac * ldv];
-        a[u] = al < mA ? av : 0.0;
-        b0[u] = cr[d0];
-        b1[u] = cr[d1];
-        b2[u] = cr[d2];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b0[u], a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b1[u], a1, 0, 0, 0);
-        a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b2[u], a2, 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = (g + 4 * i) * K1;
-      if (c0 < K1) Q[r + c0] = a0[i];
-      if (c1 < K1) Q[r + c1] = a1[i];
-      if (c2 < K1) Q[r + c2] = a2[i];
-    }
+    const int c[3] = {16 * j0 + q, 16 * (j0 + NW) + q, 16 * (j0 + 2 * NW) + q};
+    if (j0 + 2 * NW < nj)
+      q_pass<3>(vq, ldv, Cf, mA, K1, ns, c, Q, g);
+    else if (j0 + NW < nj)
+      q_pass<2>(vq, ldv, Cf, mA, K1, ns, c, Q, g);
+    else
+      q_pass<1>(vq, ldv, Cf, mA, K1, ns, c, Q, g);
   }
 }
 
