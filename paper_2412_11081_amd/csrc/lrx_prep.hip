@@ -15,11 +15,15 @@
 // from the derivative of M^-1 (Eq. V_inverse); on-site blocks do not move
 // with their atom, so their dC is zero.
 //
-// One workgroup per key (a grid of workgroups takes the keys in turn): M is
-// assembled in the workgroup's slice of a device workspace and factorised in
-// place, M = L L^T (left-looking, one thread per row of the current column);
-// L^-1 follows by forward substitution (one thread per column) and
-// M^-1 = L^-T L^-1 on the matrix cores.  The products with the right-hand
+// One workgroup per key (a grid of one workgroup per CU takes the keys in
+// turn).  For n <= 201 the lower triangle of M is assembled in LDS (packed
+// rows, n (n + 1) / 2 doubles, at most 158.6 KiB), factorised in place,
+// M = L L^T (left-looking, one thread per row of the current column), and
+// inverted in place, L -> L^-1 (column by column from the last, each column
+// a triangular product with the part already inverted, one thread per
+// row).  Larger M go through the workgroup's slice of a device workspace
+// with the same factorisation and L^-1 by forward substitution (one thread
+// per column).  M^-1 = L^-T L^-1 then runs on the matrix cores.  The products with the right-hand
 // sides -- C = M^-1 (P|phi phi), the derivative columns -dV C + dP, and
 // dC = M^-1 W -- are GEMMs on the matrix cores.  FP64 throughout; no atomics
 // but the error flag.
@@ -36,7 +40,10 @@
 
 namespace {
 
-constexpr int kPT = 256;
+constexpr int kPT = 512;
+constexpr int kTriMax = 201;                             // largest n whose packed triangle fits the LDS
+constexpr int kTriLds = kTriMax * (kTriMax + 1) / 2;     // doubles (162408 bytes)
+static_assert(kTriMax <= kPT, "one thread per row of the triangle");
 
 struct PrepItem {
   int A, F, onsite;
@@ -99,6 +106,70 @@ __device__ void invert_lower(const double* L, int n, double* Y) {
   }
 }
 
+// element (i, k), k <= i, of a packed lower triangle
+__device__ inline int tri(int i, int k) { return i * (i + 1) / 2 + k; }
+
+// L L^T = M for the packed lower triangle T (LDS) of an n x n matrix, n <=
+// kTriMax, in place: left-looking, thread i owns row i; returns false when
+// a pivot is not positive
+__device__ bool cholesky_tri(double* T, int n) {
+  const int i = threadIdx.x;
+  bool ok = true;
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+    if (i >= j && i < n) {
+      const double* ri = T + tri(i, 0);
+      const double* rj = T + tri(j, 0);
+      double s0 = ri[j], s1 = 0, s2 = 0, s3 = 0;
+      int k = 0;
+      for (; k + 4 <= j; k += 4) {
+        s0 -= ri[k] * rj[k];
+        s1 -= ri[k + 1] * rj[k + 1];
+        s2 -= ri[k + 2] * rj[k + 2];
+        s3 -= ri[k + 3] * rj[k + 3];
+      }
+      for (; k < j; ++k) s0 -= ri[k] * rj[k];
+      s = (s0 + s1) + (s2 + s3);
+      if (i == j) T[tri(j, j)] = s;
+    }
+    __syncthreads();
+    const double djj = T[tri(j, j)];
+    ok = ok && djj > 0.0;
+    const double d = djj > 0.0 ? sqrt(djj) : 1.0;
+    __syncthreads();
+    if (i >= j && i < n) T[tri(i, j)] = i == j ? d : s / d;
+    __syncthreads();
+  }
+  return ok;
+}
+
+// L -> L^-1 for the packed lower triangle T (LDS), in place: for j from the
+// last column down, Y(j,j) = 1 / L(j,j) and Y(i,j) = -Y(j,j) sum_{j<k<=i}
+// Y(i,k) L(k,j) for i > j (the columns right of j already hold Y); thread i
+// owns row i
+__device__ void invert_tri(double* T, int n) {
+  const int i = threadIdx.x;
+  for (int j = n - 1; j >= 0; --j) {
+    const double yjj = 1.0 / T[tri(j, j)];
+    double t = 0.0;
+    if (i > j && i < n) {
+      const double* yi = T + tri(i, 0);
+      double t0 = 0, t1 = 0;
+      int k = j + 1;
+      for (; k + 2 <= i + 1; k += 2) {
+        t0 += yi[k] * T[tri(k, j)];
+        t1 += yi[k + 1] * T[tri(k + 1, j)];
+      }
+      for (; k <= i; ++k) t0 += yi[k] * T[tri(k, j)];
+      t = t0 + t1;
+    }
+    __syncthreads();
+    if (i > j && i < n) T[tri(i, j)] = -yjj * t;
+    if (i == j) T[tri(j, j)] = yjj;
+    __syncthreads();
+  }
+}
+
 // C[i][j] = alpha sum_k A(i,k) B(k,j) (+ Cadd[i][j]) for i < M, j < N on the
 // matrix cores; A(i,k) = A[i sai + k sak], B(k,j) = B[k sbk + j sbj].  The
 // workgroup's four waves take 16 x 16 tiles in turn; f64 16x16x4 MFMA with
@@ -136,15 +207,17 @@ __device__ void wg_gemm(int M, int N, int K, const double* __restrict__ A, int64
   }
 }
 
-// Workspace of a workgroup: L (the factor, in place of M), Linv, Minv (each
-// nmax x nmax), then X [n][ld]: C in columns [0, K1), the derivative
-// right-hand sides W_x in columns K1 + x K1 + [0, K1).
+// Workspace of a workgroup: L (the factor, in place of M, when n >
+// kTriMax), Linv, Minv (each nmax x nmax), then X [n][ld]: C in columns
+// [0, K1), the derivative right-hand sides W_x in columns K1 + x K1 + [0,
+// K1).  Dynamic LDS: the packed triangle (kTriLds doubles).
 __global__ void __launch_bounds__(kPT) k_prep(const PrepItem* __restrict__ items, int nitem, const int* __restrict__ nao,
                                               const int* __restrict__ nabf, const double* __restrict__ Tval,
                                               const double* __restrict__ Tdval, const double* __restrict__ Vval,
                                               const double* __restrict__ Vdval, double* __restrict__ Cval,
                                               double* __restrict__ Cdval, double* __restrict__ ws, int64_t wsStride,
                                               int nmax, int* __restrict__ err) {
+  extern __shared__ double tl[];
   double* M = ws + blockIdx.x * wsStride;
   double* Li = M + (int64_t)nmax * nmax;
   double* Mi = Li + (int64_t)nmax * nmax;
@@ -157,18 +230,31 @@ __global__ void __launch_bounds__(kPT) k_prep(const PrepItem* __restrict__ items
     const double* VAA = Vval + it.vAA;
     const double* VFF = Vval + it.vFF;
     const double* VAF = Vval + it.vAF;
-    for (int64_t e = tid; e < (int64_t)n * n; e += kPT) {
-      const int i = (int)(e / n), j = (int)(e % n);
-      double v;
-      if (i < mA)
-        v = j < mA ? VAA[i * mA + j] : VAF[i * mF + (j - mA)];
-      else
-        v = j < mA ? VAF[j * mF + (i - mA)] : VFF[(i - mA) * mF + (j - mA)];
-      M[e] = v;
+    auto mval = [&](int i, int j) {
+      if (i < mA) return j < mA ? VAA[i * mA + j] : VAF[i * mF + (j - mA)];
+      return j < mA ? VAF[j * mF + (i - mA)] : VFF[(i - mA) * mF + (j - mA)];
+    };
+    if (n <= kTriMax) {
+      // lower triangle in LDS: row i holds j <= i
+      for (int e = tid; e < n * (n + 1) / 2; e += kPT) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        if (tri(i + 1, 0) <= e) ++i;       // guard the rounding of the root
+        if (tri(i, 0) > e) --i;
+        tl[e] = mval(i, e - tri(i, 0));
+      }
+      __syncthreads();
+      if (!cholesky_tri(tl, n) && tid == 0) atomicMax(err, 1);
+      invert_tri(tl, n);
+      for (int64_t e = tid; e < (int64_t)n * n; e += kPT) {
+        const int i = (int)(e / n), k = (int)(e % n);
+        Li[e] = k <= i ? tl[tri(i, k)] : 0.0;
+      }
+    } else {
+      for (int64_t e = tid; e < (int64_t)n * n; e += kPT) M[e] = mval((int)(e / n), (int)(e % n));
+      __syncthreads();
+      if (!cholesky(M, n) && tid == 0) atomicMax(err, 1);
+      invert_lower(M, n, Li);
     }
-    __syncthreads();
-    if (!cholesky(M, n) && tid == 0) atomicMax(err, 1);
-    invert_lower(M, n, Li);
     __syncthreads();
     // M^-1 = L^-T L^-1: Mi(i,j) = sum_k Li[k][i] Li[k][j]
     wg_gemm(n, n, n, Li, 1, n, Li, n, 1, 1.0, nullptr, 0, Mi, n);
@@ -269,7 +355,13 @@ extern "C" int lrx_prepare_c(int32_t device, int32_t natom, const int32_t* nao, 
   }
   if (flop) *flop = fl;
   if (T->nblk == 0) return LRX_OK;
-  const int grid = (int)std::min<int64_t>(T->nblk, 512);
+  // the triangle takes a CU's LDS: one workgroup per CU
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0) ncu = 256;
+  const int grid = (int)std::min<int64_t>(T->nblk, ncu);
+  const size_t lds = sizeof(double) * kTriLds;
+  if (hipFuncSetAttribute((const void*)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return LRX_EHIP;
   const int64_t wsStride = 3 * (int64_t)nmax * nmax + (int64_t)nmax * ldmax;
   DevMem dItems, dNao, dNabf, dWs, dErr, dTv, dTd, dVv, dVd, dCv, dCd;
   auto alloc = [](DevMem& m, size_t bytes) { return hipMalloc(&m.p, std::max<size_t>(bytes, 8)) == hipSuccess; };
@@ -301,7 +393,7 @@ extern "C" int lrx_prepare_c(int32_t device, int32_t natom, const int32_t* nao, 
       hipMemcpy(dNabf.p, nabf, sizeof(int) * natom, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(dErr.p, 0, sizeof(int)) != hipSuccess)
     return LRX_EHIP;
-  hipLaunchKernelGGL(k_prep, dim3(grid), dim3(kPT), 0, nullptr, (const PrepItem*)dItems.p, (int)T->nblk,
+  hipLaunchKernelGGL(k_prep, dim3(grid), dim3(kPT), lds, nullptr, (const PrepItem*)dItems.p, (int)T->nblk,
                      (const int*)dNao.p, (const int*)dNabf.p, tv, td, vv, vd, cv, cd, (double*)dWs.p, wsStride, nmax,
                      (int*)dErr.p);
   if (hipGetLastError() != hipSuccess) return LRX_EHIP;
