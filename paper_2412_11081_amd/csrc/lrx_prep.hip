@@ -172,38 +172,55 @@ __device__ void invert_tri(double* T, int n) {
 
 // C[i][j] = alpha sum_k A(i,k) B(k,j) (+ Cadd[i][j]) for i < M, j < N on the
 // matrix cores; A(i,k) = A[i sai + k sak], B(k,j) = B[k sbk + j sbj].  The
-// workgroup's four waves take 16 x 16 tiles in turn; f64 16x16x4 MFMA with
-// lane (q, g): A[m = q][k = g], B[k = g][n = q], result r is row g + 4 r.
-// Operands are read from clamped addresses (no branches); the A operand of a
-// k past K is zero; rows and columns past M, N are not stored.  The loads of
-// four k-steps are issued before their products.
+// workgroup's waves take 32 x 32 blocks in turn, four 16 x 16 tiles that
+// share their A and B fragments; f64 16x16x4 MFMA with lane (q, g):
+// A[m = q][k = g], B[k = g][n = q], result r is row g + 4 r.  Operands are
+// read from clamped addresses (no branches); the A operand of a k past K is
+// zero; rows and columns past M, N are not stored.  The loads of four
+// k-steps are issued before their products.
 __device__ void wg_gemm(int M, int N, int K, const double* __restrict__ A, int64_t sai, int64_t sak,
                         const double* __restrict__ B, int64_t sbk, int64_t sbj, double alpha, const double* Cadd,
                         int64_t ldadd, double* C, int64_t ldc) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane & 15, g = lane >> 4;
-  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, ns = (K + 3) >> 2;
-  for (int tile = w; tile < tm * tn; tile += kPT / 64) {
-    const int i0 = 16 * (tile / tn), j0 = 16 * (tile % tn);
-    const double* ap = A + (int64_t)min(i0 + q, M - 1) * sai;
-    const double* bp = B + (int64_t)min(j0 + q, N - 1) * sbj;
-    d4 acc = {0, 0, 0, 0};
+  const int tm = (M + 31) >> 5, tn = (N + 31) >> 5, ns = (K + 3) >> 2;
+  for (int blk = w; blk < tm * tn; blk += kPT / 64) {
+    const int i0 = 32 * (blk / tn), j0 = 32 * (blk % tn);
+    const double* ap[2] = {A + (int64_t)min(i0 + q, M - 1) * sai, A + (int64_t)min(i0 + 16 + q, M - 1) * sai};
+    const double* bp[2] = {B + (int64_t)min(j0 + q, N - 1) * sbj, B + (int64_t)min(j0 + 16 + q, N - 1) * sbj};
+    d4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
     for (int s0 = 0; s0 < ns; s0 += 4) {
-      double a[4], b[4];
+      double a[4][2], b[4][2];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int k = 4 * (s0 + u) + g, kc = min(k, K - 1);
-        const double av = ap[(int64_t)kc * sak];
-        a[u] = k < K ? av : 0.0;
-        b[u] = bp[(int64_t)kc * sbk];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const double av = ap[x][(int64_t)kc * sak];
+          a[u][x] = k < K ? av : 0.0;
+          b[u][x] = bp[x][(int64_t)kc * sbk];
+        }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][x], b[u][y], acc[x][y], 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + g + 4 * r, j = j0 + q;
-      if (i < M && j < N) C[(int64_t)i * ldc + j] = alpha * acc[r] + (Cadd ? Cadd[(int64_t)i * ldadd + j] : 0.0);
-    }
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + 16 * x + g + 4 * r, j = j0 + 16 * y + q;
+          if (i < M && j < N)
+            C[(int64_t)i * ldc + j] = alpha * acc[x][y][r] + (Cadd ? Cadd[(int64_t)i * ldadd + j] : 0.0);
+        }
   }
 }
 
