@@ -18,7 +18,7 @@
 // One workgroup per key (a grid of one workgroup per CU takes the keys in
 // turn).  For n <= 201 the lower triangle of M is assembled in LDS (packed
 // rows, n (n + 1) / 2 doubles, at most 158.6 KiB), factorised in place,
-// M = L L^T (left-looking, one thread per row of the current column), and
+// M = L L^T (right-looking, the trailing update spread over the workgroup), and
 // inverted in place, L -> L^-1 (column by column from the last, each column
 // a triangular product with the part already inverted, one thread per
 // row).  Larger M go through the workgroup's slice of a device workspace
@@ -110,34 +110,26 @@ __device__ void invert_lower(const double* L, int n, double* Y) {
 __device__ inline int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 
 // L L^T = M for the packed lower triangle T (LDS) of an n x n matrix, n <=
-// kTriMax, in place: left-looking, thread i owns row i; returns false when
-// a pivot is not positive
+// kTriMax, in place, right-looking: column j is scaled by the root of its
+// updated pivot, then the trailing triangle takes the rank-one update
+// T(i,k) -= L(i,j) L(k,j), j < k <= i, eight threads per row; returns
+// false when a pivot is not positive
 __device__ bool cholesky_tri(double* T, int n) {
-  const int i = threadIdx.x;
+  const int tid = threadIdx.x, sub = tid & 7;
   bool ok = true;
   for (int j = 0; j < n; ++j) {
-    double s = 0.0;
-    if (i >= j && i < n) {
-      const double* ri = T + tri(i, 0);
-      const double* rj = T + tri(j, 0);
-      double s0 = ri[j], s1 = 0, s2 = 0, s3 = 0;
-      int k = 0;
-      for (; k + 4 <= j; k += 4) {
-        s0 -= ri[k] * rj[k];
-        s1 -= ri[k + 1] * rj[k + 1];
-        s2 -= ri[k + 2] * rj[k + 2];
-        s3 -= ri[k + 3] * rj[k + 3];
-      }
-      for (; k < j; ++k) s0 -= ri[k] * rj[k];
-      s = (s0 + s1) + (s2 + s3);
-      if (i == j) T[tri(j, j)] = s;
-    }
-    __syncthreads();
     const double djj = T[tri(j, j)];
     ok = ok && djj > 0.0;
     const double d = djj > 0.0 ? sqrt(djj) : 1.0;
+    __syncthreads();   // every thread has read the pivot
+    for (int i = j + 1 + tid; i < n; i += kPT) T[tri(i, j)] /= d;
+    if (tid == 0) T[tri(j, j)] = d;
     __syncthreads();
-    if (i >= j && i < n) T[tri(i, j)] = i == j ? d : s / d;
+    for (int i = j + 1 + (tid >> 3); i < n; i += kPT / 8) {
+      const double lij = T[tri(i, j)];
+      double* ri = T + tri(i, 0);
+      for (int k = j + 1 + sub; k <= i; k += 8) ri[k] -= lij * T[tri(k, j)];
+    }
     __syncthreads();
   }
   return ok;
