@@ -18,13 +18,15 @@
 // One workgroup per key (a grid of one workgroup per CU takes the keys in
 // turn).  For n <= 201 the lower triangle of M is assembled in LDS (packed
 // rows, n (n + 1) / 2 doubles, at most 158.6 KiB), factorised in place,
-// M = L L^T (right-looking, the trailing update spread over the workgroup), and
-// inverted in place, L -> L^-1 (column by column from the last, each column
-// a triangular product with the part already inverted, one thread per
-// row).  Larger M go through the workgroup's slice of a device workspace
-// with the same factorisation and L^-1 by forward substitution (one thread
-// per column).  M^-1 = L^-T L^-1 then runs on the matrix cores.  The products with the right-hand
-// sides -- C = M^-1 (P|phi phi), the derivative columns -dV C + dP, and
+// M = L L^T (right-looking, the trailing update spread over the
+// workgroup), and inverted in place, L -> L^-1 (column by column from the
+// last, each column a triangular product with the part already inverted,
+// eight threads per row).  Larger M go through the workgroup's slice of a
+// device workspace: a left-looking factorisation (one thread per row of
+// the current column) and L^-1 by forward substitution (one thread per
+// column).  M^-1 = L^-T L^-1 then runs on the matrix cores.  The products
+// with the right-hand sides -- C = M^-1 (P|phi phi), the derivative
+// columns -dV C + dP, and
 // dC = M^-1 W -- are GEMMs on the matrix cores.  FP64 throughout; no atomics
 // but the error flag.
 #include <hip/hip_runtime.h>
@@ -43,7 +45,6 @@ namespace {
 constexpr int kPT = 512;
 constexpr int kTriMax = 201;                             // largest n whose packed triangle fits the LDS
 constexpr int kTriLds = kTriMax * (kTriMax + 1) / 2;     // doubles (162408 bytes)
-static_assert(kTriMax <= kPT, "one thread per row of the triangle");
 
 struct PrepItem {
   int A, F, onsite;
@@ -137,27 +138,36 @@ __device__ bool cholesky_tri(double* T, int n) {
 
 // L -> L^-1 for the packed lower triangle T (LDS), in place: for j from the
 // last column down, Y(j,j) = 1 / L(j,j) and Y(i,j) = -Y(j,j) sum_{j<k<=i}
-// Y(i,k) L(k,j) for i > j (the columns right of j already hold Y); thread i
-// owns row i
+// Y(i,k) L(k,j) for i > j (the columns right of j already hold Y); eight
+// threads per row take every eighth k and add their partial sums with lane
+// shuffles, 64 rows per pass
 __device__ void invert_tri(double* T, int n) {
-  const int i = threadIdx.x;
+  static_assert(kTriMax - 1 <= 4 * (kPT / 8), "four passes of kPT / 8 rows");
+  const int tid = threadIdx.x, sub = tid & 7;
   for (int j = n - 1; j >= 0; --j) {
     const double yjj = 1.0 / T[tri(j, j)];
-    double t = 0.0;
-    if (i > j && i < n) {
-      const double* yi = T + tri(i, 0);
-      double t0 = 0, t1 = 0;
-      int k = j + 1;
-      for (; k + 2 <= i + 1; k += 2) {
-        t0 += yi[k] * T[tri(k, j)];
-        t1 += yi[k + 1] * T[tri(k + 1, j)];
+    double t[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int i = j + 1 + (tid >> 3) + (kPT / 8) * p;
+      double acc = 0.0;
+      if (i < n) {
+        const double* yi = T + tri(i, 0);
+        for (int k = j + 1 + sub; k <= i; k += 8) acc += yi[k] * T[tri(k, j)];
       }
-      for (; k <= i; ++k) t0 += yi[k] * T[tri(k, j)];
-      t = t0 + t1;
+      t[p] = acc;
     }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int o = 4; o > 0; o >>= 1) t[p] += __shfl_xor(t[p], o, 64);
     __syncthreads();
-    if (i > j && i < n) T[tri(i, j)] = -yjj * t;
-    if (i == j) T[tri(j, j)] = yjj;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int i = j + 1 + (tid >> 3) + (kPT / 8) * p;
+      if (i < n && sub == 0) T[tri(i, j)] = -yjj * t[p];
+    }
+    if (tid == 0) T[tri(j, j)] = yjj;
     __syncthreads();
   }
 }
