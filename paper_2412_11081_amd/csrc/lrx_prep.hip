@@ -226,6 +226,61 @@ __device__ void wg_gemm(int M, int N, int K, const double* __restrict__ A, int64
   }
 }
 
+// Mi = L^-T L^-1 for the lower-triangular n x n Y = L^-1 (row-major):
+// Mi(i,j) = sum_{k >= max(i,j)} Y[k][i] Y[k][j].  The 32 x 32 blocks on and
+// below the diagonal are formed, as in wg_gemm, with their depth starting
+// at the block's first row (the terms before it are products with exact
+// zeros of Y); a block below the diagonal is also written to its mirror
+// position (one writer per element).
+__device__ void wg_ltl(int n, const double* __restrict__ Y, double* Mi) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane & 15, g = lane >> 4;
+  const int tm = (n + 31) >> 5, ns = (n + 3) >> 2;
+  for (int blk = w; blk < tm * (tm + 1) / 2; blk += kPT / 64) {
+    int bi = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+    if ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;    // guard the rounding of the root
+    if (bi * (bi + 1) / 2 > blk) --bi;
+    const int bj = blk - bi * (bi + 1) / 2, i0 = 32 * bi, j0 = 32 * bj;
+    const double* ap[2] = {Y + min(i0 + q, n - 1), Y + min(i0 + 16 + q, n - 1)};
+    const double* bp[2] = {Y + min(j0 + q, n - 1), Y + min(j0 + 16 + q, n - 1)};
+    d4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+    for (int s0 = i0 / 4; s0 < ns; s0 += 4) {
+      double a[4][2], b[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 4 * (s0 + u) + g, kc = min(k, n - 1);
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const double av = ap[x][(int64_t)kc * n];
+          a[u][x] = k < n ? av : 0.0;
+          b[u][x] = bp[x][(int64_t)kc * n];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][x], b[u][y], acc[x][y], 0, 0, 0);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + 16 * x + g + 4 * r, j = j0 + 16 * y + q;
+          if (i < n && j < n) {
+            Mi[(int64_t)i * n + j] = acc[x][y][r];
+            if (bi != bj) Mi[(int64_t)j * n + i] = acc[x][y][r];   // a diagonal block holds both
+          }
+        }
+  }
+}
+
 // Workspace of a workgroup: L (the factor, in place of M, when n >
 // kTriMax), Linv, Minv (each nmax x nmax), then X [n][ld]: C in columns
 // [0, K1), the derivative right-hand sides W_x in columns K1 + x K1 + [0,
@@ -276,7 +331,7 @@ __global__ void __launch_bounds__(kPT) k_prep(const PrepItem* __restrict__ items
     }
     __syncthreads();
     // M^-1 = L^-T L^-1: Mi(i,j) = sum_k Li[k][i] Li[k][j]
-    wg_gemm(n, n, n, Li, 1, n, Li, n, 1, 1.0, nullptr, 0, Mi, n);
+    wg_ltl(n, Li, Mi);
     __syncthreads();
     // C = M^-1 (P|phi phi)  [n][K1]
     const double* T = Tval + it.t;
