@@ -33,9 +33,8 @@
 
 #include <algorithm>
 #include <cmath>
-#include <map>
 #include <string>
-#include <tuple>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/lrx.h"
@@ -385,11 +384,33 @@ extern "C" int lrx_prepare_c(int32_t device, int32_t natom, const int32_t* nao, 
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LRX_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return LRX_EHIP;
   // V keys -> block
-  std::map<std::tuple<int, int, int, int, int>, int64_t> vk;
+  // the V keys that the C keys use -- V(A,A,0), V(F,F,0), V(A,F,R) -- in a
+  // hash, filled in one pass over V's keys (the last of equal keys wins)
+  struct Key {
+    int f, s, r0, r1, r2;
+    bool operator==(const Key& o) const { return f == o.f && s == o.s && r0 == o.r0 && r1 == o.r1 && r2 == o.r2; }
+  };
+  struct KeyHash {
+    size_t operator()(const Key& k) const {   // FNV-1a over the five fields
+      uint64_t h = 1469598103934665603ull;
+      for (int x : {k.f, k.s, k.r0, k.r1, k.r2}) h = (h ^ (uint32_t)x) * 1099511628211ull;
+      return (size_t)h;
+    }
+  };
+  std::unordered_map<Key, int64_t, KeyHash> vk;
+  vk.reserve((size_t)(3 * T->nblk + 16));
+  for (int64_t b = 0; b < T->nblk; ++b) {
+    const int A = T->first[b], F = T->second[b];
+    if (A < 0 || A >= natom || F < 0 || F >= natom) return LRX_EINVAL;
+    vk.emplace(Key{A, A, 0, 0, 0}, -1);
+    vk.emplace(Key{F, F, 0, 0, 0}, -1);
+    vk.emplace(Key{A, F, T->R[3 * b], T->R[3 * b + 1], T->R[3 * b + 2]}, -1);
+  }
   for (int64_t i = 0; i < V->nblk; ++i) {
     const int f = V->first[i], s = V->second[i];
     if (f < 0 || f >= natom || s < 0 || s >= natom) return LRX_EINVAL;
-    vk[{f, s, V->R[3 * i], V->R[3 * i + 1], V->R[3 * i + 2]}] = i;
+    const auto q = vk.find(Key{f, s, V->R[3 * i], V->R[3 * i + 1], V->R[3 * i + 2]});
+    if (q != vk.end()) q->second = i;
   }
   auto vsize = [&](int64_t i) { return (int64_t)nabf[V->first[i]] * nabf[V->second[i]]; };
   for (int64_t i = 0; i < V->nblk; ++i)
@@ -410,8 +431,8 @@ extern "C" int lrx_prepare_c(int32_t device, int32_t natom, const int32_t* nao, 
     if (T->off[b] < 0 || T->off[b] + (int64_t)n * K1 > T->nval) return LRX_EINVAL;
     it.t = T->off[b];
     auto find = [&](int f, int s, int a, int c, int d, int64_t* off) {
-      auto q = vk.find({f, s, a, c, d});
-      if (q == vk.end()) return false;
+      const auto q = vk.find(Key{f, s, a, c, d});
+      if (q == vk.end() || q->second < 0) return false;
       *off = V->off[q->second];
       return true;
     };
