@@ -807,9 +807,11 @@ void build_tensors(lrx_ctx* c, const lrx_blocks* C, const lrx_blocks* V, const d
   d.slotB = c->upload(c->slotB); d.slotX = c->upload(c->slotX); d.hOff = c->upload(hOff);
   d.hSlotMap = c->upload(slotmap);
   {
-    std::vector<int> byX(nSlot);
-    for (int s = 0; s < nSlot; ++s) byX[s] = s;
-    std::stable_sort(byX.begin(), byX.end(), [&](int a, int b) { return c->slotX[a] < c->slotX[b]; });
+    // counting sort by X, stable: slots of one X keep their (B) order
+    std::vector<int> at(N + 1, 0), byX(nSlot);
+    for (int s = 0; s < nSlot; ++s) at[c->slotX[s] + 1]++;
+    for (int x = 0; x < N; ++x) at[x + 1] += at[x];
+    for (int s = 0; s < nSlot; ++s) byX[at[c->slotX[s]]++] = s;
     d.slotByX = c->upload(byX);
   }
   d.need = c->dalloc<uint8_t>(nSlot);
