@@ -172,57 +172,63 @@ __device__ void invert_tri(double* T, int n) {
 }
 
 // C[i][j] = alpha sum_k A(i,k) B(k,j) (+ Cadd[i][j]) for i < M, j < N on the
-// matrix cores; A(i,k) = A[i sai + k sak], B(k,j) = B[k sbk + j sbj].  The
-// workgroup's waves take 32 x 32 blocks in turn, four 16 x 16 tiles that
-// share their A and B fragments; f64 16x16x4 MFMA with lane (q, g):
+// matrix cores; A(i,k) = A[i sai + k sak], B(k,j) = B[k sbk + j sbj].  A
+// wave forms one 32 x 32 block at (i0, j0), four 16 x 16 tiles that share
+// their A and B fragments; f64 16x16x4 MFMA with lane (q, g):
 // A[m = q][k = g], B[k = g][n = q], result r is row g + 4 r.  Operands are
 // read from clamped addresses (no branches); the A operand of a k past K is
 // zero; rows and columns past M, N are not stored.  The loads of four
 // k-steps are issued before their products.
+__device__ inline void gemm_block(int M, int N, int K, const double* __restrict__ A, int64_t sai, int64_t sak,
+                                  const double* __restrict__ B, int64_t sbk, int64_t sbj, double alpha,
+                                  const double* Cadd, int64_t ldadd, double* C, int64_t ldc, int i0, int j0) {
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
+  const int ns = (K + 3) >> 2;
+  const double* ap[2] = {A + (int64_t)min(i0 + q, M - 1) * sai, A + (int64_t)min(i0 + 16 + q, M - 1) * sai};
+  const double* bp[2] = {B + (int64_t)min(j0 + q, N - 1) * sbj, B + (int64_t)min(j0 + 16 + q, N - 1) * sbj};
+  d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  for (int s0 = 0; s0 < ns; s0 += 4) {
+    double a[4][2], b[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * (s0 + u) + g, kc = min(k, K - 1);
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const double av = ap[x][(int64_t)kc * sak];
+        a[u][x] = k < K ? av : 0.0;
+        b[u][x] = bp[x][(int64_t)kc * sbk];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][x], b[u][y], acc[x][y], 0, 0, 0);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * x + g + 4 * r, j = j0 + 16 * y + q;
+        if (i < M && j < N)
+          C[(int64_t)i * ldc + j] = alpha * acc[x][y][r] + (Cadd ? Cadd[(int64_t)i * ldadd + j] : 0.0);
+      }
+}
+
+// one product, its 32 x 32 blocks taken by the workgroup's waves in turn
 __device__ void wg_gemm(int M, int N, int K, const double* __restrict__ A, int64_t sai, int64_t sak,
                         const double* __restrict__ B, int64_t sbk, int64_t sbj, double alpha, const double* Cadd,
                         int64_t ldadd, double* C, int64_t ldc) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane & 15, g = lane >> 4;
-  const int tm = (M + 31) >> 5, tn = (N + 31) >> 5, ns = (K + 3) >> 2;
-  for (int blk = w; blk < tm * tn; blk += kPT / 64) {
-    const int i0 = 32 * (blk / tn), j0 = 32 * (blk % tn);
-    const double* ap[2] = {A + (int64_t)min(i0 + q, M - 1) * sai, A + (int64_t)min(i0 + 16 + q, M - 1) * sai};
-    const double* bp[2] = {B + (int64_t)min(j0 + q, N - 1) * sbj, B + (int64_t)min(j0 + 16 + q, N - 1) * sbj};
-    d4 acc[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
-    for (int s0 = 0; s0 < ns; s0 += 4) {
-      double a[4][2], b[4][2];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = 4 * (s0 + u) + g, kc = min(k, K - 1);
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          const double av = ap[x][(int64_t)kc * sak];
-          a[u][x] = k < K ? av : 0.0;
-          b[u][x] = bp[x][(int64_t)kc * sbk];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][x], b[u][y], acc[x][y], 0, 0, 0);
-    }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = i0 + 16 * x + g + 4 * r, j = j0 + 16 * y + q;
-          if (i < M && j < N)
-            C[(int64_t)i * ldc + j] = alpha * acc[x][y][r] + (Cadd ? Cadd[(int64_t)i * ldadd + j] : 0.0);
-        }
-  }
+  const int w = threadIdx.x >> 6, tm = (M + 31) >> 5, tn = (N + 31) >> 5;
+  for (int blk = w; blk < tm * tn; blk += kPT / 64)
+    gemm_block(M, N, K, A, sai, sak, B, sbk, sbj, alpha, Cadd, ldadd, C, ldc, 32 * (blk / tn), 32 * (blk % tn));
 }
 
 // Mi = L^-T L^-1 for the lower-triangular n x n Y = L^-1 (row-major):
@@ -341,18 +347,29 @@ __global__ void __launch_bounds__(kPT) k_prep(const PrepItem* __restrict__ items
       //   rows of A: dP_x[top] - dV_x C[rows of F];  rows of F: dP_x[bottom] - dV_x^T C[rows of A]
       const double* dV = Vdval + 3 * it.vAF;
       const double* dP = Tdval + 3 * it.t;
-      for (int x = 0; x < 3; ++x) {
+      // the blocks of the six products (two per x) in one loop over the waves
+      const int w = tid >> 6, tn = (K1 + 31) >> 5;
+      const int nbA = ((mA + 31) >> 5) * tn, nbF = ((mF + 31) >> 5) * tn;
+      for (int blk = w; blk < 3 * (nbA + nbF); blk += kPT / 64) {
+        const int x = blk / (nbA + nbF), r = blk % (nbA + nbF);
         const double* dVx = dV + (int64_t)x * mA * mF;
         const double* dPx = dP + (int64_t)x * n * K1;
         double* Wx = X + K1 + (int64_t)x * K1;
-        wg_gemm(mA, K1, mF, dVx, mF, 1, X + (int64_t)mA * ld, ld, 1, -1.0, dPx, K1, Wx, ld);
-        wg_gemm(mF, K1, mA, dVx, 1, mF, X, ld, 1, -1.0, dPx + (int64_t)mA * K1, K1, Wx + (int64_t)mA * ld, ld);
+        if (r < nbA)
+          gemm_block(mA, K1, mF, dVx, mF, 1, X + (int64_t)mA * ld, ld, 1, -1.0, dPx, K1, Wx, ld, 32 * (r / tn),
+                     32 * (r % tn));
+        else
+          gemm_block(mF, K1, mA, dVx, 1, mF, X, ld, 1, -1.0, dPx + (int64_t)mA * K1, K1, Wx + (int64_t)mA * ld, ld,
+                     32 * ((r - nbA) / tn), 32 * ((r - nbA) % tn));
       }
       __syncthreads();
-      // dC of the key (rows of A): M^-1[rows of A] W_x, straight to the output
-      for (int x = 0; x < 3; ++x)
-        wg_gemm(mA, K1, n, Mi, n, 1, X + K1 + (int64_t)x * K1, ld, 1, 1.0, nullptr, 0,
-                Cdval + 3 * it.c + (int64_t)x * mA * K1, K1);
+      // dC of the key (rows of A): M^-1[rows of A] W_x, straight to the
+      // output; the blocks of the three products in one loop
+      for (int blk = w; blk < 3 * nbA; blk += kPT / 64) {
+        const int x = blk / nbA, r = blk % nbA;
+        gemm_block(mA, K1, n, Mi, n, 1, X + K1 + (int64_t)x * K1, ld, 1, 1.0, nullptr, 0,
+                   Cdval + 3 * it.c + (int64_t)x * mA * K1, K1, 32 * (r / tn), 32 * (r % tn));
+      }
     }
     // the key's block: the rows of A
     for (int64_t e = tid; e < (int64_t)mA * K1; e += kPT) Cval[it.c + e] = X[(e / K1) * ld + e % K1];
