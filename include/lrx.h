@@ -362,8 +362,10 @@ int lrx_hamiltonian_info(lrx_ctx* ctx, float* ms, double* flop);
  * FLOPs (n^3 / 3 for the factorisation, 2 n^2 per right-hand side column,
  * 12 mA mF nA nF for the products with dV).  Returns LRX_EINVAL for bad
  * arguments, a missing V block or an M that is not positive definite.  Uses
- * device memory of its own (a workspace of up to 512 x n_max (n_max + 4
- * nA nF max) doubles) for the duration of the call. */
+ * device memory of its own for the duration of the call: a workspace of
+ * one slice per CU of the device, 3 n_max^2 + 4 n_max (nA nF)_max doubles
+ * each (n_max = the largest mA + mF), and one workgroup per CU that takes
+ * the CU's LDS. */
 int lrx_prepare_c(int32_t device, int32_t natom, const int32_t* nao, const int32_t* nabf, const lrx_blocks* V,
                   const lrx_blocks* T, int32_t on_device, double* Cval, double* Cdval, double* flop);
 
