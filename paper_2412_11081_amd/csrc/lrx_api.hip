@@ -1815,6 +1815,34 @@ int lrx_hamiltonian(lrx_ctx* c, const lrx_options* opts, double* E, double* Hx, 
       c->hx.Hx = c->dalloc<double>(nt * nt);
       c->hx.Etile = c->dalloc<double>(lrx::hx_tiles(nt));
       c->hx.E = c->dalloc<double>(1);
+      {
+        // the D blocks (G,X) that G3 can reach: X of an H slot (B,X) of a C
+        // partner B of G (slots are stored by B), in (G, X-first-seen) order,
+        // split by the 16-wide tile count of max(nG, nX)
+        const int N = c->N;
+        require((int64_t)N * N < ((int64_t)1 << 31), "lrx_hamiltonian: more than 46340 atoms");
+        const int nSlot = (int)c->slotB.size();
+        std::vector<int> srow(N + 1, 0);
+        for (int s = 0; s < nSlot; ++s) srow[c->slotB[s] + 1]++;
+        for (int B = 0; B < N; ++B) srow[B + 1] += srow[B];
+        std::vector<int> blk[2];
+        std::vector<int> seen(N, -1);
+        for (int G = 0; G < N; ++G)
+          for (int i = c->cp.row[G]; i < c->cp.row[G + 1]; ++i) {
+            const int B = c->cp.pB[i];
+            for (int s = srow[B]; s < srow[B + 1]; ++s) {
+              const int X = c->slotX[s];
+              if (seen[X] == G) continue;
+              seen[X] = G;
+              blk[std::max(c->nao[G], c->nao[X]) > 16].push_back(G * N + X);
+            }
+          }
+        for (int k = 0; k < 2; ++k) {
+          require(blk[k].size() < ((size_t)1 << 31), "lrx_hamiltonian: too many D blocks");
+          c->hx.n3[k] = (int)blk[k].size();
+          c->hx.g3blk[k] = c->upload(blk[k]);
+        }
+      }
       c->have_hx = true;
     }
     const lrx::Opts o = make_opts(opts);

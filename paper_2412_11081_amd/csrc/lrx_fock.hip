@@ -339,13 +339,17 @@ __global__ void __launch_bounds__(64 * NW, slot_waves_per_simd(NTB, NTX))
 // takes beta = w, w + 4, ...; the four partial tiles are added in wave
 // order.  NT: 16-wide tiles for g and
 // x; the launch for NT takes the blocks with 16 (NT - 1) < max(nG, nX) <=
-// 16 NT.  Every D block (G,X) is written by one workgroup (zeros when
-// nothing reaches it).
+// 16 NT.  The launch covers the listed blocks (G,X) that a C partner B of
+// G reaches through an H slot (B,X); each is written by one workgroup
+// (zeros when nothing reaches it at this screening), the others stay at
+// the zeros G3 is filled with.
 template <int NT>
-__global__ void __launch_bounds__(kHxNT) k_hx_g3(Dev d, const double* __restrict__ Hbar, double* __restrict__ G3) {
+__global__ void __launch_bounds__(kHxNT) k_hx_g3(Dev d, const int* __restrict__ blocks, const double* __restrict__ Hbar,
+                                                 double* __restrict__ G3) {
   __shared__ double red[4 * NT * NT * 256];
   const int N = d.N;
-  const int G = blockIdx.x / N, X = blockIdx.x % N;
+  const int o = blocks[blockIdx.x];
+  const int G = o / N, X = o % N;
   const int64_t nt = d.ntot;
   const int nG = d.nao[G], nX = d.nao[X];
   const int ngx = max(nG, nX);
@@ -496,6 +500,7 @@ int64_t hx_tiles(int64_t ntot) {
 void launch_hx(const Dev& d, const HxBufs& b, hipStream_t s, hipEvent_t* ev) {
   const int64_t nt = d.ntot;
   hipLaunchKernelGGL(k_fill_f64, dim3(2048), dim3(256), 0, s, b.G12, nt * nt);
+  hipLaunchKernelGGL(k_fill_f64, dim3(2048), dim3(256), 0, s, b.G3, nt * nt);
   if (d.nSlot > 0) {
     const int nmax = b.nmax;
     // per launch (NTB, NTX): Q tile rows (or the G partials of the NW
@@ -529,11 +534,12 @@ void launch_hx(const Dev& d, const HxBufs& b, hipStream_t s, hipEvent_t* ev) {
     }
   }
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_hx_g3<1>, dim3((unsigned)((int64_t)d.N * d.N)), dim3(kHxNT), 0, s, d, (const double*)b.Hbar,
-                     b.G3);
-  if (b.nmax > 16)
-    hipLaunchKernelGGL(k_hx_g3<2>, dim3((unsigned)((int64_t)d.N * d.N)), dim3(kHxNT), 0, s, d,
-                       (const double*)b.Hbar, b.G3);
+  if (b.n3[0] > 0)
+    hipLaunchKernelGGL(k_hx_g3<1>, dim3((unsigned)b.n3[0]), dim3(kHxNT), 0, s, d, b.g3blk[0], (const double*)b.Hbar,
+                       b.G3);
+  if (b.n3[1] > 0)
+    hipLaunchKernelGGL(k_hx_g3<2>, dim3((unsigned)b.n3[1]), dim3(kHxNT), 0, s, d, b.g3blk[1], (const double*)b.Hbar,
+                       b.G3);
   if (ev) (void)hipEventRecord(ev[1], s);
   const int64_t nf = hx_tiles(nt);
   hipLaunchKernelGGL(k_hx_final, dim3((unsigned)nf), dim3(kHxNT), 0, s, d, (const double*)b.G12,

@@ -282,6 +282,8 @@ struct HxBufs {
   double* E;       // [1] <H^X, D> / 2
   int kmax;        // largest n_A n_X over the C pairs (Q tile row length)
   int nmax;        // largest NAO count of an atom
+  const int* g3blk[2];   // D blocks G N + X that G3 can reach, by 16-wide tile count of max(nG, nX)
+  int n3[2];
 };
 int64_t hx_tiles(int64_t ntot);
 // after launch_screen(..., for_hx = true) and the FP64 H build; ev
