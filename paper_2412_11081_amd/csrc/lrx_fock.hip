@@ -25,9 +25,11 @@
 //               D block (X,B) of G1 + G2.  Q tiles of 16 beta rows on the
 //               matrix cores (operands from global memory, result in LDS),
 //               then the contractions with the staged D block and H slice,
-//               also on the matrix cores.
-//   k_hx_g3     one workgroup per D block (G,X): G3 over the C partners B,
-//               on the matrix cores.
+//               also on the matrix cores.  Four launches by the 16-wide
+//               tile counts of b and x; slots in (X, B) order per XCD.
+//   k_hx_g3     one workgroup per D block (G,X) that a C partner B of G
+//               reaches through an H slot (B,X): G3 over those B, on the
+//               matrix cores.
 //   k_hx_final  32 x 32 tiles: (G + G^T) / 2 on kept D pairs, and the tile's
 //               share of <H^X, D> / 2; k_hx_sum adds the shares in order.
 // No atomics: every output element has one writer, so two calls agree bit
@@ -127,9 +129,10 @@ __device__ inline void q_tile(const double* __restrict__ Vf, int ldv, const doub
 //   G tile:             acc_g[x][b] += sum_{beta, k} Q[beta][qi(x, k)] Hb[b][beta][k]
 // qi(x, k) = k nX + x for the first kind of triple (k = a), x nF + k for the
 // second (k = f); NTB and NTX 16-wide tiles cover b and x; of NW waves, a
-// wave takes beta = w + NW j, j < 16 / NW.  As in q_tile, loads come from
-// clamped addresses; the Ds and Hb operands of a k past nk (and Ds when the
-// D pair is screened) are zero, rows and columns past nB, nX are not stored.
+// wave takes beta = w + NW j, j < 16 / NW.  The loads of two k-steps are
+// issued before their products; as in q_tile, they come from clamped
+// addresses; the Ds and Hb operands of a k past nk (and Ds when the D pair
+// is screened) are zero, rows and columns past nB, nX are not stored.
 template <int NTB, int NTX, int NW>
 __device__ inline void contract_triple(const double* __restrict__ Q, int K1, const double* __restrict__ Ds,
                                        const double* __restrict__ Hb, bool with_d, int nk, int nB, int nX,
