@@ -23,6 +23,7 @@ CELLS = [
     (4, 3, 7, 20, 8.0, 5.0, 8.0, 52),
     (2, 1, 13, 40, 9.0, 5.0, 8.0, 53),
     (3, 2, 22, 33, 9.0, 5.0, 8.0, 54),
+    (2, 1, 3, 100, 7.0, 5.0, 8.0, 56),   # four pair keys of n = 200: the LDS triangle near its 201-row limit
     (2, 1, 3, 110, 7.0, 5.0, 8.0, 55),   # four pair keys of n = 220 > 201: M in the device workspace
 ]
 REL = 1e-10
